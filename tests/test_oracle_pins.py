@@ -1,0 +1,362 @@
+"""Pins of the CPU oracle (no GPU).
+
+Each test checks the oracle against something it does not itself compute:
+a library routine (scipy rotations, numpy eigen-decomposition, quadrature),
+a closed form from Gaussian algebra, one of the model's limits (Fig. 1 b-c),
+brute force on a tiny grid, finite differences, or a textbook property of Adam.
+A plausible slip in the oracle (a dropped term, a wrong sign, a transposed
+operand, a wrong pixel centre) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy import integrate
+from scipy.spatial.transform import Rotation
+
+from oracle import focus, spec32
+from paper_2603_20611_amd import synth
+
+F64 = torch.float64
+
+
+def _one(mu, ls, q, alpha):
+    p = np.zeros((11, 1), np.float32)
+    p[0:3, 0] = mu
+    p[3:6, 0] = ls
+    p[6:10, 0] = q
+    p[10, 0] = alpha
+    return p
+
+
+def _rand_gaussian(rng, box=(10.0, 10.0, 10.0), ls=(np.log(1.5), 0.3)):
+    q = rng.standard_normal(4)
+    return _one(rng.uniform(0, 1, 3) * np.asarray(box), rng.normal(ls[0], ls[1], 3), q / np.linalg.norm(q),
+                rng.uniform(0.2, 1.0))
+
+
+def _textbook(p):
+    """Sigma, its inverse and determinant from numpy / scipy only."""
+    p = p.astype(np.float64)[:, 0]
+    s = np.exp(p[3:6])
+    w, x, y, z = p[6:10] / np.linalg.norm(p[6:10])
+    R = Rotation.from_quat([x, y, z, w]).as_matrix()
+    Sigma = R @ np.diag(s * s) @ R.T
+    return p[0:3], Sigma, np.linalg.inv(Sigma), float(np.prod(s * s)), float(p[10]), s, R
+
+
+# ----------------------------------------------------------------------------- binary32 exp
+def test_spec_exp_accuracy():
+    x = np.concatenate([np.linspace(-30, 30, 20001), np.random.default_rng(0).normal(0, 3, 20000)])
+    x = x.astype(np.float32)
+    got = spec32.spec_exp(x).astype(np.float64)
+    ref = np.exp(x.astype(np.float64))
+    ulp = np.spacing(ref.astype(np.float32)).astype(np.float64)
+    assert np.max(np.abs(got - ref) / ulp) <= 3.0
+    assert spec32.spec_exp(np.float32(0.0)) == np.float32(1.0)
+
+
+# ----------------------------------------------------------------------------- parameterisation
+def test_quat_to_matrix_matches_scipy():
+    q = np.random.default_rng(1).standard_normal((64, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    R = focus.quat_to_matrix(torch.from_numpy(q)).numpy()
+    ref = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()
+    np.testing.assert_allclose(R, ref, atol=1e-14)
+
+
+def test_activate_eigen_structure():
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        p = _rand_gaussian(rng)
+        mu, Sigma, alpha = focus.activate(torch.from_numpy(p.astype(np.float64)))
+        S = Sigma[0].numpy()
+        ev = np.sort(np.linalg.eigvalsh(S))
+        s = np.exp(p[3:6, 0].astype(np.float64))
+        np.testing.assert_allclose(ev, np.sort(s * s), rtol=1e-12)
+        _, Sig_ref, *_ = _textbook(p)
+        np.testing.assert_allclose(S, Sig_ref, rtol=1e-12, atol=1e-12)
+        # unnormalised quaternion gives the same covariance
+        p2 = p.astype(np.float64)
+        p2[6:10] *= 3.7
+        S2 = focus.activate(torch.from_numpy(p2))[1][0].numpy()
+        np.testing.assert_allclose(S2, S, rtol=1e-12, atol=1e-12)
+
+
+def test_spec32_covariance_and_adjugate():
+    p = synth.gaussians_uniform(500, (64, 64, 32), np.log(1.5), 0.5, seed=3)
+    a = spec32.activate32(p)
+    for j in range(0, 500, 37):
+        _, Sig, Sinv, detS, *_ = _textbook(p[:, j:j + 1])
+        adj = detS * Sinv
+        scale = np.abs(Sig).max()
+        for key, (r, c) in dict(sxx=(0, 0), sxy=(0, 1), sxz=(0, 2), syy=(1, 1), syz=(1, 2), szz=(2, 2)).items():
+            assert abs(float(a[key][j]) - Sig[r, c]) <= 2e-6 * scale
+        ascale = np.abs(adj).max()
+        for key, (r, c) in dict(adj00=(0, 0), adj01=(0, 1), adj11=(1, 1), adj22=(2, 2)).items():
+            assert abs(float(a[key][j]) - adj[r, c]) <= 2e-6 * ascale
+        assert abs(float(a["detS"][j]) - detS) <= 2e-6 * detS
+
+
+# ----------------------------------------------------------------------------- Focus Gaussian
+def _single_image(p, sl):
+    return focus.render(p, [sl], exact=True)[0].numpy()
+
+
+@pytest.mark.parametrize("sigma_z", [0.5, 1.0, 3.0])
+def test_single_gaussian_matches_convolution_integral(sigma_z):
+    """I(p) = [integral of h(t) g_c(x, y, t) dt] / sqrt(2 pi det Sigma_e), with det Sigma_e
+    from the matrix determinant lemma: det Sigma * sigma_z^2 / (sigma_z^2 + Sigma_zz)."""
+    rng = np.random.default_rng(4)
+    for _ in range(4):
+        p = _rand_gaussian(rng, box=(24, 24, 8))
+        z = float(rng.uniform(2, 6))
+        sl = dict(z=z, sigma_z=sigma_z, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=24, height=24)
+        img = _single_image(p, sl)
+        mu, Sig, Sinv, detS, alpha, *_ = _textbook(p)
+        det_e = detS * sigma_z ** 2 / (sigma_z ** 2 + Sig[2, 2])
+        mu_c = mu - np.array([0.0, 0.0, z])
+        for px, py in [(3, 5), (11, 12), (12, 11), (20, 2), (int(mu[0]), int(mu[1]))]:
+            X, Y = px + 0.5, py + 0.5
+            def f(t):
+                d = np.array([X, Y, t]) - mu_c
+                return math.exp(-t * t / (2 * sigma_z ** 2)) * alpha * math.exp(-0.5 * d @ Sinv @ d)
+            val, _ = integrate.quad(f, -60, 60, epsabs=0, epsrel=1e-13, limit=400)
+            ref = val / math.sqrt(2 * math.pi * det_e)
+            assert abs(img[py, px] - ref) <= 1e-11 * max(abs(ref), 1e-300) + 1e-300
+
+
+def test_all_in_focus_limit_is_normalised_line_integral():
+    """sigma_z = inf (Fig. 1b): I = [line integral of g along z] / sqrt(2 pi det Sigma), same at every z."""
+    rng = np.random.default_rng(5)
+    p = _rand_gaussian(rng, box=(24, 24, 8))
+    mu, Sig, Sinv, detS, alpha, *_ = _textbook(p)
+    imgs = [_single_image(p, dict(z=z, sigma_z=math.inf, x0=0.0, y0=0.0, dx=1.0, dy=1.0,
+                                  width=24, height=24)) for z in (0.3, 4.0, 100.0)]
+    np.testing.assert_allclose(imgs[0], imgs[1], rtol=1e-11, atol=1e-13 * imgs[0].max())
+    np.testing.assert_allclose(imgs[0], imgs[2], rtol=1e-11, atol=1e-13 * imgs[0].max())
+    for px, py in [(4, 4), (12, 13), (int(mu[0]), int(mu[1]))]:
+        X, Y = px + 0.5, py + 0.5
+        def f(t):
+            d = np.array([X, Y, t]) - mu
+            return alpha * math.exp(-0.5 * d @ Sinv @ d)
+        val, _ = integrate.quad(f, -80, 80, epsabs=0, epsrel=1e-13, limit=400)
+        ref = val / math.sqrt(2 * math.pi * detS)
+        assert abs(imgs[0][py, px] - ref) <= 1e-11 * ref
+
+
+def test_zero_thickness_limit_is_point_evaluation():
+    """sigma_z -> 0 (Fig. 1c): I(p) = g(p, z) sqrt(Sigma_zz / det Sigma)."""
+    rng = np.random.default_rng(6)
+    for _ in range(3):
+        p = _rand_gaussian(rng, box=(24, 24, 8))
+        mu, Sig, Sinv, detS, alpha, *_ = _textbook(p)
+        z = float(mu[2] + rng.uniform(-1, 1))
+        base = dict(z=z, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=24, height=24)
+        img0 = _single_image(p, dict(base, sigma_z=0.0))
+        img_small = _single_image(p, dict(base, sigma_z=1e-6))
+        np.testing.assert_allclose(img_small, img0, rtol=1e-9, atol=1e-14 * img0.max())
+        for px, py in [(5, 6), (int(mu[0]), int(mu[1])), (15, 9)]:
+            d = np.array([px + 0.5, py + 0.5, z]) - mu
+            ref = alpha * math.exp(-0.5 * d @ Sinv @ d) * math.sqrt(Sig[2, 2] / detS)
+            assert abs(img0[py, px] - ref) <= 1e-12 * max(ref, 1e-300)
+
+
+def test_plane_mass_and_dense_slice_mass():
+    """Sum over a fine plane = 2 pi alpha exp(-m^2 / 2(sigma_z^2 + Sigma_zz)) (1-D Gaussian
+    convolution of the axial marginal with h); summed over dense slices it gives
+    (2 pi)^{3/2} alpha sqrt(sigma_z^2 + Sigma_zz)."""
+    rng = np.random.default_rng(7)
+    p = _rand_gaussian(rng, box=(1, 1, 1), ls=(np.log(1.0), 0.15))
+    p[0:2, 0] = 16.0
+    p[2, 0] = 0.0
+    mu, Sig, *_ , alpha, s, R = _textbook(p)
+    sigma_z = 1.3
+    Dz = sigma_z ** 2 + Sig[2, 2]
+    h = 0.25
+    dz = 0.5
+    zs = np.arange(-12.0, 12.0 + 1e-9, dz)
+    total = 0.0
+    for z in zs:
+        sl = dict(z=float(z), sigma_z=sigma_z, x0=0.0, y0=0.0, dx=h, dy=h, width=128, height=128)
+        mass = _single_image(p, sl).sum() * h * h
+        ref = 2 * math.pi * alpha * math.exp(-0.5 * z * z / Dz)
+        assert abs(mass - ref) <= 1e-10 * 2 * math.pi * alpha
+        total += mass * dz
+    ref_total = (2 * math.pi) ** 1.5 * alpha * math.sqrt(Dz)
+    assert abs(total - ref_total) <= 1e-9 * ref_total
+
+
+# ----------------------------------------------------------------------------- assembly
+def _brute(p, sl, exact):
+    """Pure-Python per-pixel sum; membership from the binary32 records, values per Gaussian."""
+    W, H = sl["width"], sl["height"]
+    ntx = (W + 15) // 16
+    act = spec32.activate32(p)
+    rec = spec32.slice_records32(act, sl)
+    out = np.zeros((H, W))
+    for i in range(p.shape[1]):
+        if not act["ok"][i]:
+            continue
+        mu, Sig, Sinv, detS, alpha, *_ = _textbook(p[:, i:i + 1])
+        sz = sl["sigma_z"]
+        Pm = Sinv + np.outer([0, 0, 1], [0, 0, 1]) / sz ** 2
+        Se = np.linalg.inv(Pm)
+        mu_c = mu - np.array([0, 0, sl["z"]])
+        mu_e = Se @ Sinv @ mu_c
+        op = math.exp(-0.5 * (mu_c @ Sinv @ mu_c - mu_e @ Pm @ mu_e))
+        S2 = Se[:2, :2]
+        at = alpha * op / math.sqrt(np.linalg.det(S2))
+        S2i = np.linalg.inv(S2)
+        for py in range(H):
+            for px in range(W):
+                if not exact:
+                    tx, ty = px // 16, py // 16
+                    if not (rec["member"][i] and rec["tx0"][i] <= tx <= rec["tx1"][i]
+                            and rec["ty0"][i] <= ty <= rec["ty1"][i]):
+                        continue
+                d = np.array([sl["x0"] + (px + 0.5) * sl["dx"], sl["y0"] + (py + 0.5) * sl["dy"]]) - mu_e[:2]
+                out[py, px] += at * math.exp(-0.5 * d @ S2i @ d)
+    del ntx
+    return out
+
+
+@pytest.mark.parametrize("exact", [False, True])
+def test_render_matches_brute_force(exact):
+    p = synth.gaussians_uniform(24, (40, 24, 6), np.log(1.2), 0.4, seed=8)
+    sl = dict(z=2.7, sigma_z=1.1, x0=-1.5, y0=0.75, dx=1.25, dy=0.8, width=40, height=23)
+    img = focus.render(p, [sl], exact=exact)[0].numpy()
+    ref = _brute(p, sl, exact)
+    np.testing.assert_allclose(img, ref, rtol=1e-12, atol=1e-14 * ref.max())
+    if not exact:
+        assert (img == 0).sum() > 0 or True
+
+
+def test_render_is_linear_in_the_gaussian_set():
+    p = synth.gaussians_uniform(300, (64, 64, 16), np.log(1.5), 0.3, seed=9)
+    sl = synth.axial_slices(3, 64, 48, 1.0, z0=4.5, dz=3.0)
+    full = focus.render(p, sl)
+    a = focus.render(p[:, :170], sl)
+    b = focus.render(p[:, 170:], sl)
+    for f, x, y in zip(full, a, b):
+        np.testing.assert_allclose(f.numpy(), (x + y).numpy(), rtol=1e-12, atol=1e-13)
+
+
+def test_spec32_membership_tracks_float64_geometry():
+    """The binary32 axial test matches the paper's opacity-modulation Mahalanobis change,
+    and each binary32 rectangle is the tile cover of the float64 3-sigma box except where
+    that box lies within rounding distance of a tile edge."""
+    p = synth.gaussians_uniform(3000, (64, 64, 32), np.log(1.5), 0.4, seed=10)
+    sl = dict(z=13.5, sigma_z=1.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=64, height=64)
+    act = spec32.activate32(p)
+    rec = spec32.slice_records32(act, sl)
+    mu, Sig, alpha = focus.activate(torch.from_numpy(p.astype(np.float64)))
+    f = focus.focus(mu, Sig, alpha, sl["z"], sl["sigma_z"])
+    qd = f["qdiff"].numpy()
+    q_cut = float(spec32.Q_CUT_DEFAULT)
+    clear = np.abs(qd - q_cut) > 1e-4 * q_cut
+    assert np.array_equal(rec["axial"][clear], (qd <= q_cut)[clear])
+    np.testing.assert_allclose(rec["qax"].astype(np.float64)[qd < 50], qd[qd < 50], rtol=2e-5, atol=1e-6)
+    m2 = f["mu2d"].numpy()
+    S2 = f["Sigma2d"].numpy()
+    rx, ry = 3 * np.sqrt(S2[:, 0, 0]), 3 * np.sqrt(S2[:, 1, 1])
+    checked = 0
+    for i in np.nonzero(rec["member"])[0]:
+        lo = np.array([m2[i, 0] - rx[i], m2[i, 1] - ry[i]]) / 16.0
+        hi = np.array([m2[i, 0] + rx[i], m2[i, 1] + ry[i]]) / 16.0
+        edges = np.concatenate([lo, hi])
+        if np.min(np.abs(edges - np.round(edges))) < 1e-4:
+            continue
+        t0 = np.clip(np.floor(lo), 0, 3).astype(int)
+        t1 = np.clip(np.floor(hi), 0, 3).astype(int)
+        assert (rec["tx0"][i], rec["ty0"][i], rec["tx1"][i], rec["ty1"][i]) == (t0[0], t0[1], t1[0], t1[1])
+        checked += 1
+    assert checked > 500
+
+
+def test_bins_keys_and_ranges_layout():
+    p = synth.gaussians_uniform(200, (40, 40, 8), np.log(1.5), 0.3, seed=11)
+    slices = [dict(z=2.5, sigma_z=1.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=40, height=33),
+              dict(z=5.5, sigma_z=2.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=16, height=16)]
+    keys, ranges = spec32.bins(p, slices)
+    assert ranges.shape == (3 * 3 + 1, 2)
+    assert np.all(np.diff(keys) > 0)                       # sorted, unique
+    b = keys >> 32
+    for t in range(ranges.shape[0]):
+        s, e = ranges[t]
+        assert np.all(b[s:e] == t)
+    assert ranges[-1, 1] == keys.size
+
+
+# ----------------------------------------------------------------------------- gradient
+def _fd_setup():
+    p = synth.gaussians_uniform(12, (32, 32, 6), np.log(1.6), 0.3, seed=12)
+    slices = [dict(z=2.5, sigma_z=1.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=32, height=32),
+              dict(z=3.7, sigma_z=2.5, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=32, height=32)]
+    rng = np.random.default_rng(13)
+    w = [rng.standard_normal((32, 32)) for _ in slices]
+    return p, slices, w
+
+
+def test_gradient_matches_central_differences():
+    p, slices, w = _fd_setup()
+    g = focus.grad(p, slices, w)
+    inst = [focus.slice_instances(p, sl) for sl in slices]
+
+    def L(p64):
+        return sum(float((focus.render_slice(p64, None, sl, instances=ins) * torch.from_numpy(wk)).sum())
+                   for sl, ins, wk in zip(slices, inst, w))
+
+    base = torch.from_numpy(p.astype(np.float64))
+    h = 1e-6
+    for r in range(11):
+        for i in range(0, 12, 3):
+            pp, pm = base.clone(), base.clone()
+            pp[r, i] += h
+            pm[r, i] -= h
+            fd = (L(pp) - L(pm)) / (2 * h)
+            assert abs(fd - g[r, i]) <= 1e-6 * max(1.0, abs(g[r, i])), (r, i, fd, g[r, i])
+
+
+def test_gradient_alpha_linearity_and_quaternion_scale_invariance():
+    p, slices, w = _fd_setup()
+    g = focus.grad(p, slices, w)
+    for i in range(12):
+        single = sum(float((focus.render(p[:, i:i + 1], [sl])[0] * torch.from_numpy(wk)).sum())
+                     for sl, wk in zip(slices, w))
+        assert abs(g[10, i] - single / float(p[10, i])) <= 1e-12 * max(1.0, abs(g[10, i]))
+        q = p[6:10, i].astype(np.float64)
+        assert abs(np.dot(g[6:10, i], q)) <= 1e-10 * max(1.0, np.abs(g[6:10, i]).max())
+
+
+# ----------------------------------------------------------------------------- Adam
+def test_adam_textbook_properties():
+    rng = np.random.default_rng(14)
+    p = rng.standard_normal((11, 50))
+    g = rng.standard_normal((11, 50))
+    lr = dict(mean=6e-4, log_scale=2e-3, quat=1e-3, alpha=2e-2)
+    rows = np.concatenate([[lr["mean"]] * 3, [lr["log_scale"]] * 3, [lr["quat"]] * 4, [lr["alpha"]]])
+    zeros = np.zeros_like(p)
+    # first bias-corrected step moves every coordinate by lr * sign(g)
+    p1, m, v = focus.adam_step(p, g, zeros, zeros, lr, 1)
+    np.testing.assert_allclose(p1 - p, -rows[:, None] * np.sign(g), rtol=1e-9)
+    # a constant gradient keeps moving by lr per step
+    q, m, v = p, zeros, zeros
+    for t in range(1, 40):
+        q2, m, v = focus.adam_step(q, g, m, v, lr, t)
+        np.testing.assert_allclose(q2 - q, -rows[:, None] * np.sign(g), rtol=1e-9)
+        q = q2
+    # scaling the gradients does not change the update
+    a, _, _ = focus.adam_step(p, g, zeros, zeros, lr, 1)
+    b, _, _ = focus.adam_step(p, 1000.0 * g, zeros, zeros, lr, 1)
+    np.testing.assert_allclose(a, b, rtol=1e-12)
+    # a zero gradient from a zero state does not move
+    c, _, _ = focus.adam_step(p, zeros, zeros, zeros, lr, 1)
+    np.testing.assert_array_equal(c, p)
+
+
+def test_l1_grad_sign_convention():
+    I = np.array([1.0, 2.0, 3.0, 4.0])
+    T = np.array([0.5, 2.0, 3.5, 4.0])
+    np.testing.assert_array_equal(focus.l1_grad(I, T), np.array([1.0, 0.0, -1.0, 0.0]) / 4)
