@@ -1,0 +1,205 @@
+/*
+ * gaussianpile.h -- C-ABI of the MI355X (gfx950) Focus-Gaussian slice renderer.
+ *
+ * The library renders axial slices of a set of anisotropic 3-D Gaussians under
+ * GaussianPile's finite-thickness focus model (Sec. 4.2), differentiates the
+ * rendering (Sec. 4.3, "Backward pass"; supplement Sec. 8), updates parameters
+ * with Adam (Sec. 5.1, implementation details) and serves slices of resident
+ * volumes.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named d_* are device pointers on the calling thread's current
+ *     HIP device, owned by the caller (the library never frees them).  Pointers
+ *     named h_* are host pointers, read before the call returns.
+ *   - gp_workspace and gp_server objects are owned by the library; create and
+ *     destroy them with the matching calls.  A workspace may be used by one
+ *     thread at a time.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     Every compute entry point is asynchronous on that stream unless stated.
+ *   - Every entry point returns a gp_status.  On failure, gp_last_error()
+ *     returns a thread-local description.  No C++ exception crosses the ABI.
+ *
+ * Gaussian parameters (supplement Sec. 7: G = (mu, s, q, alpha)) are stored as
+ * planes ("SoA"): plane r of a set with row stride `stride` starts at element
+ * r * stride.  The eleven rows are
+ *     0..2  mu_x, mu_y, mu_z            position (world units)
+ *     3..5  l_x, l_y, l_z               log-scales, s = exp(l) * scale_mod
+ *     6..9  q_w, q_x, q_y, q_z          rotation quaternion, any non-zero norm
+ *     10    alpha                       intensity coefficient (used linearly)
+ * and the library reads `means` (rows 0..2) and `attrs` (rows 3..10) through
+ * two pointers so that 16-bit attributes can sit beside float32 positions.
+ *
+ * A slice is the axial plane z = const imaged with axial PSF width sigma_z
+ * (Sec. 4.1, sensitivity map h(-z_c) = exp(-z_c^2 / 2 sigma_z^2)); its camera is
+ * R_c = I, t = (0, 0, -z) (supplement Sec. 7).  Pixel (px, py) has centre
+ * (x0 + (px + 1/2) dx, y0 + (py + 1/2) dy).  Images of a batch are packed back
+ * to back in slice order, each row-major [height][width] float32.
+ */
+#ifndef GAUSSIANPILE_H
+#define GAUSSIANPILE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gp_status;
+#define GP_OK          0
+#define GP_EINVAL     -1   /* bad argument (null pointer, size, dtype, ...) */
+#define GP_ENOMEM     -2   /* device or host allocation failed */
+#define GP_EHIP       -3   /* a HIP runtime call failed */
+#define GP_EOVERFLOW  -4   /* a fixed-capacity workspace was too small */
+#define GP_EAGAIN     -5   /* serving: result not ready yet */
+#define GP_ECANCELED  -6   /* serving: request cancelled by server shutdown */
+#define GP_ESTATE     -7   /* call order violated (e.g. backward without forward) */
+
+#define GP_F32  0
+#define GP_BF16 1
+#define GP_F16  2
+
+/* Render options.  q_cut: axial cull threshold on the Mahalanobis change of the
+ * opacity modulation (Sec. 4.2, "cull primitives with opacity below a small
+ * threshold"); a (Gaussian, slice) pair is drawn iff m^2 / (sigma_z^2 +
+ * Sigma_zz) <= q_cut.  bbox_sigmas: half-width of the tile footprint in
+ * standard deviations of Sigma_2d.  scale_mod: the `mod` factor of
+ * S = diag(mod * s) (supplement Sec. 7).  GP_FLAG_EXACT: no cull and no
+ * footprint, every Gaussian reaches every pixel (reference mode). */
+#define GP_FLAG_EXACT 1u
+typedef struct gp_render_opts {
+  float q_cut;        /* default 2 ln 255 = 11.0825...: opacity_r >= 1/255 */
+  float bbox_sigmas;  /* default 3 */
+  float scale_mod;    /* default 1 */
+  uint32_t flags;
+} gp_render_opts;
+
+typedef struct gp_gaussians {
+  const void* means;  /* d_: [3][stride], mean_dtype (GP_F32 only)            */
+  const void* attrs;  /* d_: [8][stride], attr_dtype (GP_F32, GP_BF16, GP_F16) */
+  int64_t n;          /* number of Gaussians, 0 <= n <= stride, n < 2^31      */
+  int64_t stride;     /* elements between planes                              */
+  int32_t mean_dtype;
+  int32_t attr_dtype;
+} gp_gaussians;
+
+typedef struct gp_slice {
+  float z;            /* depth of the imaging plane (world units)              */
+  float sigma_z;      /* axial PSF width, 0 <= sigma_z <= +inf                 */
+  float x0, y0;       /* world position of the grid's lower corner             */
+  float dx, dy;       /* pixel pitch, > 0                                      */
+  int32_t width;      /* pixels, 1 .. 16384                                    */
+  int32_t height;     /* pixels, 1 .. 16384                                    */
+} gp_slice;
+
+typedef struct gp_workspace gp_workspace;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t gp_version(void);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* gp_last_error(void);
+
+/* Fills *o with the defaults listed above.  GP_EINVAL if o is NULL. */
+gp_status gp_default_opts(gp_render_opts* o);
+
+/* Creates a workspace on the current device.  max_records / max_instances fix
+ * the capacity of the per-(Gaussian, slice) record and per-(record, tile) list
+ * buffers.  0 for both selects automatic sizing: each render reads the counts
+ * back once (one host synchronisation) and grows the buffers when needed.  With
+ * fixed capacities no render synchronises; an overflow drops entries, is
+ * remembered and reported as GP_EOVERFLOW by gp_workspace_check.
+ * Errors: GP_EINVAL (ws NULL, negative capacity), GP_ENOMEM, GP_EHIP. */
+gp_status gp_workspace_create(gp_workspace** ws, int64_t max_records, int64_t max_instances);
+
+/* Waits for the workspace's last stream, then frees it.  NULL is accepted. */
+gp_status gp_workspace_destroy(gp_workspace* ws);
+
+/* Counts of the most recent render: records (visible or axially kept
+ * (Gaussian, slice) pairs), instances (tile-list entries) and bins (16x16
+ * tiles over all slices).  Synchronises with the workspace's last stream.
+ * Returns GP_EOVERFLOW if any render since creation overflowed a fixed
+ * capacity (the flag is then cleared). */
+gp_status gp_workspace_check(gp_workspace* ws, int64_t* records, int64_t* instances, int64_t* bins);
+
+/* Forward rendering of n_slices axial slices (Sec. 4.2: Focus Gaussian,
+ * opacity modulation, screen-space projection, intensity normalisation and
+ * additive rasterisation; supplement Sec. 7 for the full derivation):
+ *   I_k(p) = sum over the members i of p's tile list on slice k of
+ *            alpha~_ik exp(-1/2 d^T Sigma_2d,ik^-1 d),  d = p - mu_2d,ik
+ *   alpha~ = alpha * opacity_r / sqrt(det Sigma_2d).
+ * h_slices: host array [n_slices].  d_out: device float32, sum_k width_k *
+ * height_k elements, overwritten.  The tile lists are kept in `ws` for a
+ * following gp_render_backward.  Errors: GP_EINVAL, GP_ENOMEM, GP_EHIP. */
+gp_status gp_render_slices(gp_workspace* ws, const gp_gaussians* g, const gp_slice* h_slices,
+                           int32_t n_slices, const gp_render_opts* opts, float* d_out, void* stream);
+
+/* Backward of the preceding gp_render_slices on the same workspace, Gaussian
+ * set and slices (Sec. 4.3 "Backward pass", supplement Sec. 8): given
+ * d_grad_out = dL/dI (same layout as d_out), ADDS dL/dparams to d_grad
+ * ([11][grad_stride] float32, rows as above; grad_stride >= n).  Per-pixel
+ * contributions are recomputed from the tile lists, not stored.  The result is
+ * deterministic (no floating-point atomics).
+ * Errors: GP_ESTATE if the workspace holds no matching forward, GP_EINVAL,
+ * GP_EHIP. */
+gp_status gp_render_backward(gp_workspace* ws, const gp_gaussians* g, const gp_slice* h_slices,
+                             int32_t n_slices, const gp_render_opts* opts, const float* d_grad_out,
+                             float* d_grad, int64_t grad_stride, void* stream);
+
+/* L1 term of the loss (Sec. 4.3, loss function): d_grad[j] = scale * sign(d_image[j] -
+ * d_target[j]) with sign(0) = 0, and *d_loss += scale * sum_j |d_image[j] -
+ * d_target[j]| (d_loss may be NULL).  scale is normally 1 / n.
+ * Errors: GP_EINVAL (n < 0, NULL arrays), GP_EHIP. */
+gp_status gp_l1_loss_grad(const float* d_image, const float* d_target, int64_t n, float scale,
+                          float* d_grad, float* d_loss, void* stream);
+
+/* Adam (Kingma & Ba, Algorithm 1; the optimiser named in Sec. 5.1) on float32
+ * planes [11][stride] in place: for every element
+ *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2
+ *   p -= lr_group * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)
+ * with lr_group = lr[0] for rows 0..2 (positions), lr[1] rows 3..5
+ * (log-scales), lr[2] rows 6..9 (quaternion), lr[3] row 10 (intensity).
+ * GP_ADAM_CLAMP_ALPHA projects row 10 onto alpha >= 0 after the step;
+ * GP_ADAM_ZERO_GRAD writes zero into d_grad after reading it.
+ * Errors: GP_EINVAL (step < 1, n > stride, NULL), GP_EHIP. */
+#define GP_ADAM_CLAMP_ALPHA 1u
+#define GP_ADAM_ZERO_GRAD   2u
+typedef struct gp_adam_cfg {
+  float lr[4];
+  float beta1, beta2, eps;
+  int32_t step;
+  uint32_t flags;
+} gp_adam_cfg;
+gp_status gp_adam_step(float* d_params, float* d_grad, float* d_m, float* d_v, int64_t n,
+                       int64_t stride, const gp_adam_cfg* cfg, void* stream);
+
+/* Per-stage kernel timing of a workspace, for measurement.  While enabled, each
+ * stage of a render or backward on this workspace is bracketed by HIP events
+ * recorded on the call's stream (no host synchronisation is added);
+ * gp_workspace_timings synchronises, resolves the pending events and returns,
+ * per stage, the summed milliseconds and the number of launches since timing
+ * was enabled.  Enabling resets the sums.  Errors: GP_EINVAL, GP_EHIP. */
+#define GP_STAGE_PREPROCESS      0   /* activation, axial cull, records, tile ranks */
+#define GP_STAGE_SCAN            1   /* exclusive scan of the bin counts            */
+#define GP_STAGE_SCATTER         2   /* instances to (bin start + rank)             */
+#define GP_STAGE_BIN_SORT        3   /* per-bin sort + gather into list order      */
+#define GP_STAGE_RASTER_FWD      4   /* additive rasterisation                      */
+#define GP_STAGE_RASTER_BWD      5   /* per-entry moments of the upstream gradient */
+#define GP_STAGE_PREPROCESS_BWD  6   /* chain rule to the Gaussian parameters       */
+#define GP_N_STAGES              7
+gp_status gp_workspace_set_timing(gp_workspace* ws, int32_t enable);
+gp_status gp_workspace_timings(gp_workspace* ws, double* h_ms, int64_t* h_counts, int32_t n_stages);
+
+/* Test hook: copies the tile lists of the most recent render to host memory,
+ * synchronously.  h_keys[j] = (bin << 32) | gaussian index, in list order,
+ * where bins are numbered slice by slice (in the order given) and row-major
+ * within a slice; h_ranges[2b], h_ranges[2b+1] = [start, end) of bin b.
+ * *n_keys receives the number of entries; h_keys must hold keys_cap entries and
+ * h_ranges 2 * bins entries.  Errors: GP_EINVAL (too small), GP_ESTATE. */
+gp_status gp_debug_export_bins(gp_workspace* ws, uint64_t* h_keys, int64_t keys_cap, int64_t* n_keys,
+                               int64_t* h_ranges, int64_t ranges_cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GAUSSIANPILE_H */

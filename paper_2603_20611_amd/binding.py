@@ -1,0 +1,116 @@
+"""ctypes binding of libgaussianpile.so (the C-ABI in include/gaussianpile.h).
+
+Argument marshalling only: every computation runs in the HIP library.  If the
+library has not been built, load() raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgaussianpile.so")
+_lib = None
+
+GP_OK, GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_EOVERFLOW, GP_EAGAIN, GP_ECANCELED, GP_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+GP_F32, GP_BF16, GP_F16 = 0, 1, 2
+GP_FLAG_EXACT = 1
+GP_ADAM_CLAMP_ALPHA, GP_ADAM_ZERO_GRAD = 1, 2
+STAGES = ("preprocess", "scan", "scatter", "bin_sort", "raster_fwd", "raster_bwd", "preprocess_bwd")
+STATUS_NAMES = {0: "GP_OK", -1: "GP_EINVAL", -2: "GP_ENOMEM", -3: "GP_EHIP", -4: "GP_EOVERFLOW",
+                -5: "GP_EAGAIN", -6: "GP_ECANCELED", -7: "GP_ESTATE"}
+
+
+class GpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("q_cut", C.c_float), ("bbox_sigmas", C.c_float), ("scale_mod", C.c_float),
+                ("flags", C.c_uint32)]
+
+
+class Gaussians(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("attrs", C.c_void_p), ("n", C.c_int64), ("stride", C.c_int64),
+                ("mean_dtype", C.c_int32), ("attr_dtype", C.c_int32)]
+
+
+class Slice(C.Structure):
+    _fields_ = [("z", C.c_float), ("sigma_z", C.c_float), ("x0", C.c_float), ("y0", C.c_float),
+                ("dx", C.c_float), ("dy", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class AdamCfg(C.Structure):
+    _fields_ = [("lr", C.c_float * 4), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int32), ("flags", C.c_uint32)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "gp_version": (C.c_int32, []),
+    "gp_last_error": (C.c_char_p, []),
+    "gp_default_opts": (C.c_int32, [C.POINTER(RenderOpts)]),
+    "gp_workspace_create": (C.c_int32, [C.POINTER(_P), C.c_int64, C.c_int64]),
+    "gp_workspace_destroy": (C.c_int32, [_P]),
+    "gp_workspace_check": (C.c_int32, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "gp_render_slices": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(Slice), C.c_int32,
+                                     C.POINTER(RenderOpts), _P, _P]),
+    "gp_render_backward": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(Slice), C.c_int32,
+                                       C.POINTER(RenderOpts), _P, _P, C.c_int64, _P]),
+    "gp_l1_loss_grad": (C.c_int32, [_P, _P, C.c_int64, C.c_float, _P, _P, _P]),
+    "gp_adam_step": (C.c_int32, [_P, _P, _P, _P, C.c_int64, C.c_int64, C.POINTER(AdamCfg), _P]),
+    "gp_workspace_set_timing": (C.c_int32, [_P, C.c_int32]),
+    "gp_workspace_timings": (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
+    "gp_debug_export_bins": (C.c_int32, [_P, C.POINTER(C.c_uint64), C.c_int64, C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int64), C.c_int64]),
+}
+
+
+def exported_names():
+    """Names the binding expects the library to export."""
+    return sorted(_SIGS)
+
+
+def load(path=None):
+    """Loads the HIP library (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or _LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_2603_20611_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status):
+    if status != GP_OK:
+        raise GpError(status, load().gp_last_error().decode())
+    return status
+
+
+def default_opts(**kw):
+    o = RenderOpts()
+    check(load().gp_default_opts(C.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def make_slices(slices):
+    arr = (Slice * max(len(slices), 1))()
+    for i, s in enumerate(slices):
+        arr[i] = Slice(float(s["z"]), float(s["sigma_z"]), float(s.get("x0", 0.0)), float(s.get("y0", 0.0)),
+                       float(s.get("dx", 1.0)), float(s.get("dy", 1.0)), int(s["width"]), int(s["height"]))
+    return arr
+
+
+def q_cut_default():
+    return float(2.0 * math.log(255.0))

@@ -1,0 +1,494 @@
+// Host side of the C-ABI: argument validation, the workspace, and the launch
+// sequence of a render (preprocess -> bin scan -> scatter -> per-bin sort ->
+// rasterise), its backward, Adam and the L1 loss.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gp_internal.h"
+
+namespace gp {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+gp_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return GP_EHIP;
+}
+
+static gp_status einval(const std::string& msg) {
+  set_error(msg);
+  return GP_EINVAL;
+}
+
+template <typename T>
+static hipError_t dev_alloc(T** p, int64_t count) {
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    *p = nullptr;
+    if (e != hipSuccess) return e;
+  }
+  if (count <= 0) return hipSuccess;
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)count);
+}
+
+template <typename T>
+static hipError_t host_alloc(T** p, int64_t count) {
+  if (*p) {
+    hipError_t e = hipHostFree(*p);
+    *p = nullptr;
+    if (e != hipSuccess) return e;
+  }
+  return hipHostMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)(count > 0 ? count : 1),
+                       hipHostMallocDefault);
+}
+
+static hipError_t wait_ws(Workspace* ws) {
+  if (ws->upload_done) {
+    hipError_t e = hipEventSynchronize(ws->upload_done);
+    if (e != hipSuccess) return e;
+  }
+  return hipStreamSynchronize(static_cast<hipStream_t>(ws->last_stream));
+}
+
+static gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups, int64_t n_bins,
+                               int64_t n_gauss) {
+  if (n_slices > ws->slice_cap) {
+    GP_HIP(wait_ws(ws));
+    const int64_t cap = n_slices + 64;
+    GP_HIP(dev_alloc(&ws->d_slices, cap));
+    GP_HIP(host_alloc(&ws->h_slices, cap));
+    ws->slice_cap = cap;
+  }
+  if (n_groups > ws->group_cap) {
+    GP_HIP(wait_ws(ws));
+    const int64_t cap = n_groups + 8;
+    GP_HIP(dev_alloc(&ws->d_groups, cap));
+    GP_HIP(host_alloc(&ws->h_groups, cap));
+    ws->group_cap = cap;
+  }
+  if (n_bins > ws->bin_cap) {
+    GP_HIP(wait_ws(ws));
+    const int64_t cap = n_bins + n_bins / 4 + 256;
+    GP_HIP(dev_alloc(&ws->d_bin_count, cap));
+    GP_HIP(dev_alloc(&ws->d_bin_start, cap + 1));
+    ws->bin_cap = cap;
+  }
+  if (n_gauss > ws->gauss_cap) {
+    GP_HIP(wait_ws(ws));
+    const int64_t cap = n_gauss + n_gauss / 8 + 256;
+    GP_HIP(dev_alloc(&ws->d_g_rbase, cap));
+    GP_HIP(dev_alloc(&ws->d_g_nrec, cap));
+    ws->gauss_cap = cap;
+  }
+  return GP_OK;
+}
+
+static gp_status reserve_lists(Workspace* ws, int64_t rec_cap, int64_t inst_cap) {
+  if (rec_cap > 0xFFFFFFF0ll || inst_cap > 0xFFFFFFF0ll) return einval("capacity exceeds 2^32 entries");
+  if (rec_cap > ws->rec_cap) {
+    GP_HIP(wait_ws(ws));
+    if (dev_alloc(&ws->d_rec_pay, rec_cap) != hipSuccess || dev_alloc(&ws->d_rec_meta, rec_cap) != hipSuccess) {
+      ws->rec_cap = 0;
+      set_error("record buffers: out of device memory");
+      return GP_ENOMEM;
+    }
+    ws->rec_cap = rec_cap;
+  }
+  if (inst_cap > ws->inst_cap) {
+    GP_HIP(wait_ws(ws));
+    if (dev_alloc(&ws->d_inst_rank, inst_cap) != hipSuccess || dev_alloc(&ws->d_inst_rid, inst_cap) != hipSuccess ||
+        dev_alloc(&ws->d_sort_key, inst_cap) != hipSuccess || dev_alloc(&ws->d_pay, inst_cap) != hipSuccess ||
+        dev_alloc(&ws->d_inst_pos, inst_cap) != hipSuccess || dev_alloc(&ws->d_moments, 2 * inst_cap) != hipSuccess) {
+      ws->inst_cap = 0;
+      set_error("tile-list buffers: out of device memory");
+      return GP_ENOMEM;
+    }
+    ws->inst_cap = inst_cap;
+  }
+  return GP_OK;
+}
+
+static uint64_t hash_bytes(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+static hipEvent_t take_event(Workspace* ws) {
+  if (!ws->event_pool.empty()) {
+    hipEvent_t e = ws->event_pool.back();
+    ws->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs f (which enqueues one stage on s); with timing on, brackets it by events.
+template <typename F>
+static hipError_t timed(Workspace* ws, int stage, hipStream_t s, F&& f) {
+  if (!ws->timing) return f();
+  hipEvent_t a = take_event(ws), b = take_event(ws);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = f();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  if (e != hipSuccess) return e;
+  ws->pending.push_back({stage, a, b});
+  return hipSuccess;
+}
+
+static hipError_t resolve_timings(Workspace* ws) {
+  for (auto& t : ws->pending) {
+    hipError_t e = hipEventSynchronize(t.stop);
+    if (e != hipSuccess) return e;
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, t.start, t.stop);
+    if (e != hipSuccess) return e;
+    ws->stage_ms[t.stage] += ms;
+    ws->stage_n[t.stage] += 1;
+    ws->event_pool.push_back(t.start);
+    ws->event_pool.push_back(t.stop);
+  }
+  ws->pending.clear();
+  return hipSuccess;
+}
+
+static gp_status check_gaussians(const gp_gaussians* g) {
+  if (!g) return einval("gaussians: NULL");
+  if (g->n < 0 || g->n >= (1ll << 31)) return einval("gaussians: n out of range");
+  if (g->stride < g->n) return einval("gaussians: stride < n");
+  if (g->n > 0 && (!g->means || !g->attrs)) return einval("gaussians: NULL means/attrs");
+  if (g->mean_dtype != GP_F32) return einval("gaussians: means must be GP_F32");
+  if (g->attr_dtype != GP_F32 && g->attr_dtype != GP_BF16 && g->attr_dtype != GP_F16)
+    return einval("gaussians: unknown attr_dtype");
+  return GP_OK;
+}
+
+static gp_status check_slice(const gp_slice& s, int k) {
+  char buf[128];
+  if (!(s.width >= 1 && s.width <= 16384 && s.height >= 1 && s.height <= 16384)) {
+    snprintf(buf, sizeof buf, "slice %d: width/height out of range", k);
+    return einval(buf);
+  }
+  if (!(s.dx > 0.f) || !(s.dy > 0.f) || !std::isfinite(s.dx) || !std::isfinite(s.dy)) {
+    snprintf(buf, sizeof buf, "slice %d: pixel pitch must be finite and > 0", k);
+    return einval(buf);
+  }
+  if (!std::isfinite(s.z) || !std::isfinite(s.x0) || !std::isfinite(s.y0) || !(s.sigma_z >= 0.f)) {
+    snprintf(buf, sizeof buf, "slice %d: z, x0, y0 must be finite and sigma_z >= 0", k);
+    return einval(buf);
+  }
+  return GP_OK;
+}
+
+static gp_status check_opts(const gp_render_opts* o) {
+  if (!o) return einval("opts: NULL");
+  if (!(o->q_cut >= 0.f) || !(o->bbox_sigmas > 0.f) || !(o->scale_mod > 0.f))
+    return einval("opts: q_cut >= 0, bbox_sigmas > 0 and scale_mod > 0 required");
+  if (o->flags & ~GP_FLAG_EXACT) return einval("opts: unknown flag");
+  return GP_OK;
+}
+
+// Forward over one Gaussian set sampled by all slices.
+static gp_status render_forward(Workspace* ws, const gp_gaussians* g, const gp_slice* hs, int32_t ns,
+                                const gp_render_opts* o, float* out, hipStream_t s) {
+  int64_t nbins = 0, npix = 0;
+  for (int k = 0; k < ns; ++k) {
+    const int ntx = (hs[k].width + kTile - 1) / kTile, nty = (hs[k].height + kTile - 1) / kTile;
+    nbins += (int64_t)ntx * nty;
+    npix += (int64_t)hs[k].width * hs[k].height;
+  }
+  if (nbins >= (1ll << 31)) return einval("too many tiles in one batch");
+  const int64_t total_gauss = (g->n + 63) / 64 * 64;
+  gp_status st = reserve_small(ws, ns, 1, nbins, total_gauss);
+  if (st != GP_OK) return st;
+
+  // host descriptors into pinned staging (wait until the previous upload has been consumed)
+  if (ws->upload_done) GP_HIP(hipEventSynchronize(ws->upload_done));
+  int64_t tb = 0, off = 0;
+  for (int k = 0; k < ns; ++k) {
+    SliceDev& d = ws->h_slices[k];
+    d.z = hs[k].z; d.sigma_z = hs[k].sigma_z; d.x0 = hs[k].x0; d.y0 = hs[k].y0;
+    d.dx = hs[k].dx; d.dy = hs[k].dy; d.width = hs[k].width; d.height = hs[k].height;
+    d.ntx = (hs[k].width + kTile - 1) / kTile; d.nty = (hs[k].height + kTile - 1) / kTile;
+    d.tile_base = (int32_t)tb; d.group = 0; d.out_off = off;
+    tb += (int64_t)d.ntx * d.nty;
+    off += (int64_t)hs[k].width * hs[k].height;
+  }
+  GroupDev& G = ws->h_groups[0];
+  G.means = static_cast<const float*>(g->means);
+  G.attrs = g->attrs;
+  G.stride = g->stride;
+  G.n = (int32_t)g->n;
+  G.attr_dtype = g->attr_dtype;
+  G.k0 = 0; G.k1 = ns; G.gbase = 0; G.pad = 0;
+  GP_HIP(hipMemcpyAsync(ws->d_slices, ws->h_slices, sizeof(SliceDev) * ns, hipMemcpyHostToDevice, s));
+  GP_HIP(hipMemcpyAsync(ws->d_groups, ws->h_groups, sizeof(GroupDev), hipMemcpyHostToDevice, s));
+  GP_HIP(hipEventRecord(ws->upload_done, s));
+  ws->last_stream = s;
+
+  RenderConst rc{};
+  rc.q_cut = o->q_cut; rc.bbox = o->bbox_sigmas; rc.scale_mod = o->scale_mod; rc.flags = o->flags;
+  rc.n_groups = 1; rc.n_slices = ns; rc.n_bins = (int32_t)nbins; rc.total_gauss = (int32_t)total_gauss;
+
+  if (ws->auto_size && (ws->rec_cap == 0 || ws->inst_cap == 0)) {
+    // first use: a generous guess, corrected after the first count
+    const int64_t guess_rec = std::max<int64_t>(1 << 16, g->n * (int64_t)std::min(ns, 64) / 4);
+    st = reserve_lists(ws, guess_rec, 4 * guess_rec);
+    if (st != GP_OK) return st;
+  }
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    rc.rec_cap = (uint32_t)ws->rec_cap;
+    rc.inst_cap = (uint32_t)ws->inst_cap;
+    GP_HIP(timed(ws, GP_STAGE_PREPROCESS, s, [&] {
+      hipError_t e = launch_fill_u32(ws->d_ctr, 0u, 2, s);
+      if (e == hipSuccess) e = launch_fill_u32(ws->d_bin_count, 0u, nbins, s);
+      if (e == hipSuccess) e = launch_preprocess(rc, *ws, s);
+      return e;
+    }));
+    if (!ws->auto_size) break;
+    GP_HIP(hipMemcpyAsync(ws->h_ctr, ws->d_ctr, sizeof(uint32_t) * kCtrCount, hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    const int64_t R = ws->h_ctr[kCtrRecords], K = ws->h_ctr[kCtrInstances];
+    ws->last_records = R;
+    ws->last_instances = K;
+    if (R <= ws->rec_cap && K <= ws->inst_cap) break;
+    st = reserve_lists(ws, std::max<int64_t>(ws->rec_cap, R + R / 4 + 1024),
+                       std::max<int64_t>(ws->inst_cap, K + K / 4 + 4096));
+    if (st != GP_OK) return st;
+    if (attempt == 2) {
+      set_error("workspace could not be sized");
+      return GP_EOVERFLOW;
+    }
+  }
+  GP_HIP(timed(ws, GP_STAGE_SCAN, s, [&] { return launch_scan_bins(*ws, (int32_t)nbins, s); }));
+  GP_HIP(timed(ws, GP_STAGE_SCATTER, s, [&] { return launch_scatter(rc, *ws, s); }));
+  GP_HIP(timed(ws, GP_STAGE_BIN_SORT, s, [&] { return launch_bin_sort(rc, *ws, s); }));
+  GP_HIP(timed(ws, GP_STAGE_RASTER_FWD, s, [&] { return launch_raster_fwd(rc, *ws, out, s); }));
+
+  ws->have_forward = true;
+  ws->fwd_means = g->means;
+  ws->fwd_attrs = g->attrs;
+  ws->fwd_n = g->n;
+  ws->fwd_stride = g->stride;
+  ws->fwd_nslices = ns;
+  ws->fwd_nbins = (int32_t)nbins;
+  ws->fwd_slice_hash = hash_bytes(hs, sizeof(gp_slice) * (size_t)ns, hash_bytes(o, sizeof(*o)));
+  ws->fwd_rc = rc;
+  (void)npix;
+  return GP_OK;
+}
+
+}  // namespace gp
+
+using namespace gp;
+
+extern "C" {
+
+int32_t gp_version(void) { return 100; }
+
+const char* gp_last_error(void) { return g_err.c_str(); }
+
+gp_status gp_default_opts(gp_render_opts* o) {
+  if (!o) return einval("opts: NULL");
+  o->q_cut = (float)(2.0 * std::log(255.0));
+  o->bbox_sigmas = 3.0f;
+  o->scale_mod = 1.0f;
+  o->flags = 0u;
+  return GP_OK;
+}
+
+gp_status gp_workspace_create(gp_workspace** out, int64_t max_records, int64_t max_instances) {
+  if (!out) return einval("workspace_create: NULL");
+  *out = nullptr;
+  if (max_records < 0 || max_instances < 0) return einval("workspace_create: negative capacity");
+  if ((max_records == 0) != (max_instances == 0))
+    return einval("workspace_create: give both capacities or neither");
+  Workspace* ws = new (std::nothrow) Workspace();
+  if (!ws) {
+    set_error("workspace_create: host allocation");
+    return GP_ENOMEM;
+  }
+  hipError_t e = hipGetDevice(&ws->device);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->upload_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->d_ctr), sizeof(uint32_t) * kCtrCount);
+  if (e == hipSuccess) e = hipMemset(ws->d_ctr, 0, sizeof(uint32_t) * kCtrCount);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_ctr), sizeof(uint32_t) * kCtrCount, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    gp_workspace_destroy(reinterpret_cast<gp_workspace*>(ws));
+    return hip_fail(e, "workspace_create");
+  }
+  ws->auto_size = max_records == 0;
+  if (!ws->auto_size) {
+    gp_status st = reserve_lists(ws, max_records, max_instances);
+    if (st != GP_OK) {
+      gp_workspace_destroy(reinterpret_cast<gp_workspace*>(ws));
+      return st;
+    }
+  }
+  *out = reinterpret_cast<gp_workspace*>(ws);
+  return GP_OK;
+}
+
+gp_status gp_workspace_destroy(gp_workspace* w) {
+  if (!w) return GP_OK;
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  (void)wait_ws(ws);
+  (void)hipFree(ws->d_slices); (void)hipFree(ws->d_groups); hipFree(ws->d_ctr); hipFree(ws->d_bin_count);
+  hipFree(ws->d_bin_start); hipFree(ws->d_rec_pay); hipFree(ws->d_rec_meta); hipFree(ws->d_g_rbase);
+  hipFree(ws->d_g_nrec); hipFree(ws->d_inst_rank); hipFree(ws->d_inst_rid); hipFree(ws->d_sort_key);
+  hipFree(ws->d_pay); hipFree(ws->d_inst_pos); hipFree(ws->d_moments);
+  if (ws->h_slices) hipHostFree(ws->h_slices);
+  if (ws->h_groups) hipHostFree(ws->h_groups);
+  if (ws->h_ctr) hipHostFree(ws->h_ctr);
+  if (ws->upload_done) hipEventDestroy(ws->upload_done);
+  (void)resolve_timings(ws);
+  for (hipEvent_t e : ws->event_pool) hipEventDestroy(e);
+  delete ws;
+  return GP_OK;
+}
+
+gp_status gp_workspace_check(gp_workspace* w, int64_t* records, int64_t* instances, int64_t* bins) {
+  if (!w) return einval("workspace_check: NULL");
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  GP_HIP(wait_ws(ws));
+  GP_HIP(hipMemcpy(ws->h_ctr, ws->d_ctr, sizeof(uint32_t) * kCtrCount, hipMemcpyDeviceToHost));
+  if (records) *records = ws->h_ctr[kCtrRecords];
+  if (instances) *instances = ws->h_ctr[kCtrInstances];
+  if (bins) *bins = ws->have_forward ? ws->fwd_nbins : 0;
+  if (ws->h_ctr[kCtrOverflow] || ws->overflowed) {
+    ws->overflowed = false;
+    GP_HIP(hipMemset(ws->d_ctr + kCtrOverflow, 0, sizeof(uint32_t)));
+    set_error("a render overflowed the workspace capacity");
+    return GP_EOVERFLOW;
+  }
+  return GP_OK;
+}
+
+gp_status gp_render_slices(gp_workspace* w, const gp_gaussians* g, const gp_slice* hs, int32_t ns,
+                           const gp_render_opts* o, float* out, void* stream) {
+  if (!w) return einval("render: NULL workspace");
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  gp_status st = check_gaussians(g);
+  if (st != GP_OK) return st;
+  if ((st = check_opts(o)) != GP_OK) return st;
+  if (ns < 0 || (ns > 0 && (!hs || !out))) return einval("render: bad slices/out");
+  for (int k = 0; k < ns; ++k)
+    if ((st = check_slice(hs[k], k)) != GP_OK) return st;
+  GP_HIP(hipSetDevice(ws->device));
+  ws->have_forward = false;
+  if (ns == 0) return GP_OK;
+  return render_forward(ws, g, hs, ns, o, out, static_cast<hipStream_t>(stream));
+}
+
+gp_status gp_render_backward(gp_workspace* w, const gp_gaussians* g, const gp_slice* hs, int32_t ns,
+                             const gp_render_opts* o, const float* grad_out, float* grad, int64_t grad_stride,
+                             void* stream) {
+  if (!w) return einval("backward: NULL workspace");
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  gp_status st = check_gaussians(g);
+  if (st != GP_OK) return st;
+  if ((st = check_opts(o)) != GP_OK) return st;
+  if (grad_stride < g->n) return einval("backward: grad_stride < n");
+  if (ns < 0 || (ns > 0 && (!hs || !grad_out || !grad))) return einval("backward: bad arguments");
+  if (!ws->have_forward || ws->fwd_means != g->means || ws->fwd_attrs != g->attrs || ws->fwd_n != g->n ||
+      ws->fwd_stride != g->stride || ws->fwd_nslices != ns ||
+      ws->fwd_slice_hash != hash_bytes(hs, sizeof(gp_slice) * (size_t)ns, hash_bytes(o, sizeof(*o)))) {
+    set_error("backward: the workspace does not hold the forward of these Gaussians and slices");
+    return GP_ESTATE;
+  }
+  if (ns == 0 || g->n == 0) return GP_OK;
+  GP_HIP(hipSetDevice(ws->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GP_HIP(timed(ws, GP_STAGE_RASTER_BWD, s, [&] { return launch_raster_bwd(ws->fwd_rc, *ws, grad_out, s); }));
+  GP_HIP(timed(ws, GP_STAGE_PREPROCESS_BWD, s,
+               [&] { return launch_preprocess_bwd(ws->fwd_rc, *ws, grad, grad_stride, s); }));
+  ws->last_stream = s;
+  return GP_OK;
+}
+
+gp_status gp_l1_loss_grad(const float* img, const float* tgt, int64_t n, float scale, float* grad, float* loss,
+                          void* stream) {
+  if (n < 0) return einval("l1: n < 0");
+  if (n > 0 && (!img || !tgt || !grad)) return einval("l1: NULL array");
+  GP_HIP(launch_l1(img, tgt, n, scale, grad, loss, static_cast<hipStream_t>(stream)));
+  return GP_OK;
+}
+
+gp_status gp_adam_step(float* p, float* g, float* m, float* v, int64_t n, int64_t stride, const gp_adam_cfg* c,
+                       void* stream) {
+  if (!c) return einval("adam: NULL cfg");
+  if (n < 0 || stride < n) return einval("adam: need 0 <= n <= stride");
+  if (c->step < 1) return einval("adam: step must be >= 1");
+  if (!(c->beta1 >= 0.f && c->beta1 < 1.f && c->beta2 >= 0.f && c->beta2 < 1.f && c->eps >= 0.f))
+    return einval("adam: betas in [0,1), eps >= 0");
+  if (c->flags & ~(GP_ADAM_CLAMP_ALPHA | GP_ADAM_ZERO_GRAD)) return einval("adam: unknown flag");
+  if (n > 0 && (!p || !g || !m || !v)) return einval("adam: NULL array");
+  GP_HIP(launch_adam(p, g, m, v, n, stride, *c, static_cast<hipStream_t>(stream)));
+  return GP_OK;
+}
+
+gp_status gp_workspace_set_timing(gp_workspace* w, int32_t enable) {
+  if (!w) return einval("set_timing: NULL");
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  GP_HIP(resolve_timings(ws));
+  for (int i = 0; i < GP_N_STAGES; ++i) {
+    ws->stage_ms[i] = 0.0;
+    ws->stage_n[i] = 0;
+  }
+  ws->timing = enable != 0;
+  return GP_OK;
+}
+
+gp_status gp_workspace_timings(gp_workspace* w, double* ms, int64_t* counts, int32_t n) {
+  if (!w || n < 0 || (n > 0 && (!ms || !counts))) return einval("timings: bad arguments");
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  GP_HIP(resolve_timings(ws));
+  for (int i = 0; i < n; ++i) {
+    ms[i] = i < GP_N_STAGES ? ws->stage_ms[i] : 0.0;
+    counts[i] = i < GP_N_STAGES ? ws->stage_n[i] : 0;
+  }
+  return GP_OK;
+}
+
+gp_status gp_debug_export_bins(gp_workspace* w, uint64_t* h_keys, int64_t keys_cap, int64_t* n_keys,
+                               int64_t* h_ranges, int64_t ranges_cap) {
+  if (!w || !n_keys) return einval("export_bins: NULL");
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  if (!ws->have_forward) {
+    set_error("export_bins: no forward in this workspace");
+    return GP_ESTATE;
+  }
+  GP_HIP(wait_ws(ws));
+  const int64_t nb = ws->fwd_nbins;
+  std::vector<uint32_t> start((size_t)nb + 1);
+  GP_HIP(hipMemcpy(start.data(), ws->d_bin_start, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToHost));
+  const int64_t K = start[nb];
+  *n_keys = K;
+  if (keys_cap < K || ranges_cap < 2 * nb || (K > 0 && !h_keys) || (nb > 0 && !h_ranges))
+    return einval("export_bins: output too small");
+  std::vector<RecPay> pay((size_t)K);
+  if (K > 0) GP_HIP(hipMemcpy(pay.data(), ws->d_pay, sizeof(RecPay) * K, hipMemcpyDeviceToHost));
+  for (int64_t b = 0; b < nb; ++b) {
+    h_ranges[2 * b] = start[b];
+    h_ranges[2 * b + 1] = start[b + 1];
+    for (uint32_t i = start[b]; i < start[b + 1]; ++i) h_keys[i] = ((uint64_t)b << 32) | pay[i].gid;
+  }
+  return GP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+// Backward of the preprocess (Sec. 4.3 "Backward pass": screen-space
+// projection -> Focus Gaussian (mu_e, Sigma_e) -> camera space -> world
+// parameters (mu, s, q, alpha), with the determinant coupling of alpha~;
+// supplement Sec. 8).  The chain implemented is the exact derivative of the
+// forward as computed, through the closed form of the Focus Gaussian:
+//
+//   D = sigma_z^2 + Sigma_zz, u = Sigma_xz / D, v = Sigma_yz / D, m = mu_z - z
+//   A = Sigma_xx - u Sigma_xz, B = Sigma_xy - u Sigma_yz, C = Sigma_yy - v Sigma_yz
+//   mu_2d = (mu_x - u m, mu_y - v m), q_ax = m^2 / D, opacity_r = exp(-q_ax / 2)
+//   alpha~ = alpha opacity_r / sqrt(AC - B^2), conic = (C, -B, A) / (AC - B^2)
+//
+// One thread per Gaussian sums, for each of its records (one per slice it
+// reaches), the six moments of the record's list entries in footprint order,
+// applies the chain rule, accumulates over records in slice order and finally
+// maps Sigma = R diag(s^2) R^T back to (log-scale, quaternion).  The gradient is
+// added to the caller's buffer with plain loads and stores: every element has
+// exactly one writer, so the result is deterministic.
+#include "gp_internal.h"
+#include "gp_spec.h"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+namespace gp {
+namespace {
+
+template <int DT>
+__device__ __forceinline__ float load_attr(const void* base, int64_t idx) {
+  if constexpr (DT == GP_F32) {
+    return static_cast<const float*>(base)[idx];
+  } else if constexpr (DT == GP_BF16) {
+    return __bfloat162float(static_cast<const __hip_bfloat16*>(base)[idx]);
+  } else {
+    return __half2float(static_cast<const __half*>(base)[idx]);
+  }
+}
+
+struct BwdPreArgs {
+  RenderConst rc;
+  const GroupDev* groups;
+  const SliceDev* slices;
+  const RecPay* rec_pay;
+  const RecMeta* rec_meta;
+  const uint32_t* g_rbase;
+  const uint32_t* g_nrec;
+  const uint32_t* inst_pos;
+  const float4* moments;
+  float* grad;
+  int64_t grad_stride;
+};
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.rc.total_gauss) return;
+  const uint32_t nrec = a.g_nrec[t];
+  if (nrec == 0) return;
+  int g = 0;
+  for (int jg = 1; jg < a.rc.n_groups; ++jg)
+    if (a.groups[jg].gbase <= (t & ~63)) g = jg;
+  const GroupDev G = a.groups[g];
+  const int j = t - G.gbase;
+  if (j >= G.n) return;
+  const uint32_t rbase = a.g_rbase[t];
+
+  float p[11];
+  p[0] = G.means[j];
+  p[1] = G.means[G.stride + j];
+  p[2] = G.means[2 * G.stride + j];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) p[3 + r] = load_attr<DT>(G.attrs, r * G.stride + j);
+  SpecCov c;
+  spec_cov(p[3], p[4], p[5], p[6], p[7], p[8], p[9], a.rc.scale_mod, c);
+  const float alpha = p[10];
+
+  float gmx = 0.f, gmy = 0.f, gmz = 0.f, galpha = 0.f;
+  float gxx = 0.f, gxy = 0.f, gxz = 0.f, gyy = 0.f, gyz = 0.f, gzz = 0.f;
+
+  for (uint32_t r = rbase; r < rbase + nrec && r < a.rc.rec_cap; ++r) {
+    const RecMeta meta = a.rec_meta[r];
+    if (meta.ntiles == 0) continue;
+    const RecPay pay = a.rec_pay[r];
+    const SliceDev sl = a.slices[pay.slice];
+    float M0 = 0.f, Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+    for (uint32_t s = 0; s < meta.ntiles; ++s) {
+      const uint32_t pos = a.inst_pos[meta.ibase + s];
+      const float4 m0 = a.moments[2 * (size_t)pos];
+      const float4 m1 = a.moments[2 * (size_t)pos + 1];
+      M0 += m0.x; Mx += m0.y; My += m0.z; Mxx += m0.w; Mxy += m1.x; Myy += m1.y;
+    }
+    // forward quantities of this (Gaussian, slice) pair
+    const SpecAxial ax = spec_axial(p[2], c.szz, sl.z, sl.sigma_z);
+    const float invD = 1.0f / ax.D;
+    const float w = 1.0f / (1.0f + c.szz / ax.s2);
+    const float A = w * c.sxx + c.a11 * invD;
+    const float C = w * c.syy + c.a00 * invD;
+    const float B = w * c.sxy - c.a01 * invD;
+    const float u = c.sxz * invD, v = c.syz * invD;
+    const float det = w * c.a22 + c.detS * invD;
+    if (!(det > 0.0f) || !isfinite(det)) continue;
+    const float rho = expf(-0.5f * ax.q);
+    const float sq = sqrtf(det);
+    const float at = alpha * rho / sq;
+    const float inv_det = 1.0f / det;
+    const float ca = C * inv_det, cb = -B * inv_det, cc = A * inv_det;
+    const float m = ax.m;
+    const float ddx = sl.dx, ddy = sl.dy;
+
+    // record gradients in world units
+    const float g_at = M0;
+    const float g_m2x = at * (ca * ddx * Mx + cb * ddy * My);
+    const float g_m2y = at * (cb * ddx * Mx + cc * ddy * My);
+    const float g_ca = -0.5f * at * Mxx * ddx * ddx;
+    const float g_cb = -at * Mxy * ddx * ddy;
+    const float g_cc = -0.5f * at * Myy * ddy * ddy;
+    // conic -> Sigma_2d (inverse of a symmetric 2x2, b counted once)
+    float gA = -(ca * ca * g_ca + ca * cb * g_cb + cb * cb * g_cc);
+    float gB = -(2.f * ca * cb * g_ca + (ca * cc + cb * cb) * g_cb + 2.f * cb * cc * g_cc);
+    float gC = -(cb * cb * g_ca + cb * cc * g_cb + cc * cc * g_cc);
+    // alpha~ = alpha opacity_r det^(-1/2)
+    const float g_det = -0.5f * g_at * at * inv_det;
+    gA += C * g_det;
+    gB += -2.f * B * g_det;
+    gC += A * g_det;
+    galpha += g_at * rho / sq;
+    const float g_rho = g_at * alpha / sq;
+    const float g_q = -0.5f * rho * g_rho;
+    // Focus Gaussian -> Sigma, mu
+    const float g_u = -m * g_m2x, g_v = -m * g_m2y;
+    gxx += gA;
+    gxy += gB;
+    gyy += gC;
+    gxz += -2.f * u * gA - v * gB + g_u * invD;
+    gyz += -2.f * v * gC - u * gB + g_v * invD;
+    gzz += u * u * gA + u * v * gB + v * v * gC - (u * g_u + v * g_v) * invD - g_q * m * m * invD * invD;
+    gmx += g_m2x;
+    gmy += g_m2y;
+    gmz += -(u * g_m2x + v * g_m2y) + 2.f * g_q * m * invD;
+  }
+
+  // Sigma = M M^T with M = R diag(s): dL/dM = 2 Gs M, Gs symmetric
+  const float Gs[3][3] = {{gxx, 0.5f * gxy, 0.5f * gxz},
+                          {0.5f * gxy, gyy, 0.5f * gyz},
+                          {0.5f * gxz, 0.5f * gyz, gzz}};
+  const float s[3] = {c.s0, c.s1, c.s2};
+  float gM[3][3], gR[3][3], gl[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      const float mij = 2.f * (Gs[i][0] * c.R[0][jj] + Gs[i][1] * c.R[1][jj] + Gs[i][2] * c.R[2][jj]) * s[jj];
+      gM[i][jj] = mij;
+      gR[i][jj] = mij * s[jj];
+    }
+#pragma unroll
+  for (int jj = 0; jj < 3; ++jj) gl[jj] = (gM[0][jj] * c.R[0][jj] + gM[1][jj] * c.R[1][jj] + gM[2][jj] * c.R[2][jj]) * s[jj];
+  // rotation matrix of (w, x, y, z) -> quaternion gradient
+  const float qw = c.w, qx = c.x, qy = c.y, qz = c.z;
+  const float gqw = 2.f * (-qz * gR[0][1] + qy * gR[0][2] + qz * gR[1][0] - qx * gR[1][2] - qy * gR[2][0] + qx * gR[2][1]);
+  const float gqx = 2.f * (qy * gR[0][1] + qz * gR[0][2] + qy * gR[1][0] - qw * gR[1][2] + qz * gR[2][0] + qw * gR[2][1])
+                    - 4.f * qx * (gR[1][1] + gR[2][2]);
+  const float gqy = 2.f * (qx * gR[0][1] + qw * gR[0][2] + qx * gR[1][0] + qz * gR[1][2] - qw * gR[2][0] + qz * gR[2][1])
+                    - 4.f * qy * (gR[0][0] + gR[2][2]);
+  const float gqz = 2.f * (-qw * gR[0][1] + qx * gR[0][2] + qw * gR[1][0] + qy * gR[1][2] + qx * gR[2][0] + qy * gR[2][1])
+                    - 4.f * qz * (gR[0][0] + gR[1][1]);
+  const float dotq = qw * gqw + qx * gqx + qy * gqy + qz * gqz;
+  const float inv_n = 1.0f / sqrtf(c.n2);
+  const float gq[4] = {(gqw - qw * dotq) * inv_n, (gqx - qx * dotq) * inv_n, (gqy - qy * dotq) * inv_n,
+                       (gqz - qz * dotq) * inv_n};
+
+  float* gp = a.grad + j;
+  const int64_t gs = a.grad_stride;
+  gp[0] += gmx;
+  gp[gs] += gmy;
+  gp[2 * gs] += gmz;
+  gp[3 * gs] += gl[0];
+  gp[4 * gs] += gl[1];
+  gp[5 * gs] += gl[2];
+  gp[6 * gs] += gq[0];
+  gp[7 * gs] += gq[1];
+  gp[8 * gs] += gq[2];
+  gp[9 * gs] += gq[3];
+  gp[10 * gs] += galpha;
+}
+
+}  // namespace
+
+hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, float* grad,
+                                 int64_t grad_stride, hipStream_t s) {
+  if (rc.total_gauss <= 0) return hipSuccess;
+  BwdPreArgs a{rc, ws.d_groups, ws.d_slices, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase, ws.d_g_nrec,
+               ws.d_inst_pos, ws.d_moments, grad, grad_stride};
+  const unsigned blocks = (unsigned)((rc.total_gauss + 255) / 256);
+  switch (ws.h_groups[0].attr_dtype) {
+    case GP_BF16: k_preprocess_bwd<GP_BF16><<<blocks, 256, 0, s>>>(a); break;
+    case GP_F16: k_preprocess_bwd<GP_F16><<<blocks, 256, 0, s>>>(a); break;
+    default: k_preprocess_bwd<GP_F32><<<blocks, 256, 0, s>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gp

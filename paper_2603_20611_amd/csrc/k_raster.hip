@@ -1,0 +1,204 @@
+// Additive rasterisation of the tile lists (Sec. 4.2, additive rasterisation:
+// I(p) = sum over N(p) of alpha~ exp(-1/2 d^T Sigma_2d^-1 d), no occlusion) and
+// its adjoint (Sec. 4.3: dI/dalpha~ = exp(.), chain through mu_2d and the conic).
+//
+// Records arrive in pixel space: with dx, dy the offsets of the pixel index
+// from the record's mean, a contribution is w * exp2(a dx^2 + b dx dy + c dy^2)
+// (the exponent coefficients carry -1/2 log2(e) and the pixel pitch).
+//
+// Forward: one 64-lane wavefront per 16x16 tile.  Lane l owns the four
+// horizontally adjacent pixels (4 (l & 3) + 0..3, l >> 2) so the row terms
+// b dy and c dy^2 are shared by four pixels, and the four pixel chains give the
+// instruction stream the independent operations gfx950 needs to issue VALU at
+// full rate.  Records are staged 64 at a time in LDS and read back as
+// wavefront-wide broadcasts into VGPRs (operands held in SGPRs halve VALU
+// issue on gfx950).
+//
+// Backward: one lane per list entry; the lane sweeps the tile's 256 pixels in
+// row order with the upstream gradient staged in LDS, and accumulates six
+// moments of G(p) e(p) (sum e, sum e dx, sum e dy, sum e dx^2, sum e dx dy,
+// sum e dy^2).  The moments fully determine the entry's gradient with respect
+// to its record, so no per-pixel reduction and no atomics are needed; they are
+// written per list entry and summed per record, in a fixed order, later.
+#include "gp_internal.h"
+
+namespace gp {
+namespace {
+
+__device__ __forceinline__ int slice_of_bin(const SliceDev* __restrict__ slices, int n_slices, int bin) {
+  int lo = 0, hi = n_slices - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (slices[mid].tile_base <= bin) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct FwdArgs {
+  const SliceDev* slices;
+  const uint32_t* bin_start;
+  const RecPay* pay;
+  float* out;
+  int32_t n_slices;
+};
+
+__global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
+  __shared__ float4 buf0[64];   // x, y, a, b
+  __shared__ float2 buf1[64];   // c, w
+  const int bin = blockIdx.x;
+  const int k = slice_of_bin(a.slices, a.n_slices, bin);
+  const SliceDev sl = a.slices[k];
+  const int tile = bin - sl.tile_base;
+  const int tx = tile % sl.ntx, ty = tile / sl.ntx;
+  const int lane = threadIdx.x;
+  const int row = lane >> 2;
+  const int col0 = (lane & 3) * 4;
+  const int px0 = tx * kTile + col0;
+  const int py = ty * kTile + row;
+  const float fx0 = (float)px0, fy = (float)py;
+
+  const uint32_t start = a.bin_start[bin], end = a.bin_start[bin + 1];
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+
+  float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float2 n1 = make_float2(0.f, 0.f);
+  if (start + lane < end) {
+    const float4* src = reinterpret_cast<const float4*>(a.pay + start + lane);
+    n0 = src[0];
+    const float4 t = src[1];
+    n1 = make_float2(t.x, t.y);
+  }
+  for (uint32_t base = start; base < end; base += 64) {
+    buf0[lane] = n0;
+    buf1[lane] = n1;
+    __syncthreads();
+    const int cnt = (int)min(64u, end - base);
+    // prefetch the next batch while this one is consumed
+    const uint32_t nb = base + 64;
+    if (nb + lane < end) {
+      const float4* src = reinterpret_cast<const float4*>(a.pay + nb + lane);
+      n0 = src[0];
+      const float4 t = src[1];
+      n1 = make_float2(t.x, t.y);
+    }
+#pragma unroll 2
+    for (int j = 0; j < cnt; ++j) {
+      const float4 r0 = buf0[j];
+      const float2 r1 = buf1[j];
+      const float dy = fy - r0.y;
+      const float by = r0.w * dy;
+      const float cy = r1.x * dy * dy;
+      const float d0 = fx0 - r0.x;
+      const float d1 = d0 + 1.0f, d2 = d0 + 2.0f, d3 = d0 + 3.0f;
+      const float p0 = fmaf(fmaf(r0.z, d0, by), d0, cy);
+      const float p1 = fmaf(fmaf(r0.z, d1, by), d1, cy);
+      const float p2 = fmaf(fmaf(r0.z, d2, by), d2, cy);
+      const float p3 = fmaf(fmaf(r0.z, d3, by), d3, cy);
+      acc0 = fmaf(r1.y, __builtin_amdgcn_exp2f(p0), acc0);
+      acc1 = fmaf(r1.y, __builtin_amdgcn_exp2f(p1), acc1);
+      acc2 = fmaf(r1.y, __builtin_amdgcn_exp2f(p2), acc2);
+      acc3 = fmaf(r1.y, __builtin_amdgcn_exp2f(p3), acc3);
+    }
+    __syncthreads();
+  }
+  if (py < sl.height) {
+    float* o = a.out + sl.out_off + (int64_t)py * sl.width;
+    if (px0 + 3 < sl.width && (reinterpret_cast<uintptr_t>(o + px0) & 15) == 0) {
+      *reinterpret_cast<float4*>(o + px0) = make_float4(acc0, acc1, acc2, acc3);
+    } else {
+      if (px0 < sl.width) o[px0] = acc0;
+      if (px0 + 1 < sl.width) o[px0 + 1] = acc1;
+      if (px0 + 2 < sl.width) o[px0 + 2] = acc2;
+      if (px0 + 3 < sl.width) o[px0 + 3] = acc3;
+    }
+  }
+}
+
+struct BwdArgs {
+  const SliceDev* slices;
+  const uint32_t* bin_start;
+  const RecPay* pay;
+  const float* grad_out;
+  float4* moments;
+  int32_t n_slices;
+};
+
+__global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
+  __shared__ float G[kTilePix];
+  const int bin = blockIdx.x;
+  const uint32_t start = a.bin_start[bin], end = a.bin_start[bin + 1];
+  if (start == end) return;
+  const int k = slice_of_bin(a.slices, a.n_slices, bin);
+  const SliceDev sl = a.slices[k];
+  const int tile = bin - sl.tile_base;
+  const int tx = tile % sl.ntx, ty = tile / sl.ntx;
+  {
+    const int t = threadIdx.x;
+    const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
+    G[t] = (px < sl.width && py < sl.height) ? a.grad_out[sl.out_off + (int64_t)py * sl.width + px] : 0.f;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const float fx0 = (float)(tx * kTile), fy0 = (float)(ty * kTile);
+  for (uint32_t cb = start + wave * 64; cb < end; cb += 256) {
+    const uint32_t idx = cb + lane;
+    if (idx >= end) continue;
+    const float4* src = reinterpret_cast<const float4*>(a.pay + idx);
+    const float4 r0 = src[0];
+    const float4 r1 = src[1];
+    const float ca = r0.z, cb2 = r0.w, cc = r1.x;
+    float dx[kTile];
+#pragma unroll
+    for (int c = 0; c < kTile; ++c) dx[c] = (fx0 - r0.x) + (float)c;
+    float M0 = 0.f, Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+    for (int row = 0; row < kTile; ++row) {
+      const float dy = (fy0 + (float)row) - r0.y;
+      const float by = cb2 * dy;
+      const float cy = cc * dy * dy;
+      const float4* grow = reinterpret_cast<const float4*>(G + row * kTile);
+      float s0 = 0.f, sx = 0.f, sxx = 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 g4 = grow[q];
+        const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float d = dx[4 * q + c];
+          const float p = fmaf(fmaf(ca, d, by), d, cy);
+          const float we = gv[c] * __builtin_amdgcn_exp2f(p);
+          const float wd = we * d;
+          s0 += we;
+          sx += wd;
+          sxx = fmaf(wd, d, sxx);
+        }
+      }
+      M0 += s0;
+      Mx += sx;
+      Mxx += sxx;
+      My = fmaf(dy, s0, My);
+      Mxy = fmaf(dy, sx, Mxy);
+      Myy = fmaf(dy * dy, s0, Myy);
+    }
+    a.moments[2 * (size_t)idx] = make_float4(M0, Mx, My, Mxx);
+    a.moments[2 * (size_t)idx + 1] = make_float4(Mxy, Myy, 0.f, 0.f);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_raster_fwd(const RenderConst& rc, const Workspace& ws, float* out, hipStream_t s) {
+  if (rc.n_bins <= 0) return hipSuccess;
+  FwdArgs a{ws.d_slices, ws.d_bin_start, ws.d_pay, out, rc.n_slices};
+  k_raster_fwd<<<(unsigned)rc.n_bins, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const float* grad_out,
+                             hipStream_t s) {
+  if (rc.n_bins <= 0) return hipSuccess;
+  BwdArgs a{ws.d_slices, ws.d_bin_start, ws.d_pay, grad_out, ws.d_moments, rc.n_slices};
+  k_raster_bwd<<<(unsigned)rc.n_bins, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace gp

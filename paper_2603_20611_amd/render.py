@@ -1,0 +1,162 @@
+"""Torch-facing wrappers of the HIP library: workspaces, the differentiable
+renderer (a torch.autograd.Function whose backward is the library's hand-written
+adjoint), fused Adam and the L1 loss.  PyTorch provides device memory and the
+stream; every step runs in the library's kernels.
+
+Gaussian parameters are a float32 CUDA tensor of shape [11, stride] (rows
+mu_x, mu_y, mu_z, l_x, l_y, l_z, q_w, q_x, q_y, q_z, alpha); the first n
+columns are the Gaussians.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class Workspace:
+    """Library-owned scratch for tile lists.  capacity=(records, instances) fixes the
+    buffers (no host synchronisation per render); None sizes them automatically."""
+
+    def __init__(self, capacity=None):
+        lib = B.load()
+        self._h = C.c_void_p()
+        rec, inst = capacity if capacity else (0, 0)
+        B.check(lib.gp_workspace_create(C.byref(self._h), int(rec), int(inst)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check(self):
+        """(records, instances, bins) of the last render; raises GpError on overflow."""
+        r, i, b = C.c_int64(), C.c_int64(), C.c_int64()
+        B.check(B.load().gp_workspace_check(self._h, C.byref(r), C.byref(i), C.byref(b)))
+        return r.value, i.value, b.value
+
+    def set_timing(self, enable=True):
+        B.check(B.load().gp_workspace_set_timing(self._h, 1 if enable else 0))
+
+    def timings(self):
+        """{stage: (milliseconds summed, launches)} since timing was enabled (synchronises)."""
+        n = len(B.STAGES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        B.check(B.load().gp_workspace_timings(self._h, ms, cnt, n))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(B.STAGES)}
+
+    def export_bins(self, n_bins, max_keys):
+        keys = np.zeros(max(max_keys, 1), np.uint64)
+        ranges = np.zeros(2 * max(n_bins, 1), np.int64)
+        n = C.c_int64()
+        B.check(B.load().gp_debug_export_bins(self._h, keys.ctypes.data_as(C.POINTER(C.c_uint64)), keys.size,
+                                              C.byref(n), ranges.ctypes.data_as(C.POINTER(C.c_int64)),
+                                              ranges.size))
+        return keys[: n.value].astype(np.int64), ranges.reshape(-1, 2)[:n_bins]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            B.load().gp_workspace_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gaussians_struct(params, n=None, attrs=None, attr_dtype=B.GP_F32):
+    """gp_gaussians for a [11, stride] float32 tensor (or float32 means [3, stride] plus
+    16-bit attrs [8, stride])."""
+    if attrs is None:
+        assert params.dtype == torch.float32 and params.is_cuda and params.is_contiguous()
+        stride = params.shape[1]
+        n = stride if n is None else n
+        g = B.Gaussians(params.data_ptr(), params.data_ptr() + 3 * stride * 4, n, stride, B.GP_F32, B.GP_F32)
+    else:
+        stride = params.shape[1]
+        assert attrs.shape[1] == stride and attrs.is_contiguous() and params.is_contiguous()
+        n = stride if n is None else n
+        g = B.Gaussians(params.data_ptr(), attrs.data_ptr(), n, stride, B.GP_F32, attr_dtype)
+    return g
+
+
+def slice_pixels(slices):
+    return sum(int(s["width"]) * int(s["height"]) for s in slices)
+
+
+def render(params, slices, opts=None, ws=None, out=None, n=None, attrs=None, attr_dtype=B.GP_F32):
+    """Forward render; returns the packed float32 images (1-D tensor)."""
+    lib = B.load()
+    ws = ws or Workspace()
+    opts = opts or B.default_opts()
+    sl = B.make_slices(slices)
+    if out is None:
+        out = torch.empty(slice_pixels(slices), device=params.device, dtype=torch.float32)
+    g = gaussians_struct(params, n, attrs, attr_dtype)
+    B.check(lib.gp_render_slices(ws.handle, C.byref(g), sl, len(slices), C.byref(opts), _ptr(out), _stream()))
+    return out
+
+
+def render_backward(params, slices, grad_out, ws, opts=None, grad=None, n=None):
+    lib = B.load()
+    opts = opts or B.default_opts()
+    sl = B.make_slices(slices)
+    if grad is None:
+        grad = torch.zeros_like(params)
+    g = gaussians_struct(params, n)
+    B.check(lib.gp_render_backward(ws.handle, C.byref(g), sl, len(slices), C.byref(opts),
+                                   _ptr(grad_out.contiguous()), _ptr(grad), grad.shape[1], _stream()))
+    return grad
+
+
+class FocusRender(torch.autograd.Function):
+    """I = render(params, slices); backward by the library's adjoint (recomputes the
+    per-pixel contributions from the forward's tile lists)."""
+
+    @staticmethod
+    def forward(ctx, params, slices, opts, ws):
+        out = render(params, slices, opts, ws)
+        ctx.slices, ctx.opts, ctx.ws = slices, opts, ws
+        ctx.save_for_backward(params)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (params,) = ctx.saved_tensors
+        grad = render_backward(params, ctx.slices, grad_out, ctx.ws, ctx.opts)
+        return grad, None, None, None
+
+
+def focus_render(params, slices, opts=None, ws=None):
+    return FocusRender.apply(params, slices, opts or B.default_opts(), ws or Workspace())
+
+
+def l1_loss_grad(image, target, grad=None, loss=None, scale=None):
+    lib = B.load()
+    n = image.numel()
+    grad = torch.empty_like(image) if grad is None else grad
+    scale = 1.0 / n if scale is None else scale
+    B.check(lib.gp_l1_loss_grad(_ptr(image), _ptr(target), n, float(scale), _ptr(grad), _ptr(loss), _stream()))
+    return grad
+
+
+def adam_step(params, grad, m, v, step, lr, betas=(0.9, 0.999), eps=1e-15, n=None, flags=0):
+    """lr: (mean, log_scale, quat, alpha) learning rates."""
+    lib = B.load()
+    cfg = B.AdamCfg((C.c_float * 4)(*[float(x) for x in lr]), betas[0], betas[1], eps, int(step), int(flags))
+    stride = params.shape[1]
+    n = stride if n is None else n
+    B.check(lib.gp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), n, stride, C.byref(cfg), _stream()))

@@ -1,0 +1,297 @@
+"""Parity of the HIP renderer with the CPU oracle (GPU).
+
+Bars: tile lists bit-exact; images within 1e-5 of the oracle relative to the
+image's maximum (L-infinity); gradients within 1e-4 per parameter block
+(mu, log-scale, quaternion, alpha), L-infinity relative to the block's oracle
+L-infinity norm.  Inputs are seeded and synthetic; the upstream gradient of the
+backward tests is a seeded random field (a linear functional of the images).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import focus, spec32
+from paper_2603_20611_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 1e-5
+GRAD_TOL = 1e-4
+BLOCKS = {"mean": (0, 3), "log_scale": (3, 6), "quat": (6, 10), "alpha": (10, 11)}
+
+
+def _say(msg):
+    print(f"[parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_params(p, stride=None):
+    n = p.shape[1]
+    stride = stride or n
+    t = torch.zeros((11, stride), dtype=torch.float32)
+    t[:, :n] = torch.from_numpy(p)
+    return t.cuda().contiguous()
+
+
+def _split(flat, slices):
+    out, o = [], 0
+    for s in slices:
+        k = int(s["width"]) * int(s["height"])
+        out.append(flat[o:o + k].reshape(int(s["height"]), int(s["width"])))
+        o += k
+    return out
+
+
+def _fwd_err(gpu_imgs, ref_imgs):
+    ref_max = max(float(np.abs(r).max()) for r in ref_imgs)
+    err = max(float(np.abs(g - r).max()) for g, r in zip(gpu_imgs, ref_imgs))
+    return err / max(ref_max, 1e-30), ref_max
+
+
+def _render_gpu(gp, p, slices, opts=None, ws=None, stride=None):
+    from paper_2603_20611_amd import render
+    params = _gpu_params(p, stride)
+    ws = ws or render.Workspace()
+    out = render.render(params, slices, opts, ws, n=p.shape[1])
+    torch.cuda.synchronize()
+    return params, ws, _split(out.cpu().numpy().astype(np.float64), slices)
+
+
+def _check_bins(ws, p, slices, opts_kw=None):
+    opts_kw = opts_kw or {}
+    keys_ref, ranges_ref = spec32.bins(p, slices, **opts_kw)
+    n_bins = ranges_ref.shape[0]
+    keys, ranges = ws.export_bins(n_bins, max(keys_ref.size, 1) + 16)
+    assert keys.size == keys_ref.size
+    assert np.array_equal(keys, keys_ref)
+    assert np.array_equal(ranges, ranges_ref)
+
+
+# --------------------------------------------------------------------------- forward
+def test_tiny_forward_and_bins(gp):
+    _say("tiny forward: 2000 Gaussians, 32 slices 64x64")
+    p, slices, _ = synth.tiny(0)
+    params, ws, imgs = _render_gpu(gp, p, slices)
+    _check_bins(ws, p, slices)
+    ref = [x.numpy() for x in focus.render(p, slices)]
+    err, mx = _fwd_err(imgs, ref)
+    _say(f"tiny forward rel err {err:.3e} (max {mx:.3f})")
+    assert err <= FWD_TOL
+
+
+@pytest.mark.parametrize("case", ["ragged", "offset_grid", "sigma0", "sigma_inf", "mixed_grids", "one_gaussian",
+                                  "stride_pad"])
+def test_forward_edge_cases(gp, case):
+    _say(f"edge case {case}")
+    rng_seed = 21
+    p = synth.gaussians_uniform(400, (70, 45, 12), np.log(1.4), 0.45, seed=rng_seed)
+    stride = None
+    if case == "ragged":
+        slices = synth.axial_slices(3, 70, 45, 1.5, z0=2.0, dz=3.5)
+    elif case == "offset_grid":
+        slices = [dict(z=5.0, sigma_z=0.7, x0=-3.25, y0=4.5, dx=0.8, dy=1.3, width=81, height=33)]
+    elif case == "sigma0":
+        slices = synth.axial_slices(2, 64, 48, 0.0, z0=3.3, dz=4.0)
+    elif case == "sigma_inf":
+        slices = synth.axial_slices(2, 64, 48, math.inf, z0=3.3, dz=4.0)
+    elif case == "mixed_grids":
+        slices = [dict(z=4.0, sigma_z=1.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=70, height=45),
+                  dict(z=6.5, sigma_z=3.0, x0=0.0, y0=0.0, dx=0.5, dy=0.5, width=140, height=90),
+                  dict(z=8.0, sigma_z=0.5, x0=10.0, y0=5.0, dx=2.0, dy=2.0, width=20, height=17)]
+    elif case == "one_gaussian":
+        p = p[:, :1].copy()
+        p[0:3, 0] = (31.0, 17.0, 6.0)
+        slices = synth.axial_slices(3, 64, 32, 1.0, z0=5.0, dz=1.0)
+    else:  # stride_pad
+        slices = synth.axial_slices(2, 64, 48, 1.0, z0=3.3, dz=4.0)
+        stride = 448
+    params, ws, imgs = _render_gpu(gp, p, slices, stride=stride)
+    _check_bins(ws, p, slices)
+    ref = [x.numpy() for x in focus.render(p, slices)]
+    err, mx = _fwd_err(imgs, ref)
+    _say(f"{case}: rel err {err:.3e} (max {mx:.3f})")
+    assert err <= FWD_TOL
+
+
+def test_forward_exact_mode_matches_brute_force(gp):
+    from paper_2603_20611_amd import binding as B
+    _say("exact mode")
+    p = synth.gaussians_uniform(60, (40, 40, 8), np.log(1.3), 0.3, seed=5)
+    slices = synth.axial_slices(2, 40, 36, 1.2, z0=2.5, dz=3.0)
+    opts = B.default_opts(flags=B.GP_FLAG_EXACT)
+    params, ws, imgs = _render_gpu(gp, p, slices, opts)
+    _check_bins(ws, p, slices, dict(exact=True))
+    ref = [x.numpy() for x in focus.render(p, slices, exact=True)]
+    err, _ = _fwd_err(imgs, ref)
+    assert err <= FWD_TOL
+
+
+def test_forward_non_finite_and_empty(gp):
+    _say("non-finite parameters and empty set")
+    p = synth.gaussians_uniform(300, (64, 64, 10), np.log(1.5), 0.3, seed=7)
+    p[0, 3] = np.nan
+    p[4, 10] = np.inf
+    p[6:10, 20] = 0.0          # zero quaternion
+    p[10, 30] = np.nan
+    slices = synth.axial_slices(2, 64, 64, 1.0, z0=3.0, dz=4.0)
+    params, ws, imgs = _render_gpu(gp, p, slices)
+    _check_bins(ws, p, slices)
+    ref = [x.numpy() for x in focus.render(p, slices)]
+    err, _ = _fwd_err(imgs, ref)
+    assert err <= FWD_TOL and all(np.isfinite(x).all() for x in imgs)
+    # empty Gaussian set renders zeros
+    params, ws, imgs = _render_gpu(gp, p[:, :0], slices, stride=64)
+    assert all((x == 0).all() for x in imgs)
+
+
+def test_forward_is_deterministic(gp):
+    from paper_2603_20611_amd import render
+    _say("determinism")
+    p, slices, _ = synth.tiny(3)
+    params = _gpu_params(p)
+    ws = render.Workspace()
+    a = render.render(params, slices, ws=ws).clone()
+    b = render.render(params, slices, ws=render.Workspace()).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_fixed_capacity_overflow_is_reported(gp):
+    from paper_2603_20611_amd import binding as B, render
+    _say("fixed-capacity overflow")
+    p, slices, _ = synth.tiny(0)
+    params = _gpu_params(p)
+    ws = render.Workspace(capacity=(100, 200))
+    render.render(params, slices, ws=ws)
+    with pytest.raises(B.GpError) as e:
+        ws.check()
+    assert e.value.status == B.GP_EOVERFLOW
+    # a large enough fixed workspace renders without synchronising and matches
+    ws2 = render.Workspace(capacity=(200_000, 800_000))
+    out = render.render(params, slices, ws=ws2)
+    ws2.check()
+    ref = render.render(params, slices, ws=render.Workspace())
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+
+
+# --------------------------------------------------------------------------- backward
+def _grad_check(g_gpu, g_ref):
+    worst = {}
+    for name, (r0, r1) in BLOCKS.items():
+        ref = g_ref[r0:r1]
+        scale = float(np.abs(ref).max())
+        err = float(np.abs(g_gpu[r0:r1] - ref).max()) / max(scale, 1e-30)
+        worst[name] = err
+    return worst
+
+
+def _backward_case(gp, p, slices, seed=0):
+    from paper_2603_20611_amd import render
+    params = _gpu_params(p)
+    ws = render.Workspace()
+    render.render(params, slices, ws=ws, n=p.shape[1])
+    rng = np.random.default_rng(seed)
+    w = [rng.standard_normal((int(s["height"]), int(s["width"]))) for s in slices]
+    gflat = torch.from_numpy(np.concatenate([x.ravel() for x in w]).astype(np.float32)).cuda()
+    grad = render.render_backward(params, slices, gflat, ws, n=p.shape[1])
+    torch.cuda.synchronize()
+    g_gpu = grad.cpu().numpy().astype(np.float64)[:, :p.shape[1]]
+    w64 = [x.astype(np.float32).astype(np.float64) for x in w]
+    g_ref = focus.grad(p, slices, w64)
+    return g_gpu, g_ref, (params, ws, gflat)
+
+
+def test_tiny_backward(gp):
+    _say("tiny backward")
+    p, slices, _ = synth.tiny(0)
+    g_gpu, g_ref, _ = _backward_case(gp, p, slices)
+    worst = _grad_check(g_gpu, g_ref)
+    _say(f"tiny backward worst per block {worst}")
+    assert max(worst.values()) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("case", ["sigma0", "sigma_inf", "offset_grid", "filaments"])
+def test_backward_edge_cases(gp, case):
+    _say(f"backward {case}")
+    p = synth.gaussians_uniform(300, (64, 48, 10), np.log(1.4), 0.4, seed=31)
+    if case == "sigma0":
+        slices = synth.axial_slices(2, 64, 48, 0.0, z0=3.3, dz=4.0)
+    elif case == "sigma_inf":
+        slices = synth.axial_slices(2, 64, 48, math.inf, z0=3.3, dz=4.0)
+    elif case == "offset_grid":
+        slices = [dict(z=5.0, sigma_z=0.7, x0=-3.25, y0=4.5, dx=0.8, dy=1.3, width=81, height=33)]
+    else:
+        p = synth.gaussians_microscopy(400, (64.0, 64.0, 16.0), seed=32)
+        slices = synth.axial_slices(3, 64, 64, 2.0, z0=4.5, dz=3.0)
+    g_gpu, g_ref, _ = _backward_case(gp, p, slices, seed=3)
+    worst = _grad_check(g_gpu, g_ref)
+    _say(f"{case} worst per block {worst}")
+    assert max(worst.values()) <= GRAD_TOL
+
+
+def test_backward_is_deterministic_and_accumulates(gp):
+    from paper_2603_20611_amd import render
+    _say("backward determinism")
+    p, slices, _ = synth.tiny(1)
+    _, _, (params, ws, gflat) = _backward_case(gp, p, slices)
+    g1 = render.render_backward(params, slices, gflat, ws)
+    g2 = render.render_backward(params, slices, gflat, ws)
+    g3 = render.render_backward(params, slices, gflat, ws, grad=g1.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    assert torch.allclose(g3, 2 * g1, rtol=1e-6, atol=0)
+
+
+def test_backward_requires_matching_forward(gp):
+    from paper_2603_20611_amd import binding as B, render
+    p, slices, _ = synth.tiny(0)
+    params = _gpu_params(p)
+    ws = render.Workspace()
+    render.render(params, slices, ws=ws)
+    g = torch.zeros(p.shape[1] * 64, device="cuda")
+    with pytest.raises(B.GpError) as e:
+        render.render_backward(params, slices[:3], g, ws)
+    assert e.value.status == B.GP_ESTATE
+
+
+# --------------------------------------------------------------------------- loss and Adam
+def test_l1_loss_grad(gp):
+    from paper_2603_20611_amd import render
+    rng = np.random.default_rng(4)
+    I = rng.standard_normal(100_003).astype(np.float32)
+    T = rng.standard_normal(100_003).astype(np.float32)
+    T[::7] = I[::7]
+    loss = torch.zeros(1, device="cuda")
+    g = render.l1_loss_grad(torch.from_numpy(I).cuda(), torch.from_numpy(T).cuda(), loss=loss)
+    torch.cuda.synchronize()
+    ref = focus.l1_grad(I, T)
+    assert np.array_equal(g.cpu().numpy(), ref.astype(np.float32))
+    ref_loss = np.abs(I.astype(np.float64) - T).mean()
+    assert abs(float(loss.item()) - ref_loss) <= 1e-5 * ref_loss
+
+
+def test_adam_matches_textbook(gp):
+    from paper_2603_20611_amd import render
+    rng = np.random.default_rng(5)
+    n, stride = 1001, 1024
+    p = rng.standard_normal((11, stride)).astype(np.float32)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    lr = dict(mean=6e-4, log_scale=2e-3, quat=1e-3, alpha=2e-2)
+    lrs = (lr["mean"], lr["log_scale"], lr["quat"], lr["alpha"])
+    P, M, V = (torch.from_numpy(x).cuda() for x in (p, m, v))
+    ref_p, ref_m, ref_v = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for step in range(1, 6):
+        g = rng.standard_normal((11, stride)).astype(np.float32)
+        G = torch.from_numpy(g).cuda()
+        render.adam_step(P, G, M, V, step, lrs, n=n)
+        ref_p[:, :n], ref_m[:, :n], ref_v[:, :n] = focus.adam_step(ref_p[:, :n], g[:, :n].astype(np.float64),
+                                                                   ref_m[:, :n], ref_v[:, :n], lr, step)
+    torch.cuda.synchronize()
+    got = P.cpu().numpy()
+    assert np.abs(got[:, :n] - ref_p[:, :n]).max() <= 1e-6 * max(1.0, np.abs(ref_p).max())
+    assert np.array_equal(got[:, n:], p[:, n:])   # padding untouched
