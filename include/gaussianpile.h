@@ -3,7 +3,7 @@
  *
  * The library renders axial slices of a set of anisotropic 3-D Gaussians under
  * GaussianPile's finite-thickness focus model (Sec. 4.2), differentiates the
- * rendering (Sec. 4.3, "Backward pass"; supplement Sec. 8), updates parameters
+ * rendering (Sec. 4.3, "Backward pass"; supplement, "Derivation of Differentiable Backward Pass"), updates parameters
  * with Adam (Sec. 5.1, implementation details) and serves slices of resident
  * volumes.
  *
@@ -19,7 +19,7 @@
  *   - Every entry point returns a gp_status.  On failure, gp_last_error()
  *     returns a thread-local description.  No C++ exception crosses the ABI.
  *
- * Gaussian parameters (supplement Sec. 7: G = (mu, s, q, alpha)) are stored as
+ * Gaussian parameters (supplement, "Derivation of Forward rendering process": G = (mu, s, q, alpha)) are stored as
  * planes ("SoA"): plane r of a set with row stride `stride` starts at element
  * r * stride.  The eleven rows are
  *     0..2  mu_x, mu_y, mu_z            position (world units)
@@ -31,7 +31,7 @@
  *
  * A slice is the axial plane z = const imaged with axial PSF width sigma_z
  * (Sec. 4.1, sensitivity map h(-z_c) = exp(-z_c^2 / 2 sigma_z^2)); its camera is
- * R_c = I, t = (0, 0, -z) (supplement Sec. 7).  Pixel (px, py) has centre
+ * R_c = I, t = (0, 0, -z) (supplement, "Derivation of Forward rendering process").  Pixel (px, py) has centre
  * (x0 + (px + 1/2) dx, y0 + (py + 1/2) dy).  Images of a batch are packed back
  * to back in slice order, each row-major [height][width] float32.
  */
@@ -64,7 +64,7 @@ typedef int32_t gp_status;
  * threshold"); a (Gaussian, slice) pair is drawn iff m^2 / (sigma_z^2 +
  * Sigma_zz) <= q_cut.  bbox_sigmas: half-width of the tile footprint in
  * standard deviations of Sigma_2d.  scale_mod: the `mod` factor of
- * S = diag(mod * s) (supplement Sec. 7).  GP_FLAG_EXACT: no cull and no
+ * S = diag(mod * s) (supplement, "Derivation of Forward rendering process").  GP_FLAG_EXACT: no cull and no
  * footprint, every Gaussian reaches every pixel (reference mode). */
 #define GP_FLAG_EXACT 1u
 typedef struct gp_render_opts {
@@ -124,7 +124,7 @@ gp_status gp_workspace_check(gp_workspace* ws, int64_t* records, int64_t* instan
 
 /* Forward rendering of n_slices axial slices (Sec. 4.2: Focus Gaussian,
  * opacity modulation, screen-space projection, intensity normalisation and
- * additive rasterisation; supplement Sec. 7 for the full derivation):
+ * additive rasterisation; supplement, "Derivation of Forward rendering process" for the full derivation):
  *   I_k(p) = sum over the members i of p's tile list on slice k of
  *            alpha~_ik exp(-1/2 d^T Sigma_2d,ik^-1 d),  d = p - mu_2d,ik
  *   alpha~ = alpha * opacity_r / sqrt(det Sigma_2d).
@@ -135,7 +135,7 @@ gp_status gp_render_slices(gp_workspace* ws, const gp_gaussians* g, const gp_sli
                            int32_t n_slices, const gp_render_opts* opts, float* d_out, void* stream);
 
 /* Backward of the preceding gp_render_slices on the same workspace, Gaussian
- * set and slices (Sec. 4.3 "Backward pass", supplement Sec. 8): given
+ * set and slices (Sec. 4.3 "Backward pass", supplement, "Derivation of Differentiable Backward Pass"): given
  * d_grad_out = dL/dI (same layout as d_out), ADDS dL/dparams to d_grad
  * ([11][grad_stride] float32, rows as above; grad_stride >= n).  Per-pixel
  * contributions are recomputed from the tile lists, not stored.  The result is
@@ -172,6 +172,89 @@ typedef struct gp_adam_cfg {
 } gp_adam_cfg;
 gp_status gp_adam_step(float* d_params, float* d_grad, float* d_m, float* d_v, int64_t n,
                        int64_t stride, const gp_adam_cfg* cfg, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: many fitted volumes resident in HBM, slices rendered on request.
+ * A server keeps each volume's positions in float32 and its log-scales,
+ * quaternions and intensities in attr_dtype (16-bit storage, converted to
+ * float32 in the kernels; accumulation is float32).  Requests for slices of
+ * different volumes, depths, resolutions and sigma_z are admitted while
+ * earlier batches run: a scheduler thread groups queued requests into one
+ * batch whenever one of `slots` launch slots is free (the batch's estimated
+ * list size must fit the slot's capacity), and renders the whole batch with
+ * one replay of a captured hipGraph on that slot's stream.  Each request's
+ * image goes straight into the caller's buffer.  A batch whose lists
+ * overflow is re-run one request at a time; a single request that still does
+ * not fit completes with GP_EOVERFLOW.  The rendering is the one of
+ * gp_render_slices (Sec. 4.2) with the server's options.
+ * ---------------------------------------------------------------------- */
+typedef struct gp_server gp_server;
+
+typedef struct gp_server_cfg {
+  int64_t hbm_budget_bytes;    /* bytes of resident volume storage allowed      */
+  int64_t max_gaussians;       /* per batch: sum of the batch's volume sizes    */
+  int64_t max_records;         /* per slot: record capacity                     */
+  int64_t max_instances;       /* per slot: tile-list capacity                  */
+  int32_t max_bins;            /* per batch: 16x16 tiles over all its requests  */
+  int32_t max_batch;           /* requests per batch (1 = one launch each)      */
+  int32_t slots;               /* batches in flight, 1..4                       */
+  int32_t attr_dtype;          /* GP_BF16, GP_F16 or GP_F32                     */
+  int32_t use_graphs;          /* replay a captured graph per slot (else launch) */
+  int32_t device;              /* HIP device                                    */
+  gp_render_opts opts;
+} gp_server_cfg;
+
+typedef struct gp_request {
+  int32_t volume_id;
+  float z, sigma_z;            /* depth and axial PSF width of the slice        */
+  float x0, y0, dx, dy;        /* pixel grid (see gp_slice)                     */
+  int32_t width, height;
+} gp_request;
+
+typedef struct gp_serve_result {
+  int32_t status;              /* GP_OK, GP_EOVERFLOW, GP_ECANCELED, GP_EHIP     */
+  int32_t batch_size;          /* requests in the batch that rendered it        */
+  int64_t batch_id;
+  double latency_ms;           /* submit -> completion observed by the server   */
+} gp_serve_result;
+
+typedef struct gp_server_stats {
+  int64_t submitted, completed, batches, retries, resident_bytes;
+  int32_t volumes;
+  int32_t pad;
+} gp_server_stats;
+
+/* Defaults: 16 GiB budget, 64 requests per batch, 3 slots, BF16 attributes,
+ * graphs on, capacities for 64 requests of 1024^2 at 1M Gaussians each. */
+gp_status gp_server_default_cfg(gp_server_cfg* cfg);
+
+/* Creates a server (its streams, slots and scheduler thread) on cfg->device.
+ * Errors: GP_EINVAL, GP_ENOMEM, GP_EHIP. */
+gp_status gp_server_create(gp_server** sv, const gp_server_cfg* cfg);
+
+/* Copies a fitted Gaussian set (g: float32 means and attributes, any stride)
+ * into resident storage, converting the attributes to cfg->attr_dtype.
+ * Synchronous.  *volume_id receives its id.  Errors: GP_ENOMEM if the budget
+ * would be exceeded, GP_EINVAL, GP_EHIP. */
+gp_status gp_server_add_volume(gp_server* sv, const gp_gaussians* g, int32_t* volume_id);
+
+/* Queues one request; d_out (device, width * height float32) receives the
+ * image.  Non-blocking; *ticket identifies it.  Errors: GP_EINVAL (unknown
+ * volume, bad grid, NULL), GP_ECANCELED (server shutting down). */
+gp_status gp_serve_submit(gp_server* sv, const gp_request* req, float* d_out, uint64_t* ticket);
+
+/* Waits up to timeout_us (0: do not wait, < 0: forever) for a ticket.
+ * Returns GP_OK and fills *res when the request finished (res->status tells
+ * how), GP_EAGAIN if it is still pending, GP_EINVAL for an unknown ticket.
+ * A finished ticket is forgotten once polled. */
+gp_status gp_serve_poll(gp_server* sv, uint64_t ticket, int32_t timeout_us, gp_serve_result* res);
+
+/* Counters since creation. */
+gp_status gp_server_stats_get(gp_server* sv, gp_server_stats* st);
+
+/* Stops admitting, cancels queued requests (GP_ECANCELED), waits for the
+ * batches on the GPU, frees everything.  NULL is accepted. */
+gp_status gp_server_destroy(gp_server* sv);
 
 /* Per-stage kernel timing of a workspace, for measurement.  While enabled, each
  * stage of a render or backward on this workspace is bracketed by HIP events

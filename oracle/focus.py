@@ -8,10 +8,11 @@ every pixel is a direct sum over the members of its tile.
 
 What is followed, step by step:
   * Gaussian parameterisation G = (mu, s, q, alpha), Sigma = R S S^T R^T with
-    S = diag(mod * s), R = quatToMatrix(q)  (Sec. 3; supplement Sec. 7,
-    "Derivation of Forward rendering process", first three equations);
+    S = diag(mod * s), R = quatToMatrix(q)  (Sec. 3; supplement, "Derivation
+    of Forward rendering process", first three equations);
   * slice camera: axial slice at depth z, R_c = I, t = (0, 0, -z), so
-    mu_c = mu + t and Sigma_c = Sigma  (supplement Sec. 7, camera transform);
+    mu_c = mu + t and Sigma_c = Sigma  (supplement, "Derivation of Forward
+    rendering process", camera transform);
   * axial re-parameterisation Sigma_e^-1 = Sigma_c^-1 + e3 e3^T / sigma_z^2,
     mu_e = Sigma_e Sigma_c^-1 mu_c  (Sec. 4.2, Focus Gaussian equation);
   * opacity modulation opacity_r = exp(-1/2 (mu_c^T Sigma_c^-1 mu_c -
@@ -26,7 +27,8 @@ What is followed, step by step:
     ``oracle.spec32``;
   * gradient: the exact derivative of the above, obtained by reverse-mode
     automatic differentiation in float64 (the paper's backward pass, Sec. 4.3
-    and supplement Sec. 8, computes the same derivative);
+    and the supplement's "Derivation of Differentiable Backward Pass",
+    computes the same derivative);
   * Adam: Kingma & Ba, Algorithm 1, cited by the paper's implementation details
     (Sec. 5.1), with per-group learning rates.
 

@@ -49,7 +49,7 @@ static hipError_t host_alloc(T** p, int64_t count) {
                        hipHostMallocDefault);
 }
 
-static hipError_t wait_ws(Workspace* ws) {
+hipError_t wait_ws(Workspace* ws) {
   if (ws->upload_done) {
     hipError_t e = hipEventSynchronize(ws->upload_done);
     if (e != hipSuccess) return e;
@@ -57,7 +57,7 @@ static hipError_t wait_ws(Workspace* ws) {
   return hipStreamSynchronize(static_cast<hipStream_t>(ws->last_stream));
 }
 
-static gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups, int64_t n_bins,
+gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups, int64_t n_bins,
                                int64_t n_gauss) {
   if (n_slices > ws->slice_cap) {
     GP_HIP(wait_ws(ws));
@@ -90,7 +90,7 @@ static gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups
   return GP_OK;
 }
 
-static gp_status reserve_lists(Workspace* ws, int64_t rec_cap, int64_t inst_cap) {
+gp_status reserve_lists(Workspace* ws, int64_t rec_cap, int64_t inst_cap) {
   if (rec_cap > 0xFFFFFFF0ll || inst_cap > 0xFFFFFFF0ll) return einval("capacity exceeds 2^32 entries");
   if (rec_cap > ws->rec_cap) {
     GP_HIP(wait_ws(ws));
@@ -103,9 +103,8 @@ static gp_status reserve_lists(Workspace* ws, int64_t rec_cap, int64_t inst_cap)
   }
   if (inst_cap > ws->inst_cap) {
     GP_HIP(wait_ws(ws));
-    if (dev_alloc(&ws->d_inst_rank, inst_cap) != hipSuccess || dev_alloc(&ws->d_inst_rid, inst_cap) != hipSuccess ||
-        dev_alloc(&ws->d_sort_key, inst_cap) != hipSuccess || dev_alloc(&ws->d_pay, inst_cap) != hipSuccess ||
-        dev_alloc(&ws->d_inst_pos, inst_cap) != hipSuccess || dev_alloc(&ws->d_moments, 2 * inst_cap) != hipSuccess) {
+    if (dev_alloc(&ws->d_inst_rank, inst_cap) != hipSuccess || dev_alloc(&ws->d_sort_key, inst_cap) != hipSuccess ||
+        dev_alloc(&ws->d_list, inst_cap) != hipSuccess || dev_alloc(&ws->d_moments, 2 * inst_cap) != hipSuccess) {
       ws->inst_cap = 0;
       set_error("tile-list buffers: out of device memory");
       return GP_ENOMEM;
@@ -203,21 +202,19 @@ static gp_status check_opts(const gp_render_opts* o) {
   return GP_OK;
 }
 
-// Forward over one Gaussian set sampled by all slices.
-static gp_status render_forward(Workspace* ws, const gp_gaussians* g, const gp_slice* hs, int32_t ns,
-                                const gp_render_opts* o, float* out, hipStream_t s) {
-  int64_t nbins = 0, npix = 0;
-  for (int k = 0; k < ns; ++k) {
-    const int ntx = (hs[k].width + kTile - 1) / kTile, nty = (hs[k].height + kTile - 1) / kTile;
-    nbins += (int64_t)ntx * nty;
-    npix += (int64_t)hs[k].width * hs[k].height;
-  }
-  if (nbins >= (1ll << 31)) return einval("too many tiles in one batch");
-  const int64_t total_gauss = (g->n + 63) / 64 * 64;
-  gp_status st = reserve_small(ws, ns, 1, nbins, total_gauss);
+// Host descriptors of a batch (groups of slices sampling one Gaussian set
+// each) into the workspace's pinned staging.  outs[k] (if given) is where slice
+// k's image goes; otherwise images are packed back to back from out_base.
+gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_slice* hs, int ns, float* out_base,
+                      float* const* outs, BatchPlan* plan) {
+  int64_t nbins = 0, total_gauss = 0;
+  for (int k = 0; k < ns; ++k)
+    nbins += (int64_t)((hs[k].width + kTile - 1) / kTile) * ((hs[k].height + kTile - 1) / kTile);
+  for (int g = 0; g < ng; ++g) total_gauss += (groups[g].g->n + 63) / 64 * 64;
+  if (nbins >= (1ll << 31) || total_gauss >= (1ll << 31)) return einval("batch too large");
+  gp_status st = reserve_small(ws, ns, ng, nbins, total_gauss);
   if (st != GP_OK) return st;
-
-  // host descriptors into pinned staging (wait until the previous upload has been consumed)
+  // the previous batch's upload must have been consumed before staging is reused
   if (ws->upload_done) GP_HIP(hipEventSynchronize(ws->upload_done));
   int64_t tb = 0, off = 0;
   for (int k = 0; k < ns; ++k) {
@@ -226,38 +223,72 @@ static gp_status render_forward(Workspace* ws, const gp_gaussians* g, const gp_s
     d.dx = hs[k].dx; d.dy = hs[k].dy; d.width = hs[k].width; d.height = hs[k].height;
     d.ntx = (hs[k].width + kTile - 1) / kTile; d.nty = (hs[k].height + kTile - 1) / kTile;
     d.tile_base = (int32_t)tb; d.group = 0; d.out_off = off;
+    d.out = outs ? outs[k] : out_base + off;
+    d.pad = 0;
     tb += (int64_t)d.ntx * d.nty;
     off += (int64_t)hs[k].width * hs[k].height;
   }
-  GroupDev& G = ws->h_groups[0];
-  G.means = static_cast<const float*>(g->means);
-  G.attrs = g->attrs;
-  G.stride = g->stride;
-  G.n = (int32_t)g->n;
-  G.attr_dtype = g->attr_dtype;
-  G.k0 = 0; G.k1 = ns; G.gbase = 0; G.pad = 0;
-  GP_HIP(hipMemcpyAsync(ws->d_slices, ws->h_slices, sizeof(SliceDev) * ns, hipMemcpyHostToDevice, s));
-  GP_HIP(hipMemcpyAsync(ws->d_groups, ws->h_groups, sizeof(GroupDev), hipMemcpyHostToDevice, s));
+  int64_t gb = 0;
+  for (int g = 0; g < ng; ++g) {
+    GroupDev& G = ws->h_groups[g];
+    G.means = static_cast<const float*>(groups[g].g->means);
+    G.attrs = groups[g].g->attrs;
+    G.stride = groups[g].g->stride;
+    G.n = (int32_t)groups[g].g->n;
+    G.attr_dtype = groups[g].g->attr_dtype;
+    G.k0 = groups[g].k0; G.k1 = groups[g].k1;
+    G.gbase = (int32_t)gb;
+    // non-decreasing z and one sigma_z: kept slices form a range (binary search)
+    bool sorted = true;
+    for (int k = G.k0 + 1; k < G.k1 && sorted; ++k)
+      sorted = hs[k].z >= hs[k - 1].z && hs[k].sigma_z == hs[G.k0].sigma_z;
+    G.flags = sorted ? kGroupSortedZ : 0;
+    for (int k = G.k0; k < G.k1; ++k) ws->h_slices[k].group = g;
+    gb += (groups[g].g->n + 63) / 64 * 64;
+  }
+  ws->h_hdr->n_groups = ng;
+  ws->h_hdr->n_slices = ns;
+  ws->h_hdr->n_bins = (int32_t)nbins;
+  ws->h_hdr->total_gauss = (int32_t)total_gauss;
+  plan->ns = ns; plan->ng = ng; plan->nbins = nbins; plan->total_gauss = total_gauss; plan->npix = off;
+  plan->attr_dtype = ng > 0 ? groups[0].g->attr_dtype : GP_F32;
+  return GP_OK;
+}
+
+gp_status upload_batch(Workspace* ws, const BatchPlan& p, hipStream_t s) {
+  GP_HIP(hipMemcpyAsync(ws->d_hdr, ws->h_hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s));
+  if (p.ns > 0) GP_HIP(hipMemcpyAsync(ws->d_slices, ws->h_slices, sizeof(SliceDev) * p.ns, hipMemcpyHostToDevice, s));
+  if (p.ng > 0) GP_HIP(hipMemcpyAsync(ws->d_groups, ws->h_groups, sizeof(GroupDev) * p.ng, hipMemcpyHostToDevice, s));
   GP_HIP(hipEventRecord(ws->upload_done, s));
   ws->last_stream = s;
+  return GP_OK;
+}
 
+RenderConst make_render_const(const gp_render_opts* o, int attr_dtype, const Workspace* ws) {
   RenderConst rc{};
   rc.q_cut = o->q_cut; rc.bbox = o->bbox_sigmas; rc.scale_mod = o->scale_mod; rc.flags = o->flags;
-  rc.n_groups = 1; rc.n_slices = ns; rc.n_bins = (int32_t)nbins; rc.total_gauss = (int32_t)total_gauss;
+  rc.rec_cap = (uint32_t)ws->rec_cap; rc.inst_cap = (uint32_t)ws->inst_cap;
+  rc.attr_dtype = attr_dtype;
+  return rc;
+}
 
+// Launch sequence of a forward on the uploaded batch.  With automatic sizing
+// the counts are read back once (host synchronisation) and the buffers grown.
+gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hipStream_t s) {
   if (ws->auto_size && (ws->rec_cap == 0 || ws->inst_cap == 0)) {
     // first use: a generous guess, corrected after the first count
-    const int64_t guess_rec = std::max<int64_t>(1 << 16, g->n * (int64_t)std::min(ns, 64) / 4);
-    st = reserve_lists(ws, guess_rec, 4 * guess_rec);
+    const int64_t guess_rec = std::max<int64_t>(1 << 16, d.gauss / 4);
+    gp_status st = reserve_lists(ws, guess_rec, 4 * guess_rec);
     if (st != GP_OK) return st;
   }
   for (int attempt = 0; attempt < 3; ++attempt) {
     rc.rec_cap = (uint32_t)ws->rec_cap;
     rc.inst_cap = (uint32_t)ws->inst_cap;
+    // auto sizing re-runs an overflowed attempt, so its flag is cleared per attempt;
+    // with fixed capacities the flag persists until gp_workspace_check reports it
     GP_HIP(timed(ws, GP_STAGE_PREPROCESS, s, [&] {
-      hipError_t e = launch_fill_u32(ws->d_ctr, 0u, 2, s);
-      if (e == hipSuccess) e = launch_fill_u32(ws->d_bin_count, 0u, nbins, s);
-      if (e == hipSuccess) e = launch_preprocess(rc, *ws, s);
+      hipError_t e = launch_reset(*ws, ws->auto_size || ws->overflow_per_forward, d, s);
+      if (e == hipSuccess) e = launch_preprocess(rc, *ws, d, s);
       return e;
     }));
     if (!ws->auto_size) break;
@@ -267,30 +298,72 @@ static gp_status render_forward(Workspace* ws, const gp_gaussians* g, const gp_s
     ws->last_records = R;
     ws->last_instances = K;
     if (R <= ws->rec_cap && K <= ws->inst_cap) break;
-    st = reserve_lists(ws, std::max<int64_t>(ws->rec_cap, R + R / 4 + 1024),
-                       std::max<int64_t>(ws->inst_cap, K + K / 4 + 4096));
-    if (st != GP_OK) return st;
     if (attempt == 2) {
       set_error("workspace could not be sized");
       return GP_EOVERFLOW;
     }
+    gp_status st = reserve_lists(ws, std::max<int64_t>(ws->rec_cap, R + R / 4 + 1024),
+                                 std::max<int64_t>(ws->inst_cap, K + K / 4 + 4096));
+    if (st != GP_OK) return st;
   }
-  GP_HIP(timed(ws, GP_STAGE_SCAN, s, [&] { return launch_scan_bins(*ws, (int32_t)nbins, s); }));
+  GP_HIP(timed(ws, GP_STAGE_SCAN, s, [&] { return launch_scan_bins(*ws, s); }));
   GP_HIP(timed(ws, GP_STAGE_SCATTER, s, [&] { return launch_scatter(rc, *ws, s); }));
-  GP_HIP(timed(ws, GP_STAGE_BIN_SORT, s, [&] { return launch_bin_sort(rc, *ws, s); }));
-  GP_HIP(timed(ws, GP_STAGE_RASTER_FWD, s, [&] { return launch_raster_fwd(rc, *ws, out, s); }));
-
-  ws->have_forward = true;
-  ws->fwd_means = g->means;
-  ws->fwd_attrs = g->attrs;
-  ws->fwd_n = g->n;
-  ws->fwd_stride = g->stride;
-  ws->fwd_nslices = ns;
-  ws->fwd_nbins = (int32_t)nbins;
-  ws->fwd_slice_hash = hash_bytes(hs, sizeof(gp_slice) * (size_t)ns, hash_bytes(o, sizeof(*o)));
+  GP_HIP(timed(ws, GP_STAGE_BIN_SORT, s, [&] { return launch_bin_sort(rc, *ws, d, s); }));
+  GP_HIP(timed(ws, GP_STAGE_RASTER_FWD, s, [&] { return launch_raster_fwd(rc, *ws, d, s); }));
   ws->fwd_rc = rc;
-  (void)npix;
   return GP_OK;
+}
+
+gp_status check_gaussians_pub(const gp_gaussians* g) { return check_gaussians(g); }
+gp_status check_slice_pub(const gp_slice& sl, int k) { return check_slice(sl, k); }
+gp_status check_opts_pub(const gp_render_opts* o) { return check_opts(o); }
+
+gp_status workspace_new(Workspace** out, int64_t max_records, int64_t max_instances) {
+  *out = nullptr;
+  Workspace* ws = new (std::nothrow) Workspace();
+  if (!ws) {
+    set_error("workspace: host allocation");
+    return GP_ENOMEM;
+  }
+  hipError_t e = hipGetDevice(&ws->device);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->upload_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->d_ctr), sizeof(uint32_t) * kCtrCount);
+  if (e == hipSuccess) e = hipMemset(ws->d_ctr, 0, sizeof(uint32_t) * kCtrCount);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->d_work), sizeof(uint32_t) * kWorkCount);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->d_hdr), sizeof(BatchHdr));
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_ctr), sizeof(uint32_t) * kCtrCount, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_hdr), sizeof(BatchHdr), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    workspace_free(ws);
+    return hip_fail(e, "workspace_create");
+  }
+  ws->auto_size = max_records == 0;
+  if (!ws->auto_size) {
+    gp_status st = reserve_lists(ws, max_records, max_instances);
+    if (st != GP_OK) {
+      workspace_free(ws);
+      return st;
+    }
+  }
+  *out = ws;
+  return GP_OK;
+}
+
+void workspace_free(Workspace* ws) {
+  if (!ws) return;
+  (void)wait_ws(ws);
+  void* dev[] = {ws->d_slices, ws->d_groups, ws->d_hdr, ws->d_work, ws->d_ctr, ws->d_bin_count, ws->d_bin_start,
+                 ws->d_rec_pay, ws->d_rec_meta, ws->d_g_rbase, ws->d_g_nrec, ws->d_inst_rank, ws->d_sort_key,
+                 ws->d_list, ws->d_moments};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  void* host[] = {ws->h_slices, ws->h_groups, ws->h_hdr, ws->h_ctr};
+  for (void* p : host)
+    if (p) (void)hipHostFree(p);
+  (void)resolve_timings(ws);
+  for (hipEvent_t e : ws->event_pool) (void)hipEventDestroy(e);
+  if (ws->upload_done) (void)hipEventDestroy(ws->upload_done);
+  delete ws;
 }
 
 }  // namespace gp
@@ -318,47 +391,15 @@ gp_status gp_workspace_create(gp_workspace** out, int64_t max_records, int64_t m
   if (max_records < 0 || max_instances < 0) return einval("workspace_create: negative capacity");
   if ((max_records == 0) != (max_instances == 0))
     return einval("workspace_create: give both capacities or neither");
-  Workspace* ws = new (std::nothrow) Workspace();
-  if (!ws) {
-    set_error("workspace_create: host allocation");
-    return GP_ENOMEM;
-  }
-  hipError_t e = hipGetDevice(&ws->device);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->upload_done, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->d_ctr), sizeof(uint32_t) * kCtrCount);
-  if (e == hipSuccess) e = hipMemset(ws->d_ctr, 0, sizeof(uint32_t) * kCtrCount);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_ctr), sizeof(uint32_t) * kCtrCount, hipHostMallocDefault);
-  if (e != hipSuccess) {
-    gp_workspace_destroy(reinterpret_cast<gp_workspace*>(ws));
-    return hip_fail(e, "workspace_create");
-  }
-  ws->auto_size = max_records == 0;
-  if (!ws->auto_size) {
-    gp_status st = reserve_lists(ws, max_records, max_instances);
-    if (st != GP_OK) {
-      gp_workspace_destroy(reinterpret_cast<gp_workspace*>(ws));
-      return st;
-    }
-  }
+  Workspace* ws = nullptr;
+  gp_status st = workspace_new(&ws, max_records, max_instances);
+  if (st != GP_OK) return st;
   *out = reinterpret_cast<gp_workspace*>(ws);
   return GP_OK;
 }
 
 gp_status gp_workspace_destroy(gp_workspace* w) {
-  if (!w) return GP_OK;
-  Workspace* ws = reinterpret_cast<Workspace*>(w);
-  (void)wait_ws(ws);
-  (void)hipFree(ws->d_slices); (void)hipFree(ws->d_groups); hipFree(ws->d_ctr); hipFree(ws->d_bin_count);
-  hipFree(ws->d_bin_start); hipFree(ws->d_rec_pay); hipFree(ws->d_rec_meta); hipFree(ws->d_g_rbase);
-  hipFree(ws->d_g_nrec); hipFree(ws->d_inst_rank); hipFree(ws->d_inst_rid); hipFree(ws->d_sort_key);
-  hipFree(ws->d_pay); hipFree(ws->d_inst_pos); hipFree(ws->d_moments);
-  if (ws->h_slices) hipHostFree(ws->h_slices);
-  if (ws->h_groups) hipHostFree(ws->h_groups);
-  if (ws->h_ctr) hipHostFree(ws->h_ctr);
-  if (ws->upload_done) hipEventDestroy(ws->upload_done);
-  (void)resolve_timings(ws);
-  for (hipEvent_t e : ws->event_pool) hipEventDestroy(e);
-  delete ws;
+  workspace_free(reinterpret_cast<Workspace*>(w));
   return GP_OK;
 }
 
@@ -392,7 +433,23 @@ gp_status gp_render_slices(gp_workspace* w, const gp_gaussians* g, const gp_slic
   GP_HIP(hipSetDevice(ws->device));
   ws->have_forward = false;
   if (ns == 0) return GP_OK;
-  return render_forward(ws, g, hs, ns, o, out, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GroupIn grp{g, 0, ns};
+  BatchPlan plan{};
+  if ((st = stage_batch(ws, &grp, 1, hs, ns, out, nullptr, &plan)) != GP_OK) return st;
+  if ((st = upload_batch(ws, plan, s)) != GP_OK) return st;
+  const LaunchDims d{plan.total_gauss, plan.nbins};
+  if ((st = enqueue_forward(ws, make_render_const(o, g->attr_dtype, ws), d, s)) != GP_OK) return st;
+  ws->have_forward = true;
+  ws->fwd_means = g->means;
+  ws->fwd_attrs = g->attrs;
+  ws->fwd_n = g->n;
+  ws->fwd_stride = g->stride;
+  ws->fwd_nslices = ns;
+  ws->fwd_nbins = (int32_t)plan.nbins;
+  ws->fwd_gauss = plan.total_gauss;
+  ws->fwd_slice_hash = hash_bytes(hs, sizeof(gp_slice) * (size_t)ns, hash_bytes(o, sizeof(*o)));
+  return GP_OK;
 }
 
 gp_status gp_render_backward(gp_workspace* w, const gp_gaussians* g, const gp_slice* hs, int32_t ns,
@@ -414,9 +471,10 @@ gp_status gp_render_backward(gp_workspace* w, const gp_gaussians* g, const gp_sl
   if (ns == 0 || g->n == 0) return GP_OK;
   GP_HIP(hipSetDevice(ws->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  GP_HIP(timed(ws, GP_STAGE_RASTER_BWD, s, [&] { return launch_raster_bwd(ws->fwd_rc, *ws, grad_out, s); }));
+  const LaunchDims d{ws->fwd_gauss, ws->fwd_nbins};
+  GP_HIP(timed(ws, GP_STAGE_RASTER_BWD, s, [&] { return launch_raster_bwd(ws->fwd_rc, *ws, grad_out, d, s); }));
   GP_HIP(timed(ws, GP_STAGE_PREPROCESS_BWD, s,
-               [&] { return launch_preprocess_bwd(ws->fwd_rc, *ws, grad, grad_stride, s); }));
+               [&] { return launch_preprocess_bwd(ws->fwd_rc, *ws, grad, grad_stride, d, s); }));
   ws->last_stream = s;
   return GP_OK;
 }
@@ -481,12 +539,17 @@ gp_status gp_debug_export_bins(gp_workspace* w, uint64_t* h_keys, int64_t keys_c
   *n_keys = K;
   if (keys_cap < K || ranges_cap < 2 * nb || (K > 0 && !h_keys) || (nb > 0 && !h_ranges))
     return einval("export_bins: output too small");
-  std::vector<RecPay> pay((size_t)K);
-  if (K > 0) GP_HIP(hipMemcpy(pay.data(), ws->d_pay, sizeof(RecPay) * K, hipMemcpyDeviceToHost));
+  std::vector<uint32_t> list((size_t)K);
+  std::vector<RecPay> pay;
+  if (K > 0) GP_HIP(hipMemcpy(list.data(), ws->d_list, sizeof(uint32_t) * K, hipMemcpyDeviceToHost));
+  GP_HIP(hipMemcpy(ws->h_ctr, ws->d_ctr, sizeof(uint32_t) * kCtrCount, hipMemcpyDeviceToHost));
+  const int64_t R = std::min<int64_t>(ws->h_ctr[kCtrRecords], ws->rec_cap);
+  pay.resize((size_t)std::max<int64_t>(R, 1));
+  if (R > 0) GP_HIP(hipMemcpy(pay.data(), ws->d_rec_pay, sizeof(RecPay) * R, hipMemcpyDeviceToHost));
   for (int64_t b = 0; b < nb; ++b) {
     h_ranges[2 * b] = start[b];
     h_ranges[2 * b + 1] = start[b + 1];
-    for (uint32_t i = start[b]; i < start[b + 1]; ++i) h_keys[i] = ((uint64_t)b << 32) | pay[i].gid;
+    for (uint32_t i = start[b]; i < start[b + 1]; ++i) h_keys[i] = ((uint64_t)b << 32) | pay[list[i]].gid;
   }
   return GP_OK;
 }

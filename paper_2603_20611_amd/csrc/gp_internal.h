@@ -22,8 +22,20 @@ struct SliceDev {
   int32_t width, height, ntx, nty;
   int32_t tile_base;   // index of the slice's first bin
   int32_t group;       // which Gaussian set the slice samples
-  int64_t out_off;     // offset of the slice's image in the packed output
+  int64_t out_off;     // offset of the slice's image in a packed batch
+  float* out;          // where the forward writes the slice's image
+  int64_t pad;
 };
+
+// Sizes of one batch, read by the kernels from device memory so that a launch
+// sequence can be captured once and replayed for batches of any size up to the
+// workspace capacity.
+struct BatchHdr {
+  int32_t n_groups, n_slices, n_bins, total_gauss;
+};
+
+// Work counters handed out by atomics (reset at the start of every forward).
+enum { kWorkRasterFwd = 0, kWorkRasterBwd = 1, kWorkCount = 4 };
 
 // One Gaussian set and the contiguous range of slices that sample it.
 struct GroupDev {
@@ -34,43 +46,63 @@ struct GroupDev {
   int32_t attr_dtype;
   int32_t k0, k1;      // slices [k0, k1) of the batch
   int32_t gbase;       // first flattened Gaussian index (multiple of 64)
-  int32_t pad;
+  int32_t flags;       // kGroupSortedZ
 };
 
-// Rendering constants of one call.
+// Rendering constants of one call (sizes that vary per batch live in BatchHdr).
 struct RenderConst {
   float q_cut, bbox, scale_mod;
   uint32_t flags;
-  int32_t n_groups, n_slices, n_bins;
-  int32_t total_gauss;   // flattened Gaussian count (groups padded to 64)
   uint32_t rec_cap, inst_cap;
+  int32_t attr_dtype;
+  int32_t pad;
+};
+
+// Grid sizes of a launch sequence: exact for one known batch, or the
+// workspace capacity when the sequence is captured for replay.
+struct LaunchDims {
+  int64_t gauss;   // flattened Gaussians to cover (multiple of 64)
+  int64_t bins;    // bins to cover
 };
 
 // Counters written by the preprocess.
 enum { kCtrRecords = 0, kCtrInstances = 1, kCtrOverflow = 2, kCtrCount = 4 };
 
-// Record payload in pixel space (what the rasteriser streams), 32 bytes:
-//   x = mean x in pixel-index units, y = mean y, a/b/c = exponent coefficients
-//   of exp2(a dx^2 + b dx dy + c dy^2), w = alpha~, gid = Gaussian index,
-//   slice = slice index within the batch.
+// Record payload in pixel space, 32 bytes, gathered by the rasterisers:
+//   x, y = mean in pixel-index units; a, b, c = exponent coefficients of
+//   exp2(a dx^2 + b dx dy + c dy^2); w = alpha~; g = 2^(2a) (the per-pixel
+//   ratio of the row recurrence); gid = Gaussian index within its set.
 struct alignas(16) RecPay {
   float x, y, a, b;
-  float c, w;
-  uint32_t gid, slice;
+  float c, w, g;
+  uint32_t gid;
 };
 
-// Record bookkeeping, 16 bytes.
+// Record bookkeeping, 16 bytes.  Records are the visible (Gaussian, slice)
+// pairs; the instance slots [ibase, ibase + ntiles) enumerate the footprint
+// row-major.
 struct alignas(16) RecMeta {
   uint32_t ibase;   // first instance slot
   uint32_t rx;      // tx0 | tx1 << 16
   uint32_t ry;      // ty0 | ty1 << 16
-  uint32_t ntiles;
+  uint32_t slice;   // slice index within the batch
 };
+
+constexpr uint32_t kInvalidSlice = 0xFFFFFFFFu;   // RecMeta.slice of an unused record slot
+
+__host__ __device__ inline uint32_t rec_ntiles(const RecMeta& m) {
+  return ((m.rx >> 16) - (m.rx & 0xFFFFu) + 1u) * ((m.ry >> 16) - (m.ry & 0xFFFFu) + 1u);
+}
+
+// GroupDev.flags: the group's slices have non-decreasing z and one sigma_z, so
+// each Gaussian's kept slices form a range found by binary search.
+constexpr int32_t kGroupSortedZ = 1;
 
 // The workspace: library-owned device buffers, sized by capacity.
 struct Workspace {
   int device = 0;
   bool auto_size = true;
+  bool overflow_per_forward = false;  // clear the overflow flag at every forward
   bool overflowed = false;
   void* last_stream = nullptr;
 
@@ -80,6 +112,8 @@ struct Workspace {
   // device buffers
   SliceDev* d_slices = nullptr;
   GroupDev* d_groups = nullptr;
+  BatchHdr* d_hdr = nullptr;
+  uint32_t* d_work = nullptr;       // kWorkCount work counters
   uint32_t* d_ctr = nullptr;        // kCtrCount counters
   uint32_t* d_bin_count = nullptr;  // [bin_cap]
   uint32_t* d_bin_start = nullptr;  // [bin_cap + 1]
@@ -87,16 +121,15 @@ struct Workspace {
   RecMeta* d_rec_meta = nullptr;    // [rec_cap]
   uint32_t* d_g_rbase = nullptr;    // [gauss_cap]
   uint32_t* d_g_nrec = nullptr;     // [gauss_cap]
-  uint32_t* d_inst_rank = nullptr;  // [inst_cap]
-  uint32_t* d_inst_rid = nullptr;   // [inst_cap]
-  uint64_t* d_sort_key = nullptr;   // [inst_cap]
-  RecPay* d_pay = nullptr;          // [inst_cap] payload in list order
-  uint32_t* d_inst_pos = nullptr;   // [inst_cap] instance slot -> list position
-  float4* d_moments = nullptr;      // [2 * inst_cap] backward moments per list entry
+  uint32_t* d_inst_rank = nullptr;  // [inst_cap] rank of an instance slot in its bin
+  uint64_t* d_sort_key = nullptr;   // [inst_cap] (Gaussian index << 32 | record) by bin
+  uint32_t* d_list = nullptr;       // [inst_cap] record ids in list order
+  float4* d_moments = nullptr;      // [2 * inst_cap] backward moments per instance slot
 
   // pinned staging for uploads / readbacks
   SliceDev* h_slices = nullptr;
   GroupDev* h_groups = nullptr;
+  BatchHdr* h_hdr = nullptr;
   uint32_t* h_ctr = nullptr;
   hipEvent_t upload_done = nullptr;
 
@@ -106,6 +139,7 @@ struct Workspace {
   const void* fwd_attrs = nullptr;
   int64_t fwd_n = 0, fwd_stride = 0;
   int32_t fwd_nslices = 0, fwd_nbins = 0;
+  int64_t fwd_gauss = 0;
   uint64_t fwd_slice_hash = 0;
   RenderConst fwd_rc{};
   int64_t last_records = 0, last_instances = 0;
@@ -128,21 +162,46 @@ gp_status hip_fail(hipError_t e, const char* what);
     if (_e != hipSuccess) return gp::hip_fail(_e, #call); \
   } while (0)
 
+// ---- batches (gp_api.hip) ----
+struct GroupIn {
+  const gp_gaussians* g;
+  int32_t k0, k1;   // its slices [k0, k1) of the batch
+};
+struct BatchPlan {
+  int32_t ns, ng;
+  int64_t nbins, total_gauss, npix;
+  int32_t attr_dtype;
+};
+hipError_t wait_ws(Workspace* ws);
+gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups, int64_t n_bins, int64_t n_gauss);
+gp_status reserve_lists(Workspace* ws, int64_t rec_cap, int64_t inst_cap);
+gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_slice* hs, int ns, float* out_base,
+                      float* const* outs, BatchPlan* plan);
+gp_status upload_batch(Workspace* ws, const BatchPlan& p, hipStream_t s);
+RenderConst make_render_const(const gp_render_opts* o, int attr_dtype, const Workspace* ws);
+gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hipStream_t s);
+gp_status check_gaussians_pub(const gp_gaussians* g);
+gp_status check_slice_pub(const gp_slice& sl, int k);
+gp_status check_opts_pub(const gp_render_opts* o);
+gp_status workspace_new(Workspace** out, int64_t max_records, int64_t max_instances);
+void workspace_free(Workspace* ws);
+
 // ---- launch wrappers (one per kernel file) ----
 // k_preprocess.hip
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
-hipError_t launch_preprocess(const RenderConst& rc, const Workspace& ws, hipStream_t s);
+hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDims& d, hipStream_t s);
+hipError_t launch_preprocess(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s);
 // k_bins.hip
-hipError_t launch_scan_bins(const Workspace& ws, int32_t n_bins, hipStream_t s);
+hipError_t launch_scan_bins(const Workspace& ws, hipStream_t s);
 hipError_t launch_scatter(const RenderConst& rc, const Workspace& ws, hipStream_t s);
-hipError_t launch_bin_sort(const RenderConst& rc, const Workspace& ws, hipStream_t s);
+hipError_t launch_bin_sort(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s);
 // k_raster.hip
-hipError_t launch_raster_fwd(const RenderConst& rc, const Workspace& ws, float* out, hipStream_t s);
+hipError_t launch_raster_fwd(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s);
 hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const float* grad_out,
-                             hipStream_t s);
+                             const LaunchDims& d, hipStream_t s);
 // k_backward.hip
 hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, float* grad,
-                                 int64_t grad_stride, hipStream_t s);
+                                 int64_t grad_stride, const LaunchDims& d, hipStream_t s);
 // k_optim.hip
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, int64_t stride,
                        const gp_adam_cfg& c, hipStream_t s);

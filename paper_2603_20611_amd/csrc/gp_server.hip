@@ -1,0 +1,568 @@
+// Serving of slices from resident volumes (continuous batching).
+//
+// A scheduler thread owns the launch slots.  Whenever a slot is free and
+// requests are queued it takes a batch from the head of the queue (bounded by
+// the slot's capacity for requests, tiles, Gaussians and estimated list
+// entries), stages one descriptor table for the whole batch (one group per
+// volume, one slice per request, each slice writing into its caller's
+// buffer), uploads it on the slot's stream and replays the slot's captured
+// hipGraph of the forward launch sequence (reset, preprocess, bin scan,
+// scatter, per-tile sort, rasterise).  A host function queued behind the batch
+// wakes the scheduler when it finishes, so new requests are admitted while
+// other batches are still on the GPU.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "gp_internal.h"
+
+namespace gp {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(Clock::now().time_since_epoch()).count();
+}
+
+// float32 [11][src_stride] -> float32 means [3][dst_stride] + attrs [8][dst_stride] of type DT
+template <int DT>
+__global__ void k_pack_volume(const float* __restrict__ means, const float* __restrict__ attrs, int64_t src_stride,
+                              int64_t n, float* __restrict__ out_means, void* __restrict__ out_attrs,
+                              int64_t dst_stride) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int r = 0; r < 3; ++r) out_means[r * dst_stride + i] = means[r * src_stride + i];
+  for (int r = 0; r < 8; ++r) {
+    const float v = attrs[r * src_stride + i];
+    if constexpr (DT == GP_BF16) {
+      static_cast<__hip_bfloat16*>(out_attrs)[r * dst_stride + i] = __float2bfloat16(v);
+    } else if constexpr (DT == GP_F16) {
+      static_cast<__half*>(out_attrs)[r * dst_stride + i] = __float2half(v);
+    } else {
+      static_cast<float*>(out_attrs)[r * dst_stride + i] = v;
+    }
+  }
+}
+
+size_t dtype_bytes(int dt) { return dt == GP_F32 ? 4 : 2; }
+
+struct Volume {
+  float* means = nullptr;
+  void* attrs = nullptr;
+  int64_t n = 0, stride = 0;
+  size_t bytes = 0;
+  // admission estimate: mu_z histogram (unit bins from z_lo) and lateral size
+  float z_lo = 0.f;
+  std::vector<int64_t> zcum;   // zcum[i] = Gaussians with mu_z < z_lo + i
+  float s_axial_max = 0.f;     // largest scale (bounds sqrt(Sigma_zz))
+  float s_lateral_mean = 0.f;  // mean of each Gaussian's largest scale
+};
+
+struct Request {
+  uint64_t ticket;
+  gp_request r;
+  float* out;
+  double t_submit;
+  bool solo;       // render alone (after an overflow)
+};
+
+struct TicketState {
+  bool done = false;
+  gp_serve_result res{};
+};
+
+struct Server;
+
+struct Slot {
+  Server* sv = nullptr;
+  Workspace* ws = nullptr;
+  hipStream_t stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<Request> reqs;
+  bool busy = false, finished = false;
+  int64_t batch_id = 0;
+  double t_done = 0.0;
+};
+
+struct Server {
+  gp_server_cfg cfg{};
+  std::vector<Volume> vols;
+  int64_t resident = 0;
+  std::mutex mu;
+  std::condition_variable cv;       // scheduler wake-up
+  std::condition_variable cv_done;  // pollers
+  std::deque<Request> queue;
+  std::unordered_map<uint64_t, TicketState> tickets;
+  std::vector<Slot*> slots;
+  std::thread sched;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  int64_t next_batch = 1;
+  double tiles_factor = 1.0;        // grows after an overflow
+  gp_server_stats stats{};
+  RenderConst rc{};
+  LaunchDims cap_dims{};
+};
+
+int64_t tiles_of(const gp_request& r) {
+  return (int64_t)((r.width + kTile - 1) / kTile) * ((r.height + kTile - 1) / kTile);
+}
+
+// Upper estimate of a request's tile-list entries from the volume's mu_z
+// histogram (Gaussians inside the widest axial window) and its mean footprint.
+double est_instances(const Server* sv, const gp_request& r) {
+  const Volume& v = sv->vols[r.volume_id];
+  const double D = (double)r.sigma_z * r.sigma_z + (double)v.s_axial_max * v.s_axial_max;
+  const double w = std::sqrt((double)sv->cfg.opts.q_cut * D);
+  const int nb = (int)v.zcum.size() - 1;
+  auto cum = [&](double z) {
+    const double u = z - v.z_lo;
+    if (u <= 0) return (int64_t)0;
+    if (u >= nb) return v.zcum[nb];
+    return v.zcum[(int)u];
+  };
+  const double kept = (double)(cum(r.z + w + 1.0) - cum(r.z - w));
+  const double px = 2.0 * sv->cfg.opts.bbox_sigmas * v.s_lateral_mean / std::min(r.dx, r.dy);
+  const double per = (px / kTile + 1.0) * (px / kTile + 1.0);
+  return kept * per * sv->tiles_factor;
+}
+
+void on_batch_done(void* p) {
+  Slot* sl = static_cast<Slot*>(p);
+  Server* sv = sl->sv;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sl->finished = true;
+    sl->t_done = now_ms();
+  }
+  sv->cv.notify_all();
+}
+
+gp_status launch_batch(Server* sv, Slot* sl) {
+  Workspace* ws = sl->ws;
+  auto& reqs = sl->reqs;
+  std::stable_sort(reqs.begin(), reqs.end(),
+                   [](const Request& a, const Request& b) { return a.r.volume_id < b.r.volume_id; });
+  std::vector<gp_gaussians> sets;
+  std::vector<GroupIn> groups;
+  std::vector<gp_slice> hs(reqs.size());
+  std::vector<float*> outs(reqs.size());
+  sets.reserve(reqs.size());
+  for (size_t k = 0; k < reqs.size(); ++k) {
+    const gp_request& r = reqs[k].r;
+    hs[k] = gp_slice{r.z, r.sigma_z, r.x0, r.y0, r.dx, r.dy, r.width, r.height};
+    outs[k] = reqs[k].out;
+    if (groups.empty() || sets.back().means != sv->vols[r.volume_id].means) {
+      const Volume& v = sv->vols[r.volume_id];
+      sets.push_back(gp_gaussians{v.means, v.attrs, v.n, v.stride, GP_F32, sv->cfg.attr_dtype});
+      groups.push_back(GroupIn{nullptr, (int32_t)k, (int32_t)k + 1});
+    } else {
+      groups.back().k1 = (int32_t)k + 1;
+    }
+  }
+  for (size_t g = 0; g < groups.size(); ++g) groups[g].g = &sets[g];
+  BatchPlan plan{};
+  gp_status st = stage_batch(ws, groups.data(), (int)groups.size(), hs.data(), (int)hs.size(), nullptr,
+                             outs.data(), &plan);
+  if (st != GP_OK) return st;
+  if ((st = upload_batch(ws, plan, sl->stream)) != GP_OK) return st;
+  if (sv->cfg.use_graphs) {
+    if (!sl->exec) {
+      hipGraph_t graph = nullptr;
+      GP_HIP(hipStreamBeginCapture(sl->stream, hipStreamCaptureModeThreadLocal));
+      st = enqueue_forward(ws, sv->rc, sv->cap_dims, sl->stream);
+      hipError_t e = hipStreamEndCapture(sl->stream, &graph);
+      if (st != GP_OK) return st;
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&sl->exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    }
+    GP_HIP(hipGraphLaunch(sl->exec, sl->stream));
+  } else {
+    if ((st = enqueue_forward(ws, sv->rc, LaunchDims{plan.total_gauss, plan.nbins}, sl->stream)) != GP_OK)
+      return st;
+  }
+  GP_HIP(hipMemcpyAsync(ws->h_ctr, ws->d_ctr, sizeof(uint32_t) * kCtrCount, hipMemcpyDeviceToHost, sl->stream));
+  GP_HIP(hipLaunchHostFunc(sl->stream, on_batch_done, sl));
+  return GP_OK;
+}
+
+// Called with the lock held: completes a finished slot's requests.
+void retire(Server* sv, Slot* sl) {
+  const bool overflow = sl->ws->h_ctr[kCtrOverflow] != 0;
+  if (overflow && sl->reqs.size() > 1) {
+    // re-run each request alone, at the head of the queue, in the original order
+    sv->tiles_factor *= 1.5;
+    for (auto it = sl->reqs.rbegin(); it != sl->reqs.rend(); ++it) {
+      Request r = *it;
+      r.solo = true;
+      sv->queue.push_front(r);
+    }
+    sv->stats.retries += (int64_t)sl->reqs.size();
+  } else {
+    for (const Request& r : sl->reqs) {
+      TicketState& t = sv->tickets[r.ticket];
+      t.done = true;
+      t.res.status = overflow ? GP_EOVERFLOW : GP_OK;
+      t.res.batch_size = (int32_t)sl->reqs.size();
+      t.res.batch_id = sl->batch_id;
+      t.res.latency_ms = sl->t_done - r.t_submit;
+      sv->stats.completed += 1;
+    }
+  }
+  sl->reqs.clear();
+  sl->busy = false;
+  sl->finished = false;
+}
+
+// Takes a batch from the head of the queue (lock held).  Returns false if empty.
+bool take_batch(Server* sv, Slot* sl) {
+  if (sv->queue.empty()) return false;
+  int64_t bins = 0, gauss = 0;
+  double inst = 0.0;
+  std::vector<int32_t> vols_in;
+  while (!sv->queue.empty() && (int)sl->reqs.size() < sv->cfg.max_batch) {
+    const Request& r = sv->queue.front();
+    if (r.solo && !sl->reqs.empty()) break;
+    const bool new_vol = std::find(vols_in.begin(), vols_in.end(), r.r.volume_id) == vols_in.end();
+    const int64_t add_g = new_vol ? (sv->vols[r.r.volume_id].n + 63) / 64 * 64 : 0;
+    const double add_i = est_instances(sv, r.r);
+    if (!sl->reqs.empty() && (bins + tiles_of(r.r) > sv->cfg.max_bins || gauss + add_g > sv->cfg.max_gaussians ||
+                              inst + add_i > (double)sv->cfg.max_instances))
+      break;
+    bins += tiles_of(r.r);
+    gauss += add_g;
+    inst += add_i;
+    if (new_vol) vols_in.push_back(r.r.volume_id);
+    sl->reqs.push_back(r);
+    const bool solo = r.solo;
+    sv->queue.pop_front();
+    if (solo) break;
+  }
+  return true;
+}
+
+void scheduler(Server* sv) {
+  (void)hipSetDevice(sv->cfg.device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    bool progressed = false;
+    for (Slot* sl : sv->slots) {
+      if (sl->busy && sl->finished) {
+        retire(sv, sl);
+        progressed = true;
+      }
+    }
+    if (progressed) sv->cv_done.notify_all();
+    if (sv->stop) {
+      bool any_busy = false;
+      for (Slot* sl : sv->slots) any_busy = any_busy || sl->busy;
+      if (!any_busy) break;
+      sv->cv.wait(lk);
+      continue;
+    }
+    Slot* free_slot = nullptr;
+    for (Slot* sl : sv->slots)
+      if (!sl->busy) { free_slot = sl; break; }
+    if (free_slot && take_batch(sv, free_slot)) {
+      free_slot->busy = true;
+      free_slot->batch_id = sv->next_batch++;
+      sv->stats.batches += 1;
+      lk.unlock();
+      const gp_status st = launch_batch(sv, free_slot);
+      lk.lock();
+      if (st != GP_OK) {
+        for (const Request& r : free_slot->reqs) {
+          TicketState& t = sv->tickets[r.ticket];
+          t.done = true;
+          t.res.status = st;
+          t.res.batch_id = free_slot->batch_id;
+          sv->stats.completed += 1;
+        }
+        free_slot->reqs.clear();
+        free_slot->busy = false;
+        sv->cv_done.notify_all();
+      }
+      continue;
+    }
+    sv->cv.wait(lk);
+  }
+  // cancel what is still queued
+  for (const Request& r : sv->queue) {
+    TicketState& t = sv->tickets[r.ticket];
+    t.done = true;
+    t.res.status = GP_ECANCELED;
+  }
+  sv->queue.clear();
+  sv->cv_done.notify_all();
+}
+
+void free_server(Server* sv) {
+  for (Slot* sl : sv->slots) {
+    if (sl->stream) (void)hipStreamSynchronize(sl->stream);
+    if (sl->exec) (void)hipGraphExecDestroy(sl->exec);
+    if (sl->ws) workspace_free(sl->ws);
+    if (sl->stream) (void)hipStreamDestroy(sl->stream);
+    delete sl;
+  }
+  for (Volume& v : sv->vols) {
+    if (v.means) (void)hipFree(v.means);
+    if (v.attrs) (void)hipFree(v.attrs);
+  }
+  delete sv;
+}
+
+}  // namespace
+}  // namespace gp
+
+using namespace gp;
+
+extern "C" {
+
+gp_status gp_server_default_cfg(gp_server_cfg* c) {
+  if (!c) {
+    set_error("server_default_cfg: NULL");
+    return GP_EINVAL;
+  }
+  *c = gp_server_cfg{};
+  c->hbm_budget_bytes = 16ll << 30;
+  c->max_gaussians = 64ll << 20;
+  c->max_records = 16ll << 20;
+  c->max_instances = 64ll << 20;
+  c->max_bins = 64 * 4096;
+  c->max_batch = 64;
+  c->slots = 3;
+  c->attr_dtype = GP_BF16;
+  c->use_graphs = 1;
+  c->device = 0;
+  gp_default_opts(&c->opts);
+  return GP_OK;
+}
+
+gp_status gp_server_create(gp_server** out, const gp_server_cfg* cfg) {
+  if (!out || !cfg) {
+    set_error("server_create: NULL");
+    return GP_EINVAL;
+  }
+  *out = nullptr;
+  gp_status st = check_opts_pub(&cfg->opts);
+  if (st != GP_OK) return st;
+  if (cfg->slots < 1 || cfg->slots > 4 || cfg->max_batch < 1 || cfg->max_bins < 1 || cfg->max_gaussians < 64 ||
+      cfg->max_records < 1 || cfg->max_instances < 1 || cfg->hbm_budget_bytes < 0 ||
+      (cfg->attr_dtype != GP_F32 && cfg->attr_dtype != GP_BF16 && cfg->attr_dtype != GP_F16)) {
+    set_error("server_create: bad configuration");
+    return GP_EINVAL;
+  }
+  GP_HIP(hipSetDevice(cfg->device));
+  Server* sv = new (std::nothrow) Server();
+  if (!sv) {
+    set_error("server_create: host allocation");
+    return GP_ENOMEM;
+  }
+  sv->cfg = *cfg;
+  sv->cap_dims = LaunchDims{(cfg->max_gaussians + 63) / 64 * 64 + 64ll * cfg->max_batch, cfg->max_bins};
+  for (int i = 0; i < cfg->slots; ++i) {
+    Slot* sl = new (std::nothrow) Slot();
+    if (!sl) {
+      free_server(sv);
+      set_error("server_create: host allocation");
+      return GP_ENOMEM;
+    }
+    sl->sv = sv;
+    sv->slots.push_back(sl);
+    st = workspace_new(&sl->ws, cfg->max_records, cfg->max_instances);
+    if (st == GP_OK) sl->ws->overflow_per_forward = true;
+    // descriptor buffers sized for the largest batch so captured graphs stay valid
+    if (st == GP_OK) st = reserve_small(sl->ws, cfg->max_batch, cfg->max_batch, cfg->max_bins, sv->cap_dims.gauss);
+    hipError_t e = st == GP_OK ? hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) : hipSuccess;
+    if (st != GP_OK || e != hipSuccess) {
+      free_server(sv);
+      return st != GP_OK ? st : hip_fail(e, "hipStreamCreate");
+    }
+  }
+  sv->rc = make_render_const(&cfg->opts, cfg->attr_dtype, sv->slots[0]->ws);
+  sv->sched = std::thread(scheduler, sv);
+  *out = reinterpret_cast<gp_server*>(sv);
+  return GP_OK;
+}
+
+gp_status gp_server_add_volume(gp_server* s, const gp_gaussians* g, int32_t* volume_id) {
+  if (!s || !volume_id) {
+    set_error("add_volume: NULL");
+    return GP_EINVAL;
+  }
+  Server* sv = reinterpret_cast<Server*>(s);
+  gp_status st = check_gaussians_pub(g);
+  if (st != GP_OK) return st;
+  if (g->attr_dtype != GP_F32 || g->n < 1) {
+    set_error("add_volume: give float32 attributes and n >= 1");
+    return GP_EINVAL;
+  }
+  if ((g->n + 63) / 64 * 64 > sv->cfg.max_gaussians) {
+    set_error("add_volume: volume larger than max_gaussians");
+    return GP_EINVAL;
+  }
+  Volume v;
+  v.n = g->n;
+  v.stride = (g->n + 63) / 64 * 64;
+  v.bytes = (size_t)v.stride * (3 * 4 + 8 * dtype_bytes(sv->cfg.attr_dtype));
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->resident + (int64_t)v.bytes > sv->cfg.hbm_budget_bytes) {
+      set_error("add_volume: HBM budget exceeded");
+      return GP_ENOMEM;
+    }
+    sv->resident += (int64_t)v.bytes;   // reserved
+  }
+  auto release = [&](gp_status code) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->resident -= (int64_t)v.bytes;
+    if (v.means) (void)hipFree(v.means);
+    if (v.attrs) (void)hipFree(v.attrs);
+    return code;
+  };
+  GP_HIP(hipSetDevice(sv->cfg.device));
+  if (hipMalloc(reinterpret_cast<void**>(&v.means), sizeof(float) * 3 * v.stride) != hipSuccess ||
+      hipMalloc(&v.attrs, dtype_bytes(sv->cfg.attr_dtype) * 8 * v.stride) != hipSuccess) {
+    set_error("add_volume: out of device memory");
+    return release(GP_ENOMEM);
+  }
+  const unsigned blocks = (unsigned)((g->n + 255) / 256);
+  const float* m = static_cast<const float*>(g->means);
+  const float* a = static_cast<const float*>(g->attrs);
+  switch (sv->cfg.attr_dtype) {
+    case GP_BF16: k_pack_volume<GP_BF16><<<blocks, 256>>>(m, a, g->stride, g->n, v.means, v.attrs, v.stride); break;
+    case GP_F16: k_pack_volume<GP_F16><<<blocks, 256>>>(m, a, g->stride, g->n, v.means, v.attrs, v.stride); break;
+    default: k_pack_volume<GP_F32><<<blocks, 256>>>(m, a, g->stride, g->n, v.means, v.attrs, v.stride); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  // admission statistics from the float32 source
+  std::vector<float> z((size_t)g->n), l((size_t)(3 * g->n));
+  if (e == hipSuccess) e = hipMemcpy(z.data(), m + 2 * g->stride, sizeof(float) * g->n, hipMemcpyDeviceToHost);
+  for (int r = 0; r < 3 && e == hipSuccess; ++r)
+    e = hipMemcpy(l.data() + r * g->n, a + r * g->stride, sizeof(float) * g->n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return release(hip_fail(e, "add_volume"));
+  float zl = INFINITY, zh = -INFINITY, smax = 0.f;
+  double ssum = 0.0;
+  for (int64_t i = 0; i < g->n; ++i) {
+    if (std::isfinite(z[i])) { zl = std::min(zl, z[i]); zh = std::max(zh, z[i]); }
+    float li = std::max(l[i], std::max(l[g->n + i], l[2 * g->n + i]));
+    li = std::min(li, 80.f);
+    const float si = std::exp(li) * sv->cfg.opts.scale_mod;
+    if (std::isfinite(si)) { smax = std::max(smax, si); ssum += si; }
+  }
+  if (!(zl <= zh)) zl = zh = 0.f;
+  const int nb = (int)std::min<double>(1 << 20, std::floor(zh - zl) + 2);
+  v.z_lo = std::floor(zl);
+  v.zcum.assign((size_t)nb + 1, 0);
+  for (int64_t i = 0; i < g->n; ++i) {
+    if (!std::isfinite(z[i])) continue;
+    const int b = std::min(nb - 1, std::max(0, (int)(z[i] - v.z_lo)));
+    v.zcum[(size_t)b + 1] += 1;
+  }
+  for (int i = 0; i < nb; ++i) v.zcum[(size_t)i + 1] += v.zcum[(size_t)i];
+  v.s_axial_max = smax;
+  v.s_lateral_mean = (float)(ssum / (double)g->n);
+  std::lock_guard<std::mutex> lk(sv->mu);
+  *volume_id = (int32_t)sv->vols.size();
+  sv->vols.push_back(std::move(v));
+  sv->stats.volumes = (int32_t)sv->vols.size();
+  sv->stats.resident_bytes = sv->resident;
+  return GP_OK;
+}
+
+gp_status gp_serve_submit(gp_server* s, const gp_request* req, float* out, uint64_t* ticket) {
+  if (!s || !req || !out || !ticket) {
+    set_error("submit: NULL");
+    return GP_EINVAL;
+  }
+  Server* sv = reinterpret_cast<Server*>(s);
+  const gp_slice sl{req->z, req->sigma_z, req->x0, req->y0, req->dx, req->dy, req->width, req->height};
+  gp_status st = check_slice_pub(sl, 0);
+  if (st != GP_OK) return st;
+  if (tiles_of(*req) > sv->cfg.max_bins) {
+    set_error("submit: request has more tiles than a batch may hold");
+    return GP_EINVAL;
+  }
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (req->volume_id < 0 || req->volume_id >= (int32_t)sv->vols.size()) {
+      set_error("submit: unknown volume");
+      return GP_EINVAL;
+    }
+    if (sv->stop) {
+      set_error("submit: server is shutting down");
+      return GP_ECANCELED;
+    }
+    const uint64_t t = sv->next_ticket++;
+    sv->tickets.emplace(t, TicketState{});
+    sv->queue.push_back(Request{t, *req, out, now_ms(), false});
+    sv->stats.submitted += 1;
+    *ticket = t;
+  }
+  sv->cv.notify_all();
+  return GP_OK;
+}
+
+gp_status gp_serve_poll(gp_server* s, uint64_t ticket, int32_t timeout_us, gp_serve_result* res) {
+  if (!s || !res) {
+    set_error("poll: NULL");
+    return GP_EINVAL;
+  }
+  Server* sv = reinterpret_cast<Server*>(s);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->tickets.find(ticket);
+  if (it == sv->tickets.end()) {
+    set_error("poll: unknown ticket");
+    return GP_EINVAL;
+  }
+  auto ready = [&] { return sv->tickets[ticket].done; };
+  if (!ready()) {
+    if (timeout_us < 0) sv->cv_done.wait(lk, ready);
+    else if (timeout_us > 0) sv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+  }
+  TicketState& t = sv->tickets[ticket];
+  if (!t.done) return GP_EAGAIN;
+  *res = t.res;
+  sv->tickets.erase(ticket);
+  return GP_OK;
+}
+
+gp_status gp_server_stats_get(gp_server* s, gp_server_stats* st) {
+  if (!s || !st) {
+    set_error("server_stats: NULL");
+    return GP_EINVAL;
+  }
+  Server* sv = reinterpret_cast<Server*>(s);
+  std::lock_guard<std::mutex> lk(sv->mu);
+  *st = sv->stats;
+  return GP_OK;
+}
+
+gp_status gp_server_destroy(gp_server* s) {
+  if (!s) return GP_OK;
+  Server* sv = reinterpret_cast<Server*>(s);
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv.notify_all();
+  if (sv->sched.joinable()) sv->sched.join();
+  free_server(sv);
+  return GP_OK;
+}
+
+}  // extern "C"

@@ -9,9 +9,10 @@
 // contraction off; the library is built with correctly rounded division and
 // square root and with denormals preserved.
 //
-//   s_j   = exp_spec(l_j) * mod                       (S = diag(mod * s), supplement Sec. 7)
+//   s_j   = exp_spec(l_j) * mod                       (S = diag(mod * s))
 //   q^    = q / sqrt(((qw^2 + qx^2) + qy^2) + qz^2)
-//   R     = quatToMatrix(q^)                          (supplement Sec. 7)
+//   R     = quatToMatrix(q^)
+//           (both from the supplement, "Derivation of Forward rendering process")
 //   Sigma = R diag(s^2) R^T, adj = R diag(P) R^T with P = (s1^2 s2^2, s0^2 s2^2, s0^2 s1^2)
 //           (entries summed left to right)
 //   m = mu_z - z, D = sigma_z^2 + Sigma_zz, q_ax = m^2 / D        axial test q_ax <= q_cut

@@ -1,8 +1,9 @@
 // Backward of the preprocess (Sec. 4.3 "Backward pass": screen-space
 // projection -> Focus Gaussian (mu_e, Sigma_e) -> camera space -> world
 // parameters (mu, s, q, alpha), with the determinant coupling of alpha~;
-// supplement Sec. 8).  The chain implemented is the exact derivative of the
-// forward as computed, through the closed form of the Focus Gaussian:
+// supplement, "Derivation of Differentiable Backward Pass").  The chain
+// implemented is the exact derivative of the forward as computed, through the
+// closed form of the Focus Gaussian:
 //
 //   D = sigma_z^2 + Sigma_zz, u = Sigma_xz / D, v = Sigma_yz / D, m = mu_z - z
 //   A = Sigma_xx - u Sigma_xz, B = Sigma_xy - u Sigma_yz, C = Sigma_yy - v Sigma_yz
@@ -10,7 +11,7 @@
 //   alpha~ = alpha opacity_r / sqrt(AC - B^2), conic = (C, -B, A) / (AC - B^2)
 //
 // One thread per Gaussian sums, for each of its records (one per slice it
-// reaches), the six moments of the record's list entries in footprint order,
+// reaches), the six moments of the record's tiles in footprint order,
 // applies the chain rule, accumulates over records in slice order and finally
 // maps Sigma = R diag(s^2) R^T back to (log-scale, quaternion).  The gradient is
 // added to the caller's buffer with plain loads and stores: every element has
@@ -37,26 +38,24 @@ __device__ __forceinline__ float load_attr(const void* base, int64_t idx) {
 
 struct BwdPreArgs {
   RenderConst rc;
+  const BatchHdr* hdr;
   const GroupDev* groups;
   const SliceDev* slices;
   const RecPay* rec_pay;
   const RecMeta* rec_meta;
   const uint32_t* g_rbase;
   const uint32_t* g_nrec;
-  const uint32_t* inst_pos;
   const float4* moments;
   float* grad;
   int64_t grad_stride;
 };
 
 template <int DT>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= a.rc.total_gauss) return;
+__device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, int t) {
   const uint32_t nrec = a.g_nrec[t];
   if (nrec == 0) return;
   int g = 0;
-  for (int jg = 1; jg < a.rc.n_groups; ++jg)
+  for (int jg = 1; jg < n_groups; ++jg)
     if (a.groups[jg].gbase <= (t & ~63)) g = jg;
   const GroupDev G = a.groups[g];
   const int j = t - G.gbase;
@@ -78,14 +77,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
 
   for (uint32_t r = rbase; r < rbase + nrec && r < a.rc.rec_cap; ++r) {
     const RecMeta meta = a.rec_meta[r];
-    if (meta.ntiles == 0) continue;
-    const RecPay pay = a.rec_pay[r];
-    const SliceDev sl = a.slices[pay.slice];
+    const SliceDev sl = a.slices[meta.slice];
+    const uint32_t ntiles = rec_ntiles(meta);
     float M0 = 0.f, Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
-    for (uint32_t s = 0; s < meta.ntiles; ++s) {
-      const uint32_t pos = a.inst_pos[meta.ibase + s];
-      const float4 m0 = a.moments[2 * (size_t)pos];
-      const float4 m1 = a.moments[2 * (size_t)pos + 1];
+    for (uint32_t s = 0; s < ntiles; ++s) {
+      const float4 m0 = a.moments[2 * (size_t)(meta.ibase + s)];
+      const float4 m1 = a.moments[2 * (size_t)(meta.ibase + s) + 1];
       M0 += m0.x; Mx += m0.y; My += m0.z; Mxx += m0.w; Mxy += m1.x; Myy += m1.y;
     }
     // forward quantities of this (Gaussian, slice) pair
@@ -183,18 +180,26 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
   gp[10 * gs] += galpha;
 }
 
+template <int DT>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
+  const int total = a.hdr->total_gauss;
+  const int n_groups = a.hdr->n_groups;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < total; t += gridDim.x * 256) backward_one<DT>(a, n_groups, t);
+}
+
 }  // namespace
 
 hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, float* grad,
-                                 int64_t grad_stride, hipStream_t s) {
-  if (rc.total_gauss <= 0) return hipSuccess;
-  BwdPreArgs a{rc, ws.d_groups, ws.d_slices, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase, ws.d_g_nrec,
-               ws.d_inst_pos, ws.d_moments, grad, grad_stride};
-  const unsigned blocks = (unsigned)((rc.total_gauss + 255) / 256);
-  switch (ws.h_groups[0].attr_dtype) {
-    case GP_BF16: k_preprocess_bwd<GP_BF16><<<blocks, 256, 0, s>>>(a); break;
-    case GP_F16: k_preprocess_bwd<GP_F16><<<blocks, 256, 0, s>>>(a); break;
-    default: k_preprocess_bwd<GP_F32><<<blocks, 256, 0, s>>>(a); break;
+                                 int64_t grad_stride, const LaunchDims& d, hipStream_t s) {
+  if (d.gauss <= 0) return hipSuccess;
+  BwdPreArgs a{rc, ws.d_hdr, ws.d_groups, ws.d_slices, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase, ws.d_g_nrec,
+               ws.d_moments, grad, grad_stride};
+  int64_t blocks = (d.gauss + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  switch (rc.attr_dtype) {
+    case GP_BF16: k_preprocess_bwd<GP_BF16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    case GP_F16: k_preprocess_bwd<GP_F16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    default: k_preprocess_bwd<GP_F32><<<(unsigned)blocks, 256, 0, s>>>(a); break;
   }
   return hipGetLastError();
 }

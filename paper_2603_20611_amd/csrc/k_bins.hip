@@ -1,9 +1,8 @@
 // Tile lists: exclusive scan of the per-bin counts, scatter of every instance
 // to (bin start + rank), then a per-bin sort by Gaussian index, which makes
 // each list's order unique and independent of the order in which atomics
-// handed out ranks.  The sort also gathers each entry's 32-byte record into
-// list order so that the rasterisers stream contiguous memory, and stores the
-// list position of every instance slot for the deterministic backward.
+// handed out ranks.  A list holds record ids; the rasterisers gather the
+// 32-byte records themselves.
 //
 // The paper sums over N(p), the Gaussians overlapping pixel p (Sec. 4.2); with
 // purely additive accumulation the order of a list does not change the sum, so
@@ -16,9 +15,11 @@ namespace {
 constexpr int kScanThreads = 1024;
 
 // Single-workgroup exclusive scan of n counts (n up to a few million).
-__global__ __launch_bounds__(kScanThreads) void k_scan_bins(const uint32_t* __restrict__ count,
-                                                            uint32_t* __restrict__ start, int32_t n) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_bins(const BatchHdr* __restrict__ hdr,
+                                                            const uint32_t* __restrict__ count,
+                                                            uint32_t* __restrict__ start) {
   __shared__ uint32_t part[kScanThreads];
+  const int n = hdr->n_bins;
   const int t = threadIdx.x;
   const int per = (n + kScanThreads - 1) / kScanThreads;
   const int b = t * per;
@@ -58,28 +59,25 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs a) {
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nrec; r += stride) {
     const RecMeta m = a.rec_meta[r];
-    if (m.ntiles == 0) continue;
-    const RecPay p = a.rec_pay[r];
-    const SliceDev& sl = a.slices[p.slice];
+    if (m.slice == kInvalidSlice) continue;
+    const uint64_t key_hi = (uint64_t)a.rec_pay[r].gid << 32;
+    const SliceDev& sl = a.slices[m.slice];
     const int tx0 = m.rx & 0xFFFF, tx1 = m.rx >> 16, ty0 = m.ry & 0xFFFF, ty1 = m.ry >> 16;
     uint32_t slot = m.ibase;
     for (int ty = ty0; ty <= ty1; ++ty) {
       for (int tx = tx0; tx <= tx1; ++tx, ++slot) {
         const uint32_t bin = (uint32_t)(sl.tile_base + ty * sl.ntx + tx);
-        const uint32_t pos = a.bin_start[bin] + a.inst_rank[slot];
-        a.sort_key[pos] = ((uint64_t)p.gid << 32) | slot;
+        a.sort_key[a.bin_start[bin] + a.inst_rank[slot]] = key_hi | r;
       }
     }
   }
 }
 
 struct SortArgs {
+  const BatchHdr* hdr;
   const uint32_t* bin_start;
   uint64_t* sort_key;
-  const uint32_t* inst_rid;
-  const RecPay* rec_pay;
-  RecPay* pay;
-  uint32_t* inst_pos;
+  uint32_t* list;
 };
 
 // Bitonic sorting network on [0, n) with every comparator ascending ("flip"
@@ -113,40 +111,35 @@ __device__ __forceinline__ void bitonic(int n, Load ld, Store st) {
   }
 }
 
+// One workgroup per bin, grid-stride over the batch's bins.
 __global__ __launch_bounds__(256) void k_bin_sort(SortArgs a) {
   __shared__ uint64_t keys[kBinSortCap];
-  const uint32_t bin = blockIdx.x;
-  const uint32_t start = a.bin_start[bin];
-  const int n = (int)(a.bin_start[bin + 1] - start);
-  if (n == 0) return;
-  uint64_t* gk = a.sort_key + start;
-  if (n <= kBinSortCap) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) keys[i] = gk[i];
-    __syncthreads();
-    if (n > 1)
-      bitonic(n, [&](int i) { return keys[i]; }, [&](int i, uint64_t v) { keys[i] = v; });
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const uint32_t slot = (uint32_t)(keys[i] & 0xFFFFFFFFu);
-      a.pay[start + i] = a.rec_pay[a.inst_rid[slot]];
-      a.inst_pos[slot] = start + i;
+  const int n_bins = a.hdr->n_bins;
+  for (int bin = blockIdx.x; bin < n_bins; bin += gridDim.x) {
+    const uint32_t start = a.bin_start[bin];
+    const int n = (int)(a.bin_start[bin + 1] - start);
+    if (n == 0) continue;
+    uint64_t* gk = a.sort_key + start;
+    if (n <= kBinSortCap) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) keys[i] = gk[i];
+      __syncthreads();
+      if (n > 1)
+        bitonic(n, [&](int i) { return keys[i]; }, [&](int i, uint64_t v) { keys[i] = v; });
+      for (int i = threadIdx.x; i < n; i += blockDim.x) a.list[start + i] = (uint32_t)keys[i];
+    } else {
+      // long list: the same network in global memory, this workgroup only
+      bitonic(n, [&](int i) { return gk[i]; }, [&](int i, uint64_t v) { gk[i] = v; });
+      __syncthreads();
+      for (int i = threadIdx.x; i < n; i += blockDim.x) a.list[start + i] = (uint32_t)gk[i];
     }
-  } else {
-    // long list: the same network in global memory, this workgroup only
-    bitonic(n, [&](int i) { return gk[i]; },
-            [&](int i, uint64_t v) { gk[i] = v; });
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const uint32_t slot = (uint32_t)(gk[i] & 0xFFFFFFFFu);
-      a.pay[start + i] = a.rec_pay[a.inst_rid[slot]];
-      a.inst_pos[slot] = start + i;
-    }
+    __syncthreads();   // keys[] is reused by the next bin
   }
 }
 
 }  // namespace
 
-hipError_t launch_scan_bins(const Workspace& ws, int32_t n_bins, hipStream_t s) {
-  k_scan_bins<<<1, kScanThreads, 0, s>>>(ws.d_bin_count, ws.d_bin_start, n_bins);
+hipError_t launch_scan_bins(const Workspace& ws, hipStream_t s) {
+  k_scan_bins<<<1, kScanThreads, 0, s>>>(ws.d_hdr, ws.d_bin_count, ws.d_bin_start);
   return hipGetLastError();
 }
 
@@ -160,10 +153,12 @@ hipError_t launch_scatter(const RenderConst& rc, const Workspace& ws, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_bin_sort(const RenderConst& rc, const Workspace& ws, hipStream_t s) {
-  if (rc.n_bins <= 0) return hipSuccess;
-  SortArgs a{ws.d_bin_start, ws.d_sort_key, ws.d_inst_rid, ws.d_rec_pay, ws.d_pay, ws.d_inst_pos};
-  k_bin_sort<<<(unsigned)rc.n_bins, 256, 0, s>>>(a);
+hipError_t launch_bin_sort(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s) {
+  (void)rc;
+  if (d.bins <= 0) return hipSuccess;
+  SortArgs a{ws.d_hdr, ws.d_bin_start, ws.d_sort_key, ws.d_list};
+  const int64_t blocks = d.bins < 8192 ? d.bins : 8192;
+  k_bin_sort<<<(unsigned)blocks, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

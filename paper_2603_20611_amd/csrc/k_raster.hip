@@ -19,7 +19,8 @@
 // moments of G(p) e(p) (sum e, sum e dx, sum e dy, sum e dx^2, sum e dx dy,
 // sum e dy^2).  The moments fully determine the entry's gradient with respect
 // to its record, so no per-pixel reduction and no atomics are needed; they are
-// written per list entry and summed per record, in a fixed order, later.
+// written at the record's own instance slot of that tile and summed per record,
+// in footprint order, later.
 #include "gp_internal.h"
 
 namespace gp {
@@ -35,169 +36,232 @@ __device__ __forceinline__ int slice_of_bin(const SliceDev* __restrict__ slices,
 }
 
 struct FwdArgs {
+  const BatchHdr* hdr;
   const SliceDev* slices;
   const uint32_t* bin_start;
-  const RecPay* pay;
-  float* out;
-  int32_t n_slices;
+  const uint32_t* list;
+  const RecPay* rec_pay;
+  uint32_t* work;
 };
 
+// Records with a >= kSmoothA (conditional x-sigma >= 0.42 px) are evaluated
+// along each lane's four-pixel row segment by the exact product recurrence
+//   e(d + 1) = e(d) 2^s(d),  2^s(d + 1) = 2^s(d) g,  s(d) = a (2d + 1) + b dy,  g = 2^(2a)
+// which needs two exp2 per four pixels instead of four.  For such records an
+// underflow of e at the segment start implies the rest of the segment is below
+// 2^-27 of the record's peak, and s is clamped at 126 so 2^s stays finite.
+constexpr float kSmoothA = -4.0f;
+
+__device__ __forceinline__ uint32_t wave_take(uint32_t* counter) {
+  uint32_t v = 0;
+  if (__lane_id() == 0) v = atomicAdd(counter, 1u);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// One 64-lane workgroup; tiles are pulled from an atomic work counter (the next
+// index is requested before the current tile is rendered).
 __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
-  __shared__ float4 buf0[64];   // x, y, a, b
-  __shared__ float2 buf1[64];   // c, w
-  const int bin = blockIdx.x;
-  const int k = slice_of_bin(a.slices, a.n_slices, bin);
-  const SliceDev sl = a.slices[k];
-  const int tile = bin - sl.tile_base;
-  const int tx = tile % sl.ntx, ty = tile / sl.ntx;
+  __shared__ float4 buf0[64];   // x, y, a, b of the batch's records
+  __shared__ float4 buf1[64];   // c, w, g, gid
+  const int n_bins = a.hdr->n_bins;
+  const int n_slices = a.hdr->n_slices;
   const int lane = threadIdx.x;
   const int row = lane >> 2;
   const int col0 = (lane & 3) * 4;
-  const int px0 = tx * kTile + col0;
-  const int py = ty * kTile + row;
-  const float fx0 = (float)px0, fy = (float)py;
+  uint32_t next = wave_take(&a.work[kWorkRasterFwd]);
+  while (next < (uint32_t)n_bins) {
+    const int bin = (int)next;
+    next = wave_take(&a.work[kWorkRasterFwd]);
+    const int k = slice_of_bin(a.slices, n_slices, bin);
+    const SliceDev sl = a.slices[k];
+    const int tile = bin - sl.tile_base;
+    const int tx = tile % sl.ntx, ty = tile / sl.ntx;
+    const int px0 = tx * kTile + col0;
+    const int py = ty * kTile + row;
+    const float fx0 = (float)px0, fy = (float)py;
 
-  const uint32_t start = a.bin_start[bin], end = a.bin_start[bin + 1];
-  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+    const uint32_t start = a.bin_start[bin], end = a.bin_start[bin + 1];
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
 
-  float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f);
-  float2 n1 = make_float2(0.f, 0.f);
-  if (start + lane < end) {
-    const float4* src = reinterpret_cast<const float4*>(a.pay + start + lane);
-    n0 = src[0];
-    const float4 t = src[1];
-    n1 = make_float2(t.x, t.y);
-  }
-  for (uint32_t base = start; base < end; base += 64) {
-    buf0[lane] = n0;
-    buf1[lane] = n1;
-    __syncthreads();
-    const int cnt = (int)min(64u, end - base);
-    // prefetch the next batch while this one is consumed
-    const uint32_t nb = base + 64;
-    if (nb + lane < end) {
-      const float4* src = reinterpret_cast<const float4*>(a.pay + nb + lane);
+    float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
+    if (start + lane < end) {
+      const float4* src = reinterpret_cast<const float4*>(a.rec_pay + a.list[start + lane]);
       n0 = src[0];
-      const float4 t = src[1];
-      n1 = make_float2(t.x, t.y);
+      n1 = src[1];
     }
-#pragma unroll 2
-    for (int j = 0; j < cnt; ++j) {
-      const float4 r0 = buf0[j];
-      const float2 r1 = buf1[j];
-      const float dy = fy - r0.y;
-      const float by = r0.w * dy;
-      const float cy = r1.x * dy * dy;
-      const float d0 = fx0 - r0.x;
-      const float d1 = d0 + 1.0f, d2 = d0 + 2.0f, d3 = d0 + 3.0f;
-      const float p0 = fmaf(fmaf(r0.z, d0, by), d0, cy);
-      const float p1 = fmaf(fmaf(r0.z, d1, by), d1, cy);
-      const float p2 = fmaf(fmaf(r0.z, d2, by), d2, cy);
-      const float p3 = fmaf(fmaf(r0.z, d3, by), d3, cy);
-      acc0 = fmaf(r1.y, __builtin_amdgcn_exp2f(p0), acc0);
-      acc1 = fmaf(r1.y, __builtin_amdgcn_exp2f(p1), acc1);
-      acc2 = fmaf(r1.y, __builtin_amdgcn_exp2f(p2), acc2);
-      acc3 = fmaf(r1.y, __builtin_amdgcn_exp2f(p3), acc3);
+    for (uint32_t base = start; base < end; base += 64) {
+      buf0[lane] = n0;
+      buf1[lane] = n1;
+      __syncthreads();
+      const int cnt = (int)min(64u, end - base);
+      // prefetch the next batch while this one is consumed
+      const uint32_t nb = base + 64;
+      if (nb + lane < end) {
+        const float4* src = reinterpret_cast<const float4*>(a.rec_pay + a.list[nb + lane]);
+        n0 = src[0];
+        n1 = src[1];
+      }
+      for (int j = 0; j < cnt; ++j) {
+        const float4 r0 = buf0[j];
+        const float4 r1 = buf1[j];
+        const float dy = fy - r0.y;
+        const float by = r0.w * dy;
+        const float cy = r1.x * dy * dy;
+        const float d0 = fx0 - r0.x;
+        const float ra = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(r0.z)));
+        if (ra >= kSmoothA) {
+          const float p0 = fmaf(fmaf(r0.z, d0, by), d0, cy);
+          const float s0 = fminf(fmaf(r0.z, fmaf(d0, 2.0f, 1.0f), by), 126.0f);
+          const float e0 = __builtin_amdgcn_exp2f(p0);
+          float q = __builtin_amdgcn_exp2f(s0);
+          const float e1 = e0 * q;
+          q *= r1.z;
+          const float e2 = e1 * q;
+          q *= r1.z;
+          const float e3 = e2 * q;
+          acc0 = fmaf(r1.y, e0, acc0);
+          acc1 = fmaf(r1.y, e1, acc1);
+          acc2 = fmaf(r1.y, e2, acc2);
+          acc3 = fmaf(r1.y, e3, acc3);
+        } else {
+          const float d1 = d0 + 1.0f, d2 = d0 + 2.0f, d3 = d0 + 3.0f;
+          const float p0 = fmaf(fmaf(r0.z, d0, by), d0, cy);
+          const float p1 = fmaf(fmaf(r0.z, d1, by), d1, cy);
+          const float p2 = fmaf(fmaf(r0.z, d2, by), d2, cy);
+          const float p3 = fmaf(fmaf(r0.z, d3, by), d3, cy);
+          acc0 = fmaf(r1.y, __builtin_amdgcn_exp2f(p0), acc0);
+          acc1 = fmaf(r1.y, __builtin_amdgcn_exp2f(p1), acc1);
+          acc2 = fmaf(r1.y, __builtin_amdgcn_exp2f(p2), acc2);
+          acc3 = fmaf(r1.y, __builtin_amdgcn_exp2f(p3), acc3);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  if (py < sl.height) {
-    float* o = a.out + sl.out_off + (int64_t)py * sl.width;
-    if (px0 + 3 < sl.width && (reinterpret_cast<uintptr_t>(o + px0) & 15) == 0) {
-      *reinterpret_cast<float4*>(o + px0) = make_float4(acc0, acc1, acc2, acc3);
-    } else {
-      if (px0 < sl.width) o[px0] = acc0;
-      if (px0 + 1 < sl.width) o[px0 + 1] = acc1;
-      if (px0 + 2 < sl.width) o[px0 + 2] = acc2;
-      if (px0 + 3 < sl.width) o[px0 + 3] = acc3;
+    if (py < sl.height) {
+      float* o = sl.out + (int64_t)py * sl.width;
+      if (px0 + 3 < sl.width && (reinterpret_cast<uintptr_t>(o + px0) & 15) == 0) {
+        *reinterpret_cast<float4*>(o + px0) = make_float4(acc0, acc1, acc2, acc3);
+      } else {
+        if (px0 < sl.width) o[px0] = acc0;
+        if (px0 + 1 < sl.width) o[px0 + 1] = acc1;
+        if (px0 + 2 < sl.width) o[px0 + 2] = acc2;
+        if (px0 + 3 < sl.width) o[px0 + 3] = acc3;
+      }
     }
   }
 }
 
 struct BwdArgs {
+  const BatchHdr* hdr;
   const SliceDev* slices;
   const uint32_t* bin_start;
-  const RecPay* pay;
+  const uint32_t* list;
+  const RecPay* rec_pay;
+  const RecMeta* rec_meta;
   const float* grad_out;
   float4* moments;
-  int32_t n_slices;
+  uint32_t* work;
 };
 
+// 256 lanes per tile, tiles pulled from an atomic work counter.
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   __shared__ float G[kTilePix];
-  const int bin = blockIdx.x;
-  const uint32_t start = a.bin_start[bin], end = a.bin_start[bin + 1];
-  if (start == end) return;
-  const int k = slice_of_bin(a.slices, a.n_slices, bin);
-  const SliceDev sl = a.slices[k];
-  const int tile = bin - sl.tile_base;
-  const int tx = tile % sl.ntx, ty = tile / sl.ntx;
-  {
-    const int t = threadIdx.x;
-    const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
-    G[t] = (px < sl.width && py < sl.height) ? a.grad_out[sl.out_off + (int64_t)py * sl.width + px] : 0.f;
-  }
-  __syncthreads();
+  __shared__ uint32_t s_bin;
+  const int n_bins = a.hdr->n_bins;
+  const int n_slices = a.hdr->n_slices;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const float fx0 = (float)(tx * kTile), fy0 = (float)(ty * kTile);
-  for (uint32_t cb = start + wave * 64; cb < end; cb += 256) {
-    const uint32_t idx = cb + lane;
-    if (idx >= end) continue;
-    const float4* src = reinterpret_cast<const float4*>(a.pay + idx);
-    const float4 r0 = src[0];
-    const float4 r1 = src[1];
-    const float ca = r0.z, cb2 = r0.w, cc = r1.x;
-    float dx[kTile];
-#pragma unroll
-    for (int c = 0; c < kTile; ++c) dx[c] = (fx0 - r0.x) + (float)c;
-    float M0 = 0.f, Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
-    for (int row = 0; row < kTile; ++row) {
-      const float dy = (fy0 + (float)row) - r0.y;
-      const float by = cb2 * dy;
-      const float cy = cc * dy * dy;
-      const float4* grow = reinterpret_cast<const float4*>(G + row * kTile);
-      float s0 = 0.f, sx = 0.f, sxx = 0.f;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float4 g4 = grow[q];
-        const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const float d = dx[4 * q + c];
-          const float p = fmaf(fmaf(ca, d, by), d, cy);
-          const float we = gv[c] * __builtin_amdgcn_exp2f(p);
-          const float wd = we * d;
-          s0 += we;
-          sx += wd;
-          sxx = fmaf(wd, d, sxx);
-        }
-      }
-      M0 += s0;
-      Mx += sx;
-      Mxx += sxx;
-      My = fmaf(dy, s0, My);
-      Mxy = fmaf(dy, sx, Mxy);
-      Myy = fmaf(dy * dy, s0, Myy);
+  for (;;) {
+    if (threadIdx.x == 0) s_bin = atomicAdd(&a.work[kWorkRasterBwd], 1u);
+    __syncthreads();
+    const uint32_t ub = s_bin;
+    __syncthreads();   // s_bin is rewritten by the next iteration
+    if (ub >= (uint32_t)n_bins) break;
+    const int bin = (int)ub;
+    const uint32_t start = a.bin_start[bin], end = a.bin_start[bin + 1];
+    if (start == end) continue;
+    const int k = slice_of_bin(a.slices, n_slices, bin);
+    const SliceDev sl = a.slices[k];
+    const int tile = bin - sl.tile_base;
+    const int tx = tile % sl.ntx, ty = tile / sl.ntx;
+    {
+      const int t = threadIdx.x;
+      const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
+      G[t] = (px < sl.width && py < sl.height) ? a.grad_out[sl.out_off + (int64_t)py * sl.width + px] : 0.f;
     }
-    a.moments[2 * (size_t)idx] = make_float4(M0, Mx, My, Mxx);
-    a.moments[2 * (size_t)idx + 1] = make_float4(Mxy, Myy, 0.f, 0.f);
+    __syncthreads();
+    const float fx0 = (float)(tx * kTile), fy0 = (float)(ty * kTile);
+    for (uint32_t cb = start + wave * 64; cb < end; cb += 256) {
+      const uint32_t idx = cb + lane;
+      if (idx >= end) continue;
+      const uint32_t rid = a.list[idx];
+      const float4* src = reinterpret_cast<const float4*>(a.rec_pay + rid);
+      const float4 r0 = src[0];
+      const float4 r1 = src[1];
+      const RecMeta meta = a.rec_meta[rid];
+      const float ca = r0.z, cb2 = r0.w, cc = r1.x;
+      float dx[kTile];
+#pragma unroll
+      for (int c = 0; c < kTile; ++c) dx[c] = (fx0 - r0.x) + (float)c;
+      float M0 = 0.f, Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+      for (int row = 0; row < kTile; ++row) {
+        const float dy = (fy0 + (float)row) - r0.y;
+        const float by = cb2 * dy;
+        const float cy = cc * dy * dy;
+        const float4* grow = reinterpret_cast<const float4*>(G + row * kTile);
+        float s0 = 0.f, sx = 0.f, sxx = 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 g4 = grow[q];
+          const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float d = dx[4 * q + c];
+            const float p = fmaf(fmaf(ca, d, by), d, cy);
+            const float we = gv[c] * __builtin_amdgcn_exp2f(p);
+            const float wd = we * d;
+            s0 += we;
+            sx += wd;
+            sxx = fmaf(wd, d, sxx);
+          }
+        }
+        M0 += s0;
+        Mx += sx;
+        Mxx += sxx;
+        My = fmaf(dy, s0, My);
+        Mxy = fmaf(dy, sx, Mxy);
+        Myy = fmaf(dy * dy, s0, Myy);
+      }
+      // the record's instance slot of this tile (footprint enumerated row-major)
+      const uint32_t tx0 = meta.rx & 0xFFFFu, tx1 = meta.rx >> 16, ty0 = meta.ry & 0xFFFFu;
+      const uint32_t slot = meta.ibase + ((uint32_t)ty - ty0) * (tx1 - tx0 + 1u) + ((uint32_t)tx - tx0);
+      a.moments[2 * (size_t)slot] = make_float4(M0, Mx, My, Mxx);
+      a.moments[2 * (size_t)slot + 1] = make_float4(Mxy, Myy, 0.f, 0.f);
+    }
+    __syncthreads();   // G[] is reused by the next tile
   }
 }
 
 }  // namespace
 
-hipError_t launch_raster_fwd(const RenderConst& rc, const Workspace& ws, float* out, hipStream_t s) {
-  if (rc.n_bins <= 0) return hipSuccess;
-  FwdArgs a{ws.d_slices, ws.d_bin_start, ws.d_pay, out, rc.n_slices};
-  k_raster_fwd<<<(unsigned)rc.n_bins, 64, 0, s>>>(a);
+hipError_t launch_raster_fwd(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s) {
+  (void)rc;
+  if (d.bins <= 0) return hipSuccess;
+  FwdArgs a{ws.d_hdr, ws.d_slices, ws.d_bin_start, ws.d_list, ws.d_rec_pay, ws.d_work};
+  const int64_t blocks = d.bins < 8192 ? d.bins : 8192;
+  k_raster_fwd<<<(unsigned)blocks, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const float* grad_out,
-                             hipStream_t s) {
-  if (rc.n_bins <= 0) return hipSuccess;
-  BwdArgs a{ws.d_slices, ws.d_bin_start, ws.d_pay, grad_out, ws.d_moments, rc.n_slices};
-  k_raster_bwd<<<(unsigned)rc.n_bins, 256, 0, s>>>(a);
+                             const LaunchDims& d, hipStream_t s) {
+  (void)rc;
+  if (d.bins <= 0) return hipSuccess;
+  hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterBwd, 0u, 1, s);
+  if (e != hipSuccess) return e;
+  BwdArgs a{ws.d_hdr, ws.d_slices, ws.d_bin_start, ws.d_list, ws.d_rec_pay, ws.d_rec_meta, grad_out, ws.d_moments,
+            ws.d_work};
+  const int64_t blocks = d.bins < 2048 ? d.bins : 2048;
+  k_raster_bwd<<<(unsigned)blocks, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

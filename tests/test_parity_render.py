@@ -159,6 +159,21 @@ def test_forward_is_deterministic(gp):
     assert torch.equal(a, b)
 
 
+def test_auto_workspace_grows_without_reporting_overflow(gp):
+    from paper_2603_20611_amd import render
+    _say("auto-sized workspace growth")
+    p = synth.gaussians_uniform(20000, (64, 64, 8), np.log(3.0), 0.3, seed=9)
+    slices = synth.axial_slices(8, 64, 64, 2.0, z0=0.5, dz=1.0)
+    params = _gpu_params(p)
+    ws = render.Workspace()
+    out = render.render(params, slices, ws=ws)
+    rec, inst, bins = ws.check()
+    assert rec > 0 and inst > 4 * (1 << 16) and bins == 8 * 16
+    ref = render.render(params, slices, ws=render.Workspace(capacity=(2 * rec, 2 * inst)))
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+
+
 def test_fixed_capacity_overflow_is_reported(gp):
     from paper_2603_20611_amd import binding as B, render
     _say("fixed-capacity overflow")
