@@ -9,7 +9,7 @@ Gaussians and multiplied by Rayleigh(1) speckle.
 Timed phases (each K steps after W warm-up steps, bracketed by a device
 synchronisation on both sides):
   forward   one step = the whole 400-slice stack rendered in one launch sequence
-            (activation, axial cull, projection, binning, per-tile sort,
+            (activation, axial cull, projection, tile-key emission, radix sort,
             additive rasterisation).  `value` = rendered megapixels per second.
   train     one step = one reconstruction iteration on a batch of 8 consecutive
             slices at a random depth: forward, L1 loss gradient, backward,
@@ -18,7 +18,8 @@ synchronisation on both sides):
 
 The dominant kernel (additive rasterisation of the forward) is timed with HIP
 events recorded by the library on the stream it launches on; its roofline is
-the VALU + transcendental issue rate of the chip.  The CPU
+the VALU + transcendental issue rate of the chip (4 (pixel, Gaussian) pairs per
+clock per SIMD, derived below).  The CPU
 oracle is timed on 8 slices of 256 x 256 of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -69,6 +70,79 @@ def cpu_baseline(params_np, slices):
                       f"{N_GAUSS}-Gaussian workload, float64 oracle, {dt:.1f} s"}
 
 
+def serving_leg(dev, n_requests, seed=3):
+    """Serving workload: 64 resident volumes (log-uniform 20k..1M Gaussians, the
+    microscopy generator in a 512x512x128 extent), Poisson requests at 2,000/s
+    for slices at z ~ U(0, 128), resolution in {256^2, 512^2, 1024^2}, sigma_z
+    in {0.5, 1, 2, 3}.  The batched server (continuous batching, graph replay,
+    3 slots) is compared with one launch per request (max_batch 1, 1 slot, no
+    graphs) at the same offered load and in a closed loop (all requests queued
+    at once: saturation throughput)."""
+    import torch
+    from paper_2603_20611_amd import serve, synth
+
+    vols = synth.serving_volumes(64, 20_000, 1_000_000, (512.0, 512.0, 128.0), seed=seed)
+    reqs = synth.serving_requests(n_requests, len(vols), depth=128.0, extent=512.0, seed=seed, rate=2000.0)
+    total_g = sum(v.shape[1] for v in vols)
+    log(f"serving: {len(vols)} volumes, {total_g} Gaussians, {len(reqs)} requests")
+    outs = [torch.empty(r["res"] * r["res"], device=dev) for r in reqs]
+    systems = {
+        "batched": dict(max_batch=64, slots=3, use_graphs=1),
+        "plain": dict(max_batch=1, slots=1, use_graphs=0),
+    }
+    result = {"volumes": len(vols), "gaussians": int(total_g), "requests": len(reqs), "offered_req_per_s": 2000.0,
+              "attr_storage": "q16 (fp16 log-scales and intensity, int16 unit quaternion)"}
+    for name, cfg in systems.items():
+        sv = serve.Server(max_gaussians=64 << 20, max_records=24 << 20, max_instances=48 << 20,
+                          max_bins=64 * 4096, **cfg)
+        for v in vols:
+            t = torch.from_numpy(v).to(dev).contiguous()
+            sv.add_volume(t)
+            del t
+        torch.cuda.synchronize()
+
+        def submit(r, o):
+            return sv.submit(r["volume"], r["z"], r["sigma_z"], o, r["res"], r["res"], dx=r["dx"], dy=r["dx"])
+
+        # warm-up (graph capture, first launches)
+        for r, o in zip(reqs[:8], outs[:8]):
+            sv.poll(submit(r, o), -1)
+        # open loop at the offered rate
+        t0 = time.perf_counter()
+        tickets = []
+        for r, o in zip(reqs, outs):
+            delay = t0 + r["t"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(submit(r, o))
+        res = [sv.poll(t, -1) for t in tickets]
+        wall = time.perf_counter() - t0
+        lat = np.array([x.latency_ms for x in res])
+        bs = np.array([x.batch_size for x in res])
+        # closed loop: everything queued at once
+        t1 = time.perf_counter()
+        tickets = [submit(r, o) for r, o in zip(reqs, outs)]
+        res2 = [sv.poll(t, -1) for t in tickets]
+        wall2 = time.perf_counter() - t1
+        lat2 = np.array([x.latency_ms for x in res2])
+        ok = all(x.status == 0 for x in res + res2)
+        st = sv.stats()
+        result[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                        "slices_per_s": round(len(reqs) / wall, 1),
+                        "mean_batch": round(float(bs.mean()), 2),
+                        "saturated_slices_per_s": round(len(reqs) / wall2, 1),
+                        "saturated_p50_ms": round(float(np.percentile(lat2, 50)), 3),
+                        "saturated_p99_ms": round(float(np.percentile(lat2, 99)), 3),
+                        "all_ok": bool(ok), "retries": int(st.retries)}
+        log(f"serving {name}: {result[name]}")
+        sv.close()
+        torch.cuda.synchronize()
+    result["saturated_speedup"] = round(result["batched"]["saturated_slices_per_s"]
+                                        / result["plain"]["saturated_slices_per_s"], 2)
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +150,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--train-steps", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this size (calibrates HBM byte counters)")
+    ap.add_argument("--forward-only", action="store_true", help="time the forward phase only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build"}))
@@ -86,6 +165,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe_mib:
+        a = torch.ones(args.copy_probe_mib << 18, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {a.numel() * 4} bytes read and written")
+        del a, b
     log("generating workload")
     learn = synth.ultrasound_hidden(N_GAUSS, seed=1)
     hidden = synth.ultrasound_hidden(N_GAUSS, seed=0)
@@ -94,10 +180,12 @@ def main():
     hidden_t = torch.from_numpy(hidden).to(dev).contiguous()
 
     # target stack: render the hidden set, apply speckle (input data, made once)
-    ws_t = render.Workspace()
-    target = render.render(hidden_t, slices, ws=ws_t)
-    target *= torch.from_numpy(synth.speckle(target.numel(), seed=2)).to(dev)
-    del ws_t, hidden_t
+    if not args.forward_only:
+        ws_t = render.Workspace()
+        target = render.render(hidden_t, slices, ws=ws_t)
+        target *= torch.from_numpy(synth.speckle(target.numel(), seed=2)).to(dev)
+        del ws_t
+    del hidden_t
     torch.cuda.synchronize()
 
     # size a fixed workspace from one counted render, then render without host syncs
@@ -129,6 +217,12 @@ def main():
     achieved = pairs / (raster_ms * 1e-3)
     log(f"forward: {fwd_ms:.3f} ms/step, {mpix:.0f} Mpix/s; stages (ms/launch): "
         + ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in st.items() if v[1]))
+
+    if args.forward_only:
+        print(json.dumps({"forward_ms": round(fwd_ms, 4), "mpix_per_s": round(mpix, 1),
+                          "stage_ms": {k: round(v_[0] / max(v_[1], 1), 4) for k, v_ in st.items() if v_[1]},
+                          "records": rec, "instances": inst}), flush=True)
+        return
 
     # ---------------- training phase
     n_train = args.train_steps or max(args.steps * 5, 50)
@@ -198,8 +292,10 @@ def main():
                      "frac": round(achieved / PEAK_PAIRS_PER_S, 4), "traffic": None,
                      "kernel_ms": round(raster_ms, 4)},
     }
+    if not args.no_serving:
+        result["serving"] = serving_leg(dev, args.serving_requests)
     if not args.no_cpu:
-        log("timing the CPU oracle on one slice")
+        log("timing the CPU oracle on 8 slices")
         result["cpu_baseline"] = cpu_baseline(learn, slices)
     print(json.dumps(result), flush=True)
 

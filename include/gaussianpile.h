@@ -58,6 +58,13 @@ typedef int32_t gp_status;
 #define GP_F32  0
 #define GP_BF16 1
 #define GP_F16  2
+/* GP_Q16: 16-bit storage for served volumes.  Log-scales and intensity are
+ * IEEE half precision; the quaternion is stored normalised, each component as
+ * int16 fixed point: v = rint(q_i / sqrt(((qw^2 + qx^2) + qy^2) + qz^2) * 32767)
+ * in binary32 (round half to even), read back as v / 32767.  Half-precision
+ * quaternions dominate the error of 16-bit storage for thin, elongated
+ * Gaussians; fixed point gives 2^-15 absolute resolution instead. */
+#define GP_Q16  3
 
 /* Render options.  q_cut: axial cull threshold on the Mahalanobis change of the
  * opacity modulation (Sec. 4.2, "cull primitives with opacity below a small
@@ -76,7 +83,7 @@ typedef struct gp_render_opts {
 
 typedef struct gp_gaussians {
   const void* means;  /* d_: [3][stride], mean_dtype (GP_F32 only)            */
-  const void* attrs;  /* d_: [8][stride], attr_dtype (GP_F32, GP_BF16, GP_F16) */
+  const void* attrs;  /* d_: [8][stride], attr_dtype (GP_F32, GP_BF16, GP_F16, GP_Q16) */
   int64_t n;          /* number of Gaussians, 0 <= n <= stride, n < 2^31      */
   int64_t stride;     /* elements between planes                              */
   int32_t mean_dtype;
@@ -174,6 +181,48 @@ gp_status gp_adam_step(float* d_params, float* d_grad, float* d_m, float* d_v, i
                        int64_t stride, const gp_adam_cfg* cfg, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Densify and prune (Sec. 4.3, "Prune and densification": driven by the
+ * Gaussians' footprint radii on the slices and their intensities; thresholds
+ * of Sec. 5.1).  The procedure is the usual Gaussian-splatting control:
+ *   prune  alpha < min_alpha, non-finite parameters, or largest footprint
+ *          half-width (pixels, over the accumulated backwards) > max_radius;
+ *   grow   mean norm of the projected-mean gradient (pixel units, per visible
+ *          record) > grad_threshold: clone (exact copy) if the largest scale
+ *          exp(l) <= split_scale, else split into two children at
+ *          mu + R(q) diag(s) n_k, n_k = d_noise[3k..3k+2][j], log-scales
+ *          reduced by ln(split_factor), q and alpha copied.
+ * Adam moments are carried over for kept Gaussians and zero for new ones.
+ * ---------------------------------------------------------------------- */
+typedef struct gp_densify_cfg {
+  float grad_threshold;   /* 5e-5 (Sec. 5.1)                                  */
+  float min_alpha;        /* 0.02 (Sec. 5.1)                                  */
+  float max_radius;       /* pixels                                            */
+  float split_scale;      /* world units                                       */
+  float split_factor;     /* 1.6                                               */
+  uint32_t flags;
+} gp_densify_cfg;
+gp_status gp_densify_default_cfg(gp_densify_cfg* cfg);
+
+/* While set, every gp_render_backward on ws also adds, for each Gaussian
+ * j < n: the sum over its visible records of |dL/dmu_2d| in pixel units to
+ * d_grad_norm[j], the number of those records to d_count[j], and raises
+ * d_max_radius[j] to its largest footprint half-width in pixels.  One writer
+ * per element (deterministic).  All pointers NULL disables.  Errors: GP_EINVAL. */
+gp_status gp_workspace_set_densify_stats(gp_workspace* ws, float* d_grad_norm, int32_t* d_count,
+                                         float* d_max_radius, int64_t n);
+
+/* Applies densify/prune to n Gaussians ([11][stride] parameters and Adam
+ * moments) and writes the new set, in Gaussian order (children adjacent), to
+ * the *_out planes ([11][stride_out]).  d_noise: [6][n] float32 (two 3-vectors
+ * per Gaussian; only rows of split Gaussians are read).  Synchronous:
+ * *n_out receives the new count.  GP_EOVERFLOW (nothing written, *n_out set)
+ * if stride_out is too small.  Errors: GP_EINVAL, GP_ENOMEM, GP_EHIP. */
+gp_status gp_densify_prune(const float* d_params, const float* d_m, const float* d_v, int64_t n, int64_t stride,
+                           const float* d_grad_norm, const int32_t* d_count, const float* d_max_radius,
+                           const float* d_noise, const gp_densify_cfg* cfg, float* d_params_out, float* d_m_out,
+                           float* d_v_out, int64_t stride_out, int64_t* n_out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Serving: many fitted volumes resident in HBM, slices rendered on request.
  * A server keeps each volume's positions in float32 and its log-scales,
  * quaternions and intensities in attr_dtype (16-bit storage, converted to
@@ -198,7 +247,7 @@ typedef struct gp_server_cfg {
   int32_t max_bins;            /* per batch: 16x16 tiles over all its requests  */
   int32_t max_batch;           /* requests per batch (1 = one launch each)      */
   int32_t slots;               /* batches in flight, 1..4                       */
-  int32_t attr_dtype;          /* GP_BF16, GP_F16 or GP_F32                     */
+  int32_t attr_dtype;          /* GP_Q16, GP_F16, GP_BF16 or GP_F32              */
   int32_t use_graphs;          /* replay a captured graph per slot (else launch) */
   int32_t device;              /* HIP device                                    */
   gp_render_opts opts;
@@ -224,8 +273,9 @@ typedef struct gp_server_stats {
   int32_t pad;
 } gp_server_stats;
 
-/* Defaults: 16 GiB budget, 64 requests per batch, 3 slots, BF16 attributes,
- * graphs on, capacities for 64 requests of 1024^2 at 1M Gaussians each. */
+/* Defaults: 16 GiB budget, 64 requests per batch, 3 slots, GP_Q16 attributes
+ * (on filament-shaped volumes BF16 and FP16 storage exceed a 2e-3 image error,
+ * GP_Q16 stays below it), graphs on. */
 gp_status gp_server_default_cfg(gp_server_cfg* cfg);
 
 /* Creates a server (its streams, slots and scheduler thread) on cfg->device.
@@ -262,14 +312,13 @@ gp_status gp_server_destroy(gp_server* sv);
  * gp_workspace_timings synchronises, resolves the pending events and returns,
  * per stage, the summed milliseconds and the number of launches since timing
  * was enabled.  Enabling resets the sums.  Errors: GP_EINVAL, GP_EHIP. */
-#define GP_STAGE_PREPROCESS      0   /* activation, axial cull, records, tile ranks */
-#define GP_STAGE_SCAN            1   /* exclusive scan of the bin counts            */
-#define GP_STAGE_SCATTER         2   /* instances to (bin start + rank)             */
-#define GP_STAGE_BIN_SORT        3   /* per-bin sort + gather into list order      */
-#define GP_STAGE_RASTER_FWD      4   /* additive rasterisation                      */
-#define GP_STAGE_RASTER_BWD      5   /* per-entry moments of the upstream gradient */
-#define GP_STAGE_PREPROCESS_BWD  6   /* chain rule to the Gaussian parameters       */
-#define GP_N_STAGES              7
+#define GP_STAGE_PREPROCESS      0   /* activation, axial cull, counts, slot scan   */
+#define GP_STAGE_EMIT            1   /* records and (bin, record) pairs             */
+#define GP_STAGE_SORT            2   /* stable radix sort by bin, bin ranges        */
+#define GP_STAGE_RASTER_FWD      3   /* additive rasterisation                      */
+#define GP_STAGE_RASTER_BWD      4   /* per-entry moments of the upstream gradient */
+#define GP_STAGE_PREPROCESS_BWD  5   /* chain rule to the Gaussian parameters       */
+#define GP_N_STAGES              6
 gp_status gp_workspace_set_timing(gp_workspace* ws, int32_t enable);
 gp_status gp_workspace_timings(gp_workspace* ws, double* h_ms, int64_t* h_counts, int32_t n_stages);
 

@@ -15,7 +15,7 @@ tile's list and nothing else, so membership is part of what the renderer
 computes; the image values themselves are computed in FP64 elsewhere
 (``oracle.focus``).
 
-Readings of the paper taken here (each also listed in the design doc):
+Readings of the paper taken here:
   * scale activation s = exp(l) * scale_mod (Sec. 7, S = diag(mod * s); scales are
     stored log-transformed, Sec. 4.3 quantisation);
   * quaternion order (w, x, y, z), normalised before use;

@@ -13,10 +13,10 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgaussia
 _lib = None
 
 GP_OK, GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_EOVERFLOW, GP_EAGAIN, GP_ECANCELED, GP_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
-GP_F32, GP_BF16, GP_F16 = 0, 1, 2
+GP_F32, GP_BF16, GP_F16, GP_Q16 = 0, 1, 2, 3
 GP_FLAG_EXACT = 1
 GP_ADAM_CLAMP_ALPHA, GP_ADAM_ZERO_GRAD = 1, 2
-STAGES = ("preprocess", "scan", "scatter", "bin_sort", "raster_fwd", "raster_bwd", "preprocess_bwd")
+STAGES = ("preprocess", "emit", "sort", "raster_fwd", "raster_bwd", "preprocess_bwd")
 STATUS_NAMES = {0: "GP_OK", -1: "GP_EINVAL", -2: "GP_ENOMEM", -3: "GP_EHIP", -4: "GP_EOVERFLOW",
                 -5: "GP_EAGAIN", -6: "GP_ECANCELED", -7: "GP_ESTATE"}
 
@@ -47,6 +47,35 @@ class AdamCfg(C.Structure):
                 ("step", C.c_int32), ("flags", C.c_uint32)]
 
 
+class DensifyCfg(C.Structure):
+    _fields_ = [("grad_threshold", C.c_float), ("min_alpha", C.c_float), ("max_radius", C.c_float),
+                ("split_scale", C.c_float), ("split_factor", C.c_float), ("flags", C.c_uint32)]
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_gaussians", C.c_int64), ("max_records", C.c_int64),
+                ("max_instances", C.c_int64), ("max_bins", C.c_int32), ("max_batch", C.c_int32),
+                ("slots", C.c_int32), ("attr_dtype", C.c_int32), ("use_graphs", C.c_int32),
+                ("device", C.c_int32), ("opts", RenderOpts)]
+
+
+class Request(C.Structure):
+    _fields_ = [("volume_id", C.c_int32), ("z", C.c_float), ("sigma_z", C.c_float), ("x0", C.c_float),
+                ("y0", C.c_float), ("dx", C.c_float), ("dy", C.c_float), ("width", C.c_int32),
+                ("height", C.c_int32)]
+
+
+class ServeResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("batch_size", C.c_int32), ("batch_id", C.c_int64),
+                ("latency_ms", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("retries", C.c_int64), ("resident_bytes", C.c_int64), ("volumes", C.c_int32),
+                ("pad", C.c_int32)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "gp_version": (C.c_int32, []),
@@ -63,6 +92,17 @@ _SIGS = {
     "gp_adam_step": (C.c_int32, [_P, _P, _P, _P, C.c_int64, C.c_int64, C.POINTER(AdamCfg), _P]),
     "gp_workspace_set_timing": (C.c_int32, [_P, C.c_int32]),
     "gp_workspace_timings": (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
+    "gp_densify_default_cfg": (C.c_int32, [C.POINTER(DensifyCfg)]),
+    "gp_workspace_set_densify_stats": (C.c_int32, [_P, _P, _P, _P, C.c_int64]),
+    "gp_densify_prune": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P, _P, _P, C.POINTER(DensifyCfg),
+                                     _P, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P]),
+    "gp_server_default_cfg": (C.c_int32, [C.POINTER(ServerCfg)]),
+    "gp_server_create": (C.c_int32, [C.POINTER(_P), C.POINTER(ServerCfg)]),
+    "gp_server_add_volume": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(C.c_int32)]),
+    "gp_serve_submit": (C.c_int32, [_P, C.POINTER(Request), _P, C.POINTER(C.c_uint64)]),
+    "gp_serve_poll": (C.c_int32, [_P, C.c_uint64, C.c_int32, C.POINTER(ServeResult)]),
+    "gp_server_stats_get": (C.c_int32, [_P, C.POINTER(ServerStats)]),
+    "gp_server_destroy": (C.c_int32, [_P]),
     "gp_debug_export_bins": (C.c_int32, [_P, C.POINTER(C.c_uint64), C.c_int64, C.POINTER(C.c_int64),
                                          C.POINTER(C.c_int64), C.c_int64]),
 }

@@ -76,16 +76,38 @@ gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups, int64
   if (n_bins > ws->bin_cap) {
     GP_HIP(wait_ws(ws));
     const int64_t cap = n_bins + n_bins / 4 + 256;
-    GP_HIP(dev_alloc(&ws->d_bin_count, cap));
-    GP_HIP(dev_alloc(&ws->d_bin_start, cap + 1));
+    GP_HIP(dev_alloc(&ws->d_bin_lo, cap));
+    GP_HIP(dev_alloc(&ws->d_bin_hi, cap));
     ws->bin_cap = cap;
   }
   if (n_gauss > ws->gauss_cap) {
     GP_HIP(wait_ws(ws));
-    const int64_t cap = n_gauss + n_gauss / 8 + 256;
+    const int64_t cap = (n_gauss + n_gauss / 8 + 256 + 63) / 64 * 64;
     GP_HIP(dev_alloc(&ws->d_g_rbase, cap));
     GP_HIP(dev_alloc(&ws->d_g_nrec, cap));
+    GP_HIP(dev_alloc(&ws->d_g_ninst, cap));
+    GP_HIP(dev_alloc(&ws->d_g_krange, cap));
+    GP_HIP(dev_alloc(&ws->d_wave_cnt, cap / 64 + 1));
     ws->gauss_cap = cap;
+    ws->wave_cap = cap / 64 + 1;
+  }
+  return GP_OK;
+}
+
+// Radix-sort scratch for keys of `bits` bits over the instance capacity, and
+// scan partials for both the digit counts and the wavefront counts.
+gp_status reserve_sort(Workspace* ws, int bits) {
+  const int64_t hist = radix_hist_entries(bits, ws->inst_cap);
+  const int64_t part = std::max(scan_parts_needed(hist), scan_parts_needed(ws->wave_cap));
+  if (hist > ws->hist_cap) {
+    GP_HIP(wait_ws(ws));
+    GP_HIP(dev_alloc(&ws->d_hist, hist));
+    ws->hist_cap = hist;
+  }
+  if (part > ws->part_cap) {
+    GP_HIP(wait_ws(ws));
+    GP_HIP(dev_alloc(&ws->d_scan_part, part));
+    ws->part_cap = part;
   }
   return GP_OK;
 }
@@ -103,8 +125,9 @@ gp_status reserve_lists(Workspace* ws, int64_t rec_cap, int64_t inst_cap) {
   }
   if (inst_cap > ws->inst_cap) {
     GP_HIP(wait_ws(ws));
-    if (dev_alloc(&ws->d_inst_rank, inst_cap) != hipSuccess || dev_alloc(&ws->d_sort_key, inst_cap) != hipSuccess ||
-        dev_alloc(&ws->d_list, inst_cap) != hipSuccess || dev_alloc(&ws->d_moments, 2 * inst_cap) != hipSuccess) {
+    if (dev_alloc(&ws->d_inst_key, inst_cap) != hipSuccess || dev_alloc(&ws->d_inst_val, inst_cap) != hipSuccess ||
+        dev_alloc(&ws->d_key2, inst_cap) != hipSuccess || dev_alloc(&ws->d_val2, inst_cap) != hipSuccess ||
+        dev_alloc(&ws->d_moments, 2 * inst_cap) != hipSuccess) {
       ws->inst_cap = 0;
       set_error("tile-list buffers: out of device memory");
       return GP_ENOMEM;
@@ -172,7 +195,7 @@ static gp_status check_gaussians(const gp_gaussians* g) {
   if (g->stride < g->n) return einval("gaussians: stride < n");
   if (g->n > 0 && (!g->means || !g->attrs)) return einval("gaussians: NULL means/attrs");
   if (g->mean_dtype != GP_F32) return einval("gaussians: means must be GP_F32");
-  if (g->attr_dtype != GP_F32 && g->attr_dtype != GP_BF16 && g->attr_dtype != GP_F16)
+  if (g->attr_dtype != GP_F32 && g->attr_dtype != GP_BF16 && g->attr_dtype != GP_F16 && g->attr_dtype != GP_Q16)
     return einval("gaussians: unknown attr_dtype");
   return GP_OK;
 }
@@ -211,7 +234,8 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
   for (int k = 0; k < ns; ++k)
     nbins += (int64_t)((hs[k].width + kTile - 1) / kTile) * ((hs[k].height + kTile - 1) / kTile);
   for (int g = 0; g < ng; ++g) total_gauss += (groups[g].g->n + 63) / 64 * 64;
-  if (nbins >= (1ll << 31) || total_gauss >= (1ll << 31)) return einval("batch too large");
+  if (nbins >= (1ll << 30) || total_gauss >= (1ll << 31)) return einval("batch too large");
+  if (ns > 65535) return einval("at most 65535 slices per batch");
   gp_status st = reserve_small(ws, ns, ng, nbins, total_gauss);
   if (st != GP_OK) return st;
   // the previous batch's upload must have been consumed before staging is reused
@@ -250,6 +274,7 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
   ws->h_hdr->n_slices = ns;
   ws->h_hdr->n_bins = (int32_t)nbins;
   ws->h_hdr->total_gauss = (int32_t)total_gauss;
+  ws->h_hdr->n_waves = (int32_t)(total_gauss / 64);
   plan->ns = ns; plan->ng = ng; plan->nbins = nbins; plan->total_gauss = total_gauss; plan->npix = off;
   plan->attr_dtype = ng > 0 ? groups[0].g->attr_dtype : GP_F32;
   return GP_OK;
@@ -272,8 +297,10 @@ RenderConst make_render_const(const gp_render_opts* o, int attr_dtype, const Wor
   return rc;
 }
 
-// Launch sequence of a forward on the uploaded batch.  With automatic sizing
-// the counts are read back once (host synchronisation) and the buffers grown.
+// Launch sequence of a forward on the uploaded batch:
+//   reset -> count -> wavefront scan -> (automatic sizing: read the counts,
+//   grow) -> emit -> radix sort by bin -> bin ranges -> rasterise.
+// With fixed capacities nothing synchronises, so the sequence can be captured.
 gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hipStream_t s) {
   if (ws->auto_size && (ws->rec_cap == 0 || ws->inst_cap == 0)) {
     // first use: a generous guess, corrected after the first count
@@ -281,34 +308,45 @@ gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hi
     gp_status st = reserve_lists(ws, guess_rec, 4 * guess_rec);
     if (st != GP_OK) return st;
   }
-  for (int attempt = 0; attempt < 3; ++attempt) {
-    rc.rec_cap = (uint32_t)ws->rec_cap;
-    rc.inst_cap = (uint32_t)ws->inst_cap;
-    // auto sizing re-runs an overflowed attempt, so its flag is cleared per attempt;
-    // with fixed capacities the flag persists until gp_workspace_check reports it
-    GP_HIP(timed(ws, GP_STAGE_PREPROCESS, s, [&] {
-      hipError_t e = launch_reset(*ws, ws->auto_size || ws->overflow_per_forward, d, s);
-      if (e == hipSuccess) e = launch_preprocess(rc, *ws, d, s);
-      return e;
-    }));
-    if (!ws->auto_size) break;
+  const int bits = key_bits(d.bins);
+  gp_status st = reserve_sort(ws, bits);
+  if (st != GP_OK) return st;
+  const bool clear_ovf = ws->auto_size || ws->overflow_per_forward;
+  GP_HIP(timed(ws, GP_STAGE_PREPROCESS, s, [&] {
+    hipError_t e = launch_reset(*ws, clear_ovf, d, s);
+    if (e == hipSuccess) e = launch_pre_count(rc, *ws, d, s);
+    if (e == hipSuccess)
+      e = launch_scan_u32x2(ws->d_wave_cnt, ws->d_wave_cnt, &ws->d_hdr->n_waves, d.gauss / 64, ws->d_scan_part,
+                            reinterpret_cast<uint2*>(ws->d_ctr + kCtrRecords), s);
+    return e;
+  }));
+  if (ws->auto_size) {
     GP_HIP(hipMemcpyAsync(ws->h_ctr, ws->d_ctr, sizeof(uint32_t) * kCtrCount, hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
     const int64_t R = ws->h_ctr[kCtrRecords], K = ws->h_ctr[kCtrInstances];
     ws->last_records = R;
     ws->last_instances = K;
-    if (R <= ws->rec_cap && K <= ws->inst_cap) break;
-    if (attempt == 2) {
-      set_error("workspace could not be sized");
-      return GP_EOVERFLOW;
+    if (R > ws->rec_cap || K > ws->inst_cap) {
+      st = reserve_lists(ws, std::max<int64_t>(ws->rec_cap, R + R / 4 + 1024),
+                         std::max<int64_t>(ws->inst_cap, K + K / 4 + 4096));
+      if (st == GP_OK) st = reserve_sort(ws, bits);
+      if (st != GP_OK) return st;
     }
-    gp_status st = reserve_lists(ws, std::max<int64_t>(ws->rec_cap, R + R / 4 + 1024),
-                                 std::max<int64_t>(ws->inst_cap, K + K / 4 + 4096));
-    if (st != GP_OK) return st;
   }
-  GP_HIP(timed(ws, GP_STAGE_SCAN, s, [&] { return launch_scan_bins(*ws, s); }));
-  GP_HIP(timed(ws, GP_STAGE_SCATTER, s, [&] { return launch_scatter(rc, *ws, s); }));
-  GP_HIP(timed(ws, GP_STAGE_BIN_SORT, s, [&] { return launch_bin_sort(rc, *ws, d, s); }));
+  rc.rec_cap = (uint32_t)ws->rec_cap;
+  rc.inst_cap = (uint32_t)ws->inst_cap;
+  const uint32_t sentinel = (uint32_t)((1ll << bits) - 1);
+  const uint32_t* d_count = ws->d_ctr + kCtrInstances;
+  GP_HIP(timed(ws, GP_STAGE_EMIT, s, [&] { return launch_pre_emit(rc, *ws, d, sentinel, s); }));
+  GP_HIP(timed(ws, GP_STAGE_SORT, s, [&] {
+    const int64_t n_sort = ws->auto_size ? std::min<int64_t>(ws->last_instances, ws->inst_cap) : ws->inst_cap;
+    hipError_t e = launch_radix_sort(ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, d_count,
+                                     std::max<int64_t>(n_sort, 1), bits, ws->d_hist,
+                                     reinterpret_cast<uint32_t*>(ws->d_scan_part), s, &ws->d_list_key, &ws->d_list);
+    if (e == hipSuccess)
+      e = launch_bin_ranges(ws->d_hdr, ws->d_list_key, d_count, ws->inst_cap, ws->d_bin_lo, ws->d_bin_hi, s);
+    return e;
+  }));
   GP_HIP(timed(ws, GP_STAGE_RASTER_FWD, s, [&] { return launch_raster_fwd(rc, *ws, d, s); }));
   ws->fwd_rc = rc;
   return GP_OK;
@@ -352,9 +390,10 @@ gp_status workspace_new(Workspace** out, int64_t max_records, int64_t max_instan
 void workspace_free(Workspace* ws) {
   if (!ws) return;
   (void)wait_ws(ws);
-  void* dev[] = {ws->d_slices, ws->d_groups, ws->d_hdr, ws->d_work, ws->d_ctr, ws->d_bin_count, ws->d_bin_start,
-                 ws->d_rec_pay, ws->d_rec_meta, ws->d_g_rbase, ws->d_g_nrec, ws->d_inst_rank, ws->d_sort_key,
-                 ws->d_list, ws->d_moments};
+  void* dev[] = {ws->d_slices, ws->d_groups, ws->d_hdr, ws->d_work, ws->d_ctr, ws->d_bin_lo, ws->d_bin_hi,
+                 ws->d_rec_pay, ws->d_rec_meta, ws->d_g_rbase, ws->d_g_nrec, ws->d_g_ninst, ws->d_g_krange,
+                 ws->d_wave_cnt, ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, ws->d_hist,
+                 ws->d_scan_part, ws->d_moments};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {ws->h_slices, ws->h_groups, ws->h_hdr, ws->h_ctr};
@@ -523,6 +562,74 @@ gp_status gp_workspace_timings(gp_workspace* w, double* ms, int64_t* counts, int
   return GP_OK;
 }
 
+gp_status gp_densify_default_cfg(gp_densify_cfg* c) {
+  if (!c) return einval("densify_default_cfg: NULL");
+  c->grad_threshold = 5e-5f;
+  c->min_alpha = 0.02f;
+  c->max_radius = 256.0f;
+  c->split_scale = 2.0f;
+  c->split_factor = 1.6f;
+  c->flags = 0u;
+  return GP_OK;
+}
+
+gp_status gp_workspace_set_densify_stats(gp_workspace* w, float* grad_norm, int32_t* count, float* max_radius,
+                                         int64_t n) {
+  if (!w) return einval("set_densify_stats: NULL workspace");
+  const bool off = !grad_norm && !count && !max_radius;
+  if (!off && (!grad_norm || !count || !max_radius || n < 0)) return einval("set_densify_stats: give all or none");
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  ws->st_grad_norm = off ? nullptr : grad_norm;
+  ws->st_count = off ? nullptr : count;
+  ws->st_max_radius = off ? nullptr : max_radius;
+  ws->st_n = off ? 0 : n;
+  return GP_OK;
+}
+
+gp_status gp_densify_prune(const float* p, const float* m, const float* v, int64_t n, int64_t stride,
+                           const float* grad_norm, const int32_t* count, const float* max_radius, const float* noise,
+                           const gp_densify_cfg* cfg, float* p_out, float* m_out, float* v_out, int64_t stride_out,
+                           int64_t* n_out, void* stream) {
+  if (!cfg || !n_out) return einval("densify: NULL");
+  if (n < 0 || stride < n || n >= (1ll << 31)) return einval("densify: need 0 <= n <= stride");
+  if (n > 0 && (!p || !m || !v || !grad_norm || !count || !max_radius || !noise || !p_out || !m_out || !v_out))
+    return einval("densify: NULL array");
+  if (!(cfg->split_factor > 0.f) || cfg->flags != 0u) return einval("densify: bad configuration");
+  *n_out = 0;
+  if (n == 0) return GP_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t *action = nullptr, *outs = nullptr, *part = nullptr, *total = nullptr;
+  const int64_t nparts = scan_parts_needed(n);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&action), sizeof(uint32_t) * n);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&outs), sizeof(uint32_t) * n);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&part), sizeof(uint32_t) * nparts);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&total), sizeof(uint32_t));
+  uint32_t h_total = 0;
+  if (e == hipSuccess)
+    e = launch_densify(p, m, v, n, stride, grad_norm, count, max_radius, noise, *cfg, action, outs, part, total,
+                       p_out, m_out, v_out, stride_out, false, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h_total, total, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  gp_status st = GP_OK;
+  if (e == hipSuccess) {
+    *n_out = h_total;
+    if ((int64_t)h_total > stride_out) {
+      set_error("densify: output stride too small");
+      st = GP_EOVERFLOW;
+    } else {
+      e = launch_densify(p, m, v, n, stride, grad_norm, count, max_radius, noise, *cfg, action, outs, part, total,
+                         p_out, m_out, v_out, stride_out, true, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+  }
+  if (e != hipSuccess) st = hip_fail(e, "densify");
+  (void)hipFree(action);
+  (void)hipFree(outs);
+  (void)hipFree(part);
+  (void)hipFree(total);
+  return st;
+}
+
 gp_status gp_debug_export_bins(gp_workspace* w, uint64_t* h_keys, int64_t keys_cap, int64_t* n_keys,
                                int64_t* h_ranges, int64_t ranges_cap) {
   if (!w || !n_keys) return einval("export_bins: NULL");
@@ -533,23 +640,29 @@ gp_status gp_debug_export_bins(gp_workspace* w, uint64_t* h_keys, int64_t keys_c
   }
   GP_HIP(wait_ws(ws));
   const int64_t nb = ws->fwd_nbins;
-  std::vector<uint32_t> start((size_t)nb + 1);
-  GP_HIP(hipMemcpy(start.data(), ws->d_bin_start, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToHost));
-  const int64_t K = start[nb];
+  std::vector<uint32_t> lo((size_t)nb), hi((size_t)nb);
+  if (nb > 0) {
+    GP_HIP(hipMemcpy(lo.data(), ws->d_bin_lo, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost));
+    GP_HIP(hipMemcpy(hi.data(), ws->d_bin_hi, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost));
+  }
+  GP_HIP(hipMemcpy(ws->h_ctr, ws->d_ctr, sizeof(uint32_t) * kCtrCount, hipMemcpyDeviceToHost));
+  int64_t K = 0;
+  for (int64_t b = 0; b < nb; ++b) K += hi[b] - lo[b];
   *n_keys = K;
   if (keys_cap < K || ranges_cap < 2 * nb || (K > 0 && !h_keys) || (nb > 0 && !h_ranges))
     return einval("export_bins: output too small");
-  std::vector<uint32_t> list((size_t)K);
-  std::vector<RecPay> pay;
-  if (K > 0) GP_HIP(hipMemcpy(list.data(), ws->d_list, sizeof(uint32_t) * K, hipMemcpyDeviceToHost));
-  GP_HIP(hipMemcpy(ws->h_ctr, ws->d_ctr, sizeof(uint32_t) * kCtrCount, hipMemcpyDeviceToHost));
+  const int64_t n_list = std::min<int64_t>(ws->h_ctr[kCtrInstances], ws->inst_cap);
   const int64_t R = std::min<int64_t>(ws->h_ctr[kCtrRecords], ws->rec_cap);
-  pay.resize((size_t)std::max<int64_t>(R, 1));
+  std::vector<uint32_t> list((size_t)std::max<int64_t>(n_list, 1));
+  std::vector<RecPay> pay((size_t)std::max<int64_t>(R, 1));
+  if (n_list > 0) GP_HIP(hipMemcpy(list.data(), ws->d_list, sizeof(uint32_t) * n_list, hipMemcpyDeviceToHost));
   if (R > 0) GP_HIP(hipMemcpy(pay.data(), ws->d_rec_pay, sizeof(RecPay) * R, hipMemcpyDeviceToHost));
+  // lists are contiguous and in bin order; report them packed, bin by bin
+  int64_t o = 0;
   for (int64_t b = 0; b < nb; ++b) {
-    h_ranges[2 * b] = start[b];
-    h_ranges[2 * b + 1] = start[b + 1];
-    for (uint32_t i = start[b]; i < start[b + 1]; ++i) h_keys[i] = ((uint64_t)b << 32) | pay[list[i]].gid;
+    h_ranges[2 * b] = o;
+    for (uint32_t i = lo[b]; i < hi[b]; ++i) h_keys[o++] = ((uint64_t)b << 32) | pay[list[i]].gid;
+    h_ranges[2 * b + 1] = o;
   }
   return GP_OK;
 }

@@ -2,6 +2,8 @@
 // Device-side layouts, the workspace object and the kernel launch wrappers.
 #pragma once
 
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -11,6 +13,23 @@
 #include "../../include/gaussianpile.h"
 
 namespace gp {
+
+// Attribute row r (0..7: l_x, l_y, l_z, q_w, q_x, q_y, q_z, alpha) of Gaussian
+// j, converted to float32.
+template <int DT>
+__device__ __forceinline__ float load_attr(const void* base, int r, int64_t stride, int64_t j) {
+  const int64_t i = r * stride + j;
+  if constexpr (DT == GP_F32) {
+    return static_cast<const float*>(base)[i];
+  } else if constexpr (DT == GP_BF16) {
+    return __bfloat162float(static_cast<const __hip_bfloat16*>(base)[i]);
+  } else if constexpr (DT == GP_F16) {
+    return __half2float(static_cast<const __half*>(base)[i]);
+  } else {   // GP_Q16
+    if (r >= 3 && r <= 6) return (float)static_cast<const int16_t*>(base)[i] / 32767.0f;
+    return __half2float(static_cast<const __half*>(base)[i]);
+  }
+}
 
 constexpr int kTile = 16;            // tile edge in pixels (16 x 16 tiles)
 constexpr int kTilePix = kTile * kTile;
@@ -32,6 +51,8 @@ struct SliceDev {
 // workspace capacity.
 struct BatchHdr {
   int32_t n_groups, n_slices, n_bins, total_gauss;
+  int32_t n_waves;     // total_gauss / 64
+  int32_t pad[3];
 };
 
 // Work counters handed out by atomics (reset at the start of every forward).
@@ -62,10 +83,11 @@ struct RenderConst {
 // workspace capacity when the sequence is captured for replay.
 struct LaunchDims {
   int64_t gauss;   // flattened Gaussians to cover (multiple of 64)
-  int64_t bins;    // bins to cover
+  int64_t bins;    // bins to cover (also fixes the sort's key width)
 };
 
 // Counters written by the preprocess.
+// (records and instances are adjacent: the wavefront scan writes both as one uint2)
 enum { kCtrRecords = 0, kCtrInstances = 1, kCtrOverflow = 2, kCtrCount = 4 };
 
 // Record payload in pixel space, 32 bytes, gathered by the rasterisers:
@@ -115,16 +137,25 @@ struct Workspace {
   BatchHdr* d_hdr = nullptr;
   uint32_t* d_work = nullptr;       // kWorkCount work counters
   uint32_t* d_ctr = nullptr;        // kCtrCount counters
-  uint32_t* d_bin_count = nullptr;  // [bin_cap]
-  uint32_t* d_bin_start = nullptr;  // [bin_cap + 1]
+  uint32_t* d_bin_lo = nullptr;     // [bin_cap] list range [lo, hi) of each bin
+  uint32_t* d_bin_hi = nullptr;     // [bin_cap]
   RecPay* d_rec_pay = nullptr;      // [rec_cap]
   RecMeta* d_rec_meta = nullptr;    // [rec_cap]
   uint32_t* d_g_rbase = nullptr;    // [gauss_cap]
   uint32_t* d_g_nrec = nullptr;     // [gauss_cap]
-  uint32_t* d_inst_rank = nullptr;  // [inst_cap] rank of an instance slot in its bin
-  uint64_t* d_sort_key = nullptr;   // [inst_cap] (Gaussian index << 32 | record) by bin
-  uint32_t* d_list = nullptr;       // [inst_cap] record ids in list order
+  uint32_t* d_g_ninst = nullptr;    // [gauss_cap]
+  uint32_t* d_g_krange = nullptr;   // [gauss_cap] kept slices kb | ke << 16
+  uint2* d_wave_cnt = nullptr;      // [wave_cap] per-wavefront counts, then bases
+  uint32_t* d_inst_key = nullptr;   // [inst_cap] bin of each instance slot
+  uint32_t* d_inst_val = nullptr;   // [inst_cap] record of each instance slot
+  uint32_t* d_key2 = nullptr;       // [inst_cap] sort ping-pong
+  uint32_t* d_val2 = nullptr;       // [inst_cap]
+  uint32_t* d_list = nullptr;       // record ids in list order (one of the above)
+  uint32_t* d_list_key = nullptr;   // their bins
+  uint32_t* d_hist = nullptr;       // [hist_cap] radix digit counts
+  uint2* d_scan_part = nullptr;     // [part_cap] scan partials
   float4* d_moments = nullptr;      // [2 * inst_cap] backward moments per instance slot
+  int64_t hist_cap = 0, part_cap = 0, wave_cap = 0;
 
   // pinned staging for uploads / readbacks
   SliceDev* h_slices = nullptr;
@@ -143,6 +174,12 @@ struct Workspace {
   uint64_t fwd_slice_hash = 0;
   RenderConst fwd_rc{};
   int64_t last_records = 0, last_instances = 0;
+
+  // optional densification statistics, accumulated by the backward
+  float* st_grad_norm = nullptr;
+  int32_t* st_count = nullptr;
+  float* st_max_radius = nullptr;
+  int64_t st_n = 0;
 
   // optional per-stage timing (events recorded around each stage)
   bool timing = false;
@@ -175,6 +212,7 @@ struct BatchPlan {
 hipError_t wait_ws(Workspace* ws);
 gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups, int64_t n_bins, int64_t n_gauss);
 gp_status reserve_lists(Workspace* ws, int64_t rec_cap, int64_t inst_cap);
+gp_status reserve_sort(Workspace* ws, int bits);
 gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_slice* hs, int ns, float* out_base,
                       float* const* outs, BatchPlan* plan);
 gp_status upload_batch(Workspace* ws, const BatchPlan& p, hipStream_t s);
@@ -190,11 +228,27 @@ void workspace_free(Workspace* ws);
 // k_preprocess.hip
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDims& d, hipStream_t s);
-hipError_t launch_preprocess(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s);
-// k_bins.hip
-hipError_t launch_scan_bins(const Workspace& ws, hipStream_t s);
-hipError_t launch_scatter(const RenderConst& rc, const Workspace& ws, hipStream_t s);
-hipError_t launch_bin_sort(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s);
+hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s);
+hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, uint32_t sentinel_bin,
+                           hipStream_t s);
+// k_sort.hip
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, const int32_t* d_n, int64_t max_n, uint32_t* part,
+                           uint32_t* total, hipStream_t s);
+hipError_t launch_scan_u32x2(const uint2* in, uint2* out, const int32_t* d_n, int64_t max_n, uint2* part,
+                             uint2* total, hipStream_t s);
+int64_t scan_parts_needed(int64_t max_n);
+int radix_passes(int bits);
+int64_t radix_hist_entries(int bits, int64_t cap);
+hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* d_count,
+                             int64_t cap, int bits, uint32_t* hist, uint32_t* scan_part, hipStream_t s,
+                             uint32_t** k_out, uint32_t** v_out);
+hipError_t launch_bin_ranges(const BatchHdr* hdr, const uint32_t* key, const uint32_t* d_count, int64_t cap,
+                             uint32_t* lo, uint32_t* hi, hipStream_t s);
+inline int key_bits(int64_t n_bins) {
+  int b = 0;
+  while (b < 31 && ((int64_t)1 << b) <= n_bins) ++b;
+  return b;   // 2^b > n_bins, so n_bins itself (the overflow sentinel) fits
+}
 // k_raster.hip
 hipError_t launch_raster_fwd(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s);
 hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const float* grad_out,
@@ -202,6 +256,12 @@ hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const f
 // k_backward.hip
 hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, float* grad,
                                  int64_t grad_stride, const LaunchDims& d, hipStream_t s);
+// k_densify.hip
+hipError_t launch_densify(const float* p, const float* m, const float* v, int64_t n, int64_t stride,
+                          const float* grad_norm, const int32_t* count, const float* max_radius, const float* noise,
+                          const gp_densify_cfg& cfg, uint32_t* action, uint32_t* outs, uint32_t* scan_part,
+                          uint32_t* total, float* p_out, float* m_out, float* v_out, int64_t stride_out,
+                          bool emit, hipStream_t s);
 // k_optim.hip
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, int64_t stride,
                        const gp_adam_cfg& c, hipStream_t s);

@@ -43,14 +43,29 @@ __global__ void k_pack_volume(const float* __restrict__ means, const float* __re
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int r = 0; r < 3; ++r) out_means[r * dst_stride + i] = means[r * src_stride + i];
-  for (int r = 0; r < 8; ++r) {
-    const float v = attrs[r * src_stride + i];
-    if constexpr (DT == GP_BF16) {
-      static_cast<__hip_bfloat16*>(out_attrs)[r * dst_stride + i] = __float2bfloat16(v);
-    } else if constexpr (DT == GP_F16) {
-      static_cast<__half*>(out_attrs)[r * dst_stride + i] = __float2half(v);
-    } else {
-      static_cast<float*>(out_attrs)[r * dst_stride + i] = v;
+  float v[8];
+  for (int r = 0; r < 8; ++r) v[r] = attrs[r * src_stride + i];
+  if constexpr (DT == GP_Q16) {
+#pragma clang fp contract(off)
+    // unit quaternion in int16 fixed point (the binary32 rule in the header)
+    const float n2 = ((v[3] * v[3] + v[4] * v[4]) + v[5] * v[5]) + v[6] * v[6];
+    const float rn = sqrtf(n2);
+    for (int r = 3; r < 7; ++r) {
+      float qn = v[r] / rn;
+      qn = (n2 > 0.0f && isfinite(qn)) ? qn : 0.0f;
+      const float q = fminf(fmaxf(rintf(qn * 32767.0f), -32767.0f), 32767.0f);
+      static_cast<int16_t*>(out_attrs)[r * dst_stride + i] = (int16_t)q;
+    }
+    for (int r : {0, 1, 2, 7}) static_cast<__half*>(out_attrs)[r * dst_stride + i] = __float2half(v[r]);
+  } else {
+    for (int r = 0; r < 8; ++r) {
+      if constexpr (DT == GP_BF16) {
+        static_cast<__hip_bfloat16*>(out_attrs)[r * dst_stride + i] = __float2bfloat16(v[r]);
+      } else if constexpr (DT == GP_F16) {
+        static_cast<__half*>(out_attrs)[r * dst_stride + i] = __float2half(v[r]);
+      } else {
+        static_cast<float*>(out_attrs)[r * dst_stride + i] = v[r];
+      }
     }
   }
 }
@@ -119,9 +134,9 @@ int64_t tiles_of(const gp_request& r) {
   return (int64_t)((r.width + kTile - 1) / kTile) * ((r.height + kTile - 1) / kTile);
 }
 
-// Upper estimate of a request's tile-list entries from the volume's mu_z
-// histogram (Gaussians inside the widest axial window) and its mean footprint.
-double est_instances(const Server* sv, const gp_request& r) {
+// Gaussians of the request's volume whose mu_z lies inside the widest axial
+// window any of them can have on this slice: an upper bound of its records.
+double est_records(const Server* sv, const gp_request& r) {
   const Volume& v = sv->vols[r.volume_id];
   const double D = (double)r.sigma_z * r.sigma_z + (double)v.s_axial_max * v.s_axial_max;
   const double w = std::sqrt((double)sv->cfg.opts.q_cut * D);
@@ -132,10 +147,16 @@ double est_instances(const Server* sv, const gp_request& r) {
     if (u >= nb) return v.zcum[nb];
     return v.zcum[(int)u];
   };
-  const double kept = (double)(cum(r.z + w + 1.0) - cum(r.z - w));
+  return (double)(cum(r.z + w + 1.0) - cum(r.z - w));
+}
+
+// Estimate of a request's tile-list entries: its record bound times the tiles
+// of a footprint of the volume's mean size (scaled up after each overflow).
+double est_instances(const Server* sv, const gp_request& r, double records) {
+  const Volume& v = sv->vols[r.volume_id];
   const double px = 2.0 * sv->cfg.opts.bbox_sigmas * v.s_lateral_mean / std::min(r.dx, r.dy);
   const double per = (px / kTile + 1.0) * (px / kTile + 1.0);
-  return kept * per * sv->tiles_factor;
+  return records * per * sv->tiles_factor;
 }
 
 void on_batch_done(void* p) {
@@ -231,20 +252,23 @@ void retire(Server* sv, Slot* sl) {
 bool take_batch(Server* sv, Slot* sl) {
   if (sv->queue.empty()) return false;
   int64_t bins = 0, gauss = 0;
-  double inst = 0.0;
+  double inst = 0.0, recs = 0.0;
   std::vector<int32_t> vols_in;
   while (!sv->queue.empty() && (int)sl->reqs.size() < sv->cfg.max_batch) {
     const Request& r = sv->queue.front();
     if (r.solo && !sl->reqs.empty()) break;
     const bool new_vol = std::find(vols_in.begin(), vols_in.end(), r.r.volume_id) == vols_in.end();
     const int64_t add_g = new_vol ? (sv->vols[r.r.volume_id].n + 63) / 64 * 64 : 0;
-    const double add_i = est_instances(sv, r.r);
+    const double add_r = est_records(sv, r.r);
+    const double add_i = est_instances(sv, r.r, add_r);
     if (!sl->reqs.empty() && (bins + tiles_of(r.r) > sv->cfg.max_bins || gauss + add_g > sv->cfg.max_gaussians ||
-                              inst + add_i > (double)sv->cfg.max_instances))
+                              inst + add_i > (double)sv->cfg.max_instances ||
+                              recs + add_r > (double)sv->cfg.max_records))
       break;
     bins += tiles_of(r.r);
     gauss += add_g;
     inst += add_i;
+    recs += add_r;
     if (new_vol) vols_in.push_back(r.r.volume_id);
     sl->reqs.push_back(r);
     const bool solo = r.solo;
@@ -344,7 +368,7 @@ gp_status gp_server_default_cfg(gp_server_cfg* c) {
   c->max_bins = 64 * 4096;
   c->max_batch = 64;
   c->slots = 3;
-  c->attr_dtype = GP_BF16;
+  c->attr_dtype = GP_Q16;
   c->use_graphs = 1;
   c->device = 0;
   gp_default_opts(&c->opts);
@@ -361,7 +385,8 @@ gp_status gp_server_create(gp_server** out, const gp_server_cfg* cfg) {
   if (st != GP_OK) return st;
   if (cfg->slots < 1 || cfg->slots > 4 || cfg->max_batch < 1 || cfg->max_bins < 1 || cfg->max_gaussians < 64 ||
       cfg->max_records < 1 || cfg->max_instances < 1 || cfg->hbm_budget_bytes < 0 ||
-      (cfg->attr_dtype != GP_F32 && cfg->attr_dtype != GP_BF16 && cfg->attr_dtype != GP_F16)) {
+      (cfg->attr_dtype != GP_F32 && cfg->attr_dtype != GP_BF16 && cfg->attr_dtype != GP_F16 &&
+       cfg->attr_dtype != GP_Q16)) {
     set_error("server_create: bad configuration");
     return GP_EINVAL;
   }
@@ -386,6 +411,7 @@ gp_status gp_server_create(gp_server** out, const gp_server_cfg* cfg) {
     if (st == GP_OK) sl->ws->overflow_per_forward = true;
     // descriptor buffers sized for the largest batch so captured graphs stay valid
     if (st == GP_OK) st = reserve_small(sl->ws, cfg->max_batch, cfg->max_batch, cfg->max_bins, sv->cap_dims.gauss);
+    if (st == GP_OK) st = reserve_sort(sl->ws, key_bits(cfg->max_bins));
     hipError_t e = st == GP_OK ? hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) : hipSuccess;
     if (st != GP_OK || e != hipSuccess) {
       free_server(sv);
@@ -445,6 +471,7 @@ gp_status gp_server_add_volume(gp_server* s, const gp_gaussians* g, int32_t* vol
   switch (sv->cfg.attr_dtype) {
     case GP_BF16: k_pack_volume<GP_BF16><<<blocks, 256>>>(m, a, g->stride, g->n, v.means, v.attrs, v.stride); break;
     case GP_F16: k_pack_volume<GP_F16><<<blocks, 256>>>(m, a, g->stride, g->n, v.means, v.attrs, v.stride); break;
+    case GP_Q16: k_pack_volume<GP_Q16><<<blocks, 256>>>(m, a, g->stride, g->n, v.means, v.attrs, v.stride); break;
     default: k_pack_volume<GP_F32><<<blocks, 256>>>(m, a, g->stride, g->n, v.means, v.attrs, v.stride); break;
   }
   hipError_t e = hipGetLastError();

@@ -25,16 +25,6 @@
 namespace gp {
 namespace {
 
-template <int DT>
-__device__ __forceinline__ float load_attr(const void* base, int64_t idx) {
-  if constexpr (DT == GP_F32) {
-    return static_cast<const float*>(base)[idx];
-  } else if constexpr (DT == GP_BF16) {
-    return __bfloat162float(static_cast<const __hip_bfloat16*>(base)[idx]);
-  } else {
-    return __half2float(static_cast<const __half*>(base)[idx]);
-  }
-}
 
 struct BwdPreArgs {
   RenderConst rc;
@@ -48,6 +38,10 @@ struct BwdPreArgs {
   const float4* moments;
   float* grad;
   int64_t grad_stride;
+  float* st_grad_norm;      // optional densification statistics
+  int32_t* st_count;
+  float* st_max_radius;
+  int64_t st_n;
 };
 
 template <int DT>
@@ -67,12 +61,14 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
   p[1] = G.means[G.stride + j];
   p[2] = G.means[2 * G.stride + j];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) p[3 + r] = load_attr<DT>(G.attrs, r * G.stride + j);
+  for (int r = 0; r < 8; ++r) p[3 + r] = load_attr<DT>(G.attrs, r, G.stride, j);
   SpecCov c;
   spec_cov(p[3], p[4], p[5], p[6], p[7], p[8], p[9], a.rc.scale_mod, c);
   const float alpha = p[10];
 
   float gmx = 0.f, gmy = 0.f, gmz = 0.f, galpha = 0.f;
+  float st_norm = 0.f, st_rad = 0.f;
+  int32_t st_cnt = 0;
   float gxx = 0.f, gxy = 0.f, gxz = 0.f, gyy = 0.f, gyz = 0.f, gzz = 0.f;
 
   for (uint32_t r = rbase; r < rbase + nrec && r < a.rc.rec_cap; ++r) {
@@ -132,6 +128,10 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
     gzz += u * u * gA + u * v * gB + v * v * gC - (u * g_u + v * g_v) * invD - g_q * m * m * invD * invD;
     gmx += g_m2x;
     gmy += g_m2y;
+    // densification statistics in pixel units
+    st_norm += sqrtf((g_m2x * ddx) * (g_m2x * ddx) + (g_m2y * ddy) * (g_m2y * ddy));
+    st_rad = fmaxf(st_rad, a.rc.bbox * fmaxf(sqrtf(A) / ddx, sqrtf(C) / ddy));
+    st_cnt += 1;
     gmz += -(u * g_m2x + v * g_m2y) + 2.f * g_q * m * invD;
   }
 
@@ -178,6 +178,11 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
   gp[8 * gs] += gq[2];
   gp[9 * gs] += gq[3];
   gp[10 * gs] += galpha;
+  if (a.st_grad_norm && j < a.st_n) {
+    a.st_grad_norm[j] += st_norm;
+    a.st_count[j] += st_cnt;
+    a.st_max_radius[j] = fmaxf(a.st_max_radius[j], st_rad);
+  }
 }
 
 template <int DT>
@@ -192,13 +197,27 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
 hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, float* grad,
                                  int64_t grad_stride, const LaunchDims& d, hipStream_t s) {
   if (d.gauss <= 0) return hipSuccess;
-  BwdPreArgs a{rc, ws.d_hdr, ws.d_groups, ws.d_slices, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase, ws.d_g_nrec,
-               ws.d_moments, grad, grad_stride};
+  BwdPreArgs a{rc,
+               ws.d_hdr,
+               ws.d_groups,
+               ws.d_slices,
+               ws.d_rec_pay,
+               ws.d_rec_meta,
+               ws.d_g_rbase,
+               ws.d_g_nrec,
+               ws.d_moments,
+               grad,
+               grad_stride,
+               ws.st_grad_norm,
+               ws.st_count,
+               ws.st_max_radius,
+               ws.st_n};
   int64_t blocks = (d.gauss + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   switch (rc.attr_dtype) {
     case GP_BF16: k_preprocess_bwd<GP_BF16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
     case GP_F16: k_preprocess_bwd<GP_F16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    case GP_Q16: k_preprocess_bwd<GP_Q16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
     default: k_preprocess_bwd<GP_F32><<<(unsigned)blocks, 256, 0, s>>>(a); break;
   }
   return hipGetLastError();

@@ -8,11 +8,14 @@
 // of slices with non-decreasing z and one sigma_z, the kept slices of a
 // Gaussian are a contiguous range (the binary32 axial test is monotone in |m|
 // on either side of mu_z) found by binary search with the exact test, so the
-// loop visits only those.  A first pass counts the Gaussian's visible records
-// and footprint tiles; one atomic per wavefront (an inclusive scan across the
-// lanes) then reserves contiguous record and instance slots, and a second
-// pass writes them.  Every footprint tile takes a rank in its bin with an
-// atomic increment; the bin scan turns (bin, rank) into a list position.
+// loop visits only those.
+//
+// Two kernels and a scan, no atomics: k_pre_count counts each Gaussian's
+// visible records and footprint tiles (and sums them per wavefront); an
+// exclusive scan of the wavefront sums gives every Gaussian contiguous record
+// and instance slots in Gaussian order; k_pre_emit writes the records and one
+// (bin, record) pair per footprint tile.  Slots are therefore identical from
+// run to run.
 #include "gp_internal.h"
 #include "gp_spec.h"
 
@@ -24,45 +27,16 @@ namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
 
-template <int DT>
-__device__ __forceinline__ float load_attr(const void* base, int64_t idx) {
-  if constexpr (DT == GP_F32) {
-    return static_cast<const float*>(base)[idx];
-  } else if constexpr (DT == GP_BF16) {
-    return __bfloat162float(static_cast<const __hip_bfloat16*>(base)[idx]);
-  } else {
-    return __half2float(static_cast<const __half*>(base)[idx]);
-  }
-}
-
-// Reserves n consecutive slots for every lane of a full wavefront; returns the
-// lane's first slot.  All 64 lanes must call it together.
-__device__ __forceinline__ uint32_t wave_reserve(uint32_t* ctr, uint32_t n) {
-  const int lane = __lane_id();
-  uint32_t incl = n;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t t = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += t;
-  }
-  const uint32_t total = __shfl(incl, 63, 64);
-  uint32_t base = 0;
-  if (total != 0) {
-    if (lane == 63) base = atomicAdd(ctr, total);
-    base = __shfl(base, 63, 64);
-  }
-  return base + incl - n;
-}
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = value;
 }
 
-// Zeroes the per-forward counters, the work queues and the bin counts of the
+// Zeroes the per-forward counters, the work queues and the bin ranges of the
 // batch described by the device header.
 __global__ void k_reset(const BatchHdr* __restrict__ hdr, uint32_t* __restrict__ ctr, uint32_t* __restrict__ work,
-                        uint32_t* __restrict__ bin_count, int clear_overflow) {
+                        uint32_t* __restrict__ bin_lo, uint32_t* __restrict__ bin_hi, int clear_overflow) {
   const int64_t n = hdr->n_bins;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -72,7 +46,10 @@ __global__ void k_reset(const BatchHdr* __restrict__ hdr, uint32_t* __restrict__
     if (clear_overflow) ctr[kCtrOverflow] = 0u;
     for (int i = 0; i < kWorkCount; ++i) work[i] = 0u;
   }
-  for (int64_t i = t; i < n; i += stride) bin_count[i] = 0u;
+  for (int64_t i = t; i < n; i += stride) {
+    bin_lo[i] = 0u;
+    bin_hi[i] = 0u;
+  }
 }
 
 struct PreArgs {
@@ -81,12 +58,16 @@ struct PreArgs {
   const GroupDev* groups;
   const SliceDev* slices;
   uint32_t* ctr;
-  uint32_t* bin_count;
   RecPay* rec_pay;
   RecMeta* rec_meta;
   uint32_t* g_rbase;
   uint32_t* g_nrec;
-  uint32_t* inst_rank;
+  uint32_t* g_ninst;
+  uint32_t* g_krange;
+  uint2* wave_cnt;      // per wavefront (records, instances); scanned in place
+  uint32_t* inst_key;   // bin of every instance slot
+  uint32_t* inst_val;   // record of every instance slot
+  uint32_t sentinel_bin;
 };
 
 __device__ __forceinline__ bool kept_on(const PreArgs& a, float muz, float szz, int k) {
@@ -124,94 +105,127 @@ __device__ __forceinline__ void kept_range(const PreArgs& a, const GroupDev& G, 
   *ke = lo + 1;
 }
 
-// One flattened Gaussian t (all 64 lanes of a wavefront call this together).
+struct Loaded {
+  GroupDev G;
+  int j;
+  float p[11];
+  SpecCov c;
+  bool ok;
+};
+
 template <int DT>
-__device__ __forceinline__ void preprocess_one(const PreArgs& a, int n_groups, int t) {
+__device__ __forceinline__ void load_gaussian(const PreArgs& a, int n_groups, int t, Loaded& L) {
   const int wave0 = t & ~63;
-  // group of this wavefront (groups start at multiples of 64)
-  int g = 0;
+  int g = 0;   // groups start at multiples of 64
   for (int jg = 1; jg < n_groups; ++jg)
     if (a.groups[jg].gbase <= wave0) g = jg;
-  const GroupDev G = a.groups[g];
-  const int j = t - G.gbase;
-  const bool in_range = j < G.n;
-
-  float p[11];
+  L.G = a.groups[g];
+  L.j = t - L.G.gbase;
+  const bool in_range = L.j < L.G.n;
   if (in_range) {
-    p[0] = G.means[j];
-    p[1] = G.means[G.stride + j];
-    p[2] = G.means[2 * G.stride + j];
+    L.p[0] = L.G.means[L.j];
+    L.p[1] = L.G.means[L.G.stride + L.j];
+    L.p[2] = L.G.means[2 * L.G.stride + L.j];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) p[3 + r] = load_attr<DT>(G.attrs, r * G.stride + j);
+    for (int r = 0; r < 8; ++r) L.p[3 + r] = load_attr<DT>(L.G.attrs, r, L.G.stride, L.j);
   } else {
 #pragma unroll
-    for (int r = 0; r < 11; ++r) p[r] = 0.0f;
+    for (int r = 0; r < 11; ++r) L.p[r] = 0.0f;
   }
   bool finite = in_range;
 #pragma unroll
-  for (int r = 0; r < 11; ++r) finite = finite && isfinite(p[r]);
+  for (int r = 0; r < 11; ++r) finite = finite && isfinite(L.p[r]);
+  spec_cov(L.p[3], L.p[4], L.p[5], L.p[6], L.p[7], L.p[8], L.p[9], a.rc.scale_mod, L.c);
+  L.ok = finite && (L.c.n2 > 0.0f);
+}
 
-  SpecCov c;
-  spec_cov(p[3], p[4], p[5], p[6], p[7], p[8], p[9], a.rc.scale_mod, c);
-  const bool ok = finite && (c.n2 > 0.0f);
+// Footprint of (Gaussian, slice k); false if the pair is culled or off-grid.
+__device__ __forceinline__ bool footprint(const PreArgs& a, const Loaded& L, int k, SpecAxial& ax, SpecRect& rect) {
+  const SliceDev& sl = a.slices[k];
   const bool exact = (a.rc.flags & GP_FLAG_EXACT) != 0;
-
-  // candidate slices
-  int kb = G.k0, ke = G.k1;
-  if (!ok) {
-    ke = kb;
-  } else if (!exact && (G.flags & kGroupSortedZ)) {
-    kept_range(a, G, p[2], c.szz, &kb, &ke);
+  ax = spec_axial(L.p[2], L.c.szz, sl.z, sl.sigma_z);
+  if (!exact && !(ax.q <= a.rc.q_cut)) return false;
+  const bool vis = spec_rect(L.c, L.p[0], L.p[1], ax, sl.x0, sl.y0, sl.dx, sl.dy, sl.ntx, sl.nty, a.rc.bbox, rect);
+  if (exact) {
+    rect.tx0 = 0; rect.tx1 = sl.ntx - 1; rect.ty0 = 0; rect.ty1 = sl.nty - 1;
+    return true;
   }
+  return vis;
+}
 
-  // pass 1: count visible records and their footprint tiles
+template <int DT>
+__device__ __forceinline__ void count_one(const PreArgs& a, int n_groups, int t) {
+  Loaded L;
+  load_gaussian<DT>(a, n_groups, t, L);
+  int kb = L.G.k0, ke = L.G.k1;
+  if (!L.ok) {
+    ke = kb;
+  } else if (!(a.rc.flags & GP_FLAG_EXACT) && (L.G.flags & kGroupSortedZ)) {
+    kept_range(a, L.G, L.p[2], L.c.szz, &kb, &ke);
+  }
   uint32_t nrec = 0, ninst = 0;
   for (int k = kb; k < ke; ++k) {
-    const SliceDev& sl = a.slices[k];
-    const SpecAxial ax = spec_axial(p[2], c.szz, sl.z, sl.sigma_z);
-    if (!exact && !(ax.q <= a.rc.q_cut)) continue;
+    SpecAxial ax;
     SpecRect rect;
-    if (exact) {
-      rect.tx0 = 0; rect.tx1 = sl.ntx - 1; rect.ty0 = 0; rect.ty1 = sl.nty - 1;
-    } else if (!spec_rect(c, p[0], p[1], ax, sl.x0, sl.y0, sl.dx, sl.dy, sl.ntx, sl.nty, a.rc.bbox, rect)) {
-      continue;
-    }
+    if (!footprint(a, L, k, ax, rect)) continue;
     nrec += 1u;
     ninst += (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
   }
-  const uint32_t rbase = wave_reserve(&a.ctr[kCtrRecords], nrec);
-  const uint32_t ibase = wave_reserve(&a.ctr[kCtrInstances], ninst);
+  a.g_nrec[t] = nrec;
+  a.g_ninst[t] = ninst;
+  a.g_krange[t] = (uint32_t)kb | ((uint32_t)ke << 16);
+  // wavefront sums
+  uint32_t sr = nrec, si = ninst;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    sr += __shfl_xor(sr, o, 64);
+    si += __shfl_xor(si, o, 64);
+  }
+  if ((t & 63) == 0) a.wave_cnt[t >> 6] = make_uint2(sr, si);
+}
+
+template <int DT>
+__device__ __forceinline__ void emit_one(const PreArgs& a, int n_groups, int t) {
+  const int lane = t & 63;
+  const uint32_t nrec = a.g_nrec[t], ninst = a.g_ninst[t];
+  // exclusive prefix within the wavefront + the wavefront's base
+  uint32_t pr = nrec, pi = ninst;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t ur = __shfl_up(pr, d, 64), ui = __shfl_up(pi, d, 64);
+    if (lane >= d) { pr += ur; pi += ui; }
+  }
+  const uint2 wb = a.wave_cnt[t >> 6];
+  const uint32_t rbase = wb.x + pr - nrec, ibase = wb.y + pi - ninst;
   const bool fits = (uint64_t)rbase + nrec <= a.rc.rec_cap && (uint64_t)ibase + ninst <= a.rc.inst_cap;
   a.g_rbase[t] = rbase;
-  a.g_nrec[t] = fits ? nrec : 0u;
   if (!fits) {
-    // overflow: the reserved record slots inside the capacity stay unused and
-    // are marked so that no later kernel reads them
+    // overflow: this Gaussian's slots inside the capacity stay unused and are
+    // marked so that no later kernel reads them
     a.ctr[kCtrOverflow] = 1u;
+    a.g_nrec[t] = 0u;
     for (uint32_t r = rbase; r < rbase + nrec && r < a.rc.rec_cap; ++r) a.rec_meta[r].slice = kInvalidSlice;
+    for (uint32_t s = ibase; s < ibase + ninst && s < a.rc.inst_cap; ++s) a.inst_key[s] = a.sentinel_bin;
     return;
   }
   if (nrec == 0) return;
-
-  // pass 2: write the records and rank their tiles in the bins
+  Loaded L;
+  load_gaussian<DT>(a, n_groups, t, L);
+  const uint32_t kr = a.g_krange[t];
+  const int kb = (int)(kr & 0xFFFFu), ke = (int)(kr >> 16);
   uint32_t rid = rbase, slot = ibase;
   for (int k = kb; k < ke; ++k) {
-    const SliceDev sl = a.slices[k];
-    const SpecAxial ax = spec_axial(p[2], c.szz, sl.z, sl.sigma_z);
-    if (!exact && !(ax.q <= a.rc.q_cut)) continue;
+    SpecAxial ax;
     SpecRect rect;
-    const bool vis = spec_rect(c, p[0], p[1], ax, sl.x0, sl.y0, sl.dx, sl.dy, sl.ntx, sl.nty, a.rc.bbox, rect);
-    if (exact) {
-      rect.tx0 = 0; rect.tx1 = sl.ntx - 1; rect.ty0 = 0; rect.ty1 = sl.nty - 1;
-    } else if (!vis) {
-      continue;
-    }
+    if (!footprint(a, L, k, ax, rect)) continue;
+    const SliceDev& sl = a.slices[k];
     // image quantities (binary32; not part of the membership specification)
+    const SpecCov& c = L.c;
     RecPay pay;
     const float B = rect.w * c.sxy - c.a01 * rect.invD;
     const float det = rect.w * c.a22 + c.detS * rect.invD;
     const float rho = expf(-0.5f * ax.q);
-    const float at = p[10] * rho / sqrtf(det);
+    const float at = L.p[10] * rho / sqrtf(det);
     const float inv_det = 1.0f / det;
     const float ca = rect.C * inv_det, cb = -B * inv_det, cc = rect.A * inv_det;
     pay.x = (rect.mx - sl.x0) / sl.dx - 0.5f;
@@ -224,7 +238,7 @@ __device__ __forceinline__ void preprocess_one(const PreArgs& a, int n_groups, i
                       isfinite(pay.b) && isfinite(pay.c);
     if (!good) pay.x = pay.y = pay.a = pay.b = pay.c = pay.w = 0.0f;
     pay.g = exp2f(2.0f * pay.a);
-    pay.gid = (uint32_t)j;
+    pay.gid = (uint32_t)L.j;
     RecMeta meta;
     meta.ibase = slot;
     meta.rx = (uint32_t)rect.tx0 | ((uint32_t)rect.tx1 << 16);
@@ -232,24 +246,32 @@ __device__ __forceinline__ void preprocess_one(const PreArgs& a, int n_groups, i
     meta.slice = (uint32_t)k;
     a.rec_pay[rid] = pay;
     a.rec_meta[rid] = meta;
-    ++rid;
     for (int ty = rect.ty0; ty <= rect.ty1; ++ty) {
       for (int tx = rect.tx0; tx <= rect.tx1; ++tx, ++slot) {
-        const uint32_t bin = (uint32_t)(sl.tile_base + ty * sl.ntx + tx);
-        a.inst_rank[slot] = atomicAdd(&a.bin_count[bin], 1u);
+        a.inst_key[slot] = (uint32_t)(sl.tile_base + ty * sl.ntx + tx);
+        a.inst_val[slot] = rid;
       }
     }
+    ++rid;
   }
 }
 
 // Grid-stride over whole wavefronts of flattened Gaussians, so that a launch
 // sized for the workspace capacity serves any batch (sizes from the header).
 template <int DT>
-__global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
+__global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   const int stride = gridDim.x * 256;
-  for (int t = blockIdx.x * 256 + threadIdx.x; (t & ~63) < total; t += stride) preprocess_one<DT>(a, n_groups, t);
+  for (int t = blockIdx.x * 256 + threadIdx.x; (t & ~63) < total; t += stride) count_one<DT>(a, n_groups, t);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
+  const int total = a.hdr->total_gauss;
+  const int n_groups = a.hdr->n_groups;
+  const int stride = gridDim.x * 256;
+  for (int t = blockIdx.x * 256 + threadIdx.x; (t & ~63) < total; t += stride) emit_one<DT>(a, n_groups, t);
 }
 
 }  // namespace
@@ -264,20 +286,42 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDims& d, hipStream_t s) {
   int64_t blocks = (d.bins + 255) / 256;
   blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
-  k_reset<<<(unsigned)blocks, 256, 0, s>>>(ws.d_hdr, ws.d_ctr, ws.d_work, ws.d_bin_count, clear_overflow ? 1 : 0);
+  k_reset<<<(unsigned)blocks, 256, 0, s>>>(ws.d_hdr, ws.d_ctr, ws.d_work, ws.d_bin_lo, ws.d_bin_hi,
+                                          clear_overflow ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_preprocess(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s) {
-  PreArgs a{rc, ws.d_hdr, ws.d_groups, ws.d_slices, ws.d_ctr, ws.d_bin_count, ws.d_rec_pay, ws.d_rec_meta,
-            ws.d_g_rbase, ws.d_g_nrec, ws.d_inst_rank};
+static PreArgs pre_args(const RenderConst& rc, const Workspace& ws, uint32_t sentinel_bin) {
+  return PreArgs{rc, ws.d_hdr, ws.d_groups, ws.d_slices, ws.d_ctr, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase,
+                 ws.d_g_nrec, ws.d_g_ninst, ws.d_g_krange, ws.d_wave_cnt, ws.d_inst_key, ws.d_inst_val,
+                 sentinel_bin};
+}
+
+hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s) {
   if (d.gauss <= 0) return hipSuccess;
+  const PreArgs a = pre_args(rc, ws, 0u);
   int64_t blocks = (d.gauss + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   switch (rc.attr_dtype) {
-    case GP_BF16: k_preprocess<GP_BF16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    case GP_F16: k_preprocess<GP_F16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    default: k_preprocess<GP_F32><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    case GP_BF16: k_pre_count<GP_BF16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    case GP_F16: k_pre_count<GP_F16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    case GP_Q16: k_pre_count<GP_Q16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    default: k_pre_count<GP_F32><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, uint32_t sentinel_bin,
+                           hipStream_t s) {
+  if (d.gauss <= 0) return hipSuccess;
+  const PreArgs a = pre_args(rc, ws, sentinel_bin);
+  int64_t blocks = (d.gauss + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  switch (rc.attr_dtype) {
+    case GP_BF16: k_pre_emit<GP_BF16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    case GP_F16: k_pre_emit<GP_F16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    case GP_Q16: k_pre_emit<GP_Q16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    default: k_pre_emit<GP_F32><<<(unsigned)blocks, 256, 0, s>>>(a); break;
   }
   return hipGetLastError();
 }

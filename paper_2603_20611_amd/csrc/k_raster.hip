@@ -38,7 +38,8 @@ __device__ __forceinline__ int slice_of_bin(const SliceDev* __restrict__ slices,
 struct FwdArgs {
   const BatchHdr* hdr;
   const SliceDev* slices;
-  const uint32_t* bin_start;
+  const uint32_t* bin_lo;
+  const uint32_t* bin_hi;
   const uint32_t* list;
   const RecPay* rec_pay;
   uint32_t* work;
@@ -80,27 +81,30 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     const int py = ty * kTile + row;
     const float fx0 = (float)px0, fy = (float)py;
 
-    const uint32_t start = a.bin_start[bin], end = a.bin_start[bin + 1];
+    const uint32_t start = a.bin_lo[bin], end = a.bin_hi[bin];
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
 
+    // software pipeline: record ids are loaded two batches ahead and records
+    // one batch ahead, so no gather waits on the id load it depends on
     float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
     if (start + lane < end) {
       const float4* src = reinterpret_cast<const float4*>(a.rec_pay + a.list[start + lane]);
       n0 = src[0];
       n1 = src[1];
     }
+    uint32_t rid_next = (start + 64 + lane < end) ? a.list[start + 64 + lane] : 0u;
     for (uint32_t base = start; base < end; base += 64) {
       buf0[lane] = n0;
       buf1[lane] = n1;
       __syncthreads();
       const int cnt = (int)min(64u, end - base);
-      // prefetch the next batch while this one is consumed
       const uint32_t nb = base + 64;
       if (nb + lane < end) {
-        const float4* src = reinterpret_cast<const float4*>(a.rec_pay + a.list[nb + lane]);
+        const float4* src = reinterpret_cast<const float4*>(a.rec_pay + rid_next);
         n0 = src[0];
         n1 = src[1];
       }
+      if (nb + 64 + lane < end) rid_next = a.list[nb + 64 + lane];
       for (int j = 0; j < cnt; ++j) {
         const float4 r0 = buf0[j];
         const float4 r1 = buf1[j];
@@ -154,7 +158,8 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
 struct BwdArgs {
   const BatchHdr* hdr;
   const SliceDev* slices;
-  const uint32_t* bin_start;
+  const uint32_t* bin_lo;
+  const uint32_t* bin_hi;
   const uint32_t* list;
   const RecPay* rec_pay;
   const RecMeta* rec_meta;
@@ -177,7 +182,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     __syncthreads();   // s_bin is rewritten by the next iteration
     if (ub >= (uint32_t)n_bins) break;
     const int bin = (int)ub;
-    const uint32_t start = a.bin_start[bin], end = a.bin_start[bin + 1];
+    const uint32_t start = a.bin_lo[bin], end = a.bin_hi[bin];
     if (start == end) continue;
     const int k = slice_of_bin(a.slices, n_slices, bin);
     const SliceDev sl = a.slices[k];
@@ -246,7 +251,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
 hipError_t launch_raster_fwd(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s) {
   (void)rc;
   if (d.bins <= 0) return hipSuccess;
-  FwdArgs a{ws.d_hdr, ws.d_slices, ws.d_bin_start, ws.d_list, ws.d_rec_pay, ws.d_work};
+  FwdArgs a{ws.d_hdr, ws.d_slices, ws.d_bin_lo, ws.d_bin_hi, ws.d_list, ws.d_rec_pay, ws.d_work};
   const int64_t blocks = d.bins < 8192 ? d.bins : 8192;
   k_raster_fwd<<<(unsigned)blocks, 64, 0, s>>>(a);
   return hipGetLastError();
@@ -258,8 +263,8 @@ hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const f
   if (d.bins <= 0) return hipSuccess;
   hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterBwd, 0u, 1, s);
   if (e != hipSuccess) return e;
-  BwdArgs a{ws.d_hdr, ws.d_slices, ws.d_bin_start, ws.d_list, ws.d_rec_pay, ws.d_rec_meta, grad_out, ws.d_moments,
-            ws.d_work};
+  BwdArgs a{ws.d_hdr, ws.d_slices, ws.d_bin_lo, ws.d_bin_hi, ws.d_list, ws.d_rec_pay, ws.d_rec_meta, grad_out,
+            ws.d_moments, ws.d_work};
   const int64_t blocks = d.bins < 2048 ? d.bins : 2048;
   k_raster_bwd<<<(unsigned)blocks, 256, 0, s>>>(a);
   return hipGetLastError();

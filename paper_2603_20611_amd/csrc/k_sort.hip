@@ -1,0 +1,278 @@
+// Device-wide exclusive scan and stable LSD radix sort of (bin, record) pairs.
+//
+// The preprocess writes every (record, footprint tile) pair in Gaussian order
+// (slots come from a scan, not from atomics).  A stable sort by bin therefore
+// leaves each tile list in Gaussian-index order, the unique order the oracle
+// also uses, without any per-list sort.  One pass of the sort:
+//   hist:    each block counts the digits of its 4096-element tile (LDS atomics;
+//            counts only, so their order does not matter);
+//   scan:    exclusive scan of the digit-major [digit][block] count matrix;
+//   scatter: each block re-reads its tile in 256-element chunks and gives every
+//            element its stable rank among equal digits: within a wavefront by
+//            matching digits bit by bit with ballots, across the block's four
+//            wavefronts through per-digit counts in LDS.
+// Element counts are read from the device, so launches sized for a capacity
+// serve any batch (graph replay).
+#include "gp_internal.h"
+
+#include <algorithm>
+
+namespace gp {
+namespace {
+
+constexpr int kScanItems = 8;                       // per thread
+constexpr int kScanTile = 256 * kScanItems;         // per block
+
+template <typename T>
+__device__ __forceinline__ T zero_of() { return T{}; }
+
+__device__ __forceinline__ uint2 add2(uint2 a, uint2 b) { return make_uint2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ uint32_t add2(uint32_t a, uint32_t b) { return a + b; }
+__device__ __forceinline__ uint2 sub2(uint2 a, uint2 b) { return make_uint2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ uint32_t sub2(uint32_t a, uint32_t b) { return a - b; }
+
+// Block-wide inclusive scan of one value per thread (256 threads).
+template <typename T>
+__device__ __forceinline__ T block_incl_scan(T v, T* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {
+    T o = t >= d ? sh[t - d] : zero_of<T>();
+    __syncthreads();
+    if (t >= d) sh[t] = add2(sh[t], o);
+    __syncthreads();
+  }
+  T r = sh[t];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_reduce(const T* __restrict__ in, const int32_t* __restrict__ n_ptr,
+                                                     int64_t n_fixed, T* __restrict__ part) {
+  __shared__ T sh[256];
+  const int64_t n = n_ptr ? *n_ptr : n_fixed;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  T s = zero_of<T>();
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t j = base + (int64_t)i * 256 + threadIdx.x;
+    if (j < n) s = add2(s, in[j]);
+  }
+  const T tot = block_incl_scan(s, sh);
+  if (threadIdx.x == 255) part[blockIdx.x] = tot;
+}
+
+// Single-block exclusive scan of the block partials (any count).
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_parts(T* __restrict__ part, int nparts, T* __restrict__ total) {
+  __shared__ T sh[256];
+  __shared__ T chunk_total;
+  T carry = zero_of<T>();
+  for (int b0 = 0; b0 < nparts; b0 += 256) {
+    const int j = b0 + threadIdx.x;
+    const T v = j < nparts ? part[j] : zero_of<T>();
+    const T inc = block_incl_scan(v, sh);
+    if (j < nparts) part[j] = add2(carry, sub2(inc, v));
+    if (threadIdx.x == 255) chunk_total = inc;
+    __syncthreads();
+    carry = add2(carry, chunk_total);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_down(const T* __restrict__ in, const int32_t* __restrict__ n_ptr,
+                                                   int64_t n_fixed, const T* __restrict__ part, T* __restrict__ out) {
+  __shared__ T sh[256];
+  const int64_t n = n_ptr ? *n_ptr : n_fixed;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  T v[kScanItems];
+  T s = zero_of<T>();
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t j = base + i;
+    v[i] = j < n ? in[j] : zero_of<T>();
+    s = add2(s, v[i]);
+  }
+  const T inc = block_incl_scan(s, sh);
+  T run = add2(part[blockIdx.x], sub2(inc, s));   // exclusive prefix of this thread
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t j = base + i;
+    if (j < n) out[j] = run;
+    run = add2(run, v[i]);
+  }
+}
+
+}  // namespace
+
+// Exclusive scan of n values (n on the host, or *d_n on the device when given;
+// the launch covers max_n).  part must hold ceil(max_n / 2048) values.
+template <typename T>
+static hipError_t scan_impl(const T* in, T* out, const int32_t* d_n, int64_t max_n, T* part, T* total,
+                            hipStream_t s) {
+  const int64_t nb = (max_n + kScanTile - 1) / kScanTile;
+  if (nb <= 0) return hipSuccess;
+  k_scan_reduce<T><<<(unsigned)nb, 256, 0, s>>>(in, d_n, max_n, part);
+  k_scan_parts<T><<<1, 256, 0, s>>>(part, (int)nb, total);
+  k_scan_down<T><<<(unsigned)nb, 256, 0, s>>>(in, d_n, max_n, part, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, const int32_t* d_n, int64_t max_n, uint32_t* part,
+                           uint32_t* total, hipStream_t s) {
+  return scan_impl<uint32_t>(in, out, d_n, max_n, part, total, s);
+}
+
+hipError_t launch_scan_u32x2(const uint2* in, uint2* out, const int32_t* d_n, int64_t max_n, uint2* part,
+                             uint2* total, hipStream_t s) {
+  return scan_impl<uint2>(in, out, d_n, max_n, part, total, s);
+}
+
+int64_t scan_parts_needed(int64_t max_n) { return (max_n + kScanTile - 1) / kScanTile + 1; }
+
+// ---------------------------------------------------------------------------
+// Radix sort
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kSortTile = 4096;    // elements per block
+constexpr int kSortChunk = 256;    // elements per block step (one per thread)
+constexpr int kMaxDigitBits = 9;
+constexpr int kMaxDigits = 1 << kMaxDigitBits;
+
+struct RadixArgs {
+  const uint32_t* key_in;
+  const uint32_t* val_in;
+  uint32_t* key_out;
+  uint32_t* val_out;
+  uint32_t* hist;         // [digits][nblocks]
+  const uint32_t* count;  // element count (device)
+  uint32_t cap;           // element capacity
+  int nblocks, shift, bits;
+};
+
+__global__ __launch_bounds__(256) void k_radix_hist(RadixArgs a) {
+  __shared__ uint32_t h[kMaxDigits];
+  const int R = 1 << a.bits;
+  for (int i = threadIdx.x; i < R; i += 256) h[i] = 0u;
+  __syncthreads();
+  const uint32_t n = min(*a.count, a.cap);
+  const uint32_t base = blockIdx.x * kSortTile;
+  for (int i = threadIdx.x; i < kSortTile; i += 256) {
+    const uint32_t j = base + i;
+    if (j < n) atomicAdd(&h[(a.key_in[j] >> a.shift) & (R - 1)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < R; i += 256) a.hist[(size_t)i * a.nblocks + blockIdx.x] = h[i];
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(RadixArgs a) {
+  __shared__ uint32_t run[kMaxDigits];        // running count per digit within the block
+  __shared__ uint32_t wcnt[4][kMaxDigits];    // per-wavefront digit counts of the chunk
+  const int R = 1 << a.bits;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t n = min(*a.count, a.cap);
+  const uint32_t base = blockIdx.x * kSortTile;
+  if (base >= n) return;   // whole block past the end (uniform)
+  for (int i = threadIdx.x; i < R; i += 256) run[i] = a.hist[(size_t)i * a.nblocks + blockIdx.x];
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int c = 0; c < kSortTile; c += kSortChunk) {
+    for (int i = threadIdx.x; i < R; i += 256) wcnt[0][i] = wcnt[1][i] = wcnt[2][i] = wcnt[3][i] = 0u;
+    __syncthreads();
+    const uint32_t j = base + c + threadIdx.x;
+    const bool valid = j < n;
+    uint32_t key = 0, val = 0, digit = 0;
+    if (valid) {
+      key = a.key_in[j];
+      val = a.val_in[j];
+      digit = (key >> a.shift) & (R - 1);
+    }
+    // lanes of this wavefront holding the same digit
+    uint64_t same = __ballot(valid);
+    for (int b = 0; b < a.bits; ++b) {
+      const uint64_t bb = __ballot((digit >> b) & 1u);
+      same &= ((digit >> b) & 1u) ? bb : ~bb;
+    }
+    const uint32_t rank_w = (uint32_t)__popcll(same & lt_mask);
+    if (valid && rank_w == 0) wcnt[wave][digit] = (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t before = 0;
+      for (int w = 0; w < wave; ++w) before += wcnt[w][digit];
+      const uint32_t dst = run[digit] + before + rank_w;
+      a.key_out[dst] = key;
+      a.val_out[dst] = val;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < R; i += 256) run[i] += wcnt[0][i] + wcnt[1][i] + wcnt[2][i] + wcnt[3][i];
+    __syncthreads();
+  }
+}
+
+// Bin ranges from the sorted keys: [lo, hi) of every non-empty bin (the reset
+// kernel zeroes both arrays first, so empty bins read as empty).
+__global__ __launch_bounds__(256) void k_bin_ranges(const BatchHdr* __restrict__ hdr, const uint32_t* __restrict__ key,
+                                                    const uint32_t* __restrict__ count, uint32_t cap,
+                                                    uint32_t* __restrict__ lo, uint32_t* __restrict__ hi) {
+  const uint32_t n = min(*count, cap);
+  const uint32_t n_bins = (uint32_t)hdr->n_bins;
+  for (uint32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
+    const uint32_t b = key[p];
+    if (b >= n_bins) continue;   // slots of an overflowed Gaussian (sorted last)
+    if (p == 0 || key[p - 1] != b) lo[b] = p;
+    if (p + 1 == n || key[p + 1] != b) hi[b] = p + 1;
+  }
+}
+
+}  // namespace
+
+int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + kMaxDigitBits - 1) / kMaxDigitBits; }
+
+int64_t radix_hist_entries(int bits, int64_t cap) {
+  const int passes = radix_passes(bits);
+  if (passes == 0) return 1;
+  const int db = (bits + passes - 1) / passes;
+  return ((int64_t)1 << db) * ((cap + kSortTile - 1) / kSortTile);
+}
+
+// Stable sort of `count` (device) pairs by the low `bits` bits of the key.
+// Ping-pongs between (k0, v0) and (k1, v1); returns in *k_out / *v_out the
+// buffers that hold the result.
+hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* d_count,
+                             int64_t cap, int bits, uint32_t* hist, uint32_t* scan_part, hipStream_t s,
+                             uint32_t** k_out, uint32_t** v_out) {
+  const int passes = radix_passes(bits);
+  *k_out = k0;
+  *v_out = v0;
+  if (passes == 0 || cap <= 0) return hipSuccess;
+  const int db = (bits + passes - 1) / passes;
+  const int nblocks = (int)((cap + kSortTile - 1) / kSortTile);
+  uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * db;
+    const int pb = std::min(db, bits - shift);
+    RadixArgs a{ki, vi, ko, vo, hist, d_count, (uint32_t)cap, nblocks, shift, pb};
+    k_radix_hist<<<nblocks, 256, 0, s>>>(a);
+    hipError_t e = launch_scan_u32(hist, hist, nullptr, ((int64_t)1 << pb) * nblocks, scan_part, nullptr, s);
+    if (e != hipSuccess) return e;
+    k_radix_scatter<<<nblocks, 256, 0, s>>>(a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  *k_out = ki;
+  *v_out = vi;
+  return hipSuccess;
+}
+
+hipError_t launch_bin_ranges(const BatchHdr* hdr, const uint32_t* key, const uint32_t* d_count, int64_t cap,
+                             uint32_t* lo, uint32_t* hi, hipStream_t s) {
+  int64_t blocks = (cap + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
+  k_bin_ranges<<<(unsigned)blocks, 256, 0, s>>>(hdr, key, d_count, (uint32_t)cap, lo, hi);
+  return hipGetLastError();
+}
+
+}  // namespace gp

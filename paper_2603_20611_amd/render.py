@@ -56,6 +56,14 @@ class Workspace:
         B.check(B.load().gp_workspace_timings(self._h, ms, cnt, n))
         return {name: (ms[i], cnt[i]) for i, name in enumerate(B.STAGES)}
 
+    def set_densify_stats(self, grad_norm=None, count=None, max_radius=None):
+        """Accumulate densification statistics in every later backward (None disables).
+        grad_norm, max_radius: float32 [n]; count: int32 [n] (all on the device)."""
+        self._stats = (grad_norm, count, max_radius)      # keep them alive
+        n = grad_norm.numel() if grad_norm is not None else 0
+        B.check(B.load().gp_workspace_set_densify_stats(self._h, _ptr(grad_norm), _ptr(count),
+                                                         _ptr(max_radius), n))
+
     def export_bins(self, n_bins, max_keys):
         keys = np.zeros(max(max_keys, 1), np.uint64)
         ranges = np.zeros(2 * max(n_bins, 1), np.int64)
@@ -160,3 +168,30 @@ def adam_step(params, grad, m, v, step, lr, betas=(0.9, 0.999), eps=1e-15, n=Non
     stride = params.shape[1]
     n = stride if n is None else n
     B.check(lib.gp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), n, stride, C.byref(cfg), _stream()))
+
+
+def densify_cfg(**kw):
+    """gp_densify_cfg with the library's defaults, overridden by kw."""
+    c = B.DensifyCfg()
+    B.check(B.load().gp_densify_default_cfg(C.byref(c)))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def densify_prune(params, m, v, grad_norm, count, max_radius, noise, cfg=None, n=None, capacity=None):
+    """Densify and prune; returns (params, m, v, n_new) as new [11, capacity] tensors.
+
+    noise: float32 [6, n] (two 3-vectors per Gaussian for split children)."""
+    n = params.shape[1] if n is None else int(n)
+    cap = capacity if capacity is not None else 2 * n
+    cfg = cfg if cfg is not None else densify_cfg()
+    dev = params.device
+    po = torch.empty(11, max(cap, 1), device=dev)
+    mo = torch.empty_like(po)
+    vo = torch.empty_like(po)
+    n_out = C.c_int64()
+    B.check(B.load().gp_densify_prune(_ptr(params), _ptr(m), _ptr(v), n, params.stride(0), _ptr(grad_norm),
+                                      _ptr(count), _ptr(max_radius), _ptr(noise), C.byref(cfg), _ptr(po),
+                                      _ptr(mo), _ptr(vo), po.stride(0), C.byref(n_out), _stream()))
+    return po, mo, vo, n_out.value

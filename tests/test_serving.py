@@ -1,0 +1,218 @@
+"""Serving (continuous batching over resident 16-bit volumes) against the oracle (GPU).
+
+Bars: each served image is within 1e-5 (relative to its maximum) of the
+oracle evaluated on the dequantised parameters (the kernels' arithmetic), and
+for the default 16-bit storage (GP_Q16) within 2e-3 of the oracle on the
+float32 masters; a request renders bitwise the same alone and inside a batch.
+FP16 and BF16 storage are checked for arithmetic only: on these thin
+filaments their quaternion rounding alone exceeds 2e-3.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import focus
+from paper_2603_20611_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+EXTENT = (128.0, 128.0, 32.0)
+
+
+def _say(msg):
+    print(f"[serving] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _bf16(x):
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32).view(np.float32)
+
+
+def _q16_quat(q):
+    """The header's fixed-point rule for unit quaternions, in binary32."""
+    f = np.float32
+    q = np.asarray(q, f)
+    with np.errstate(all="ignore"):
+        n2 = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]
+        qn = q / np.sqrt(n2)
+        qn = np.where((n2 > 0) & np.isfinite(qn), qn, f(0))
+    v = np.clip(np.rint(qn * f(32767.0)), -32767, 32767).astype(np.int16)
+    return v.astype(f) / f(32767.0)
+
+
+def _dequant(p, dtype):
+    from paper_2603_20611_amd import binding as B
+    q = p.copy()
+    if dtype == B.GP_F16:
+        q[3:11] = p[3:11].astype(np.float16).astype(np.float32)
+    elif dtype == B.GP_BF16:
+        q[3:11] = _bf16(p[3:11])
+    elif dtype == B.GP_Q16:
+        q[3:6] = p[3:6].astype(np.float16).astype(np.float32)
+        q[10] = p[10].astype(np.float16).astype(np.float32)
+        q[6:10] = _q16_quat(p[6:10])
+    return q
+
+
+def _volumes(sizes, seed=40):
+    return [synth.gaussians_microscopy(n, EXTENT, seed + i) for i, n in enumerate(sizes)]
+
+
+def _requests(n, n_vol, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        res = int(rng.choice([64, 96, 128]))
+        out.append(dict(volume=int(rng.integers(0, n_vol)), z=float(rng.uniform(0, EXTENT[2])),
+                        sigma_z=float(rng.choice([0.5, 1.0, 2.0, 3.0])), width=res, height=res,
+                        dx=EXTENT[0] / res, dy=EXTENT[1] / res))
+    return out
+
+
+def _server(vols, **cfg):
+    from paper_2603_20611_amd import serve
+    base = dict(max_gaussians=1 << 20, max_records=1 << 20, max_instances=4 << 20, max_bins=64 * 64,
+                max_batch=32, slots=2)
+    base.update(cfg)
+    sv = serve.Server(**base)
+    ids = [sv.add_volume(torch.from_numpy(v).cuda().contiguous()) for v in vols]
+    return sv, ids
+
+
+def _run(sv, reqs):
+    outs, tickets = [], []
+    for r in reqs:
+        o = torch.empty(r["width"] * r["height"], device="cuda")
+        outs.append(o)
+        tickets.append(sv.submit(r["volume"], r["z"], r["sigma_z"], o, r["width"], r["height"], dx=r["dx"],
+                                 dy=r["dy"]))
+    res = [sv.poll(t, timeout_us=30_000_000) for t in tickets]
+    torch.cuda.synchronize()
+    return [o.cpu().numpy().reshape(r["height"], r["width"]) for o, r in zip(outs, reqs)], res
+
+
+def _slice(r):
+    return dict(z=r["z"], sigma_z=r["sigma_z"], x0=0.0, y0=0.0, dx=r["dx"], dy=r["dy"], width=r["width"],
+                height=r["height"])
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max()) / max(float(np.abs(b).max()), 1e-30)
+
+
+@pytest.mark.parametrize("dtype_name", ["q16", "f16", "bf16"])
+def test_served_images_match_oracle(gp, dtype_name):
+    from paper_2603_20611_amd import binding as B
+    dtype = {"q16": B.GP_Q16, "f16": B.GP_F16, "bf16": B.GP_BF16}[dtype_name]
+    _say(f"served images vs oracle ({dtype_name})")
+    vols = _volumes([3000, 8000, 15000, 30000])
+    sv, ids = _server(vols, attr_dtype=dtype)
+    reqs = _requests(24, len(vols), seed=1)
+    imgs, res = _run(sv, reqs)
+    assert all(r.status == 0 for r in res)
+    assert max(r.batch_size for r in res) > 1
+    worst_k, worst_m = 0.0, 0.0
+    for img, r in zip(imgs, reqs):
+        p = vols[r["volume"]]
+        ref_q = focus.render(_dequant(p, dtype), [_slice(r)])[0].numpy()
+        worst_k = max(worst_k, _rel(img, ref_q))
+        ref_m = focus.render(p, [_slice(r)])[0].numpy()
+        worst_m = max(worst_m, _rel(img, ref_m))
+    _say(f"{dtype_name}: kernel arithmetic {worst_k:.2e}, vs float32 masters {worst_m:.2e}")
+    assert worst_k <= 1e-5
+    if dtype == B.GP_Q16:
+        assert worst_m <= 2e-3
+    st = sv.stats()
+    assert st.completed == len(reqs) and st.volumes == 4
+    sv.close()
+
+
+def test_same_alone_and_in_a_batch(gp):
+    _say("alone vs in a batch")
+    vols = _volumes([5000, 12000, 20000])
+    sv, ids = _server(vols)
+    reqs = _requests(40, len(vols), seed=2)
+    target = reqs[17]
+    alone, res_a = _run(sv, [target])
+    mix, res_m = _run(sv, reqs)
+    assert res_a[0].batch_size == 1 and res_m[17].batch_size > 1
+    assert np.array_equal(alone[0], mix[17])
+    sv.close()
+
+
+def test_graph_and_plain_launches_agree(gp):
+    _say("graph replay vs plain launches")
+    vols = _volumes([6000, 9000])
+    reqs = _requests(20, len(vols), seed=3)
+    sv_g, _ = _server(vols, use_graphs=1)
+    a, _ = _run(sv_g, reqs)
+    sv_g.close()
+    sv_p, _ = _server(vols, use_graphs=0, max_batch=1, slots=1)
+    b, res = _run(sv_p, reqs)
+    sv_p.close()
+    assert all(r.batch_size == 1 for r in res)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def _slab_volume(n, seed):
+    """A thin slab (mu_z in [15, 17]) of 95 % small and 5 % very wide
+    Gaussians: the admission estimate, built on the mean footprint, undercounts
+    its tile-list entries by about 1.6-1.9x."""
+    rng = np.random.default_rng(seed)
+    p = _volumes([n], seed=seed)[0].copy()
+    big = rng.uniform(size=n) < 0.05
+    p[2] = rng.uniform(15.0, 17.0, n)
+    p[3:6] = np.log(0.4)
+    p[3:6, big] = np.log(15.0)
+    return p.astype(np.float32), rng
+
+
+def test_overflowing_batches_are_rerun_alone(gp):
+    from paper_2603_20611_amd import binding as B
+    _say("overflow retry")
+    vol, rng = _slab_volume(4000, seed=44)
+    reqs = []
+    for _ in range(12):
+        res = int(rng.choice([192, 256]))
+        reqs.append(dict(volume=0, z=float(rng.uniform(15.0, 17.0)), sigma_z=3.0, width=res, height=res,
+                         dx=EXTENT[0] / res, dy=EXTENT[1] / res))
+    # a request alone needs at most ~26k entries; two together overflow 30k
+    sv, _ = _server([vol], max_instances=30000, max_records=1 << 16, slots=1)
+    imgs, res = _run(sv, reqs)
+    st = sv.stats()
+    assert st.retries > 0
+    for img, r, rr in zip(imgs, reqs, res):
+        assert rr.status == 0
+        ref = focus.render(_dequant(vol, B.GP_Q16), [_slice(r)])[0].numpy()
+        assert _rel(img, ref) <= 1e-5
+    sv.close()
+
+
+def test_errors_budget_and_shutdown(gp):
+    from paper_2603_20611_amd import binding as B, serve
+    _say("errors, budget, shutdown")
+    vols = _volumes([4000, 4000])
+    per_volume = 4032 * (12 + 16)   # float32 means + 16-bit attributes
+    sv = serve.Server(hbm_budget_bytes=per_volume + 100, max_gaussians=1 << 16, max_records=1 << 18,
+                      max_instances=1 << 20, max_bins=4096, max_batch=8, slots=2)
+    vid = sv.add_volume(torch.from_numpy(vols[0]).cuda())
+    with pytest.raises(B.GpError) as e:
+        sv.add_volume(torch.from_numpy(vols[1]).cuda())
+    assert e.value.status == B.GP_ENOMEM
+    out = torch.empty(64 * 64, device="cuda")
+    with pytest.raises(B.GpError) as e:
+        sv.submit(vid + 5, 1.0, 1.0, out, 64, 64)
+    assert e.value.status == B.GP_EINVAL
+    with pytest.raises(B.GpError) as e:
+        sv.poll(123456, 0)
+    assert e.value.status == B.GP_EINVAL
+    outs = [torch.empty(128 * 128, device="cuda") for _ in range(60)]
+    tickets = [sv.submit(vid, float(i % 30), 1.0, o, 128, 128) for i, o in enumerate(outs)]
+    first = sv.poll(tickets[-1], 0)
+    assert first is None or first.status == 0
+    sv.close()      # cancels what is queued, waits for what runs
+    torch.cuda.synchronize()
