@@ -12,7 +12,7 @@ synchronisation on both sides):
             (activation, axial cull, projection, tile-key emission, radix sort,
             additive rasterisation).  `value` = rendered megapixels per second.
   train     one step = one reconstruction iteration on a batch of 8 consecutive
-            slices at a random depth: forward, L1 loss gradient, backward,
+            slices at a random depth: forward, L1 + 0.2 D-SSIM loss gradient, backward,
             fused Adam (learning rates decayed exponentially to 0.1x over
             30,000 iterations).  Reported as fwd_bwd_iter_per_s.
 
@@ -20,7 +20,7 @@ The dominant kernel (additive rasterisation of the forward) is timed with HIP
 events recorded by the library on the stream it launches on; its roofline is
 the VALU + transcendental issue rate of the chip (4 (pixel, Gaussian) pairs per
 clock per SIMD, derived below).  The CPU
-oracle is timed on 8 slices of 256 x 256 of the same workload.
+oracle is timed on 64 slices of 256 x 256 of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -42,6 +42,7 @@ N_SLICES = 400
 RES = 256
 SIGMA_Z = 3.0
 TRAIN_BATCH = 8
+LAMBDA_SSIM = 0.2   # weight of the D-SSIM term of the loss
 # raster roofline: per (pixel, Gaussian) pair the method needs one exp2 and four
 # fp32 VALU operations (offset, two FMAs of the quadratic form, accumulate).
 # gfx950 issues 32 fp32 lanes/clk/SIMD (157.3 TFLOP/s fp32 over 1024 SIMDs at
@@ -50,15 +51,35 @@ TRAIN_BATCH = 8
 PEAK_PAIRS_PER_S = 1024 * 2.4e9 * 4.0
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed byte-counter summary,
+    or None if the kernel's source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_bytes.md")):
+        for line in open(path):
+            f = line.split()
+            if len(f) < 5 or f[0] != "traffic" or f[1] != kernel:
+                continue
+            kv = dict(x.split("=", 1) for x in f[2:])
+            src = os.path.join(ROOT, kv["source"])
+            if not os.path.exists(src):
+                return None
+            if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv["sha256_16"]:
+                return None
+            return int(kv["bytes_per_launch"])
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(params_np, slices):
-    """The oracle, as it stands, on 8 slices of the workload."""
+    """The oracle, as it stands, on 64 slices of the workload."""
     import torch
     from oracle import focus
-    sample = slices[N_SLICES // 2:N_SLICES // 2 + 8]
+    sample = slices[N_SLICES // 2 - 32:N_SLICES // 2 + 32]
     t0 = time.perf_counter()
     imgs = focus.render(params_np, sample)
     dt = time.perf_counter() - t0
@@ -66,7 +87,7 @@ def cpu_baseline(params_np, slices):
     px = sum(s["width"] * s["height"] for s in sample)
     return {"value": round(px / dt / 1e6, 4), "unit": "Mpix/s", "cores": int(torch.get_num_threads()),
             "kind": "oracle",
-            "sample": f"8 consecutive {RES}x{RES} slices (z={sample[0]['z']}..{sample[-1]['z']}) of the "
+            "sample": f"{len(sample)} consecutive {RES}x{RES} slices (z={sample[0]['z']}..{sample[-1]['z']}) of the "
                       f"{N_GAUSS}-Gaussian workload, float64 oracle, {dt:.1f} s"}
 
 
@@ -231,7 +252,7 @@ def main():
     v = torch.zeros_like(params)
     img = torch.empty(TRAIN_BATCH * RES * RES, device=dev)
     gimg = torch.empty_like(img)
-    loss = torch.zeros(1, device=dev)
+    loss = torch.zeros(2, device=dev)
     rng = np.random.default_rng(7)
     starts = rng.integers(0, N_SLICES - TRAIN_BATCH + 1, size=n_train + args.warmup)
     batches = [slices[int(k):int(k) + TRAIN_BATCH] for k in starts]
@@ -244,7 +265,7 @@ def main():
     def train_step(it, batch, k0):
         render.render(params, batch, opts, ws_tr, out=img)
         tgt = target[k0 * RES * RES:(k0 + TRAIN_BATCH) * RES * RES]
-        render.l1_loss_grad(img, tgt, grad=gimg, loss=loss)
+        render.l1_dssim_loss_grad(img, tgt, TRAIN_BATCH, RES, RES, ws_tr, lam=LAMBDA_SSIM, grad=gimg, loss=loss)
         render.render_backward(params, batch, gimg, ws_tr, opts, grad=grad)
         lr = lr0 * 0.1 ** (it / total_iters)
         render.adam_step(params, grad, m, v, it + 1, lr, flags=B.GP_ADAM_ZERO_GRAD | B.GP_ADAM_CLAMP_ALPHA)
@@ -289,13 +310,14 @@ def main():
         "records": rec, "instances": inst, "pairs_per_step": int(pairs),
         "roofline": {"bound": "alu", "kernel": "k_raster_fwd", "achieved": round(achieved / 1e9, 1),
                      "peak": round(PEAK_PAIRS_PER_S / 1e9, 1), "unit": "Gpair/s",
-                     "frac": round(achieved / PEAK_PAIRS_PER_S, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_PAIRS_PER_S, 4), "traffic": measured_traffic("k_raster_fwd"),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel_ms": round(raster_ms, 4)},
     }
     if not args.no_serving:
         result["serving"] = serving_leg(dev, args.serving_requests)
     if not args.no_cpu:
-        log("timing the CPU oracle on 8 slices")
+        log("timing the CPU oracle on 64 slices")
         result["cpu_baseline"] = cpu_baseline(learn, slices)
     print(json.dumps(result), flush=True)
 

@@ -160,6 +160,21 @@ gp_status gp_render_backward(gp_workspace* ws, const gp_gaussians* g, const gp_s
 gp_status gp_l1_loss_grad(const float* d_image, const float* d_target, int64_t n, float scale,
                           float* d_grad, float* d_loss, void* stream);
 
+/* The full slice loss (Sec. 4.3, loss function; lambda = 0.2 in Sec. 5.1):
+ *   L = mean |I - T| + lambda * (1 - mean SSIM(I, T))
+ * over a batch of n_slices slices of one grid, packed [n_slices][height][width]
+ * float32.  SSIM (Wang et al. 2004): 11 x 11 Gaussian window of standard
+ * deviation 1.5 with unit sum, zeros outside the slice, C1 = 0.01^2,
+ * C2 = 0.03^2, evaluated at every pixel.  d_grad receives dL/dI (written,
+ * sign(0) = 0 in the L1 part); d_loss, if not NULL, float[2]: += the L1 term,
+ * += the D-SSIM term (1 - mean SSIM).  ws provides scratch of 24 bytes per
+ * pixel (grown on demand, which synchronises).  Arithmetic in float64.
+ * Errors: GP_EINVAL (NULL, negative sizes, n_slices > 65535, lambda < 0 or
+ * not finite), GP_ENOMEM/GP_EHIP. */
+gp_status gp_l1_dssim_loss_grad(gp_workspace* ws, const float* d_image, const float* d_target, int32_t n_slices,
+                                int32_t width, int32_t height, float lambda, float* d_grad, float* d_loss,
+                                void* stream);
+
 /* Adam (Kingma & Ba, Algorithm 1; the optimiser named in Sec. 5.1) on float32
  * planes [11][stride] in place: for every element
  *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2

@@ -92,6 +92,7 @@ _SIGS = {
     "gp_adam_step": (C.c_int32, [_P, _P, _P, _P, C.c_int64, C.c_int64, C.POINTER(AdamCfg), _P]),
     "gp_workspace_set_timing": (C.c_int32, [_P, C.c_int32]),
     "gp_workspace_timings": (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
+    "gp_l1_dssim_loss_grad": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_float, _P, _P, _P]),
     "gp_densify_default_cfg": (C.c_int32, [C.POINTER(DensifyCfg)]),
     "gp_workspace_set_densify_stats": (C.c_int32, [_P, _P, _P, _P, C.c_int64]),
     "gp_densify_prune": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P, _P, _P, C.POINTER(DensifyCfg),

@@ -393,7 +393,7 @@ void workspace_free(Workspace* ws) {
   void* dev[] = {ws->d_slices, ws->d_groups, ws->d_hdr, ws->d_work, ws->d_ctr, ws->d_bin_lo, ws->d_bin_hi,
                  ws->d_rec_pay, ws->d_rec_meta, ws->d_g_rbase, ws->d_g_nrec, ws->d_g_ninst, ws->d_g_krange,
                  ws->d_wave_cnt, ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, ws->d_hist,
-                 ws->d_scan_part, ws->d_moments};
+                 ws->d_scan_part, ws->d_moments, ws->d_ssim};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {ws->h_slices, ws->h_groups, ws->h_hdr, ws->h_ctr};
@@ -523,6 +523,32 @@ gp_status gp_l1_loss_grad(const float* img, const float* tgt, int64_t n, float s
   if (n < 0) return einval("l1: n < 0");
   if (n > 0 && (!img || !tgt || !grad)) return einval("l1: NULL array");
   GP_HIP(launch_l1(img, tgt, n, scale, grad, loss, static_cast<hipStream_t>(stream)));
+  return GP_OK;
+}
+
+gp_status gp_l1_dssim_loss_grad(gp_workspace* w, const float* img, const float* tgt, int32_t n_slices,
+                                int32_t width, int32_t height, float lambda, float* grad, float* loss,
+                                void* stream) {
+  if (!w) return einval("l1_dssim: NULL workspace");
+  if (n_slices < 0 || width < 0 || height < 0 || n_slices > 65535) return einval("l1_dssim: bad sizes");
+  if (!(lambda >= 0.f) || !std::isfinite(lambda)) return einval("l1_dssim: lambda must be finite and >= 0");
+  const int64_t npix = (int64_t)n_slices * width * height;
+  if (npix == 0) return GP_OK;
+  if (!img || !tgt || !grad) return einval("l1_dssim: NULL array");
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (3 * npix > ws->ssim_cap) {
+    GP_HIP(hipStreamSynchronize(s));
+    GP_HIP(wait_ws(ws));
+    hipError_t e = dev_alloc(&ws->d_ssim, 3 * npix);
+    if (e != hipSuccess) {
+      ws->ssim_cap = 0;
+      set_error("l1_dssim: cannot allocate scratch");
+      return GP_ENOMEM;
+    }
+    ws->ssim_cap = 3 * npix;
+  }
+  GP_HIP(launch_ssim_loss(img, tgt, n_slices, width, height, (double)lambda, ws->d_ssim, grad, loss, s));
   return GP_OK;
 }
 

@@ -155,6 +155,8 @@ struct Workspace {
   uint32_t* d_hist = nullptr;       // [hist_cap] radix digit counts
   uint2* d_scan_part = nullptr;     // [part_cap] scan partials
   float4* d_moments = nullptr;      // [2 * inst_cap] backward moments per instance slot
+  double* d_ssim = nullptr;         // [ssim_cap] coefficient maps of the D-SSIM gradient
+  int64_t ssim_cap = 0;
   int64_t hist_cap = 0, part_cap = 0, wave_cap = 0;
 
   // pinned staging for uploads / readbacks
@@ -265,6 +267,8 @@ hipError_t launch_densify(const float* p, const float* m, const float* v, int64_
 // k_optim.hip
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, int64_t stride,
                        const gp_adam_cfg& c, hipStream_t s);
+hipError_t launch_ssim_loss(const float* x, const float* y, int n_slices, int width, int height, double lam,
+                            double* maps, float* grad, float* loss, hipStream_t s);
 hipError_t launch_l1(const float* img, const float* tgt, int64_t n, float scale, float* grad,
                      float* loss, hipStream_t s);
 

@@ -161,6 +161,16 @@ def l1_loss_grad(image, target, grad=None, loss=None, scale=None):
     return grad
 
 
+def l1_dssim_loss_grad(image, target, n_slices, width, height, ws, lam=0.2, grad=None, loss=None):
+    """dL/dI of L = mean|I - T| + lam (1 - mean SSIM) over [n_slices, height, width] packed slices.
+    loss, if given, is a float32 [2] device tensor: += (L1 term, D-SSIM term)."""
+    if grad is None:
+        grad = torch.empty_like(image)
+    B.check(B.load().gp_l1_dssim_loss_grad(ws.handle, _ptr(image), _ptr(target), int(n_slices), int(width),
+                                            int(height), float(lam), _ptr(grad), _ptr(loss), _stream()))
+    return grad
+
+
 def adam_step(params, grad, m, v, step, lr, betas=(0.9, 0.999), eps=1e-15, n=None, flags=0):
     """lr: (mean, log_scale, quat, alpha) learning rates."""
     lib = B.load()
