@@ -196,6 +196,37 @@ gp_status gp_adam_step(float* d_params, float* d_grad, float* d_m, float* d_v, i
                        int64_t stride, const gp_adam_cfg* cfg, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Differentiable voxeliser (Sec. 4.3, "Differentiable Voxelization"): the
+ * volume sigma(x) = sum_i alpha_i exp(-1/2 (x - mu_i)^T Sigma_i^-1 (x - mu_i))
+ * of the world-space Gaussians (no focus re-parameterisation), accumulated over
+ * 8 x 8 x 8-voxel tiles, each keeping the Gaussians whose 3-sigma box (half-
+ * widths bbox_sigmas * sqrt(Sigma_aa), decided in binary32) reaches it; with
+ * GP_FLAG_EXACT every finite Gaussian reaches every voxel.  Voxel (i, j, k)
+ * has centre (x0 + (i + 1/2) dx, y0 + (j + 1/2) dy, z0 + (k + 1/2) dz).
+ * ---------------------------------------------------------------------- */
+typedef struct gp_volume_grid {
+  float x0, y0, z0;     /* corner of the volume */
+  float dx, dy, dz;     /* voxel pitch, > 0 */
+  int32_t nx, ny, nz;   /* voxels per axis, >= 0 */
+  int32_t pad;
+} gp_volume_grid;
+
+/* Writes the volume [nz][ny][nx] float32 into d_volume.  Uses ws for the tile
+ * lists (replacing any slice forward it held) and synchronises once on stream
+ * (the tile-list size is read back).  Deterministic.
+ * Errors: GP_EINVAL (bad grid, more than 2^30 tiles, NULL), GP_ENOMEM, GP_EHIP. */
+gp_status gp_voxelize(gp_workspace* ws, const gp_gaussians* g, const gp_volume_grid* grid,
+                      const gp_render_opts* opts, float* d_volume, void* stream);
+
+/* Adds dL/dparams of L = sum_v d_grad_volume[v] * V[v] into d_grad ([11][grad_stride]
+ * float32) for the Gaussians and grid of the last gp_voxelize on ws.
+ * Deterministic (no floating-point atomics).
+ * Errors: GP_ESTATE (ws holds no matching voxelisation), GP_EINVAL, GP_EHIP. */
+gp_status gp_voxelize_backward(gp_workspace* ws, const gp_gaussians* g, const gp_volume_grid* grid,
+                               const gp_render_opts* opts, const float* d_grad_volume, float* d_grad,
+                               int64_t grad_stride, void* stream);
+
+/* ------------------------------------------------------------------------
  * Densify and prune (Sec. 4.3, "Prune and densification": driven by the
  * Gaussians' footprint radii on the slices and their intensities; thresholds
  * of Sec. 5.1).  The procedure is the usual Gaussian-splatting control:
@@ -337,10 +368,10 @@ gp_status gp_server_destroy(gp_server* sv);
 gp_status gp_workspace_set_timing(gp_workspace* ws, int32_t enable);
 gp_status gp_workspace_timings(gp_workspace* ws, double* h_ms, int64_t* h_counts, int32_t n_stages);
 
-/* Test hook: copies the tile lists of the most recent render to host memory,
- * synchronously.  h_keys[j] = (bin << 32) | gaussian index, in list order,
- * where bins are numbered slice by slice (in the order given) and row-major
- * within a slice; h_ranges[2b], h_ranges[2b+1] = [start, end) of bin b.
+/* Test hook: copies the tile lists of the most recent render (or voxelisation)
+ * to host memory, synchronously.  h_keys[j] = (bin << 32) | gaussian index, in
+ * list order, where bins are numbered slice by slice (in the order given) and
+ * row-major within a slice (for a voxelisation: (tz * nty + ty) * ntx + tx); h_ranges[2b], h_ranges[2b+1] = [start, end) of bin b.
  * *n_keys receives the number of entries; h_keys must hold keys_cap entries and
  * h_ranges 2 * bins entries.  Errors: GP_EINVAL (too small), GP_ESTATE. */
 gp_status gp_debug_export_bins(gp_workspace* ws, uint64_t* h_keys, int64_t keys_cap, int64_t* n_keys,

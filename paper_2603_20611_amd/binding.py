@@ -47,6 +47,18 @@ class AdamCfg(C.Structure):
                 ("step", C.c_int32), ("flags", C.c_uint32)]
 
 
+class VolumeGrid(C.Structure):
+    _fields_ = [("x0", C.c_float), ("y0", C.c_float), ("z0", C.c_float), ("dx", C.c_float), ("dy", C.c_float),
+                ("dz", C.c_float), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("pad", C.c_int32)]
+
+
+def make_grid(grid):
+    """VolumeGrid from a dict with nx, ny, nz and optional x0, y0, z0, dx, dy, dz."""
+    return VolumeGrid(float(grid.get("x0", 0.0)), float(grid.get("y0", 0.0)), float(grid.get("z0", 0.0)),
+                      float(grid.get("dx", 1.0)), float(grid.get("dy", 1.0)), float(grid.get("dz", 1.0)),
+                      int(grid["nx"]), int(grid["ny"]), int(grid["nz"]), 0)
+
+
 class DensifyCfg(C.Structure):
     _fields_ = [("grad_threshold", C.c_float), ("min_alpha", C.c_float), ("max_radius", C.c_float),
                 ("split_scale", C.c_float), ("split_factor", C.c_float), ("flags", C.c_uint32)]
@@ -92,6 +104,9 @@ _SIGS = {
     "gp_adam_step": (C.c_int32, [_P, _P, _P, _P, C.c_int64, C.c_int64, C.POINTER(AdamCfg), _P]),
     "gp_workspace_set_timing": (C.c_int32, [_P, C.c_int32]),
     "gp_workspace_timings": (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
+    "gp_voxelize": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(VolumeGrid), C.POINTER(RenderOpts), _P, _P]),
+    "gp_voxelize_backward": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(VolumeGrid), C.POINTER(RenderOpts),
+                                         _P, _P, C.c_int64, _P]),
     "gp_l1_dssim_loss_grad": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_float, _P, _P, _P]),
     "gp_densify_default_cfg": (C.c_int32, [C.POINTER(DensifyCfg)]),
     "gp_workspace_set_densify_stats": (C.c_int32, [_P, _P, _P, _P, C.c_int64]),

@@ -275,6 +275,10 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
   ws->h_hdr->n_bins = (int32_t)nbins;
   ws->h_hdr->total_gauss = (int32_t)total_gauss;
   ws->h_hdr->n_waves = (int32_t)(total_gauss / 64);
+  int32_t tps = ns > 0 ? ws->h_slices[0].ntx * ws->h_slices[0].nty : 0;
+  for (int k = 1; k < ns && tps > 0; ++k)
+    if (ws->h_slices[k].ntx * ws->h_slices[k].nty != tps) tps = 0;
+  ws->h_hdr->tiles_per_slice = tps;
   plan->ns = ns; plan->ng = ng; plan->nbins = nbins; plan->total_gauss = total_gauss; plan->npix = off;
   plan->attr_dtype = ng > 0 ? groups[0].g->attr_dtype : GP_F32;
   return GP_OK;
@@ -393,7 +397,7 @@ void workspace_free(Workspace* ws) {
   void* dev[] = {ws->d_slices, ws->d_groups, ws->d_hdr, ws->d_work, ws->d_ctr, ws->d_bin_lo, ws->d_bin_hi,
                  ws->d_rec_pay, ws->d_rec_meta, ws->d_g_rbase, ws->d_g_nrec, ws->d_g_ninst, ws->d_g_krange,
                  ws->d_wave_cnt, ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, ws->d_hist,
-                 ws->d_scan_part, ws->d_moments, ws->d_ssim};
+                 ws->d_scan_part, ws->d_moments, ws->d_ssim, ws->d_vox_rec, ws->d_vox_box, ws->d_vox_mom};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {ws->h_slices, ws->h_groups, ws->h_hdr, ws->h_ctr};
@@ -471,13 +475,14 @@ gp_status gp_render_slices(gp_workspace* w, const gp_gaussians* g, const gp_slic
     if ((st = check_slice(hs[k], k)) != GP_OK) return st;
   GP_HIP(hipSetDevice(ws->device));
   ws->have_forward = false;
+  ws->vox_have = false;
   if (ns == 0) return GP_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   GroupIn grp{g, 0, ns};
   BatchPlan plan{};
   if ((st = stage_batch(ws, &grp, 1, hs, ns, out, nullptr, &plan)) != GP_OK) return st;
   if ((st = upload_batch(ws, plan, s)) != GP_OK) return st;
-  const LaunchDims d{plan.total_gauss, plan.nbins};
+  const LaunchDims d{plan.total_gauss, plan.nbins, emit_width_for(ns)};
   if ((st = enqueue_forward(ws, make_render_const(o, g->attr_dtype, ws), d, s)) != GP_OK) return st;
   ws->have_forward = true;
   ws->fwd_means = g->means;
@@ -588,6 +593,126 @@ gp_status gp_workspace_timings(gp_workspace* w, double* ms, int64_t* counts, int
   return GP_OK;
 }
 
+static gp_status check_grid(const gp_volume_grid* v) {
+  if (!v) return einval("voxelize: NULL grid");
+  if (v->nx < 0 || v->ny < 0 || v->nz < 0) return einval("voxelize: negative grid size");
+  const float h[3] = {v->dx, v->dy, v->dz};
+  const float o[3] = {v->x0, v->y0, v->z0};
+  for (int a = 0; a < 3; ++a)
+    if (!(h[a] > 0.f) || !std::isfinite(h[a]) || !std::isfinite(o[a])) return einval("voxelize: bad pitch or origin");
+  if ((int64_t)v->nx > (8ll << 16) || (int64_t)v->ny > (8ll << 16) || (int64_t)v->nz > (8ll << 16))
+    return einval("voxelize: more than 2^19 voxels along an axis");
+  return GP_OK;
+}
+
+static gp_status reserve_vox(Workspace* ws, int64_t n, int64_t inst) {
+  if (n > ws->vox_gcap) {
+    GP_HIP(wait_ws(ws));
+    const int64_t cap = n + n / 8 + 64;
+    if (dev_alloc(&ws->d_vox_rec, 3 * cap) != hipSuccess || dev_alloc(&ws->d_vox_box, 3 * cap) != hipSuccess) {
+      ws->vox_gcap = 0;
+      set_error("voxelize: out of device memory");
+      return GP_ENOMEM;
+    }
+    ws->vox_gcap = cap;
+  }
+  if (inst > ws->vox_icap) {
+    GP_HIP(wait_ws(ws));
+    if (dev_alloc(&ws->d_vox_mom, 3 * inst) != hipSuccess) {
+      ws->vox_icap = 0;
+      set_error("voxelize: out of device memory");
+      return GP_ENOMEM;
+    }
+    ws->vox_icap = inst;
+  }
+  return GP_OK;
+}
+
+gp_status gp_voxelize(gp_workspace* w, const gp_gaussians* g, const gp_volume_grid* grid, const gp_render_opts* o,
+                      float* vol, void* stream) {
+  if (!w) return einval("voxelize: NULL workspace");
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  gp_status st = check_gaussians(g);
+  if (st != GP_OK) return st;
+  if ((st = check_opts(o)) != GP_OK) return st;
+  if ((st = check_grid(grid)) != GP_OK) return st;
+  const int64_t nvox = (int64_t)grid->nx * grid->ny * grid->nz;
+  if (nvox > 0 && !vol) return einval("voxelize: NULL volume");
+  if (g->n > 0x7FFFFFF0ll) return einval("voxelize: too many Gaussians");
+  GP_HIP(hipSetDevice(ws->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ws->have_forward = false;
+  ws->vox_have = false;
+  if (nvox == 0) return GP_OK;
+  const VoxLaunch L = vox_prepare(g, grid, o);
+  if (L.n_tiles >= (1ll << 30)) return einval("voxelize: more than 2^30 tiles");
+  if (L.n == 0) {
+    GP_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(vol), 0u, nvox, s));
+  } else {
+    if ((st = reserve_small(ws, 0, 0, L.n_tiles, L.n)) != GP_OK) return st;
+    if ((st = reserve_vox(ws, L.n, 0)) != GP_OK) return st;
+    const int64_t part = scan_parts_needed(L.n);
+    if (part > ws->part_cap) {
+      GP_HIP(wait_ws(ws));
+      GP_HIP(dev_alloc(&ws->d_scan_part, part));
+      ws->part_cap = part;
+    }
+    ws->last_stream = s;
+    GP_HIP(launch_vox_count(*ws, g, grid, o, L, s));
+    GP_HIP(launch_scan_u32(ws->d_g_ninst, ws->d_g_rbase, nullptr, L.n, reinterpret_cast<uint32_t*>(ws->d_scan_part),
+                           ws->d_ctr + kCtrInstances, s));
+    GP_HIP(hipMemcpyAsync(ws->h_ctr, ws->d_ctr, sizeof(uint32_t) * kCtrCount, hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    const int64_t K = ws->h_ctr[kCtrInstances];
+    if ((st = reserve_lists(ws, 0, std::max<int64_t>(K, 1))) != GP_OK) return st;
+    if ((st = reserve_vox(ws, L.n, ws->inst_cap)) != GP_OK) return st;
+    const int bits = key_bits(L.n_tiles);
+    if ((st = reserve_sort(ws, bits)) != GP_OK) return st;
+    ws->last_stream = s;
+    GP_HIP(launch_vox_emit(*ws, g, grid, o, L, s));
+    GP_HIP(launch_radix_sort(ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, ws->d_ctr + kCtrInstances,
+                             std::max<int64_t>(K, 1), bits, ws->d_hist, reinterpret_cast<uint32_t*>(ws->d_scan_part),
+                             s, &ws->d_list_key, &ws->d_list));
+    GP_HIP(launch_vox_ranges(*ws, L, (uint32_t)K, s));
+    GP_HIP(launch_vox_fwd(*ws, g, grid, o, L, vol, s));
+  }
+  ws->vox_have = true;
+  ws->vox_ntiles = L.n == 0 ? 0 : L.n_tiles;
+  ws->vox_ninst = L.n == 0 ? 0 : (int64_t)ws->h_ctr[kCtrInstances];
+  ws->vox_means = g->means;
+  ws->vox_attrs = g->attrs;
+  ws->vox_n = g->n;
+  ws->vox_stride = g->stride;
+  ws->vox_hash = hash_bytes(grid, sizeof(*grid), hash_bytes(o, sizeof(*o)));
+  return GP_OK;
+}
+
+gp_status gp_voxelize_backward(gp_workspace* w, const gp_gaussians* g, const gp_volume_grid* grid,
+                               const gp_render_opts* o, const float* gvol, float* grad, int64_t grad_stride,
+                               void* stream) {
+  if (!w) return einval("voxelize_backward: NULL workspace");
+  Workspace* ws = reinterpret_cast<Workspace*>(w);
+  gp_status st = check_gaussians(g);
+  if (st != GP_OK) return st;
+  if ((st = check_opts(o)) != GP_OK) return st;
+  if ((st = check_grid(grid)) != GP_OK) return st;
+  if (grad_stride < g->n) return einval("voxelize_backward: grad_stride < n");
+  const int64_t nvox = (int64_t)grid->nx * grid->ny * grid->nz;
+  if (!ws->vox_have || ws->vox_means != g->means || ws->vox_attrs != g->attrs || ws->vox_n != g->n ||
+      ws->vox_stride != g->stride || ws->vox_hash != hash_bytes(grid, sizeof(*grid), hash_bytes(o, sizeof(*o)))) {
+    set_error("voxelize_backward: the workspace does not hold the voxelisation of these Gaussians and grid");
+    return GP_ESTATE;
+  }
+  if (nvox == 0 || g->n == 0) return GP_OK;
+  if (!gvol || !grad) return einval("voxelize_backward: NULL array");
+  GP_HIP(hipSetDevice(ws->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const VoxLaunch L = vox_prepare(g, grid, o);
+  ws->last_stream = s;
+  GP_HIP(launch_vox_bwd(*ws, g, grid, o, L, gvol, grad, grad_stride, s));
+  return GP_OK;
+}
+
 gp_status gp_densify_default_cfg(gp_densify_cfg* c) {
   if (!c) return einval("densify_default_cfg: NULL");
   c->grad_threshold = 5e-5f;
@@ -660,11 +785,32 @@ gp_status gp_debug_export_bins(gp_workspace* w, uint64_t* h_keys, int64_t keys_c
                                int64_t* h_ranges, int64_t ranges_cap) {
   if (!w || !n_keys) return einval("export_bins: NULL");
   Workspace* ws = reinterpret_cast<Workspace*>(w);
-  if (!ws->have_forward) {
+  if (!ws->have_forward && !ws->vox_have) {
     set_error("export_bins: no forward in this workspace");
     return GP_ESTATE;
   }
   GP_HIP(wait_ws(ws));
+  if (ws->vox_have) {
+    // voxelisation: the lists hold Gaussian indices directly
+    const int64_t nb = ws->vox_ntiles, K = ws->vox_ninst;
+    *n_keys = K;
+    if (keys_cap < K || ranges_cap < 2 * nb || (K > 0 && !h_keys) || (nb > 0 && !h_ranges))
+      return einval("export_bins: output too small");
+    std::vector<uint32_t> lo((size_t)std::max<int64_t>(nb, 1)), hi((size_t)std::max<int64_t>(nb, 1)),
+        list((size_t)std::max<int64_t>(K, 1));
+    if (nb > 0) {
+      GP_HIP(hipMemcpy(lo.data(), ws->d_bin_lo, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost));
+      GP_HIP(hipMemcpy(hi.data(), ws->d_bin_hi, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost));
+    }
+    if (K > 0) GP_HIP(hipMemcpy(list.data(), ws->d_list, sizeof(uint32_t) * K, hipMemcpyDeviceToHost));
+    int64_t o = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      h_ranges[2 * b] = o;
+      for (uint32_t i = lo[b]; i < hi[b]; ++i) h_keys[o++] = ((uint64_t)b << 32) | list[i];
+      h_ranges[2 * b + 1] = o;
+    }
+    return GP_OK;
+  }
   const int64_t nb = ws->fwd_nbins;
   std::vector<uint32_t> lo((size_t)nb), hi((size_t)nb);
   if (nb > 0) {

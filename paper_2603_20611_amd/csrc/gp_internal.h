@@ -52,11 +52,56 @@ struct SliceDev {
 struct BatchHdr {
   int32_t n_groups, n_slices, n_bins, total_gauss;
   int32_t n_waves;     // total_gauss / 64
-  int32_t pad[3];
+  int32_t tiles_per_slice;   // the common tile count of every slice, or 0 if they differ
+  int32_t pad[2];
 };
 
 // Work counters handed out by atomics (reset at the start of every forward).
-enum { kWorkRasterFwd = 0, kWorkRasterBwd = 1, kWorkCount = 4 };
+// Rasteriser work queues: one per XCD for the forward and for the backward.
+constexpr int kXcds = 8;
+enum { kWorkRasterFwd = 0, kWorkRasterBwd = kXcds, kWorkCount = 2 * kXcds };
+
+__device__ __forceinline__ uint32_t wave_take(uint32_t* counter) {
+  uint32_t v = 0;
+  if (__lane_id() == 0) v = atomicAdd(counter, 1u);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// kXcds work queues over n_items items.  Workgroups are dispatched to the XCDs
+// round-robin, so workgroup b runs on XCD b mod 8; queue q holds the q-th
+// contiguous eighth of the items, and a workgroup drains its own XCD's queue
+// first, then helps the others, so neighbouring items share one L2.
+struct WorkQueues {
+  uint32_t* ctr;   // kXcds counters
+  int n_items, home, tried;
+
+  __device__ WorkQueues(uint32_t* c, int n, unsigned block) : ctr(c), n_items(n), home((int)(block % kXcds)), tried(0) {}
+
+  // Next work item (0 <= item < n_items) for the calling wavefront, or -1.
+  __device__ __forceinline__ int take_wave() {
+    while (tried < kXcds) {
+      const int q = (home + tried) % kXcds;
+      const int lo = (int)((int64_t)q * n_items / kXcds), hi = (int)((int64_t)(q + 1) * n_items / kXcds);
+      const uint32_t c = wave_take(&ctr[q]);
+      if ((int64_t)lo + c < hi) return lo + (int)c;
+      ++tried;
+    }
+    return -1;
+  }
+
+  // The same for a whole workgroup (thread 0 takes; the caller broadcasts).
+  __device__ __forceinline__ int take_thread() {
+    while (tried < kXcds) {
+      const int q = (home + tried) % kXcds;
+      const int lo = (int)((int64_t)q * n_items / kXcds), hi = (int)((int64_t)(q + 1) * n_items / kXcds);
+      const uint32_t c = atomicAdd(&ctr[q], 1u);
+      if ((int64_t)lo + c < hi) return lo + (int)c;
+      ++tried;
+    }
+    return -1;
+  }
+};
+
 
 // One Gaussian set and the contiguous range of slices that sample it.
 struct GroupDev {
@@ -82,9 +127,16 @@ struct RenderConst {
 // Grid sizes of a launch sequence: exact for one known batch, or the
 // workspace capacity when the sequence is captured for replay.
 struct LaunchDims {
-  int64_t gauss;   // flattened Gaussians to cover (multiple of 64)
-  int64_t bins;    // bins to cover (also fixes the sort's key width)
+  int64_t gauss;        // flattened Gaussians to cover (multiple of 64)
+  int64_t bins;         // bins to cover (also fixes the sort's key width)
+  int32_t emit_width = 1;   // lanes per Gaussian in the emit (1, 2, 4, 8 or 16)
 };
+// Emit width for groups of at most `slices` slices each.
+inline int32_t emit_width_for(int64_t slices) {
+  int32_t w = 1;
+  while (w < 16 && w < slices) w <<= 1;
+  return w;
+}
 
 // Counters written by the preprocess.
 // (records and instances are adjacent: the wavefront scan writes both as one uint2)
@@ -157,6 +209,16 @@ struct Workspace {
   float4* d_moments = nullptr;      // [2 * inst_cap] backward moments per instance slot
   double* d_ssim = nullptr;         // [ssim_cap] coefficient maps of the D-SSIM gradient
   int64_t ssim_cap = 0;
+  // voxeliser: records and tile boxes per Gaussian, moments per instance
+  float4* d_vox_rec = nullptr;      // [3 * vox_gcap]
+  uint32_t* d_vox_box = nullptr;    // [3 * vox_gcap]
+  float4* d_vox_mom = nullptr;      // [3 * vox_icap]
+  int64_t vox_gcap = 0, vox_icap = 0;
+  bool vox_have = false;            // holds the lists of a voxelisation
+  const void* vox_means = nullptr;
+  const void* vox_attrs = nullptr;
+  int64_t vox_n = 0, vox_stride = 0, vox_ntiles = 0, vox_ninst = 0;
+  uint64_t vox_hash = 0;
   int64_t hist_cap = 0, part_cap = 0, wave_cap = 0;
 
   // pinned staging for uploads / readbacks
@@ -258,6 +320,23 @@ hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const f
 // k_backward.hip
 hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, float* grad,
                                  int64_t grad_stride, const LaunchDims& d, hipStream_t s);
+// k_voxel.hip
+struct VoxLaunch {
+  int n;
+  int ntx, nty, ntz;
+  int64_t n_tiles;
+};
+VoxLaunch vox_prepare(const gp_gaussians* g, const gp_volume_grid* grid, const gp_render_opts* o);
+hipError_t launch_vox_count(const Workspace& ws, const gp_gaussians* g, const gp_volume_grid* grid,
+                            const gp_render_opts* o, const VoxLaunch& L, hipStream_t s);
+hipError_t launch_vox_emit(const Workspace& ws, const gp_gaussians* g, const gp_volume_grid* grid,
+                           const gp_render_opts* o, const VoxLaunch& L, hipStream_t s);
+hipError_t launch_vox_ranges(const Workspace& ws, const VoxLaunch& L, uint32_t n_inst, hipStream_t s);
+hipError_t launch_vox_fwd(const Workspace& ws, const gp_gaussians* g, const gp_volume_grid* grid,
+                          const gp_render_opts* o, const VoxLaunch& L, float* vol, hipStream_t s);
+hipError_t launch_vox_bwd(const Workspace& ws, const gp_gaussians* g, const gp_volume_grid* grid,
+                          const gp_render_opts* o, const VoxLaunch& L, const float* gvol, float* grad,
+                          int64_t grad_stride, hipStream_t s);
 // k_densify.hip
 hipError_t launch_densify(const float* p, const float* m, const float* v, int64_t n, int64_t stride,
                           const float* grad_norm, const int32_t* count, const float* max_radius, const float* noise,

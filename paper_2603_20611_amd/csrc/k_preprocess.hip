@@ -184,18 +184,59 @@ __device__ __forceinline__ void count_one(const PreArgs& a, int n_groups, int t)
   if ((t & 63) == 0) a.wave_cnt[t >> 6] = make_uint2(sr, si);
 }
 
-template <int DT>
-__device__ __forceinline__ void emit_one(const PreArgs& a, int n_groups, int t) {
-  const int lane = t & 63;
-  const uint32_t nrec = a.g_nrec[t], ninst = a.g_ninst[t];
-  // exclusive prefix within the wavefront + the wavefront's base
+// Image quantities of a kept (Gaussian, slice) pair (binary32; not part of the
+// membership specification).
+__device__ __forceinline__ void make_record(const Loaded& L, const SliceDev& sl, const SpecAxial& ax,
+                                            const SpecRect& rect, int k, uint32_t ibase, RecPay& pay,
+                                            RecMeta& meta) {
+  const SpecCov& c = L.c;
+  const float B = rect.w * c.sxy - c.a01 * rect.invD;
+  const float det = rect.w * c.a22 + c.detS * rect.invD;
+  const float rho = expf(-0.5f * ax.q);
+  const float at = L.p[10] * rho / sqrtf(det);
+  const float inv_det = 1.0f / det;
+  const float ca = rect.C * inv_det, cb = -B * inv_det, cc = rect.A * inv_det;
+  pay.x = (rect.mx - sl.x0) / sl.dx - 0.5f;
+  pay.y = (rect.my - sl.y0) / sl.dy - 0.5f;
+  pay.a = -0.5f * kLog2e * ca * sl.dx * sl.dx;
+  pay.b = -kLog2e * cb * sl.dx * sl.dy;
+  pay.c = -0.5f * kLog2e * cc * sl.dy * sl.dy;
+  pay.w = at;
+  const bool good = det > 0.0f && isfinite(at) && isfinite(pay.x) && isfinite(pay.y) && isfinite(pay.a) &&
+                    isfinite(pay.b) && isfinite(pay.c);
+  if (!good) pay.x = pay.y = pay.a = pay.b = pay.c = pay.w = 0.0f;
+  pay.g = exp2f(2.0f * pay.a);
+  pay.gid = (uint32_t)L.j;
+  meta.ibase = ibase;
+  meta.rx = (uint32_t)rect.tx0 | ((uint32_t)rect.tx1 << 16);
+  meta.ry = (uint32_t)rect.ty0 | ((uint32_t)rect.ty1 << 16);
+  meta.slice = (uint32_t)k;
+}
+
+// Emit of the 64 consecutive Gaussians t0 .. t0 + 63 by one wavefront.
+//
+// Record and instance slots come from an exclusive scan over the wavefront
+// (plus the wavefront's base), so the wavefront's output is one contiguous
+// range of records and one of instances.  W lanes cooperate on one Gaussian:
+// lane i of the group takes slices kb + i, kb + i + W, ... of its kept window,
+// and the group's kept slices are compacted with a ballot, so consecutive
+// lanes write consecutive records and adjacent instance runs.  (With one lane
+// per Gaussian and many slices per Gaussian, every lane would stream to its own
+// region and L2 would evict partly written lines.)  W = 1 is the one-lane
+// form, used when each Gaussian has at most one slice.
+template <int DT, int W>
+__device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0) {
+  const int lane = threadIdx.x & 63;
+  const int t = t0 + lane;
+  uint32_t nrec = a.g_nrec[t];
+  const uint32_t ninst = a.g_ninst[t];
   uint32_t pr = nrec, pi = ninst;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const uint32_t ur = __shfl_up(pr, d, 64), ui = __shfl_up(pi, d, 64);
     if (lane >= d) { pr += ur; pi += ui; }
   }
-  const uint2 wb = a.wave_cnt[t >> 6];
+  const uint2 wb = a.wave_cnt[t0 >> 6];
   const uint32_t rbase = wb.x + pr - nrec, ibase = wb.y + pi - ninst;
   const bool fits = (uint64_t)rbase + nrec <= a.rc.rec_cap && (uint64_t)ibase + ninst <= a.rc.inst_cap;
   a.g_rbase[t] = rbase;
@@ -206,53 +247,68 @@ __device__ __forceinline__ void emit_one(const PreArgs& a, int n_groups, int t) 
     a.g_nrec[t] = 0u;
     for (uint32_t r = rbase; r < rbase + nrec && r < a.rc.rec_cap; ++r) a.rec_meta[r].slice = kInvalidSlice;
     for (uint32_t s = ibase; s < ibase + ninst && s < a.rc.inst_cap; ++s) a.inst_key[s] = a.sentinel_bin;
-    return;
+    nrec = 0u;
   }
-  if (nrec == 0) return;
-  Loaded L;
-  load_gaussian<DT>(a, n_groups, t, L);
-  const uint32_t kr = a.g_krange[t];
-  const int kb = (int)(kr & 0xFFFFu), ke = (int)(kr >> 16);
-  uint32_t rid = rbase, slot = ibase;
-  for (int k = kb; k < ke; ++k) {
-    SpecAxial ax;
-    SpecRect rect;
-    if (!footprint(a, L, k, ax, rect)) continue;
-    const SliceDev& sl = a.slices[k];
-    // image quantities (binary32; not part of the membership specification)
-    const SpecCov& c = L.c;
-    RecPay pay;
-    const float B = rect.w * c.sxy - c.a01 * rect.invD;
-    const float det = rect.w * c.a22 + c.detS * rect.invD;
-    const float rho = expf(-0.5f * ax.q);
-    const float at = L.p[10] * rho / sqrtf(det);
-    const float inv_det = 1.0f / det;
-    const float ca = rect.C * inv_det, cb = -B * inv_det, cc = rect.A * inv_det;
-    pay.x = (rect.mx - sl.x0) / sl.dx - 0.5f;
-    pay.y = (rect.my - sl.y0) / sl.dy - 0.5f;
-    pay.a = -0.5f * kLog2e * ca * sl.dx * sl.dx;
-    pay.b = -kLog2e * cb * sl.dx * sl.dy;
-    pay.c = -0.5f * kLog2e * cc * sl.dy * sl.dy;
-    pay.w = at;
-    const bool good = det > 0.0f && isfinite(at) && isfinite(pay.x) && isfinite(pay.y) && isfinite(pay.a) &&
-                      isfinite(pay.b) && isfinite(pay.c);
-    if (!good) pay.x = pay.y = pay.a = pay.b = pay.c = pay.w = 0.0f;
-    pay.g = exp2f(2.0f * pay.a);
-    pay.gid = (uint32_t)L.j;
-    RecMeta meta;
-    meta.ibase = slot;
-    meta.rx = (uint32_t)rect.tx0 | ((uint32_t)rect.tx1 << 16);
-    meta.ry = (uint32_t)rect.ty0 | ((uint32_t)rect.ty1 << 16);
-    meta.slice = (uint32_t)k;
-    a.rec_pay[rid] = pay;
-    a.rec_meta[rid] = meta;
-    for (int ty = rect.ty0; ty <= rect.ty1; ++ty) {
-      for (int tx = rect.tx0; tx <= rect.tx1; ++tx, ++slot) {
-        a.inst_key[slot] = (uint32_t)(sl.tile_base + ty * sl.ntx + tx);
-        a.inst_val[slot] = rid;
+  const uint32_t krange = a.g_krange[t];
+  const int sub = lane / W, li = lane % W;
+  for (int it = 0; it < W; ++it) {
+    // 64 / W groups per round, W rounds: Gaussian gi of the 64.  Every lane
+    // takes part in the exchanges; divergence starts after them.
+    const int gi = it * (64 / W) + sub;
+    const uint32_t g_nrec = __shfl(nrec, gi, 64);
+    const uint32_t g_rb = __shfl(rbase, gi, 64);
+    const uint32_t g_ib = __shfl(ibase, gi, 64);
+    const uint32_t g_kr = __shfl(krange, gi, 64);
+    if (g_nrec == 0u) continue;
+    Loaded L;
+    load_gaussian<DT>(a, n_groups, t0 + gi, L);
+    const int kb = (int)(g_kr & 0xFFFFu), ke = (int)(g_kr >> 16);
+    uint32_t rec_run = g_rb, inst_run = g_ib;
+    for (int c0 = kb; c0 < ke; c0 += W) {
+      const int k = c0 + li;
+      SpecAxial ax;
+      SpecRect rect;
+      const bool kept = k < ke && footprint(a, L, k, ax, rect);
+      const uint32_t nt = kept ? (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1)) : 0u;
+      uint32_t rpos = 0u, ipos = 0u, rtot = 1u, itot = nt;
+      if (W > 1) {
+        const uint64_t m = __ballot(kept);
+        const uint32_t gm = (uint32_t)(m >> (sub * W)) & (uint32_t)((1ull << W) - 1ull);
+        rpos = (uint32_t)__popc(gm & ((1u << li) - 1u));
+        rtot = (uint32_t)__popc(gm);
+        uint32_t inc = nt;
+#pragma unroll
+        for (int d = 1; d < W; d <<= 1) {
+          const uint32_t u = __shfl_up(inc, d, W);
+          if (li >= d) inc += u;
+        }
+        ipos = inc - nt;
+        itot = __shfl(inc, W - 1, W);
+      }
+      if (kept) {
+        const SliceDev& sl = a.slices[k];
+        const uint32_t rid = rec_run + rpos;
+        uint32_t slot = inst_run + ipos;
+        RecPay pay;
+        RecMeta meta;
+        make_record(L, sl, ax, rect, k, slot, pay, meta);
+        a.rec_pay[rid] = pay;
+        a.rec_meta[rid] = meta;
+        for (int ty = rect.ty0; ty <= rect.ty1; ++ty) {
+          for (int tx = rect.tx0; tx <= rect.tx1; ++tx, ++slot) {
+            a.inst_key[slot] = (uint32_t)(sl.tile_base + ty * sl.ntx + tx);
+            a.inst_val[slot] = rid;
+          }
+        }
+      }
+      if (W > 1) {
+        rec_run += rtot;
+        inst_run += itot;
+      } else if (kept) {
+        rec_run += 1u;
+        inst_run += nt;
       }
     }
-    ++rid;
   }
 }
 
@@ -266,12 +322,24 @@ __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
   for (int t = blockIdx.x * 256 + threadIdx.x; (t & ~63) < total; t += stride) count_one<DT>(a, n_groups, t);
 }
 
-template <int DT>
+template <int DT, int W>
 __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   const int stride = gridDim.x * 256;
-  for (int t = blockIdx.x * 256 + threadIdx.x; (t & ~63) < total; t += stride) emit_one<DT>(a, n_groups, t);
+  for (int t0 = blockIdx.x * 256 + (threadIdx.x & ~63); t0 < total; t0 += stride) emit_wave<DT, W>(a, n_groups, t0);
+}
+
+template <int DT>
+hipError_t launch_emit_dt(const PreArgs& a, int width, unsigned blocks, hipStream_t s) {
+  switch (width) {
+    case 16: k_pre_emit<DT, 16><<<blocks, 256, 0, s>>>(a); break;
+    case 8: k_pre_emit<DT, 8><<<blocks, 256, 0, s>>>(a); break;
+    case 4: k_pre_emit<DT, 4><<<blocks, 256, 0, s>>>(a); break;
+    case 2: k_pre_emit<DT, 2><<<blocks, 256, 0, s>>>(a); break;
+    default: k_pre_emit<DT, 1><<<blocks, 256, 0, s>>>(a); break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -318,12 +386,11 @@ hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const Lau
   int64_t blocks = (d.gauss + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   switch (rc.attr_dtype) {
-    case GP_BF16: k_pre_emit<GP_BF16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    case GP_F16: k_pre_emit<GP_F16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    case GP_Q16: k_pre_emit<GP_Q16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    default: k_pre_emit<GP_F32><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    case GP_BF16: return launch_emit_dt<GP_BF16>(a, d.emit_width, (unsigned)blocks, s);
+    case GP_F16: return launch_emit_dt<GP_F16>(a, d.emit_width, (unsigned)blocks, s);
+    case GP_Q16: return launch_emit_dt<GP_Q16>(a, d.emit_width, (unsigned)blocks, s);
+    default: return launch_emit_dt<GP_F32>(a, d.emit_width, (unsigned)blocks, s);
   }
-  return hipGetLastError();
 }
 
 }  // namespace gp

@@ -53,11 +53,25 @@ struct FwdArgs {
 // 2^-27 of the record's peak, and s is clamped at 126 so 2^s stays finite.
 constexpr float kSmoothA = -4.0f;
 
-__device__ __forceinline__ uint32_t wave_take(uint32_t* counter) {
-  uint32_t v = 0;
-  if (__lane_id() == 0) v = atomicAdd(counter, 1u);
-  return __builtin_amdgcn_readfirstlane(v);
+// Work order and placement.  Workgroups are dispatched to the XCDs round-robin,
+// so workgroup b runs on XCD b mod 8; each XCD first drains its own queue, a
+// contiguous eighth of the work items, then helps the others.  With a common
+// tile grid, item i walks the tiles of groups of kSliceGroup consecutive
+// slices tile by tile: the slices of one group are neighbours in z, so a
+// Gaussian's records for them share cache lines (records are stored Gaussian
+// by Gaussian, slice by slice), and neighbouring tiles share records; both
+// then hit in the XCD's own L2 instead of being fetched again from HBM.
+constexpr int kSliceGroup = 4;
+
+__device__ __forceinline__ int item_bin(int i, int n_slices, int tps) {
+  if (tps <= 0) return i;
+  const int gsz = kSliceGroup * tps;
+  const int g = i / gsz, r = i - g * gsz;
+  const int gs = min(kSliceGroup, n_slices - g * kSliceGroup);
+  const int t = r / gs;
+  return (g * kSliceGroup + (r - t * gs)) * tps + t;
 }
+
 
 // One 64-lane workgroup; tiles are pulled from an atomic work counter (the next
 // index is requested before the current tile is rendered).
@@ -69,10 +83,12 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   const int lane = threadIdx.x;
   const int row = lane >> 2;
   const int col0 = (lane & 3) * 4;
-  uint32_t next = wave_take(&a.work[kWorkRasterFwd]);
-  while (next < (uint32_t)n_bins) {
-    const int bin = (int)next;
-    next = wave_take(&a.work[kWorkRasterFwd]);
+  const int tps = a.hdr->tiles_per_slice;
+  WorkQueues wq(a.work + kWorkRasterFwd, n_bins, blockIdx.x);
+  int next = wq.take_wave();
+  while (next >= 0) {
+    const int bin = item_bin(next, n_slices, tps);
+    next = wq.take_wave();
     const int k = slice_of_bin(a.slices, n_slices, bin);
     const SliceDev sl = a.slices[k];
     const int tile = bin - sl.tile_base;
@@ -97,7 +113,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
       buf0[lane] = n0;
       buf1[lane] = n1;
       __syncthreads();
-      const int cnt = (int)min(64u, end - base);
+      const int cnt = __builtin_amdgcn_readfirstlane((int)min(64u, end - base));
       const uint32_t nb = base + 64;
       if (nb + lane < end) {
         const float4* src = reinterpret_cast<const float4*>(a.rec_pay + rid_next);
@@ -113,31 +129,27 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
         const float cy = r1.x * dy * dy;
         const float d0 = fx0 - r0.x;
         const float ra = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(r0.z)));
+        const float p0 = fmaf(fmaf(r0.z, d0, by), d0, cy);
+        const float e0 = __builtin_amdgcn_exp2f(p0);
+        float e1, e2, e3;
         if (ra >= kSmoothA) {
-          const float p0 = fmaf(fmaf(r0.z, d0, by), d0, cy);
           const float s0 = fminf(fmaf(r0.z, fmaf(d0, 2.0f, 1.0f), by), 126.0f);
-          const float e0 = __builtin_amdgcn_exp2f(p0);
           float q = __builtin_amdgcn_exp2f(s0);
-          const float e1 = e0 * q;
+          e1 = e0 * q;
           q *= r1.z;
-          const float e2 = e1 * q;
+          e2 = e1 * q;
           q *= r1.z;
-          const float e3 = e2 * q;
-          acc0 = fmaf(r1.y, e0, acc0);
-          acc1 = fmaf(r1.y, e1, acc1);
-          acc2 = fmaf(r1.y, e2, acc2);
-          acc3 = fmaf(r1.y, e3, acc3);
+          e3 = e2 * q;
         } else {
           const float d1 = d0 + 1.0f, d2 = d0 + 2.0f, d3 = d0 + 3.0f;
-          const float p0 = fmaf(fmaf(r0.z, d0, by), d0, cy);
-          const float p1 = fmaf(fmaf(r0.z, d1, by), d1, cy);
-          const float p2 = fmaf(fmaf(r0.z, d2, by), d2, cy);
-          const float p3 = fmaf(fmaf(r0.z, d3, by), d3, cy);
-          acc0 = fmaf(r1.y, __builtin_amdgcn_exp2f(p0), acc0);
-          acc1 = fmaf(r1.y, __builtin_amdgcn_exp2f(p1), acc1);
-          acc2 = fmaf(r1.y, __builtin_amdgcn_exp2f(p2), acc2);
-          acc3 = fmaf(r1.y, __builtin_amdgcn_exp2f(p3), acc3);
+          e1 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d1, by), d1, cy));
+          e2 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d2, by), d2, cy));
+          e3 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d3, by), d3, cy));
         }
+        acc0 = fmaf(r1.y, e0, acc0);
+        acc1 = fmaf(r1.y, e1, acc1);
+        acc2 = fmaf(r1.y, e2, acc2);
+        acc3 = fmaf(r1.y, e3, acc3);
       }
       __syncthreads();
     }
@@ -171,17 +183,19 @@ struct BwdArgs {
 // 256 lanes per tile, tiles pulled from an atomic work counter.
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   __shared__ float G[kTilePix];
-  __shared__ uint32_t s_bin;
+  __shared__ int s_item;
   const int n_bins = a.hdr->n_bins;
   const int n_slices = a.hdr->n_slices;
+  const int tps = a.hdr->tiles_per_slice;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  WorkQueues wq(a.work + kWorkRasterBwd, n_bins, blockIdx.x);
   for (;;) {
-    if (threadIdx.x == 0) s_bin = atomicAdd(&a.work[kWorkRasterBwd], 1u);
+    if (threadIdx.x == 0) s_item = wq.take_thread();
     __syncthreads();
-    const uint32_t ub = s_bin;
-    __syncthreads();   // s_bin is rewritten by the next iteration
-    if (ub >= (uint32_t)n_bins) break;
-    const int bin = (int)ub;
+    const int item = s_item;
+    __syncthreads();   // s_item is rewritten by the next iteration
+    if (item < 0) break;
+    const int bin = item_bin(item, n_slices, tps);
     const uint32_t start = a.bin_lo[bin], end = a.bin_hi[bin];
     if (start == end) continue;
     const int k = slice_of_bin(a.slices, n_slices, bin);
@@ -261,7 +275,7 @@ hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const f
                              const LaunchDims& d, hipStream_t s) {
   (void)rc;
   if (d.bins <= 0) return hipSuccess;
-  hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterBwd, 0u, 1, s);
+  hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterBwd, 0u, kXcds, s);
   if (e != hipSuccess) return e;
   BwdArgs a{ws.d_hdr, ws.d_slices, ws.d_bin_lo, ws.d_bin_hi, ws.d_list, ws.d_rec_pay, ws.d_rec_meta, grad_out,
             ws.d_moments, ws.d_work};

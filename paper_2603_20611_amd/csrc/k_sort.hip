@@ -152,43 +152,95 @@ struct RadixArgs {
   int nblocks, shift, bits;
 };
 
+// Workgroups are dispatched to the XCDs round-robin (workgroup b on XCD b mod
+// 8).  Tiles are assigned so that each XCD owns a contiguous run of them: a
+// digit's output run of one tile is followed by the same digit's run of the
+// next tile, so partial cache lines left by one workgroup are completed by its
+// neighbour in the same L2 instead of being written back half-filled.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
+  const uint32_t x = b % kXcds, i = b / kXcds;
+  return x * (nblocks / kXcds) + min(x, nblocks % kXcds) + i;
+}
+
 __global__ __launch_bounds__(256) void k_radix_hist(RadixArgs a) {
   __shared__ uint32_t h[kMaxDigits];
   const int R = 1 << a.bits;
   for (int i = threadIdx.x; i < R; i += 256) h[i] = 0u;
   __syncthreads();
   const uint32_t n = min(*a.count, a.cap);
-  const uint32_t base = blockIdx.x * kSortTile;
+  const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)a.nblocks);
+  const uint32_t base = tile * kSortTile;
   for (int i = threadIdx.x; i < kSortTile; i += 256) {
     const uint32_t j = base + i;
     if (j < n) atomicAdd(&h[(a.key_in[j] >> a.shift) & (R - 1)], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < R; i += 256) a.hist[(size_t)i * a.nblocks + blockIdx.x] = h[i];
+  for (int i = threadIdx.x; i < R; i += 256) a.hist[(size_t)i * a.nblocks + tile] = h[i];
 }
 
+// Scatter of one tile: the tile is first sorted stably by digit into LDS, then
+// written out in that order, so consecutive threads store consecutive
+// elements of each digit's run (coalesced) instead of every element landing
+// on its own cache line.
 __global__ __launch_bounds__(256) void k_radix_scatter(RadixArgs a) {
-  __shared__ uint32_t run[kMaxDigits];        // running count per digit within the block
-  __shared__ uint32_t wcnt[4][kMaxDigits];    // per-wavefront digit counts of the chunk
+  constexpr int kPer = kSortTile / 256;          // elements per thread
+  __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+  __shared__ uint32_t loc[kMaxDigits];           // local run start of each digit (exclusive scan)
+  __shared__ uint32_t run[kMaxDigits];           // running local position of each digit
+  __shared__ uint32_t glob[kMaxDigits];          // global start of this tile's run of each digit
+  __shared__ uint32_t wcnt[4][kMaxDigits];       // per-wavefront digit counts of a chunk
+  __shared__ uint32_t part[256];
   const int R = 1 << a.bits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t n = min(*a.count, a.cap);
-  const uint32_t base = blockIdx.x * kSortTile;
+  const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)a.nblocks);
+  const uint32_t base = tile * kSortTile;
   if (base >= n) return;   // whole block past the end (uniform)
-  for (int i = threadIdx.x; i < R; i += 256) run[i] = a.hist[(size_t)i * a.nblocks + blockIdx.x];
+  const uint32_t tn = min((uint32_t)kSortTile, n - base);
+  for (int i = threadIdx.x; i < R; i += 256) {
+    glob[i] = a.hist[(size_t)i * a.nblocks + tile];
+    run[i] = 0u;
+  }
+  __syncthreads();
+  // load (element c * 256 + t in register c of thread t) and count digits
+  uint32_t key[kPer], val[kPer];
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const uint32_t j = (uint32_t)(c * 256 + threadIdx.x);
+    key[c] = 0u;
+    val[c] = 0u;
+    if (j < tn) {
+      key[c] = a.key_in[base + j];
+      val[c] = a.val_in[base + j];
+      atomicAdd(&run[(key[c] >> a.shift) & (R - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the R <= 512 digit counts (two per thread)
+  {
+    const int i0 = 2 * threadIdx.x;
+    const uint32_t c0 = i0 < R ? run[i0] : 0u, c1 = i0 + 1 < R ? run[i0 + 1] : 0u;
+    uint32_t v = c0 + c1;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+      const uint32_t o = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
+      __syncthreads();
+      part[threadIdx.x] += o;
+      __syncthreads();
+    }
+    const uint32_t excl = part[threadIdx.x] - v;
+    if (i0 < R) { loc[i0] = excl; run[i0] = excl; }
+    if (i0 + 1 < R) { loc[i0 + 1] = excl + c0; run[i0 + 1] = excl + c0; }
+  }
+  // stable local ranks, chunk by chunk (chunk c = elements c * 256 .. c * 256 + 255)
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int c = 0; c < kSortTile; c += kSortChunk) {
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
     for (int i = threadIdx.x; i < R; i += 256) wcnt[0][i] = wcnt[1][i] = wcnt[2][i] = wcnt[3][i] = 0u;
     __syncthreads();
-    const uint32_t j = base + c + threadIdx.x;
-    const bool valid = j < n;
-    uint32_t key = 0, val = 0, digit = 0;
-    if (valid) {
-      key = a.key_in[j];
-      val = a.val_in[j];
-      digit = (key >> a.shift) & (R - 1);
-    }
-    // lanes of this wavefront holding the same digit
+    const bool valid = (uint32_t)(c * 256 + threadIdx.x) < tn;
+    const uint32_t digit = valid ? (key[c] >> a.shift) & (R - 1) : 0u;
     uint64_t same = __ballot(valid);
     for (int b = 0; b < a.bits; ++b) {
       const uint64_t bb = __ballot((digit >> b) & 1u);
@@ -200,13 +252,21 @@ __global__ __launch_bounds__(256) void k_radix_scatter(RadixArgs a) {
     if (valid) {
       uint32_t before = 0;
       for (int w = 0; w < wave; ++w) before += wcnt[w][digit];
-      const uint32_t dst = run[digit] + before + rank_w;
-      a.key_out[dst] = key;
-      a.val_out[dst] = val;
+      const uint32_t p = run[digit] + before + rank_w;
+      sk[p] = key[c];
+      sv[p] = val[c];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < R; i += 256) run[i] += wcnt[0][i] + wcnt[1][i] + wcnt[2][i] + wcnt[3][i];
-    __syncthreads();
+    __syncthreads();   // wcnt is cleared by the next chunk
+  }
+  // write out in local order: runs of one digit go to consecutive addresses
+  for (uint32_t p = threadIdx.x; p < tn; p += 256) {
+    const uint32_t k = sk[p];
+    const uint32_t d = (k >> a.shift) & (R - 1);
+    const uint32_t dst = glob[d] + (p - loc[d]);
+    a.key_out[dst] = k;
+    a.val_out[dst] = sv[p];
   }
 }
 

@@ -205,3 +205,28 @@ def densify_prune(params, m, v, grad_norm, count, max_radius, noise, cfg=None, n
                                       _ptr(count), _ptr(max_radius), _ptr(noise), C.byref(cfg), _ptr(po),
                                       _ptr(mo), _ptr(vo), po.stride(0), C.byref(n_out), _stream()))
     return po, mo, vo, n_out.value
+
+
+def voxelize(params, grid, ws, opts=None, out=None, n=None, attrs=None, attr_dtype=B.GP_F32):
+    """Intensity volume [nz * ny * nx] (flat float32) of the Gaussians on a voxel grid
+    (dict with nx, ny, nz and optional x0, y0, z0, dx, dy, dz)."""
+    g = B.make_grid(grid)
+    opts = opts or B.default_opts()
+    if out is None:
+        out = torch.empty(g.nx * g.ny * g.nz, device=params.device, dtype=torch.float32)
+    gs = gaussians_struct(params, n, attrs, attr_dtype)
+    B.check(B.load().gp_voxelize(ws.handle, C.byref(gs), C.byref(g), C.byref(opts), _ptr(out), _stream()))
+    return out
+
+
+def voxelize_backward(params, grid, grad_volume, ws, opts=None, grad=None, n=None, attrs=None,
+                      attr_dtype=B.GP_F32):
+    """Adds dL/dparams of L = sum grad_volume * V into grad ([11, stride]; created if None)."""
+    g = B.make_grid(grid)
+    opts = opts or B.default_opts()
+    if grad is None:
+        grad = torch.zeros_like(params)
+    gs = gaussians_struct(params, n, attrs, attr_dtype)
+    B.check(B.load().gp_voxelize_backward(ws.handle, C.byref(gs), C.byref(g), C.byref(opts), _ptr(grad_volume),
+                                          _ptr(grad), grad.stride(0), _stream()))
+    return grad
