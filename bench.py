@@ -164,6 +164,34 @@ def serving_leg(dev, n_requests, seed=3):
     return result
 
 
+def voxel_leg(params, dev, steps=10):
+    """Voxeliser on the workload's volume: the learnable Gaussians into 256 x 256 x
+    400 unit voxels (the target stack's grid), forward and backward."""
+    import torch
+    from paper_2603_20611_amd import render
+    grid = dict(nx=RES, ny=RES, nz=N_SLICES, x0=0.0, y0=0.0, z0=0.0, dx=1.0, dy=1.0, dz=1.0)
+    ws = render.Workspace()
+    vol = torch.empty(RES * RES * N_SLICES, device=dev)
+    gvol = torch.ones_like(vol)
+    grad = torch.zeros_like(params)
+    for _ in range(2):
+        render.voxelize(params, grid, ws, out=vol)
+        render.voxelize_backward(params, grid, gvol, ws, grad=grad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        render.voxelize(params, grid, ws, out=vol)
+    torch.cuda.synchronize()
+    t_f = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        render.voxelize_backward(params, grid, gvol, ws, grad=grad)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / steps
+    return {"grid": [RES, RES, N_SLICES], "forward_ms": round(1e3 * t_f, 4), "fps": round(1.0 / t_f, 1),
+            "backward_ms": round(1e3 * t_b, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +342,9 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel_ms": round(raster_ms, 4)},
     }
+    log("voxeliser")
+    result["voxelize"] = voxel_leg(params, dev)
+    log(f"voxelize: {result['voxelize']}")
     if not args.no_serving:
         result["serving"] = serving_leg(dev, args.serving_requests)
     if not args.no_cpu:

@@ -75,30 +75,37 @@ struct WorkQueues {
   uint32_t* ctr;   // kXcds counters
   int n_items, home, tried;
 
+  WorkQueues() = default;
   __device__ WorkQueues(uint32_t* c, int n, unsigned block) : ctr(c), n_items(n), home((int)(block % kXcds)), tried(0) {}
 
-  // Next work item (0 <= item < n_items) for the calling wavefront, or -1.
-  __device__ __forceinline__ int take_wave() {
-    while (tried < kXcds) {
+  __device__ __forceinline__ int first(int q) const { return (int)((int64_t)q * n_items / kXcds); }
+
+  // A ticket is requested one item ahead and resolved when the next item is
+  // needed, so the atomic's latency overlaps the current item's work.
+  __device__ __forceinline__ uint32_t issue_wave() { return wave_take(&ctr[(home + tried) % kXcds]); }
+
+  // Item (0 <= item < n_items) of a ticket, moving on to the next queue while
+  // the current one is exhausted; -1 when all are.
+  __device__ __forceinline__ int resolve_wave(uint32_t c) {
+    for (;;) {
       const int q = (home + tried) % kXcds;
-      const int lo = (int)((int64_t)q * n_items / kXcds), hi = (int)((int64_t)(q + 1) * n_items / kXcds);
-      const uint32_t c = wave_take(&ctr[q]);
+      const int lo = first(q), hi = first(q + 1);
       if ((int64_t)lo + c < hi) return lo + (int)c;
-      ++tried;
+      if (++tried >= kXcds) return -1;
+      c = wave_take(&ctr[(home + tried) % kXcds]);
     }
-    return -1;
   }
 
-  // The same for a whole workgroup (thread 0 takes; the caller broadcasts).
-  __device__ __forceinline__ int take_thread() {
-    while (tried < kXcds) {
+  // The same for one thread acting for its workgroup.
+  __device__ __forceinline__ uint32_t issue_thread() { return atomicAdd(&ctr[(home + tried) % kXcds], 1u); }
+  __device__ __forceinline__ int resolve_thread(uint32_t c) {
+    for (;;) {
       const int q = (home + tried) % kXcds;
-      const int lo = (int)((int64_t)q * n_items / kXcds), hi = (int)((int64_t)(q + 1) * n_items / kXcds);
-      const uint32_t c = atomicAdd(&ctr[q], 1u);
+      const int lo = first(q), hi = first(q + 1);
       if ((int64_t)lo + c < hi) return lo + (int)c;
-      ++tried;
+      if (++tried >= kXcds) return -1;
+      c = atomicAdd(&ctr[(home + tried) % kXcds], 1u);
     }
-    return -1;
   }
 };
 

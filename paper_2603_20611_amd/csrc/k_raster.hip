@@ -53,24 +53,6 @@ struct FwdArgs {
 // 2^-27 of the record's peak, and s is clamped at 126 so 2^s stays finite.
 constexpr float kSmoothA = -4.0f;
 
-// Work order and placement.  Workgroups are dispatched to the XCDs round-robin,
-// so workgroup b runs on XCD b mod 8; each XCD first drains its own queue, a
-// contiguous eighth of the work items, then helps the others.  With a common
-// tile grid, item i walks the tiles of groups of kSliceGroup consecutive
-// slices tile by tile: the slices of one group are neighbours in z, so a
-// Gaussian's records for them share cache lines (records are stored Gaussian
-// by Gaussian, slice by slice), and neighbouring tiles share records; both
-// then hit in the XCD's own L2 instead of being fetched again from HBM.
-constexpr int kSliceGroup = 4;
-
-__device__ __forceinline__ int item_bin(int i, int n_slices, int tps) {
-  if (tps <= 0) return i;
-  const int gsz = kSliceGroup * tps;
-  const int g = i / gsz, r = i - g * gsz;
-  const int gs = min(kSliceGroup, n_slices - g * kSliceGroup);
-  const int t = r / gs;
-  return (g * kSliceGroup + (r - t * gs)) * tps + t;
-}
 
 
 // One 64-lane workgroup; tiles are pulled from an atomic work counter (the next
@@ -83,12 +65,10 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   const int lane = threadIdx.x;
   const int row = lane >> 2;
   const int col0 = (lane & 3) * 4;
-  const int tps = a.hdr->tiles_per_slice;
   WorkQueues wq(a.work + kWorkRasterFwd, n_bins, blockIdx.x);
-  int next = wq.take_wave();
-  while (next >= 0) {
-    const int bin = item_bin(next, n_slices, tps);
-    next = wq.take_wave();
+  for (int item = wq.resolve_wave(wq.issue_wave()); item >= 0;) {
+    const int bin = item;
+    const uint32_t ticket = wq.issue_wave();
     const int k = slice_of_bin(a.slices, n_slices, bin);
     const SliceDev sl = a.slices[k];
     const int tile = bin - sl.tile_base;
@@ -164,6 +144,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
         if (px0 + 3 < sl.width) o[px0 + 3] = acc3;
       }
     }
+    item = wq.resolve_wave(ticket);
   }
 }
 
@@ -186,16 +167,19 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   __shared__ int s_item;
   const int n_bins = a.hdr->n_bins;
   const int n_slices = a.hdr->n_slices;
-  const int tps = a.hdr->tiles_per_slice;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  WorkQueues wq(a.work + kWorkRasterBwd, n_bins, blockIdx.x);
+  // one shared counter: the per-XCD queues' bookkeeping costs this kernel
+  // 17 VGPRs (occupancy 8 -> 6 waves per SIMD) for no gain
   for (;;) {
-    if (threadIdx.x == 0) s_item = wq.take_thread();
+    if (threadIdx.x == 0) {
+      const uint32_t c = atomicAdd(&a.work[kWorkRasterBwd], 1u);
+      s_item = c < (uint32_t)n_bins ? (int)c : -1;
+    }
     __syncthreads();
     const int item = s_item;
     __syncthreads();   // s_item is rewritten by the next iteration
     if (item < 0) break;
-    const int bin = item_bin(item, n_slices, tps);
+    const int bin = item;
     const uint32_t start = a.bin_lo[bin], end = a.bin_hi[bin];
     if (start == end) continue;
     const int k = slice_of_bin(a.slices, n_slices, bin);
@@ -275,7 +259,7 @@ hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const f
                              const LaunchDims& d, hipStream_t s) {
   (void)rc;
   if (d.bins <= 0) return hipSuccess;
-  hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterBwd, 0u, kXcds, s);
+  hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterBwd, 0u, 1, s);
   if (e != hipSuccess) return e;
   BwdArgs a{ws.d_hdr, ws.d_slices, ws.d_bin_lo, ws.d_bin_hi, ws.d_list, ws.d_rec_pay, ws.d_rec_meta, grad_out,
             ws.d_moments, ws.d_work};

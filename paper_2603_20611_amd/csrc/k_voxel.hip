@@ -181,7 +181,8 @@ __global__ __launch_bounds__(64) void k_vox_fwd(VoxArgs a) {
   const int lane = threadIdx.x;
   const int lx = lane & 7, ly = lane >> 3;
   WorkQueues wq(a.work + kWorkRasterFwd, a.n_tiles, blockIdx.x);
-  for (int tile = wq.take_wave(); tile >= 0; tile = wq.take_wave()) {
+  for (int tile = wq.resolve_wave(wq.issue_wave()); tile >= 0;) {
+    const uint32_t ticket = wq.issue_wave();
     int tx, ty, tz;
     vox_tile_xyz(a, tile, &tx, &ty, &tz);
     const float fx = (float)(tx * kVT + lx), fy = (float)(ty * kVT + ly), fz0 = (float)(tz * kVT);
@@ -222,6 +223,7 @@ __global__ __launch_bounds__(64) void k_vox_fwd(VoxArgs a) {
         if (iz < a.nz) a.vol[((int64_t)iz * a.ny + iy) * a.nx + ix] = acc[k];
       }
     }
+    tile = wq.resolve_wave(ticket);
   }
 }
 
@@ -231,14 +233,15 @@ __global__ __launch_bounds__(256) void k_vox_bwd(VoxArgs a) {
   __shared__ int s_item;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   WorkQueues wq(a.work + kWorkRasterBwd, a.n_tiles, blockIdx.x);
-  for (;;) {
-    if (threadIdx.x == 0) s_item = wq.take_thread();
-    __syncthreads();
-    const int tile = s_item;
-    __syncthreads();
-    if (tile < 0) break;
+  if (threadIdx.x == 0) s_item = wq.resolve_thread(wq.issue_thread());
+  __syncthreads();
+  int tile = s_item;
+  __syncthreads();   // s_item is rewritten at the end of the first tile
+  while (tile >= 0) {
+    uint32_t ticket = 0u;
+    if (threadIdx.x == 0) ticket = wq.issue_thread();
     const uint32_t start = a.tile_lo[tile], end = a.tile_hi[tile];
-    if (start == end) continue;
+    if (start != end) {
     int tx, ty, tz;
     vox_tile_xyz(a, tile, &tx, &ty, &tz);
     for (int v = threadIdx.x; v < kVTVox; v += 256) {
@@ -299,7 +302,12 @@ __global__ __launch_bounds__(256) void k_vox_bwd(VoxArgs a) {
       a.mom[K + slot] = make_float4(Mxx, Myy, Mzz, Mxy);
       a.mom[2 * K + slot] = make_float4(Mxz, Myz, 0.f, 0.f);
     }
+    __syncthreads();   // G[] is reused by the next tile
+    }
+    if (threadIdx.x == 0) s_item = wq.resolve_thread(ticket);
     __syncthreads();
+    tile = s_item;
+    __syncthreads();   // s_item is rewritten at the end of this tile
   }
 }
 
