@@ -55,40 +55,81 @@ constexpr float kSmoothA = -4.0f;
 
 
 
-// One 64-lane workgroup; tiles are pulled from an atomic work counter (the next
-// index is requested before the current tile is rendered).
+__device__ __forceinline__ int slice_of(const FwdArgs& a, int n_slices, int tps, int bin) {
+  return tps > 0 ? bin / tps : slice_of_bin(a.slices, n_slices, bin);
+}
+
+// One 64-lane workgroup per tile, tiles taken from a shared counter.  Two
+// software pipelines hide the memory latency: within a tile, record ids are
+// loaded two batches ahead and records one batch ahead; across tiles, the next
+// tile is fetched one step per batch of the current one (its queue ticket is
+// resolved and its list range loaded after the first batch, its slice found
+// and first ids loaded after the second, its first records gathered after the
+// third), so a new tile rarely starts by waiting on memory.
 __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   __shared__ float4 buf0[64];   // x, y, a, b of the batch's records
   __shared__ float4 buf1[64];   // c, w, g, gid
   const int n_bins = a.hdr->n_bins;
   const int n_slices = a.hdr->n_slices;
+  const int tps = a.hdr->tiles_per_slice;
   const int lane = threadIdx.x;
   const int row = lane >> 2;
   const int col0 = (lane & 3) * 4;
-  WorkQueues wq(a.work + kWorkRasterFwd, n_bins, blockIdx.x);
-  for (int item = wq.resolve_wave(wq.issue_wave()); item >= 0;) {
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  uint32_t* counter = a.work + kWorkRasterFwd;
+  auto item_of = [&](uint32_t t) { return t < (uint32_t)n_bins ? (int)t : -1; };
+
+  // the first tile, fetched without overlap
+  int item = item_of(wave_take(counter));
+  if (item < 0) return;
+  uint32_t start = a.bin_lo[item], end = a.bin_hi[item];
+  int k = slice_of(a, n_slices, tps, item);
+  float4 n0 = zero4, n1 = zero4;
+  if (start + lane < end) {
+    const float4* src = reinterpret_cast<const float4*>(a.rec_pay + a.list[start + lane]);
+    n0 = src[0];
+    n1 = src[1];
+  }
+  uint32_t rid_next = (start + 64 + lane < end) ? a.list[start + 64 + lane] : 0u;
+  uint32_t ticket = wave_take(counter);
+
+  while (item >= 0) {
     const int bin = item;
-    const uint32_t ticket = wq.issue_wave();
-    const int k = slice_of_bin(a.slices, n_slices, bin);
     const SliceDev sl = a.slices[k];
     const int tile = bin - sl.tile_base;
     const int tx = tile % sl.ntx, ty = tile / sl.ntx;
     const int px0 = tx * kTile + col0;
     const int py = ty * kTile + row;
     const float fx0 = (float)px0, fy = (float)py;
-
-    const uint32_t start = a.bin_lo[bin], end = a.bin_hi[bin];
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
 
-    // software pipeline: record ids are loaded two batches ahead and records
-    // one batch ahead, so no gather waits on the id load it depends on
-    float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
-    if (start + lane < end) {
-      const float4* src = reinterpret_cast<const float4*>(a.rec_pay + a.list[start + lane]);
-      n0 = src[0];
-      n1 = src[1];
-    }
-    uint32_t rid_next = (start + 64 + lane < end) ? a.list[start + 64 + lane] : 0u;
+    // next tile, advanced one stage per batch
+    int nitem = -1, nk = 0, stage = 0;
+    uint32_t ns = 0u, ne = 0u, nrid = 0u, nrid2 = 0u;
+    float4 m0 = zero4, m1 = zero4;
+    auto advance = [&]() {
+      if (stage == 0) {
+        nitem = item_of(ticket);
+        if (nitem >= 0) {
+          ns = a.bin_lo[nitem];
+          ne = a.bin_hi[nitem];
+        }
+      } else if (stage == 1) {
+        if (nitem >= 0) {
+          nk = slice_of(a, n_slices, tps, nitem);
+          if (ns + lane < ne) nrid = a.list[ns + lane];
+          if (ns + 64 + lane < ne) nrid2 = a.list[ns + 64 + lane];
+        }
+      } else if (stage == 2) {
+        if (nitem >= 0 && ns + lane < ne) {
+          const float4* src = reinterpret_cast<const float4*>(a.rec_pay + nrid);
+          m0 = src[0];
+          m1 = src[1];
+        }
+      }
+      ++stage;
+    };
+
     for (uint32_t base = start; base < end; base += 64) {
       buf0[lane] = n0;
       buf1[lane] = n1;
@@ -131,8 +172,11 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
         acc2 = fmaf(r1.y, e2, acc2);
         acc3 = fmaf(r1.y, e3, acc3);
       }
+      if (stage < 3) advance();
       __syncthreads();
     }
+    while (stage < 3) advance();   // short tiles: finish fetching the next one
+
     if (py < sl.height) {
       float* o = sl.out + (int64_t)py * sl.width;
       if (px0 + 3 < sl.width && (reinterpret_cast<uintptr_t>(o + px0) & 15) == 0) {
@@ -144,7 +188,15 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
         if (px0 + 3 < sl.width) o[px0 + 3] = acc3;
       }
     }
-    item = wq.resolve_wave(ticket);
+    // the next tile becomes the current one
+    item = nitem;
+    start = ns;
+    end = ne;
+    k = nk;
+    n0 = m0;
+    n1 = m1;
+    rid_next = nrid2;
+    if (item >= 0) ticket = wave_take(counter);
   }
 }
 
@@ -168,8 +220,6 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   const int n_bins = a.hdr->n_bins;
   const int n_slices = a.hdr->n_slices;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // one shared counter: the per-XCD queues' bookkeeping costs this kernel
-  // 17 VGPRs (occupancy 8 -> 6 waves per SIMD) for no gain
   for (;;) {
     if (threadIdx.x == 0) {
       const uint32_t c = atomicAdd(&a.work[kWorkRasterBwd], 1u);

@@ -152,23 +152,13 @@ struct RadixArgs {
   int nblocks, shift, bits;
 };
 
-// Workgroups are dispatched to the XCDs round-robin (workgroup b on XCD b mod
-// 8).  Tiles are assigned so that each XCD owns a contiguous run of them: a
-// digit's output run of one tile is followed by the same digit's run of the
-// next tile, so partial cache lines left by one workgroup are completed by its
-// neighbour in the same L2 instead of being written back half-filled.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
-  const uint32_t x = b % kXcds, i = b / kXcds;
-  return x * (nblocks / kXcds) + min(x, nblocks % kXcds) + i;
-}
-
 __global__ __launch_bounds__(256) void k_radix_hist(RadixArgs a) {
   __shared__ uint32_t h[kMaxDigits];
   const int R = 1 << a.bits;
   for (int i = threadIdx.x; i < R; i += 256) h[i] = 0u;
   __syncthreads();
   const uint32_t n = min(*a.count, a.cap);
-  const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)a.nblocks);
+  const uint32_t tile = blockIdx.x;
   const uint32_t base = tile * kSortTile;
   for (int i = threadIdx.x; i < kSortTile; i += 256) {
     const uint32_t j = base + i;
@@ -193,7 +183,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(RadixArgs a) {
   const int R = 1 << a.bits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t n = min(*a.count, a.cap);
-  const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)a.nblocks);
+  const uint32_t tile = blockIdx.x;
   const uint32_t base = tile * kSortTile;
   if (base >= n) return;   // whole block past the end (uniform)
   const uint32_t tn = min((uint32_t)kSortTile, n - base);

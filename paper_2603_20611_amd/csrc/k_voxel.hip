@@ -11,7 +11,7 @@
 //   scan          instance slots in Gaussian order;
 //   k_vox_emit    one (tile, Gaussian) pair per tile of each box;
 //   radix sort    stable, by tile: every list ends in Gaussian order;
-//   k_vox_fwd     one wavefront per tile (work queues per XCD); lane (x, y) of
+//   k_vox_fwd     one wavefront per tile (shared work counter); lane (x, y) of
 //                 the 8 x 8 face owns the column of 8 voxels along z, so the
 //                 x-y part of the quadratic form is shared by 8 voxels.
 // Backward:
@@ -180,9 +180,10 @@ __global__ __launch_bounds__(64) void k_vox_fwd(VoxArgs a) {
   __shared__ float4 b0[64], b1[64], b2[64];
   const int lane = threadIdx.x;
   const int lx = lane & 7, ly = lane >> 3;
-  WorkQueues wq(a.work + kWorkRasterFwd, a.n_tiles, blockIdx.x);
-  for (int tile = wq.resolve_wave(wq.issue_wave()); tile >= 0;) {
-    const uint32_t ticket = wq.issue_wave();
+  uint32_t* counter = a.work + kWorkRasterFwd;
+  uint32_t t0 = wave_take(counter);
+  for (int tile = t0 < (uint32_t)a.n_tiles ? (int)t0 : -1; tile >= 0;) {
+    const uint32_t ticket = wave_take(counter);   // resolved after this tile
     int tx, ty, tz;
     vox_tile_xyz(a, tile, &tx, &ty, &tz);
     const float fx = (float)(tx * kVT + lx), fy = (float)(ty * kVT + ly), fz0 = (float)(tz * kVT);
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(64) void k_vox_fwd(VoxArgs a) {
         if (iz < a.nz) a.vol[((int64_t)iz * a.ny + iy) * a.nx + ix] = acc[k];
       }
     }
-    tile = wq.resolve_wave(ticket);
+    tile = ticket < (uint32_t)a.n_tiles ? (int)ticket : -1;
   }
 }
 
@@ -232,14 +233,16 @@ __global__ __launch_bounds__(256) void k_vox_bwd(VoxArgs a) {
   __shared__ float G[kVTVox];
   __shared__ int s_item;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  WorkQueues wq(a.work + kWorkRasterBwd, a.n_tiles, blockIdx.x);
-  if (threadIdx.x == 0) s_item = wq.resolve_thread(wq.issue_thread());
+  if (threadIdx.x == 0) {
+    const uint32_t c = atomicAdd(&a.work[kWorkRasterBwd], 1u);
+    s_item = c < (uint32_t)a.n_tiles ? (int)c : -1;
+  }
   __syncthreads();
   int tile = s_item;
   __syncthreads();   // s_item is rewritten at the end of the first tile
   while (tile >= 0) {
     uint32_t ticket = 0u;
-    if (threadIdx.x == 0) ticket = wq.issue_thread();
+    if (threadIdx.x == 0) ticket = atomicAdd(&a.work[kWorkRasterBwd], 1u);
     const uint32_t start = a.tile_lo[tile], end = a.tile_hi[tile];
     if (start != end) {
     int tx, ty, tz;
@@ -304,7 +307,7 @@ __global__ __launch_bounds__(256) void k_vox_bwd(VoxArgs a) {
     }
     __syncthreads();   // G[] is reused by the next tile
     }
-    if (threadIdx.x == 0) s_item = wq.resolve_thread(ticket);
+    if (threadIdx.x == 0) s_item = ticket < (uint32_t)a.n_tiles ? (int)ticket : -1;
     __syncthreads();
     tile = s_item;
     __syncthreads();   // s_item is rewritten at the end of this tile
@@ -470,7 +473,7 @@ hipError_t launch_vox_ranges(const Workspace& ws, const VoxLaunch& L, uint32_t n
 hipError_t launch_vox_fwd(const Workspace& ws, const gp_gaussians* g, const gp_volume_grid* grid,
                           const gp_render_opts* o, const VoxLaunch& L, float* vol, hipStream_t s) {
   if (L.n_tiles <= 0) return hipSuccess;
-  hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterFwd, 0u, kXcds, s);
+  hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterFwd, 0u, 1, s);
   if (e != hipSuccess) return e;
   VoxArgs a = vox_args(ws, g, grid, o, L);
   a.vol = vol;
@@ -483,7 +486,7 @@ hipError_t launch_vox_bwd(const Workspace& ws, const gp_gaussians* g, const gp_v
                           const gp_render_opts* o, const VoxLaunch& L, const float* gvol, float* grad,
                           int64_t grad_stride, hipStream_t s) {
   if (L.n_tiles <= 0 || L.n <= 0) return hipSuccess;
-  hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterBwd, 0u, kXcds, s);
+  hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterBwd, 0u, 1, s);
   if (e != hipSuccess) return e;
   VoxArgs a = vox_args(ws, g, grid, o, L);
   a.gvol = gvol;
