@@ -267,6 +267,12 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
     for (int k = G.k0 + 1; k < G.k1 && sorted; ++k)
       sorted = hs[k].z >= hs[k - 1].z && hs[k].sigma_z == hs[G.k0].sigma_z;
     G.flags = sorted ? kGroupSortedZ : 0;
+    G.zlo = INFINITY; G.zhi = -INFINITY; G.sz2max = 0.f; G.pad = 0.f;
+    for (int k = G.k0; k < G.k1; ++k) {
+      G.zlo = std::min(G.zlo, hs[k].z);
+      G.zhi = std::max(G.zhi, hs[k].z);
+      G.sz2max = std::max(G.sz2max, hs[k].sigma_z * hs[k].sigma_z);
+    }
     for (int k = G.k0; k < G.k1; ++k) ws->h_slices[k].group = g;
     gb += (groups[g].g->n + 63) / 64 * 64;
   }

@@ -33,7 +33,6 @@ __device__ __forceinline__ float load_attr(const void* base, int r, int64_t stri
 
 constexpr int kTile = 16;            // tile edge in pixels (16 x 16 tiles)
 constexpr int kTilePix = kTile * kTile;
-constexpr int kBinSortCap = 4096;    // tile lists up to this length are sorted in LDS
 
 // Per-slice constants on the device (one entry per slice of a batch).
 struct SliceDev {
@@ -56,8 +55,8 @@ struct BatchHdr {
   int32_t pad[2];
 };
 
-// Work counters handed out by atomics (reset at the start of every forward).
-// Rasteriser work counters.  (One queue per XCD, each draining a contiguous
+// Rasteriser work counters, handed out by atomics (reset at the start of every
+// forward).  (One queue per XCD, each draining a contiguous
 // eighth of the tiles, was measured 35 % slower than one queue shared by all:
 // with every XCD on the same slices at once, records one XCD brings in are
 // still cached for the others.)
@@ -80,6 +79,9 @@ struct GroupDev {
   int32_t k0, k1;      // slices [k0, k1) of the batch
   int32_t gbase;       // first flattened Gaussian index (multiple of 64)
   int32_t flags;       // kGroupSortedZ
+  float zlo, zhi;      // depth range of the group's slices
+  float sz2max;        // largest sigma_z^2 of the group's slices (+inf if any is infinite)
+  float pad;
 };
 
 // Rendering constants of one call (sizes that vary per batch live in BatchHdr).

@@ -113,8 +113,9 @@ struct Loaded {
   bool ok;
 };
 
+// Parameters of flattened Gaussian t (L.ok: in range and all finite).
 template <int DT>
-__device__ __forceinline__ void load_gaussian(const PreArgs& a, int n_groups, int t, Loaded& L) {
+__device__ __forceinline__ void load_params(const PreArgs& a, int n_groups, int t, Loaded& L) {
   const int wave0 = t & ~63;
   int g = 0;   // groups start at multiples of 64
   for (int jg = 1; jg < n_groups; ++jg)
@@ -135,8 +136,12 @@ __device__ __forceinline__ void load_gaussian(const PreArgs& a, int n_groups, in
   bool finite = in_range;
 #pragma unroll
   for (int r = 0; r < 11; ++r) finite = finite && isfinite(L.p[r]);
+  L.ok = finite;
+}
+
+__device__ __forceinline__ void activate(const PreArgs& a, Loaded& L) {
   spec_cov(L.p[3], L.p[4], L.p[5], L.p[6], L.p[7], L.p[8], L.p[9], a.rc.scale_mod, L.c);
-  L.ok = finite && (L.c.n2 > 0.0f);
+  L.ok = L.ok && (L.c.n2 > 0.0f);
 }
 
 // Footprint of (Gaussian, slice k); false if the pair is culled or off-grid.
@@ -153,10 +158,27 @@ __device__ __forceinline__ bool footprint(const PreArgs& a, const Loaded& L, int
   return vis;
 }
 
+// Conservative axial pre-test on the raw parameters: true only if no slice of
+// the group can keep the Gaussian.  Sigma_zz <= max_i s_i^2, so with d the
+// distance of mu_z from the group's depth range, d^2 > q_cut (sigma_z,max^2 +
+// max_i s_i^2) implies q_ax > q_cut on every slice; the 1e-3 margin covers
+// the rounding of the specified binary32 test.  Saves the covariance of
+// Gaussians far from every slice (most of them, for a few slices of a deep
+// volume).
+__device__ __forceinline__ bool far_from_group(const PreArgs& a, const GroupDev& G, const float* p) {
+  if (a.rc.flags & GP_FLAG_EXACT) return false;
+  const float lmax = fmaxf(p[3], fmaxf(p[4], p[5]));
+  const float smax = exp_spec(lmax) * a.rc.scale_mod;
+  const float d = fmaxf(fmaxf(G.zlo - p[2], p[2] - G.zhi), 0.0f);
+  return d * d > a.rc.q_cut * (G.sz2max + smax * smax) * 1.001f;
+}
+
 template <int DT>
 __device__ __forceinline__ void count_one(const PreArgs& a, int n_groups, int t) {
   Loaded L;
-  load_gaussian<DT>(a, n_groups, t, L);
+  load_params<DT>(a, n_groups, t, L);
+  if (L.ok && far_from_group(a, L.G, L.p)) L.ok = false;   // culled on every slice
+  else activate(a, L);
   int kb = L.G.k0, ke = L.G.k1;
   if (!L.ok) {
     ke = kb;
@@ -261,7 +283,8 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0
     const uint32_t g_kr = __shfl(krange, gi, 64);
     if (g_nrec == 0u) continue;
     Loaded L;
-    load_gaussian<DT>(a, n_groups, t0 + gi, L);
+    load_params<DT>(a, n_groups, t0 + gi, L);
+    activate(a, L);
     const int kb = (int)(g_kr & 0xFFFFu), ke = (int)(g_kr >> 16);
     uint32_t rec_run = g_rb, inst_run = g_ib;
     for (int c0 = kb; c0 < ke; c0 += W) {

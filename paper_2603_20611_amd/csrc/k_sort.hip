@@ -172,13 +172,20 @@ __global__ __launch_bounds__(256) void k_radix_hist(RadixArgs a) {
 // written out in that order, so consecutive threads store consecutive
 // elements of each digit's run (coalesced) instead of every element landing
 // on its own cache line.
+//
+// Wavefront w owns elements 1024 w .. 1024 w + 1023 of the tile (16 chunks of
+// 64).  Each wavefront counts its digits; one block-wide scan turns the counts
+// into the first local position of every (digit, wavefront); each wavefront
+// then ranks its chunks on its own (lanes with equal digits matched by
+// ballots, a per-wavefront running count per digit in LDS), with no
+// workgroup barrier between chunks.
 __global__ __launch_bounds__(256) void k_radix_scatter(RadixArgs a) {
-  constexpr int kPer = kSortTile / 256;          // elements per thread
+  constexpr int kPerWave = kSortTile / 4;        // elements per wavefront
+  constexpr int kChunks = kPerWave / 64;         // chunks per wavefront
   __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+  __shared__ uint32_t wrun[4][kMaxDigits];       // per-wavefront digit counts, then running positions
   __shared__ uint32_t loc[kMaxDigits];           // local run start of each digit (exclusive scan)
-  __shared__ uint32_t run[kMaxDigits];           // running local position of each digit
   __shared__ uint32_t glob[kMaxDigits];          // global start of this tile's run of each digit
-  __shared__ uint32_t wcnt[4][kMaxDigits];       // per-wavefront digit counts of a chunk
   __shared__ uint32_t part[256];
   const int R = 1 << a.bits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -189,28 +196,31 @@ __global__ __launch_bounds__(256) void k_radix_scatter(RadixArgs a) {
   const uint32_t tn = min((uint32_t)kSortTile, n - base);
   for (int i = threadIdx.x; i < R; i += 256) {
     glob[i] = a.hist[(size_t)i * a.nblocks + tile];
-    run[i] = 0u;
+    wrun[0][i] = wrun[1][i] = wrun[2][i] = wrun[3][i] = 0u;
   }
   __syncthreads();
-  // load (element c * 256 + t in register c of thread t) and count digits
-  uint32_t key[kPer], val[kPer];
+  // load (element 1024 w + 64 c + lane in register c) and count digits per wavefront
+  uint32_t key[kChunks], val[kChunks];
 #pragma unroll
-  for (int c = 0; c < kPer; ++c) {
-    const uint32_t j = (uint32_t)(c * 256 + threadIdx.x);
+  for (int c = 0; c < kChunks; ++c) {
+    const uint32_t j = (uint32_t)(wave * kPerWave + c * 64 + lane);
     key[c] = 0u;
     val[c] = 0u;
     if (j < tn) {
       key[c] = a.key_in[base + j];
       val[c] = a.val_in[base + j];
-      atomicAdd(&run[(key[c] >> a.shift) & (R - 1)], 1u);
+      atomicAdd(&wrun[wave][(key[c] >> a.shift) & (R - 1)], 1u);
     }
   }
   __syncthreads();
-  // exclusive scan of the R <= 512 digit counts (two per thread)
+  // exclusive scan over digits of the tile's counts (two digits per thread),
+  // then the first position of each (digit, wavefront)
   {
     const int i0 = 2 * threadIdx.x;
-    const uint32_t c0 = i0 < R ? run[i0] : 0u, c1 = i0 + 1 < R ? run[i0 + 1] : 0u;
-    uint32_t v = c0 + c1;
+    uint32_t c0 = 0u, c1 = 0u;
+    if (i0 < R) c0 = wrun[0][i0] + wrun[1][i0] + wrun[2][i0] + wrun[3][i0];
+    if (i0 + 1 < R) c1 = wrun[0][i0 + 1] + wrun[1][i0 + 1] + wrun[2][i0 + 1] + wrun[3][i0 + 1];
+    const uint32_t v = c0 + c1;
     part[threadIdx.x] = v;
     __syncthreads();
     for (int d = 1; d < 256; d <<= 1) {
@@ -220,36 +230,47 @@ __global__ __launch_bounds__(256) void k_radix_scatter(RadixArgs a) {
       __syncthreads();
     }
     const uint32_t excl = part[threadIdx.x] - v;
-    if (i0 < R) { loc[i0] = excl; run[i0] = excl; }
-    if (i0 + 1 < R) { loc[i0 + 1] = excl + c0; run[i0 + 1] = excl + c0; }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = i0 + h;
+      if (i >= R) continue;
+      uint32_t p = h == 0 ? excl : excl + c0;
+      loc[i] = p;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t cnt = wrun[w][i];
+        wrun[w][i] = p;
+        p += cnt;
+      }
+    }
   }
-  // stable local ranks, chunk by chunk (chunk c = elements c * 256 .. c * 256 + 255)
+  __syncthreads();
+  // stable ranks within each wavefront, chunk by chunk
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-  for (int c = 0; c < kPer; ++c) {
-    for (int i = threadIdx.x; i < R; i += 256) wcnt[0][i] = wcnt[1][i] = wcnt[2][i] = wcnt[3][i] = 0u;
-    __syncthreads();
-    const bool valid = (uint32_t)(c * 256 + threadIdx.x) < tn;
+  for (int c = 0; c < kChunks; ++c) {
+    const bool valid = (uint32_t)(wave * kPerWave + c * 64 + lane) < tn;
     const uint32_t digit = valid ? (key[c] >> a.shift) & (R - 1) : 0u;
     uint64_t same = __ballot(valid);
     for (int b = 0; b < a.bits; ++b) {
       const uint64_t bb = __ballot((digit >> b) & 1u);
       same &= ((digit >> b) & 1u) ? bb : ~bb;
     }
-    const uint32_t rank_w = (uint32_t)__popcll(same & lt_mask);
-    if (valid && rank_w == 0) wcnt[wave][digit] = (uint32_t)__popcll(same);
-    __syncthreads();
+    const uint32_t rank = (uint32_t)__popcll(same & lt_mask);
+    uint32_t p = 0u;
     if (valid) {
-      uint32_t before = 0;
-      for (int w = 0; w < wave; ++w) before += wcnt[w][digit];
-      const uint32_t p = run[digit] + before + rank_w;
+      p = wrun[wave][digit] + rank;
       sk[p] = key[c];
       sv[p] = val[c];
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < R; i += 256) run[i] += wcnt[0][i] + wcnt[1][i] + wcnt[2][i] + wcnt[3][i];
-    __syncthreads();   // wcnt is cleared by the next chunk
+    // all lanes have read the running position before its leader advances it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) wrun[wave][digit] += (uint32_t)__popcll(same);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
+  __syncthreads();
   // write out in local order: runs of one digit go to consecutive addresses
   for (uint32_t p = threadIdx.x; p < tn; p += 256) {
     const uint32_t k = sk[p];
