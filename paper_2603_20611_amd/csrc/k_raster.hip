@@ -6,13 +6,15 @@
 // from the record's mean, a contribution is w * exp2(a dx^2 + b dx dy + c dy^2)
 // (the exponent coefficients carry -1/2 log2(e) and the pixel pitch).
 //
-// Forward: one 64-lane wavefront per 16x16 tile.  Lane l owns the four
-// horizontally adjacent pixels (4 (l & 3) + 0..3, l >> 2) so the row terms
-// b dy and c dy^2 are shared by four pixels, and the four pixel chains give the
-// instruction stream the independent operations gfx950 needs to issue VALU at
-// full rate.  Records are staged 64 at a time in LDS and read back as
-// wavefront-wide broadcasts into VGPRs (operands held in SGPRs halve VALU
-// issue on gfx950).
+// Forward: one 64-lane wavefront per 16x16 tile.  The two half-wavefronts
+// take two records at a time, and lane m of a half owns the 2 x 4 pixels of
+// rows 2 (m >> 2) + {0, 1}, columns 4 (m & 3) + 0..3, so the row terms b dy and
+// c dy^2 are shared by four pixels, the column term by two rows, and eight
+// pixel chains give the instruction stream the independent operations gfx950
+// needs to issue VALU at full rate; the halves' partial sums are added at the
+// end of the tile.  Records are staged 64 at a time in LDS and read back as
+// broadcasts into VGPRs (operands held in SGPRs halve VALU issue on gfx950);
+// each LDS read serves two records.
 //
 // Backward: one lane per list entry; the lane sweeps the tile's 256 pixels in
 // row order with the upstream gradient staged in LDS, and accumulates six
@@ -73,8 +75,11 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   const int n_slices = a.hdr->n_slices;
   const int tps = a.hdr->tiles_per_slice;
   const int lane = threadIdx.x;
-  const int row = lane >> 2;
-  const int col0 = (lane & 3) * 4;
+  // the two half-wavefronts take two records at a time; within a half, lane m
+  // owns the 2 x 4 pixels of rows 2 (m >> 2) + {0, 1}, columns 4 (m & 3) + 0..3
+  const int half = lane >> 5, m = lane & 31;
+  const int row0 = (m >> 2) * 2;
+  const int col0 = (m & 3) * 4;
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
   uint32_t* counter = a.work + kWorkRasterFwd;
   auto item_of = [&](uint32_t t) { return t < (uint32_t)n_bins ? (int)t : -1; };
@@ -99,9 +104,11 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     const int tile = bin - sl.tile_base;
     const int tx = tile % sl.ntx, ty = tile / sl.ntx;
     const int px0 = tx * kTile + col0;
-    const int py = ty * kTile + row;
-    const float fx0 = (float)px0, fy = (float)py;
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+    const int py0 = ty * kTile + row0;
+    const float fx0 = (float)px0, fy0 = (float)py0;
+    float acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = 0.f;
 
     // next tile, advanced one stage per batch
     int nitem = -1, nk = 0, stage = 0;
@@ -132,60 +139,87 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
 
     for (uint32_t base = start; base < end; base += 64) {
       buf0[lane] = n0;
-      buf1[lane] = n1;
+      buf1[lane] = n1;   // slots past the end hold zeros (w = 0)
       __syncthreads();
       const int cnt = __builtin_amdgcn_readfirstlane((int)min(64u, end - base));
       const uint32_t nb = base + 64;
+      n0 = zero4;
+      n1 = zero4;
       if (nb + lane < end) {
         const float4* src = reinterpret_cast<const float4*>(a.rec_pay + rid_next);
         n0 = src[0];
         n1 = src[1];
       }
       if (nb + 64 + lane < end) rid_next = a.list[nb + 64 + lane];
-      for (int j = 0; j < cnt; ++j) {
-        const float4 r0 = buf0[j];
-        const float4 r1 = buf1[j];
-        const float dy = fy - r0.y;
-        const float by = r0.w * dy;
-        const float cy = r1.x * dy * dy;
+      for (int j = 0; j < cnt; j += 2) {
+        const float4 r0 = buf0[j + half];
+        const float4 r1 = buf1[j + half];   // j + 1 may be a zero slot: w = 0
+        const float t = fmaf(fx0 - r0.x, 2.0f, 1.0f);
         const float d0 = fx0 - r0.x;
-        const float ra = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(r0.z)));
-        const float p0 = fmaf(fmaf(r0.z, d0, by), d0, cy);
-        const float e0 = __builtin_amdgcn_exp2f(p0);
-        float e1, e2, e3;
-        if (ra >= kSmoothA) {
-          const float s0 = fminf(fmaf(r0.z, fmaf(d0, 2.0f, 1.0f), by), 126.0f);
-          float q = __builtin_amdgcn_exp2f(s0);
-          e1 = e0 * q;
-          q *= r1.z;
-          e2 = e1 * q;
-          q *= r1.z;
-          e3 = e2 * q;
+        const float dy0 = fy0 - r0.y, dy1 = dy0 + 1.0f;
+        const float by0 = r0.w * dy0, by1 = r0.w * dy1;
+        const float cy0 = r1.x * dy0 * dy0, cy1 = r1.x * dy1 * dy1;
+        const float p00 = fmaf(fmaf(r0.z, d0, by0), d0, cy0);
+        const float p10 = fmaf(fmaf(r0.z, d0, by1), d0, cy1);
+        const float e00 = __builtin_amdgcn_exp2f(p00);
+        const float e10 = __builtin_amdgcn_exp2f(p10);
+        float e01, e02, e03, e11, e12, e13;
+        // both records of the step must allow the row recurrence (uniform branch)
+        if (__builtin_amdgcn_read_exec() == __ballot(r0.z >= kSmoothA)) {
+          float q0 = __builtin_amdgcn_exp2f(fminf(fmaf(r0.z, t, by0), 126.0f));
+          float q1 = __builtin_amdgcn_exp2f(fminf(fmaf(r0.z, t, by1), 126.0f));
+          e01 = e00 * q0;
+          e11 = e10 * q1;
+          q0 *= r1.z;
+          q1 *= r1.z;
+          e02 = e01 * q0;
+          e12 = e11 * q1;
+          q0 *= r1.z;
+          q1 *= r1.z;
+          e03 = e02 * q0;
+          e13 = e12 * q1;
         } else {
           const float d1 = d0 + 1.0f, d2 = d0 + 2.0f, d3 = d0 + 3.0f;
-          e1 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d1, by), d1, cy));
-          e2 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d2, by), d2, cy));
-          e3 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d3, by), d3, cy));
+          e01 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d1, by0), d1, cy0));
+          e02 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d2, by0), d2, cy0));
+          e03 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d3, by0), d3, cy0));
+          e11 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d1, by1), d1, cy1));
+          e12 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d2, by1), d2, cy1));
+          e13 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d3, by1), d3, cy1));
         }
-        acc0 = fmaf(r1.y, e0, acc0);
-        acc1 = fmaf(r1.y, e1, acc1);
-        acc2 = fmaf(r1.y, e2, acc2);
-        acc3 = fmaf(r1.y, e3, acc3);
+        const float w = r1.y;
+        acc[0] = fmaf(w, e00, acc[0]);
+        acc[1] = fmaf(w, e01, acc[1]);
+        acc[2] = fmaf(w, e02, acc[2]);
+        acc[3] = fmaf(w, e03, acc[3]);
+        acc[4] = fmaf(w, e10, acc[4]);
+        acc[5] = fmaf(w, e11, acc[5]);
+        acc[6] = fmaf(w, e12, acc[6]);
+        acc[7] = fmaf(w, e13, acc[7]);
       }
       if (stage < 3) advance();
       __syncthreads();
     }
     while (stage < 3) advance();   // short tiles: finish fetching the next one
 
-    if (py < sl.height) {
-      float* o = sl.out + (int64_t)py * sl.width;
-      if (px0 + 3 < sl.width && (reinterpret_cast<uintptr_t>(o + px0) & 15) == 0) {
-        *reinterpret_cast<float4*>(o + px0) = make_float4(acc0, acc1, acc2, acc3);
-      } else {
-        if (px0 < sl.width) o[px0] = acc0;
-        if (px0 + 1 < sl.width) o[px0 + 1] = acc1;
-        if (px0 + 2 < sl.width) o[px0 + 2] = acc2;
-        if (px0 + 3 < sl.width) o[px0 + 3] = acc3;
+    // the two halves hold partial sums of the same pixels
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
+    if (half == 0) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int py = py0 + r;
+        if (py >= sl.height) continue;
+        float* o = sl.out + (int64_t)py * sl.width;
+        const float* v = acc + 4 * r;
+        if (px0 + 3 < sl.width && (reinterpret_cast<uintptr_t>(o + px0) & 15) == 0) {
+          *reinterpret_cast<float4*>(o + px0) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+          if (px0 < sl.width) o[px0] = v[0];
+          if (px0 + 1 < sl.width) o[px0 + 1] = v[1];
+          if (px0 + 2 < sl.width) o[px0 + 2] = v[2];
+          if (px0 + 3 < sl.width) o[px0 + 3] = v[3];
+        }
       }
     }
     // the next tile becomes the current one
