@@ -16,15 +16,17 @@ Readings, all decisions taken in binary32 with the operation order below:
   * a value v on [lo, hi] with n levels (2^14 or 2^12) has code
     floor(((v - lo) / (hi - lo)) * (n - 1) + 0.5), clamped to [0, n - 1];
     code 0 if hi == lo; non-finite values get code 0;
-  * intensity: alpha clamped to [0, 1], code floor(alpha * 4095 + 0.5);
+  * intensity: normalised to [0, 1] by the largest finite intensity amax
+    (the paper's opacities already lie on [0, 1]; the intensities here are
+    unbounded), i.e. coded like a value on [0, amax], negatives clamped to 0;
   * quaternion: q / |q|, negated if its w < 0, each component c on [-1, 1]
     coded as floor(((c + 1) * 0.5) * 4095 + 0.5);
-  * decoding: lo + code * ((hi - lo) / (n - 1)), code / 4095 for alpha,
+  * decoding: lo + code * ((hi - lo) / (n - 1)) (alpha: lo = 0, hi = amax),
     code * (2 / 4095) - 1 for quaternion components;
   * Morton key: bit 3i of the key is bit i of the x code, 3i + 1 of y,
     3i + 2 of z; the order is by key, ties by original index.
 Stored: 11 uint16 planes [11][n] in Morton order, the header
-(lo_x, lo_y, lo_z, hi_x, hi_y, hi_z, lmin, lmax) and the permutation.
+(lo_x, lo_y, lo_z, hi_x, hi_y, hi_z, lmin, lmax, amax) and the permutation.
 """
 import numpy as np
 
@@ -55,12 +57,14 @@ def _decode(code, lo, hi, levels):
 
 def header(params):
     p = np.asarray(params, f32)
-    h = np.zeros(8, f32)
+    h = np.zeros(9, f32)
     for a in range(3):
         m = p[a][np.isfinite(p[a])]
         h[a], h[3 + a] = (m.min(), m.max()) if m.size else (f32(0), f32(0))
     ls = p[3:6][np.isfinite(p[3:6])]
     h[6], h[7] = (ls.min(), ls.max()) if ls.size else (f32(0), f32(0))
+    al = p[10][np.isfinite(p[10])]
+    h[8] = max(al.max(), f32(0)) if al.size else f32(0)
     return h
 
 
@@ -84,11 +88,7 @@ def codes(params, h=None):
             cc = np.floor(u * f32(ATTR_LEVELS - 1) + f32(0.5))
         cc = np.where(np.isfinite(cc), cc, f32(0))
         c[6 + r] = np.clip(cc, 0, ATTR_LEVELS - 1).astype(np.uint16)
-    with np.errstate(all="ignore"):
-        al = np.clip(p[10], f32(0), f32(1))
-        ca = np.floor(al * f32(ATTR_LEVELS - 1) + f32(0.5))
-    ca = np.where(np.isfinite(ca), ca, f32(0))
-    c[10] = np.clip(ca, 0, ATTR_LEVELS - 1).astype(np.uint16)
+    c[10] = _code(np.maximum(p[10], f32(0)), f32(0), h[8], ATTR_LEVELS)
     return c, h
 
 
@@ -103,7 +103,7 @@ def morton(cx, cy, cz):
 
 
 def encode(params):
-    """(codes [11, n] uint16 in Morton order, header float32 [8], perm int64 [n])
+    """(codes [11, n] uint16 in Morton order, header float32 [9], perm int64 [n])
     with codes[:, i] the codes of Gaussian perm[i]."""
     c, h = codes(params)
     key = morton(c[0], c[1], c[2])
@@ -122,5 +122,5 @@ def decode(c, h):
         p[3 + a] = _decode(c[3 + a], h[6], h[7], ATTR_LEVELS)
     for r in range(4):
         p[6 + r] = (np.asarray(c[6 + r], f32) * (f32(2.0) / f32(ATTR_LEVELS - 1)) - f32(1.0)).astype(f32)
-    p[10] = (np.asarray(c[10], f32) / f32(ATTR_LEVELS - 1)).astype(f32)
+    p[10] = _decode(c[10], f32(0), h[8], ATTR_LEVELS)
     return p

@@ -27,7 +27,7 @@ def test_round_trip_within_half_a_step():
         assert np.abs(d[a] - q[a]).max() <= 0.5 * step * (1 + 1e-3) + 1e-4
     step = (h[7] - h[6]) / (quant.ATTR_LEVELS - 1)
     assert np.abs(d[3:6] - q[3:6]).max() <= 0.5 * step * (1 + 1e-3) + 1e-6
-    assert np.abs(d[10] - q[10]).max() <= 0.5 / 4095 + 1e-7
+    assert np.abs(d[10] - q[10]).max() <= 0.5 * h[8] / 4095 * (1 + 1e-3) + 1e-7
 
 
 def test_extremes_map_to_end_codes():
