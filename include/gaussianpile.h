@@ -65,6 +65,12 @@ typedef int32_t gp_status;
  * quaternions dominate the error of 16-bit storage for thin, elongated
  * Gaussians; fixed point gives 2^-15 absolute resolution instead. */
 #define GP_Q16  3
+/* GP_QM: the Morton-ordered fixed-point codec of gp_encode (both mean_dtype and
+ * attr_dtype): means points at 11 uint16 code planes [11][stride], attrs at
+ * the 9-float gp_codec_header in device memory.  Decoded in registers by the
+ * forward renderer (the backward and the voxeliser take float32 or 16-bit
+ * attributes only). */
+#define GP_QM   4
 
 /* Render options.  q_cut: axial cull threshold on the Mahalanobis change of the
  * opacity modulation (Sec. 4.2, "cull primitives with opacity below a small
@@ -82,8 +88,8 @@ typedef struct gp_render_opts {
 } gp_render_opts;
 
 typedef struct gp_gaussians {
-  const void* means;  /* d_: [3][stride], mean_dtype (GP_F32 only)            */
-  const void* attrs;  /* d_: [8][stride], attr_dtype (GP_F32, GP_BF16, GP_F16, GP_Q16) */
+  const void* means;  /* d_: [3][stride], mean_dtype (GP_F32; GP_QM: codes)   */
+  const void* attrs;  /* d_: [8][stride], attr_dtype (GP_F32, GP_BF16, GP_F16, GP_Q16; GP_QM: header) */
   int64_t n;          /* number of Gaussians, 0 <= n <= stride, n < 2^31      */
   int64_t stride;     /* elements between planes                              */
   int32_t mean_dtype;
@@ -194,6 +200,31 @@ typedef struct gp_adam_cfg {
 } gp_adam_cfg;
 gp_status gp_adam_step(float* d_params, float* d_grad, float* d_m, float* d_v, int64_t n,
                        int64_t stride, const gp_adam_cfg* cfg, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Codec (Sec. 4.3, "Quantization and compression"): Gaussians sorted along the
+ * Morton curve of their 14-bit position codes; positions normalised to the
+ * bounding box of the finite means, 14 bits per axis; log-scales on the range
+ * of the finite log-scales, 12 bits; the quaternion normalised, moved to w >= 0
+ * and each component coded on [-1, 1] with 12 bits; intensity normalised to
+ * [0, 1] by the largest finite intensity amax, 12 bits.  Codes are floor(((v - lo) / (hi - lo)) * (levels - 1) +
+ * 0.5) in binary32, clamped (0 for an empty range or a non-finite value);
+ * values decode as lo + code * ((hi - lo) / (levels - 1)).  The entropy coder
+ * that follows in the paper is not part of this codec.
+ * ---------------------------------------------------------------------- */
+typedef struct gp_codec_header {
+  float lo[3], hi[3];   /* bounding box of the means */
+  float lmin, lmax;     /* range of the log-scales */
+  float amax;           /* largest intensity (>= 0) */
+} gp_codec_header;
+
+/* Encodes n Gaussians (d_params [11][stride] float32) into d_codes ([11][stride_out]
+ * uint16, Morton order), the header into d_header (device, 9 floats) and, if
+ * d_perm is not NULL, the original index of each coded Gaussian ([n] uint32).
+ * Deterministic.  Allocates scratch and synchronises on stream.
+ * Errors: GP_EINVAL, GP_ENOMEM, GP_EHIP. */
+gp_status gp_encode(const float* d_params, int64_t n, int64_t stride, uint16_t* d_codes, int64_t stride_out,
+                    uint32_t* d_perm, float* d_header, void* stream);
 
 /* ------------------------------------------------------------------------
  * Differentiable voxeliser (Sec. 4.3, "Differentiable Voxelization"): the

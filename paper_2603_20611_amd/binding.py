@@ -13,7 +13,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgaussia
 _lib = None
 
 GP_OK, GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_EOVERFLOW, GP_EAGAIN, GP_ECANCELED, GP_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
-GP_F32, GP_BF16, GP_F16, GP_Q16 = 0, 1, 2, 3
+GP_F32, GP_BF16, GP_F16, GP_Q16, GP_QM = 0, 1, 2, 3, 4
 GP_FLAG_EXACT = 1
 GP_ADAM_CLAMP_ALPHA, GP_ADAM_ZERO_GRAD = 1, 2
 STAGES = ("preprocess", "emit", "sort", "raster_fwd", "raster_bwd", "preprocess_bwd")
@@ -104,6 +104,7 @@ _SIGS = {
     "gp_adam_step": (C.c_int32, [_P, _P, _P, _P, C.c_int64, C.c_int64, C.POINTER(AdamCfg), _P]),
     "gp_workspace_set_timing": (C.c_int32, [_P, C.c_int32]),
     "gp_workspace_timings": (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
+    "gp_encode": (C.c_int32, [_P, C.c_int64, C.c_int64, _P, C.c_int64, _P, _P, _P]),
     "gp_voxelize": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(VolumeGrid), C.POINTER(RenderOpts), _P, _P]),
     "gp_voxelize_backward": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(VolumeGrid), C.POINTER(RenderOpts),
                                          _P, _P, C.c_int64, _P]),

@@ -194,8 +194,10 @@ static gp_status check_gaussians(const gp_gaussians* g) {
   if (g->n < 0 || g->n >= (1ll << 31)) return einval("gaussians: n out of range");
   if (g->stride < g->n) return einval("gaussians: stride < n");
   if (g->n > 0 && (!g->means || !g->attrs)) return einval("gaussians: NULL means/attrs");
-  if (g->mean_dtype != GP_F32) return einval("gaussians: means must be GP_F32");
-  if (g->attr_dtype != GP_F32 && g->attr_dtype != GP_BF16 && g->attr_dtype != GP_F16 && g->attr_dtype != GP_Q16)
+  if ((g->mean_dtype == GP_QM) != (g->attr_dtype == GP_QM)) return einval("gaussians: GP_QM is for both or neither");
+  if (g->mean_dtype != GP_F32 && g->mean_dtype != GP_QM) return einval("gaussians: means must be GP_F32 or GP_QM");
+  if (g->attr_dtype != GP_F32 && g->attr_dtype != GP_BF16 && g->attr_dtype != GP_F16 && g->attr_dtype != GP_Q16 &&
+      g->attr_dtype != GP_QM)
     return einval("gaussians: unknown attr_dtype");
   return GP_OK;
 }
@@ -511,6 +513,7 @@ gp_status gp_render_backward(gp_workspace* w, const gp_gaussians* g, const gp_sl
   if (st != GP_OK) return st;
   if ((st = check_opts(o)) != GP_OK) return st;
   if (grad_stride < g->n) return einval("backward: grad_stride < n");
+  if (g->attr_dtype == GP_QM) return einval("backward: coded (GP_QM) Gaussians are render-only");
   if (ns < 0 || (ns > 0 && (!hs || !grad_out || !grad))) return einval("backward: bad arguments");
   if (!ws->have_forward || ws->fwd_means != g->means || ws->fwd_attrs != g->attrs || ws->fwd_n != g->n ||
       ws->fwd_stride != g->stride || ws->fwd_nslices != ns ||
@@ -642,6 +645,7 @@ gp_status gp_voxelize(gp_workspace* w, const gp_gaussians* g, const gp_volume_gr
   if (st != GP_OK) return st;
   if ((st = check_opts(o)) != GP_OK) return st;
   if ((st = check_grid(grid)) != GP_OK) return st;
+  if (g->attr_dtype == GP_QM) return einval("voxelize: coded (GP_QM) Gaussians are not supported");
   const int64_t nvox = (int64_t)grid->nx * grid->ny * grid->nz;
   if (nvox > 0 && !vol) return einval("voxelize: NULL volume");
   if (g->n > 0x7FFFFFF0ll) return einval("voxelize: too many Gaussians");
@@ -717,6 +721,14 @@ gp_status gp_voxelize_backward(gp_workspace* w, const gp_gaussians* g, const gp_
   ws->last_stream = s;
   GP_HIP(launch_vox_bwd(*ws, g, grid, o, L, gvol, grad, grad_stride, s));
   return GP_OK;
+}
+
+gp_status gp_encode(const float* p, int64_t n, int64_t stride, uint16_t* codes, int64_t stride_out, uint32_t* perm,
+                    float* d_header, void* stream) {
+  if (n < 0 || stride < n || stride_out < n || n >= (1ll << 31)) return einval("encode: need 0 <= n <= strides");
+  if (!d_header || (n > 0 && (!p || !codes))) return einval("encode: NULL");
+  return encode_volume(p, p ? p + 3 * stride : nullptr, n, stride, codes, stride_out, perm, d_header,
+                       static_cast<hipStream_t>(stream));
 }
 
 gp_status gp_densify_default_cfg(gp_densify_cfg* c) {

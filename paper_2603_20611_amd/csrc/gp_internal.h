@@ -289,6 +289,19 @@ hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const f
 // k_backward.hip
 hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, float* grad,
                                  int64_t grad_stride, const LaunchDims& d, hipStream_t s);
+// k_codec.hip
+struct CodecScratch {
+  uint32_t* bounds;     // [8]
+  uint32_t* count;      // [1]
+  uint16_t* codes;      // [11][n] in the original order
+  uint32_t *key_lo, *key_hi, *idx, *key2, *val2;   // [n] each
+  uint32_t* hist;       // radix_hist_entries(32, n)
+  uint32_t* scan_part;  // scan_parts_needed of the histogram
+};
+hipError_t launch_encode(const float* means, const float* attrs, int64_t n, int64_t stride, uint16_t* codes_out,
+                         int64_t stride_out, uint32_t* perm_out, float* d_hdr, const CodecScratch& t, hipStream_t s);
+gp_status encode_volume(const float* means, const float* attrs, int64_t n, int64_t stride, uint16_t* codes_out,
+                        int64_t stride_out, uint32_t* perm_out, float* d_hdr, hipStream_t s);
 // k_voxel.hip
 struct VoxLaunch {
   int n;

@@ -186,7 +186,8 @@ gp_status launch_batch(Server* sv, Slot* sl) {
     outs[k] = reqs[k].out;
     if (groups.empty() || sets.back().means != sv->vols[r.volume_id].means) {
       const Volume& v = sv->vols[r.volume_id];
-      sets.push_back(gp_gaussians{v.means, v.attrs, v.n, v.stride, GP_F32, sv->cfg.attr_dtype});
+      sets.push_back(gp_gaussians{v.means, v.attrs, v.n, v.stride,
+                                  sv->cfg.attr_dtype == GP_QM ? GP_QM : GP_F32, sv->cfg.attr_dtype});
       groups.push_back(GroupIn{nullptr, (int32_t)k, (int32_t)k + 1});
     } else {
       groups.back().k1 = (int32_t)k + 1;
@@ -386,7 +387,7 @@ gp_status gp_server_create(gp_server** out, const gp_server_cfg* cfg) {
   if (cfg->slots < 1 || cfg->slots > 4 || cfg->max_batch < 1 || cfg->max_bins < 1 || cfg->max_gaussians < 64 ||
       cfg->max_records < 1 || cfg->max_instances < 1 || cfg->hbm_budget_bytes < 0 ||
       (cfg->attr_dtype != GP_F32 && cfg->attr_dtype != GP_BF16 && cfg->attr_dtype != GP_F16 &&
-       cfg->attr_dtype != GP_Q16)) {
+       cfg->attr_dtype != GP_Q16 && cfg->attr_dtype != GP_QM)) {
     set_error("server_create: bad configuration");
     return GP_EINVAL;
   }
@@ -443,7 +444,9 @@ gp_status gp_server_add_volume(gp_server* s, const gp_gaussians* g, int32_t* vol
   Volume v;
   v.n = g->n;
   v.stride = (g->n + 63) / 64 * 64;
-  v.bytes = (size_t)v.stride * (3 * 4 + 8 * dtype_bytes(sv->cfg.attr_dtype));
+  const bool coded = sv->cfg.attr_dtype == GP_QM;
+  v.bytes = coded ? (size_t)v.stride * 11 * sizeof(uint16_t) + 12 * sizeof(float)
+                  : (size_t)v.stride * (3 * 4 + 8 * dtype_bytes(sv->cfg.attr_dtype));
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->resident + (int64_t)v.bytes > sv->cfg.hbm_budget_bytes) {
@@ -460,15 +463,22 @@ gp_status gp_server_add_volume(gp_server* s, const gp_gaussians* g, int32_t* vol
     return code;
   };
   GP_HIP(hipSetDevice(sv->cfg.device));
-  if (hipMalloc(reinterpret_cast<void**>(&v.means), sizeof(float) * 3 * v.stride) != hipSuccess ||
-      hipMalloc(&v.attrs, dtype_bytes(sv->cfg.attr_dtype) * 8 * v.stride) != hipSuccess) {
+  const size_t mean_bytes = coded ? sizeof(uint16_t) * 11 * v.stride : sizeof(float) * 3 * v.stride;
+  const size_t attr_bytes = coded ? sizeof(float) * 12 : dtype_bytes(sv->cfg.attr_dtype) * 8 * v.stride;
+  if (hipMalloc(reinterpret_cast<void**>(&v.means), mean_bytes) != hipSuccess ||
+      hipMalloc(&v.attrs, attr_bytes) != hipSuccess) {
     set_error("add_volume: out of device memory");
     return release(GP_ENOMEM);
   }
   const unsigned blocks = (unsigned)((g->n + 255) / 256);
   const float* m = static_cast<const float*>(g->means);
   const float* a = static_cast<const float*>(g->attrs);
-  switch (sv->cfg.attr_dtype) {
+  if (coded) {
+    // Morton-ordered codes in the volume's planes, the header in its attribute block
+    const gp_status cst = encode_volume(m, a, g->n, g->stride, reinterpret_cast<uint16_t*>(v.means), v.stride,
+                                        nullptr, static_cast<float*>(v.attrs), nullptr);
+    if (cst != GP_OK) return release(cst);
+  } else switch (sv->cfg.attr_dtype) {
     case GP_BF16: k_pack_volume<GP_BF16><<<blocks, 256>>>(m, a, g->stride, g->n, v.means, v.attrs, v.stride); break;
     case GP_F16: k_pack_volume<GP_F16><<<blocks, 256>>>(m, a, g->stride, g->n, v.means, v.attrs, v.stride); break;
     case GP_Q16: k_pack_volume<GP_Q16><<<blocks, 256>>>(m, a, g->stride, g->n, v.means, v.attrs, v.stride); break;

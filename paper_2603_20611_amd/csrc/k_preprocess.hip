@@ -105,6 +105,21 @@ __device__ __forceinline__ void kept_range(const PreArgs& a, const GroupDev& G, 
   *ke = lo + 1;
 }
 
+// Parameters of coded Gaussian j (GP_QM): 11 uint16 code planes and the
+// 9-float header (lo[3], hi[3], lmin, lmax, amax); the decoding of the codec, in
+// binary32 without contraction.
+__device__ __forceinline__ void decode_codes(const uint16_t* __restrict__ c, const float* __restrict__ h,
+                                             int64_t stride, int64_t j, float* p) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int a = 0; a < 3; ++a) p[a] = h[a] + (float)c[a * stride + j] * ((h[3 + a] - h[a]) / 16383.0f);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) p[3 + a] = h[6] + (float)c[(3 + a) * stride + j] * ((h[7] - h[6]) / 4095.0f);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) p[6 + r] = (float)c[(6 + r) * stride + j] * (2.0f / 4095.0f) - 1.0f;
+  p[10] = 0.0f + (float)c[10 * stride + j] * (h[8] / 4095.0f);
+}
+
 struct Loaded {
   GroupDev G;
   int j;
@@ -124,11 +139,16 @@ __device__ __forceinline__ void load_params(const PreArgs& a, int n_groups, int 
   L.j = t - L.G.gbase;
   const bool in_range = L.j < L.G.n;
   if (in_range) {
-    L.p[0] = L.G.means[L.j];
-    L.p[1] = L.G.means[L.G.stride + L.j];
-    L.p[2] = L.G.means[2 * L.G.stride + L.j];
+    if constexpr (DT == GP_QM) {
+      decode_codes(reinterpret_cast<const uint16_t*>(L.G.means), static_cast<const float*>(L.G.attrs), L.G.stride,
+                   L.j, L.p);
+    } else {
+      L.p[0] = L.G.means[L.j];
+      L.p[1] = L.G.means[L.G.stride + L.j];
+      L.p[2] = L.G.means[2 * L.G.stride + L.j];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) L.p[3 + r] = load_attr<DT>(L.G.attrs, r, L.G.stride, L.j);
+      for (int r = 0; r < 8; ++r) L.p[3 + r] = load_attr<DT>(L.G.attrs, r, L.G.stride, L.j);
+    }
   } else {
 #pragma unroll
     for (int r = 0; r < 11; ++r) L.p[r] = 0.0f;
@@ -397,6 +417,7 @@ hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const La
     case GP_BF16: k_pre_count<GP_BF16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
     case GP_F16: k_pre_count<GP_F16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
     case GP_Q16: k_pre_count<GP_Q16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
+    case GP_QM: k_pre_count<GP_QM><<<(unsigned)blocks, 256, 0, s>>>(a); break;
     default: k_pre_count<GP_F32><<<(unsigned)blocks, 256, 0, s>>>(a); break;
   }
   return hipGetLastError();
@@ -412,6 +433,7 @@ hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const Lau
     case GP_BF16: return launch_emit_dt<GP_BF16>(a, d.emit_width, (unsigned)blocks, s);
     case GP_F16: return launch_emit_dt<GP_F16>(a, d.emit_width, (unsigned)blocks, s);
     case GP_Q16: return launch_emit_dt<GP_Q16>(a, d.emit_width, (unsigned)blocks, s);
+    case GP_QM: return launch_emit_dt<GP_QM>(a, d.emit_width, (unsigned)blocks, s);
     default: return launch_emit_dt<GP_F32>(a, d.emit_width, (unsigned)blocks, s);
   }
 }

@@ -230,3 +230,36 @@ def voxelize_backward(params, grid, grad_volume, ws, opts=None, grad=None, n=Non
     B.check(B.load().gp_voxelize_backward(ws.handle, C.byref(gs), C.byref(g), C.byref(opts), _ptr(grad_volume),
                                           _ptr(grad), grad.stride(0), _stream()))
     return grad
+
+
+def encode(params, n=None, stride_out=None):
+    """Morton-ordered 14/12-bit codes of a [11, stride] float32 set.
+
+    Returns (codes uint16 [11, stride_out] as int16-typed storage, header float32 [9],
+    perm int32 [n]) on the device; codes[:, i] codes Gaussian perm[i]."""
+    n = params.shape[1] if n is None else int(n)
+    so = max(n, 1) if stride_out is None else int(stride_out)
+    codes = torch.empty(11, so, dtype=torch.int16, device=params.device)
+    header = torch.zeros(9, dtype=torch.float32, device=params.device)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=params.device)
+    B.check(B.load().gp_encode(_ptr(params), n, params.stride(0), _ptr(codes), codes.stride(0), _ptr(perm),
+                               _ptr(header), _stream()))
+    return codes, header, perm[:n]
+
+
+def coded_struct(codes, header, n):
+    """gp_gaussians of a coded set (GP_QM)."""
+    return B.Gaussians(codes.data_ptr(), header.data_ptr(), int(n), codes.shape[1], B.GP_QM, B.GP_QM)
+
+
+def render_coded(codes, header, n, slices, opts=None, ws=None, out=None):
+    """Forward render of a coded set."""
+    lib = B.load()
+    ws = ws or Workspace()
+    opts = opts or B.default_opts()
+    sl = B.make_slices(slices)
+    if out is None:
+        out = torch.empty(slice_pixels(slices), device=codes.device, dtype=torch.float32)
+    g = coded_struct(codes, header, n)
+    B.check(lib.gp_render_slices(ws.handle, C.byref(g), sl, len(slices), C.byref(opts), _ptr(out), _stream()))
+    return out
