@@ -844,14 +844,27 @@ gp_status gp_debug_export_bins(gp_workspace* w, uint64_t* h_keys, int64_t keys_c
   const int64_t n_list = std::min<int64_t>(ws->h_ctr[kCtrInstances], ws->inst_cap);
   const int64_t R = std::min<int64_t>(ws->h_ctr[kCtrRecords], ws->rec_cap);
   std::vector<uint32_t> list((size_t)std::max<int64_t>(n_list, 1));
-  std::vector<RecPay> pay((size_t)std::max<int64_t>(R, 1));
   if (n_list > 0) GP_HIP(hipMemcpy(list.data(), ws->d_list, sizeof(uint32_t) * n_list, hipMemcpyDeviceToHost));
-  if (R > 0) GP_HIP(hipMemcpy(pay.data(), ws->d_rec_pay, sizeof(RecPay) * R, hipMemcpyDeviceToHost));
+  // records are contiguous per Gaussian: record -> Gaussian index within its set
+  const int64_t T = ws->fwd_gauss;
+  std::vector<uint32_t> rbase((size_t)std::max<int64_t>(T, 1)), nrec((size_t)std::max<int64_t>(T, 1));
+  if (T > 0) {
+    GP_HIP(hipMemcpy(rbase.data(), ws->d_g_rbase, sizeof(uint32_t) * T, hipMemcpyDeviceToHost));
+    GP_HIP(hipMemcpy(nrec.data(), ws->d_g_nrec, sizeof(uint32_t) * T, hipMemcpyDeviceToHost));
+  }
+  std::vector<uint32_t> gid((size_t)std::max<int64_t>(R, 1), 0xFFFFFFFFu);
+  const int ng = ws->h_hdr->n_groups;
+  for (int64_t t = 0; t < T; ++t) {
+    int64_t gb = 0;
+    for (int g = 0; g < ng; ++g)
+      if (ws->h_groups[g].gbase <= t) gb = ws->h_groups[g].gbase;
+    for (uint32_t r = rbase[t]; r < rbase[t] + nrec[t] && r < (uint32_t)R; ++r) gid[r] = (uint32_t)(t - gb);
+  }
   // lists are contiguous and in bin order; report them packed, bin by bin
   int64_t o = 0;
   for (int64_t b = 0; b < nb; ++b) {
     h_ranges[2 * b] = o;
-    for (uint32_t i = lo[b]; i < hi[b]; ++i) h_keys[o++] = ((uint64_t)b << 32) | pay[list[i]].gid;
+    for (uint32_t i = lo[b]; i < hi[b]; ++i) h_keys[o++] = ((uint64_t)b << 32) | gid[list[i]];
     h_ranges[2 * b + 1] = o;
   }
   return GP_OK;

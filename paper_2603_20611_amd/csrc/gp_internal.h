@@ -114,11 +114,11 @@ enum { kCtrRecords = 0, kCtrInstances = 1, kCtrOverflow = 2, kCtrCount = 4 };
 // Record payload in pixel space, 32 bytes, gathered by the rasterisers:
 //   x, y = mean in pixel-index units; a, b, c = exponent coefficients of
 //   exp2(a dx^2 + b dx dy + c dy^2); w = alpha~; g = 2^(2a) (the per-pixel
-//   ratio of the row recurrence); gid = Gaussian index within its set.
+//   ratio of the row recurrence) and h = 2^b (its change from one row to the
+//   next).
 struct alignas(16) RecPay {
   float x, y, a, b;
-  float c, w, g;
-  uint32_t gid;
+  float c, w, g, h;
 };
 
 // Record bookkeeping, 16 bytes.  Records are the visible (Gaussian, slice)

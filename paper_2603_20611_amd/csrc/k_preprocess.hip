@@ -248,7 +248,7 @@ __device__ __forceinline__ void make_record(const Loaded& L, const SliceDev& sl,
                     isfinite(pay.b) && isfinite(pay.c);
   if (!good) pay.x = pay.y = pay.a = pay.b = pay.c = pay.w = 0.0f;
   pay.g = exp2f(2.0f * pay.a);
-  pay.gid = (uint32_t)L.j;
+  pay.h = exp2f(pay.b);
   meta.ibase = ibase;
   meta.rx = (uint32_t)rect.tx0 | ((uint32_t)rect.tx1 << 16);
   meta.ry = (uint32_t)rect.ty0 | ((uint32_t)rect.ty1 << 16);

@@ -53,7 +53,13 @@ struct FwdArgs {
 // which needs two exp2 per four pixels instead of four.  For such records an
 // underflow of e at the segment start implies the rest of the segment is below
 // 2^-27 of the record's peak, and s is clamped at 126 so 2^s stays finite.
+// The second row's first ratio is the first row's times h = 2^b.  With
+// |b| <= kSmoothB this stays exact where it matters: the exponent's x-slope is
+// at most 4 sqrt(-exponent) when a >= -4, so a first-row ratio clamped at 2^126
+// leaves a second-row ratio above 2^62 and that row's segment below 2^-110,
+// and one that underflows leaves the second row's below 2^-62.
 constexpr float kSmoothA = -4.0f;
+constexpr float kSmoothB = 64.0f;
 
 
 
@@ -70,7 +76,7 @@ __device__ __forceinline__ int slice_of(const FwdArgs& a, int n_slices, int tps,
 // third), so a new tile rarely starts by waiting on memory.
 __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   __shared__ float4 buf0[64];   // x, y, a, b of the batch's records
-  __shared__ float4 buf1[64];   // c, w, g, gid
+  __shared__ float4 buf1[64];   // c, w, g, h
   const int n_bins = a.hdr->n_bins;
   const int n_slices = a.hdr->n_slices;
   const int tps = a.hdr->tiles_per_slice;
@@ -165,9 +171,9 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
         const float e10 = __builtin_amdgcn_exp2f(p10);
         float e01, e02, e03, e11, e12, e13;
         // both records of the step must allow the row recurrence (uniform branch)
-        if (__builtin_amdgcn_read_exec() == __ballot(r0.z >= kSmoothA)) {
+        if (__builtin_amdgcn_read_exec() == __ballot(r0.z >= kSmoothA && fabsf(r0.w) <= kSmoothB)) {
           float q0 = __builtin_amdgcn_exp2f(fminf(fmaf(r0.z, t, by0), 126.0f));
-          float q1 = __builtin_amdgcn_exp2f(fminf(fmaf(r0.z, t, by1), 126.0f));
+          float q1 = fminf(q0 * r1.w, 8.50705917e37f);
           e01 = e00 * q0;
           e11 = e10 * q1;
           q0 *= r1.z;

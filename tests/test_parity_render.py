@@ -83,7 +83,7 @@ def test_tiny_forward_and_bins(gp):
 
 
 @pytest.mark.parametrize("case", ["ragged", "offset_grid", "sigma0", "sigma_inf", "mixed_grids", "one_gaussian",
-                                  "stride_pad"])
+                                  "stride_pad", "needles"])
 def test_forward_edge_cases(gp, case):
     _say(f"edge case {case}")
     rng_seed = 21
@@ -105,6 +105,21 @@ def test_forward_edge_cases(gp, case):
         p = p[:, :1].copy()
         p[0:3, 0] = (31.0, 17.0, 6.0)
         slices = synth.axial_slices(3, 64, 32, 1.0, z0=5.0, dz=1.0)
+    elif case == "needles":
+        # wide in x and a few hundredths of a pixel in y, tilted about z so that
+        # the x-y coupling of the exponent is large next to smooth rows along x;
+        # centres on pixel rows of both parities, exactly representable
+        sy = np.repeat([0.015, 0.02, 0.03], 4)
+        th = np.tile([-0.9, 0.9, -0.6, 0.6], 3) * 2.2 * sy
+        p = np.zeros((11, sy.size), np.float32)
+        p[0] = np.arange(sy.size) * 3.0 + 5.5
+        p[1] = np.tile([3.5, 8.5, 11.5, 16.5], 3)
+        p[2] = 4.0
+        p[3], p[4], p[5] = np.log(1.2), np.log(sy), 0.0
+        p[6], p[9] = np.cos(th / 2), np.sin(th / 2)
+        p[10] = 0.8
+        slices = [dict(z=4.0, sigma_z=0.5, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=44, height=24),
+                  dict(z=4.7, sigma_z=1.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=44, height=24)]
     else:  # stride_pad
         slices = synth.axial_slices(2, 64, 48, 1.0, z0=3.3, dz=4.0)
         stride = 448
