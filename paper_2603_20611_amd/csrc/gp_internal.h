@@ -113,13 +113,16 @@ enum { kCtrRecords = 0, kCtrInstances = 1, kCtrOverflow = 2, kCtrCount = 4 };
 
 // Record payload in pixel space, 32 bytes, gathered by the rasterisers:
 //   x, y = mean in pixel-index units; a, b, c = exponent coefficients of
-//   exp2(a dx^2 + b dx dy + c dy^2); w = alpha~; g = 2^(2a) (the per-pixel
-//   ratio of the row recurrence) and h = 2^b (its change from one row to the
-//   next).
+//   exp2(a dx^2 + b dx dy + c dy^2); w = alpha~; for records inside the row
+//   recurrence's range (a >= kSmoothA, |b| <= kSmoothB) g = 2^(2a), the
+//   change of the per-pixel ratio along a row, and h = 2^b, its change from
+//   one row to the next; g = -1 and h = 0 mark the other records.
 struct alignas(16) RecPay {
   float x, y, a, b;
   float c, w, g, h;
 };
+constexpr float kSmoothA = -4.0f;
+constexpr float kSmoothB = 16.0f;
 
 // Record bookkeeping, 16 bytes.  Records are the visible (Gaussian, slice)
 // pairs; the instance slots [ibase, ibase + ntiles) enumerate the footprint

@@ -247,8 +247,9 @@ __device__ __forceinline__ void make_record(const Loaded& L, const SliceDev& sl,
   const bool good = det > 0.0f && isfinite(at) && isfinite(pay.x) && isfinite(pay.y) && isfinite(pay.a) &&
                     isfinite(pay.b) && isfinite(pay.c);
   if (!good) pay.x = pay.y = pay.a = pay.b = pay.c = pay.w = 0.0f;
-  pay.g = exp2f(2.0f * pay.a);
-  pay.h = exp2f(pay.b);
+  const bool smooth = pay.a >= kSmoothA && fabsf(pay.b) <= kSmoothB;
+  pay.g = smooth ? exp2f(2.0f * pay.a) : -1.0f;
+  pay.h = smooth ? exp2f(pay.b) : 0.0f;
   meta.ibase = ibase;
   meta.rx = (uint32_t)rect.tx0 | ((uint32_t)rect.tx1 << 16);
   meta.ry = (uint32_t)rect.ty0 | ((uint32_t)rect.ty1 << 16);

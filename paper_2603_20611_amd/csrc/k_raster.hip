@@ -47,19 +47,35 @@ struct FwdArgs {
   uint32_t* work;
 };
 
-// Records with a >= kSmoothA (conditional x-sigma >= 0.42 px) are evaluated
-// along each lane's four-pixel row segment by the exact product recurrence
+// Records with a >= kSmoothA (conditional x-sigma >= 0.42 px) and
+// |b| <= kSmoothB are evaluated along each lane's four-pixel row segment by the
+// exact product recurrence
 //   e(d + 1) = e(d) 2^s(d),  2^s(d + 1) = 2^s(d) g,  s(d) = a (2d + 1) + b dy,  g = 2^(2a)
-// which needs two exp2 per four pixels instead of four.  For such records an
-// underflow of e at the segment start implies the rest of the segment is below
-// 2^-27 of the record's peak, and s is clamped at 126 so 2^s stays finite.
-// The second row's first ratio is the first row's times h = 2^b.  With
-// |b| <= kSmoothB this stays exact where it matters: the exponent's x-slope is
-// at most 4 sqrt(-exponent) when a >= -4, so a first-row ratio clamped at 2^126
-// leaves a second-row ratio above 2^62 and that row's segment below 2^-110,
-// and one that underflows leaves the second row's below 2^-62.
-constexpr float kSmoothA = -4.0f;
-constexpr float kSmoothB = 64.0f;
+// which needs two exp2 per four pixels instead of four; the second row's first
+// ratio is the first row's times h = 2^b.  Why this needs no clamping: with
+// a >= -4 the exponent's x-slope is at most 4 sqrt(-exponent), so
+//  * an underflow of e at the segment start leaves the rest of the segment
+//    below 2^-27 of the record's peak;
+//  * a ratio 2^s that overflows (s >= 128) forces e = 0 exactly at its own
+//    row's segment start and, with |b| <= 16 (s >= 112 on the other row), at
+//    the other row's too; the products use the multiply with 0 * inf = 0;
+//  * a ratio that underflows leaves its row's remaining pixels below 2^-133.
+
+// Work items: one tile position over a group of kSliceGroup consecutive slices
+// of one grid, rendered in turn by one wavefront.  The records of a Gaussian
+// on consecutive slices are adjacent in memory, so the gathers of a group's
+// later slices mostly hit the lines its first slice brought into the cache.
+// Used when the grouped items still outnumber the launch's workgroups several
+// times over (a deep stack); smaller batches keep one tile per item.
+constexpr int kSliceGroup = 3;
+constexpr int kGroupMinBins = 3 * 8192;
+
+// Product with 0 * anything = 0 (also 0 * inf).
+__device__ __forceinline__ float mul0(float x, float y) {
+  float r;
+  asm("v_mul_legacy_f32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
+  return r;
+}
 
 
 
@@ -67,8 +83,9 @@ __device__ __forceinline__ int slice_of(const FwdArgs& a, int n_slices, int tps,
   return tps > 0 ? bin / tps : slice_of_bin(a.slices, n_slices, bin);
 }
 
-// One 64-lane workgroup per tile, tiles taken from a shared counter.  Two
-// software pipelines hide the memory latency: within a tile, record ids are
+// One 64-lane workgroup per work item (a tile, or a tile position over a
+// slice group), items taken from a shared counter.  Two software pipelines
+// hide the memory latency: within a tile, record ids are
 // loaded two batches ahead and records one batch ahead; across tiles, the next
 // tile is fetched one step per batch of the current one (its queue ticket is
 // resolved and its list range loaded after the first batch, its slice found
@@ -87,15 +104,27 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   const int row0 = (m >> 2) * 2;
   const int col0 = (m & 3) * 4;
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 pad4 = make_float4(0.f, 0.f, 1.f, 0.f);   // w = 0, smooth
   uint32_t* counter = a.work + kWorkRasterFwd;
-  auto item_of = [&](uint32_t t) { return t < (uint32_t)n_bins ? (int)t : -1; };
+  // work items (queue tickets) -> first bin; rem = further slices of the item
+  const int sg = (tps > 0 && n_bins >= kGroupMinBins) ? kSliceGroup : 1;
+  const int n_items = sg > 1 ? ((n_slices + sg - 1) / sg) * tps : n_bins;
+  auto first_bin = [&](uint32_t t, int& rem) -> int {
+    rem = 0;
+    if (t >= (uint32_t)n_items) return -1;
+    if (sg == 1) return (int)t;
+    const int g = (int)t / tps, tt = (int)t - g * tps;
+    rem = min(sg, n_slices - g * sg) - 1;
+    return g * sg * tps + tt;
+  };
 
   // the first tile, fetched without overlap
-  int item = item_of(wave_take(counter));
+  int rem = 0;
+  int item = first_bin(wave_take(counter), rem);
   if (item < 0) return;
   uint32_t start = a.bin_lo[item], end = a.bin_hi[item];
   int k = slice_of(a, n_slices, tps, item);
-  float4 n0 = zero4, n1 = zero4;
+  float4 n0 = zero4, n1 = pad4;
   if (start + lane < end) {
     const float4* src = reinterpret_cast<const float4*>(a.rec_pay + a.list[start + lane]);
     n0 = src[0];
@@ -117,12 +146,19 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     for (int i = 0; i < 8; ++i) acc[i] = 0.f;
 
     // next tile, advanced one stage per batch
-    int nitem = -1, nk = 0, stage = 0;
+    int nitem = -1, nk = 0, stage = 0, nrem = 0;
+    bool took = false;
     uint32_t ns = 0u, ne = 0u, nrid = 0u, nrid2 = 0u;
-    float4 m0 = zero4, m1 = zero4;
+    float4 m0 = zero4, m1 = pad4;
     auto advance = [&]() {
       if (stage == 0) {
-        nitem = item_of(ticket);
+        if (rem > 0) {
+          nitem = item + tps;
+          nrem = rem - 1;
+        } else {
+          nitem = first_bin(ticket, nrem);
+          took = true;
+        }
         if (nitem >= 0) {
           ns = a.bin_lo[nitem];
           ne = a.bin_hi[nitem];
@@ -150,7 +186,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
       const int cnt = __builtin_amdgcn_readfirstlane((int)min(64u, end - base));
       const uint32_t nb = base + 64;
       n0 = zero4;
-      n1 = zero4;
+      n1 = pad4;
       if (nb + lane < end) {
         const float4* src = reinterpret_cast<const float4*>(a.rec_pay + rid_next);
         n0 = src[0];
@@ -160,35 +196,42 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
       for (int j = 0; j < cnt; j += 2) {
         const float4 r0 = buf0[j + half];
         const float4 r1 = buf1[j + half];   // j + 1 may be a zero slot: w = 0
-        const float t = fmaf(fx0 - r0.x, 2.0f, 1.0f);
+        asm volatile("" :: "v"(r1.z), "v"(r1.w));   // one 16-byte LDS read for r1
         const float d0 = fx0 - r0.x;
-        const float dy0 = fy0 - r0.y, dy1 = dy0 + 1.0f;
-        const float by0 = r0.w * dy0, by1 = r0.w * dy1;
-        const float cy0 = r1.x * dy0 * dy0, cy1 = r1.x * dy1 * dy1;
+        const float dy0 = fy0 - r0.y;
+        const float by0 = r0.w * dy0;
+        const float cy0 = r1.x * dy0 * dy0;
         const float p00 = fmaf(fmaf(r0.z, d0, by0), d0, cy0);
-        const float p10 = fmaf(fmaf(r0.z, d0, by1), d0, cy1);
-        const float e00 = __builtin_amdgcn_exp2f(p00);
-        const float e10 = __builtin_amdgcn_exp2f(p10);
-        float e01, e02, e03, e11, e12, e13;
-        // both records of the step must allow the row recurrence (uniform branch)
-        if (__builtin_amdgcn_read_exec() == __ballot(r0.z >= kSmoothA && fabsf(r0.w) <= kSmoothB)) {
-          float q0 = __builtin_amdgcn_exp2f(fminf(fmaf(r0.z, t, by0), 126.0f));
-          float q1 = fminf(q0 * r1.w, 8.50705917e37f);
-          e01 = e00 * q0;
-          e11 = e10 * q1;
+        float e00, e01, e02, e03, e10, e11, e12, e13;
+        // both records of the step must allow the row recurrence (uniform branch);
+        // the record's g is negative where it does not
+        if (__builtin_amdgcn_read_exec() == __builtin_amdgcn_ballot_w64(r1.z > 0.0f)) {
+          // second row's exponent: p(d0, dy0 + 1) = p00 + b d0 + c (2 dy0 + 1)
+          const float p10 = fmaf(r0.w, d0, fmaf(r1.x, fmaf(2.0f, dy0, 1.0f), p00));
+          const float t = fmaf(d0, 2.0f, 1.0f);
+          e00 = __builtin_amdgcn_exp2f(p00);
+          e10 = __builtin_amdgcn_exp2f(p10);
+          float q0 = __builtin_amdgcn_exp2f(fmaf(r0.z, t, by0));
+          float q1 = q0 * r1.w;
+          e01 = mul0(e00, q0);
+          e11 = mul0(e10, q1);
           q0 *= r1.z;
           q1 *= r1.z;
-          e02 = e01 * q0;
-          e12 = e11 * q1;
+          e02 = mul0(e01, q0);
+          e12 = mul0(e11, q1);
           q0 *= r1.z;
           q1 *= r1.z;
-          e03 = e02 * q0;
-          e13 = e12 * q1;
+          e03 = mul0(e02, q0);
+          e13 = mul0(e12, q1);
         } else {
+          const float dy1 = dy0 + 1.0f;
+          const float by1 = r0.w * dy1, cy1 = r1.x * dy1 * dy1;
           const float d1 = d0 + 1.0f, d2 = d0 + 2.0f, d3 = d0 + 3.0f;
+          e00 = __builtin_amdgcn_exp2f(p00);
           e01 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d1, by0), d1, cy0));
           e02 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d2, by0), d2, cy0));
           e03 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d3, by0), d3, cy0));
+          e10 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d0, by1), d0, cy1));
           e11 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d1, by1), d1, cy1));
           e12 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d2, by1), d2, cy1));
           e13 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d3, by1), d3, cy1));
@@ -230,13 +273,14 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     }
     // the next tile becomes the current one
     item = nitem;
+    rem = nrem;
     start = ns;
     end = ne;
     k = nk;
     n0 = m0;
     n1 = m1;
     rid_next = nrid2;
-    if (item >= 0) ticket = wave_take(counter);
+    if (item >= 0 && took) ticket = wave_take(counter);
   }
 }
 
