@@ -162,7 +162,18 @@ __global__ __launch_bounds__(256) void k_radix_hist(RadixArgs a) {
   const uint32_t base = tile * kSortTile;
   for (int i = threadIdx.x; i < kSortTile; i += 256) {
     const uint32_t j = base + i;
-    if (j < n) atomicAdd(&h[(a.key_in[j] >> a.shift) & (R - 1)], 1u);
+    if (j < n) {
+      const uint32_t d = (a.key_in[j] >> a.shift) & (R - 1);
+      // runs of equal digits are common (the high digit of consecutive pairs
+      // is mostly the same slice): one atomic for a wavefront that agrees
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+      const uint64_t act = __builtin_amdgcn_read_exec();
+      if (__builtin_amdgcn_ballot_w64(d == d0) == act) {
+        if (__lane_id() == (uint32_t)__builtin_ctzll(act)) atomicAdd(&h[d0], (uint32_t)__popcll(act));
+      } else {
+        atomicAdd(&h[d], 1u);
+      }
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < R; i += 256) a.hist[(size_t)i * a.nblocks + tile] = h[i];
@@ -288,11 +299,37 @@ __global__ __launch_bounds__(256) void k_bin_ranges(const BatchHdr* __restrict__
                                                     uint32_t* __restrict__ lo, uint32_t* __restrict__ hi) {
   const uint32_t n = min(*count, cap);
   const uint32_t n_bins = (uint32_t)hdr->n_bins;
-  for (uint32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
+  // four consecutive keys per thread (one 16-byte load); the neighbours across
+  // a thread boundary come from the adjacent lanes, across a wavefront
+  // boundary from memory
+  const uint32_t n4 = n / 4;
+  const int lane = threadIdx.x & 63;
+  for (uint32_t q0 = blockIdx.x * 256 + (threadIdx.x & ~63u); q0 < n4; q0 += gridDim.x * 256) {
+    const uint32_t q = q0 + lane;
+    uint4 k4 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    if (q < n4) k4 = reinterpret_cast<const uint4*>(key)[q];
+    uint32_t prev = __shfl_up(k4.w, 1, 64), next = __shfl_down(k4.x, 1, 64);
+    if (lane == 0) prev = q == 0 ? 0xFFFFFFFEu : key[4 * q - 1];
+    if (lane == 63 || q + 1 >= n4) next = 4 * q + 4 < n ? key[4 * q + 4] : 0xFFFFFFFEu;
+    if (q < n4) {
+      const uint32_t kk[6] = {prev, k4.x, k4.y, k4.z, k4.w, next};
+#pragma unroll
+      for (int i = 1; i <= 4; ++i) {
+        const uint32_t b = kk[i];
+        if (b >= n_bins) continue;   // slots of an overflowed Gaussian (sorted last)
+        if (kk[i - 1] != b) lo[b] = 4 * q + i - 1;
+        if (kk[i + 1] != b) hi[b] = 4 * q + i;
+      }
+    }
+  }
+  // the last n % 4 keys
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3u)) {
+    const uint32_t p = 4 * n4 + threadIdx.x;
     const uint32_t b = key[p];
-    if (b >= n_bins) continue;   // slots of an overflowed Gaussian (sorted last)
-    if (p == 0 || key[p - 1] != b) lo[b] = p;
-    if (p + 1 == n || key[p + 1] != b) hi[b] = p + 1;
+    if (b < n_bins) {
+      if (p == 0 || key[p - 1] != b) lo[b] = p;
+      if (p + 1 == n || key[p + 1] != b) hi[b] = p + 1;
+    }
   }
 }
 
