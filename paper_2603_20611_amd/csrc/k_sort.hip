@@ -160,10 +160,19 @@ __global__ __launch_bounds__(256) void k_radix_hist(RadixArgs a) {
   const uint32_t n = min(*a.count, a.cap);
   const uint32_t tile = blockIdx.x;
   const uint32_t base = tile * kSortTile;
-  for (int i = threadIdx.x; i < kSortTile; i += 256) {
-    const uint32_t j = base + i;
+  // all loads first (independent, in flight together), then the counting
+  constexpr int kPer = kSortTile / 256;
+  uint32_t kv[kPer];
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const uint32_t j = base + c * 256 + threadIdx.x;
+    kv[c] = j < n ? a.key_in[j] : 0u;
+  }
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const uint32_t j = base + c * 256 + threadIdx.x;
     if (j < n) {
-      const uint32_t d = (a.key_in[j] >> a.shift) & (R - 1);
+      const uint32_t d = (kv[c] >> a.shift) & (R - 1);
       // runs of equal digits are common (the high digit of consecutive pairs
       // is mostly the same slice): one atomic for a wavefront that agrees
       const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
@@ -215,13 +224,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(RadixArgs a) {
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
     const uint32_t j = (uint32_t)(wave * kPerWave + c * 64 + lane);
-    key[c] = 0u;
-    val[c] = 0u;
-    if (j < tn) {
-      key[c] = a.key_in[base + j];
-      val[c] = a.val_in[base + j];
-      atomicAdd(&wrun[wave][(key[c] >> a.shift) & (R - 1)], 1u);
-    }
+    key[c] = j < tn ? a.key_in[base + j] : 0u;
+    val[c] = j < tn ? a.val_in[base + j] : 0u;
+  }
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    const uint32_t j = (uint32_t)(wave * kPerWave + c * 64 + lane);
+    if (j < tn) atomicAdd(&wrun[wave][(key[c] >> a.shift) & (R - 1)], 1u);
   }
   __syncthreads();
   // exclusive scan over digits of the tile's counts (two digits per thread),
