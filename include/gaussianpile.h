@@ -78,8 +78,17 @@ typedef int32_t gp_status;
  * Sigma_zz) <= q_cut.  bbox_sigmas: half-width of the tile footprint in
  * standard deviations of Sigma_2d.  scale_mod: the `mod` factor of
  * S = diag(mod * s) (supplement, "Derivation of Forward rendering process").  GP_FLAG_EXACT: no cull and no
- * footprint, every Gaussian reaches every pixel (reference mode). */
+ * footprint, every Gaussian reaches every pixel (reference mode).
+ * GP_FLAG_CONV_EXACT: instead of the paper's phenomenological intensity
+ * alpha~ = alpha opacity_r / sqrt(det Sigma_2d) (Sec. 4.2, intensity
+ * normalisation), the exact value of the convolution integral of Sec. 4.2
+ * (I = integral of h(t) g_c(x, y, t) dt): alpha~ = alpha opacity_r
+ * sqrt(2 pi det Sigma_e / det Sigma_2d), i.e. the paper's value times
+ * sqrt(2 pi det Sigma_e) with det Sigma_e = det Sigma sigma_z^2 / (sigma_z^2 +
+ * Sigma_zz) (0 for sigma_z = 0, det Sigma for sigma_z = +inf).  Forward and
+ * backward; the membership (bins) does not change. */
 #define GP_FLAG_EXACT 1u
+#define GP_FLAG_CONV_EXACT 2u
 typedef struct gp_render_opts {
   float q_cut;        /* default 2 ln 255 = 11.0825...: opacity_r >= 1/255 */
   float bbox_sigmas;  /* default 3 */

@@ -20,7 +20,10 @@ What is followed, step by step:
   * screen-space marginal Sigma_2d = Sigma_e[0:2, 0:2], mu_2d = mu_e[0:2]
     (Sec. 4.2, screen-space projection equation);
   * intensity alpha~ = alpha * opacity_r / sqrt(det Sigma_2d)  (Sec. 4.2,
-    intensity normalisation equation);
+    intensity normalisation equation); with conv_exact=True instead the exact
+    value of the convolution integral of Sec. 4.2 (I = integral over t of
+    h(t) g_c(x, y, t)), which completing the square in the exponent gives as
+    alpha * opacity_r * sqrt(2 pi det Sigma_e / det Sigma_2d);
   * additive rasterisation I(p) = sum_{i in N(p)} alpha~_i exp(-1/2 d^T
     Sigma_2d^-1 d), d = p - mu_2d  (Sec. 4.2, additive rasterisation equation),
     with N(p) the members of p's 16x16 tile from the binary32 specification in
@@ -80,7 +83,7 @@ def activate(params, scale_mod=1.0):
 # --------------------------------------------------------------------------- #
 # Focus Gaussian on one axial slice
 # --------------------------------------------------------------------------- #
-def focus(mu, Sigma, alpha, z, sigma_z):
+def focus(mu, Sigma, alpha, z, sigma_z, conv_exact=False):
     """Per-Gaussian Focus-Gaussian quantities on the slice at depth z.
 
     Returns dict with mu2d [n,2], Sigma2d [n,2,2], opacity_r [n], alpha_t [n]
@@ -112,6 +115,11 @@ def focus(mu, Sigma, alpha, z, sigma_z):
     Sigma2d = Sigma_e[:, 0:2, 0:2]
     mu2d = mu_e[:, 0:2]
     alpha_t = alpha * opacity_r / torch.sqrt(torch.linalg.det(Sigma2d))
+    if conv_exact:
+        if sz > 0.0:
+            alpha_t = alpha_t * torch.sqrt(2.0 * math.pi * torch.linalg.det(Sigma_e))
+        else:
+            alpha_t = alpha_t * 0.0   # h has zero width: the integral vanishes
     return dict(mu_e=mu_e, Sigma_e=Sigma_e, mu2d=mu2d, Sigma2d=Sigma2d,
                 opacity_r=opacity_r, alpha_t=alpha_t, qdiff=qdiff)
 
@@ -139,7 +147,7 @@ def slice_instances(params32, sl, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.BBOX_D
 
 
 def render_slice(params, params32, sl, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.BBOX_DEFAULT,
-                 scale_mod=1.0, exact=False, instances=None):
+                 scale_mod=1.0, exact=False, instances=None, conv_exact=False):
     """FP64 image [H, W] of one slice.  params: float64 tensor [11, N] (may require grad);
     params32: the same values as float32 numpy (membership is decided on them)."""
     W, H = int(sl["width"]), int(sl["height"])
@@ -153,7 +161,7 @@ def render_slice(params, params32, sl, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.B
     uniq, inv = np.unique(gidx, return_inverse=True)
     u = torch.from_numpy(uniq)
     mu, Sigma, alpha = activate(params[:, u], scale_mod)
-    f = focus(mu, Sigma, alpha, sl["z"], sl["sigma_z"])
+    f = focus(mu, Sigma, alpha, sl["z"], sl["sigma_z"], conv_exact)
     inv_t = torch.from_numpy(inv)
     Sinv = torch.linalg.inv(f["Sigma2d"])[inv_t]          # [K,2,2]
     m2 = f["mu2d"][inv_t]                                 # [K,2]
@@ -177,15 +185,15 @@ def render_slice(params, params32, sl, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.B
 
 
 def render(params, slices, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.BBOX_DEFAULT,
-           scale_mod=1.0, exact=False):
+           scale_mod=1.0, exact=False, conv_exact=False):
     """List of FP64 images, one per slice.  params: float32 numpy [11, N] or tensor."""
     p64 = _as_params64(params)
     p32 = p64.detach().numpy().astype(np.float32)
-    return [render_slice(p64, p32, sl, q_cut, bbox, scale_mod, exact) for sl in slices]
+    return [render_slice(p64, p32, sl, q_cut, bbox, scale_mod, exact, conv_exact=conv_exact) for sl in slices]
 
 
 def render_pixels(params, sl, px, py, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.BBOX_DEFAULT,
-                  scale_mod=1.0):
+                  scale_mod=1.0, conv_exact=False):
     """FP64 values of selected pixels of one slice, each summed over its tile's list.
 
     For large workloads: membership is decided for the whole slice (binary32,
@@ -207,7 +215,7 @@ def render_pixels(params, sl, px, py, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.BB
         if members.size == 0:
             continue
         mu, Sigma, alpha = activate(p64[:, torch.from_numpy(members)], scale_mod)
-        f = focus(mu, Sigma, alpha, sl["z"], sl["sigma_z"])
+        f = focus(mu, Sigma, alpha, sl["z"], sl["sigma_z"], conv_exact)
         X = sl["x0"] + (x + 0.5) * sl["dx"]
         Y = sl["y0"] + (y + 0.5) * sl["dy"]
         d = torch.tensor([X, Y], dtype=F64)[None, :] - f["mu2d"]
@@ -221,14 +229,14 @@ def render_pixels(params, sl, px, py, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.BB
 # Gradient of a linear functional of the images
 # --------------------------------------------------------------------------- #
 def grad(params, slices, weights, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.BBOX_DEFAULT,
-         scale_mod=1.0, exact=False):
+         scale_mod=1.0, exact=False, conv_exact=False):
     """d/dparams of L = sum_k sum_p weights[k][p] * I_k(p), float64 [11, N].
 
     weights: list of [H, W] arrays (the upstream gradient dL/dI)."""
     p64 = _as_params64(params).detach().clone().requires_grad_(True)
     p32 = p64.detach().numpy().astype(np.float32)
     for sl, w in zip(slices, weights):
-        img = render_slice(p64, p32, sl, q_cut, bbox, scale_mod, exact)
+        img = render_slice(p64, p32, sl, q_cut, bbox, scale_mod, exact, conv_exact=conv_exact)
         L = (img * torch.as_tensor(np.asarray(w), dtype=F64)).sum()
         if L.requires_grad:
             L.backward()

@@ -223,7 +223,7 @@ static gp_status check_opts(const gp_render_opts* o) {
   if (!o) return einval("opts: NULL");
   if (!(o->q_cut >= 0.f) || !(o->bbox_sigmas > 0.f) || !(o->scale_mod > 0.f))
     return einval("opts: q_cut >= 0, bbox_sigmas > 0 and scale_mod > 0 required");
-  if (o->flags & ~GP_FLAG_EXACT) return einval("opts: unknown flag");
+  if (o->flags & ~(GP_FLAG_EXACT | GP_FLAG_CONV_EXACT)) return einval("opts: unknown flag");
   return GP_OK;
 }
 

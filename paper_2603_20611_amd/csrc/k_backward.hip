@@ -70,6 +70,7 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
   float st_norm = 0.f, st_rad = 0.f;
   int32_t st_cnt = 0;
   float gxx = 0.f, gxy = 0.f, gxz = 0.f, gyy = 0.f, gyz = 0.f, gzz = 0.f;
+  float gls = 0.f;   // common part of the three log-scale gradients (exact convolution)
 
   for (uint32_t r = rbase; r < rbase + nrec && r < a.rc.rec_cap; ++r) {
     const RecMeta meta = a.rec_meta[r];
@@ -92,7 +93,10 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
     const float det = w * c.a22 + c.detS * invD;
     if (!(det > 0.0f) || !isfinite(det)) continue;
     const float rho = expf(-0.5f * ax.q);
-    const float sq = sqrtf(det);
+    // exact convolution integral: alpha~ carries f = sqrt(2 pi det Sigma w)
+    const bool conv = (a.rc.flags & GP_FLAG_CONV_EXACT) != 0;
+    const float f = conv ? sqrtf(6.28318530717958648f * c.detS * w) : 1.0f;
+    const float sq = sqrtf(det) / f;
     const float at = alpha * rho / sq;
     const float inv_det = 1.0f / det;
     const float ca = C * inv_det, cb = -B * inv_det, cc = A * inv_det;
@@ -118,6 +122,12 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
     galpha += g_at * rho / sq;
     const float g_rho = g_at * alpha / sq;
     const float g_q = -0.5f * rho * g_rho;
+    // d ln f = (1/2) (d ln det Sigma + d ln w), d ln det Sigma / d l_i = 2,
+    // d ln w / d Sigma_zz = -1 / D
+    if (conv) {
+      gls += g_at * at;
+      gzz += -0.5f * g_at * at * invD;
+    }
     // Focus Gaussian -> Sigma, mu
     const float g_u = -m * g_m2x, g_v = -m * g_m2y;
     gxx += gA;
@@ -170,9 +180,9 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
   gp[0] += gmx;
   gp[gs] += gmy;
   gp[2 * gs] += gmz;
-  gp[3 * gs] += gl[0];
-  gp[4 * gs] += gl[1];
-  gp[5 * gs] += gl[2];
+  gp[3 * gs] += gl[0] + gls;
+  gp[4 * gs] += gl[1] + gls;
+  gp[5 * gs] += gl[2] + gls;
   gp[6 * gs] += gq[0];
   gp[7 * gs] += gq[1];
   gp[8 * gs] += gq[2];

@@ -26,6 +26,7 @@ namespace gp {
 namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kTwoPi = 6.28318530717958648f;
 
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
@@ -229,13 +230,15 @@ __device__ __forceinline__ void count_one(const PreArgs& a, int n_groups, int t)
 // Image quantities of a kept (Gaussian, slice) pair (binary32; not part of the
 // membership specification).
 __device__ __forceinline__ void make_record(const Loaded& L, const SliceDev& sl, const SpecAxial& ax,
-                                            const SpecRect& rect, int k, uint32_t ibase, RecPay& pay,
-                                            RecMeta& meta) {
+                                            const SpecRect& rect, int k, uint32_t ibase, uint32_t flags,
+                                            RecPay& pay, RecMeta& meta) {
   const SpecCov& c = L.c;
   const float B = rect.w * c.sxy - c.a01 * rect.invD;
   const float det = rect.w * c.a22 + c.detS * rect.invD;
   const float rho = expf(-0.5f * ax.q);
-  const float at = L.p[10] * rho / sqrtf(det);
+  float at = L.p[10] * rho / sqrtf(det);
+  // exact convolution integral: times sqrt(2 pi det Sigma_e), det Sigma_e = det Sigma w
+  if (flags & GP_FLAG_CONV_EXACT) at *= sqrtf(kTwoPi * c.detS * rect.w);
   const float inv_det = 1.0f / det;
   const float ca = rect.C * inv_det, cb = -B * inv_det, cc = rect.A * inv_det;
   pay.x = (rect.mx - sl.x0) / sl.dx - 0.5f;
@@ -335,7 +338,7 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0
         uint32_t slot = inst_run + ipos;
         RecPay pay;
         RecMeta meta;
-        make_record(L, sl, ax, rect, k, slot, pay, meta);
+        make_record(L, sl, ax, rect, k, slot, a.rc.flags, pay, meta);
         a.rec_pay[rid] = pay;
         a.rec_meta[rid] = meta;
         for (int ty = rect.ty0; ty <= rect.ty1; ++ty) {

@@ -188,6 +188,56 @@ def test_plane_mass_and_dense_slice_mass():
     assert abs(total - ref_total) <= 1e-9 * ref_total
 
 
+# ----------------------------------------------------------------------------- exact convolution
+@pytest.mark.parametrize("sigma_z", [0.5, 1.0, 3.0, math.inf])
+def test_exact_convolution_mode_is_the_integral(sigma_z):
+    """conv_exact: I(p) = integral of h(t) g_c(x, y, t) dt itself (Sec. 4.2), by quadrature;
+    for sigma_z = inf, h = 1 and I is the line integral of g."""
+    rng = np.random.default_rng(14)
+    for _ in range(3):
+        p = _rand_gaussian(rng, box=(24, 24, 8))
+        z = float(rng.uniform(2, 6))
+        sl = dict(z=z, sigma_z=sigma_z, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=24, height=24)
+        img = focus.render(p, [sl], exact=True, conv_exact=True)[0].numpy()
+        mu, Sig, Sinv, detS, alpha, *_ = _textbook(p)
+        mu_c = mu - np.array([0.0, 0.0, z])
+        for px, py in [(3, 5), (12, 11), (20, 2), (int(mu[0]), int(mu[1]))]:
+            X, Y = px + 0.5, py + 0.5
+            def f(t):
+                d = np.array([X, Y, t]) - mu_c
+                h = 1.0 if math.isinf(sigma_z) else math.exp(-t * t / (2 * sigma_z ** 2))
+                return h * alpha * math.exp(-0.5 * d @ Sinv @ d)
+            ref, _ = integrate.quad(f, -80, 80, epsabs=0, epsrel=1e-13, limit=400)
+            assert abs(img[py, px] - ref) <= 1e-11 * max(abs(ref), 1e-300) + 1e-300
+
+
+def test_exact_convolution_mass_and_zero_width():
+    """conv_exact, summed over a plane: alpha (2 pi)^{3/2} sqrt(det Sigma) sigma_z / sqrt(D)
+    exp(-m^2 / 2D), D = sigma_z^2 + Sigma_zz; over dense slices: (integral of h) x (mass of g)
+    = sqrt(2 pi) sigma_z alpha (2 pi)^{3/2} sqrt(det Sigma).  sigma_z = 0: h has no width, I = 0."""
+    rng = np.random.default_rng(15)
+    p = _rand_gaussian(rng, box=(1, 1, 1), ls=(np.log(1.0), 0.15))
+    p[0:2, 0] = 16.0
+    p[2, 0] = 0.0
+    mu, Sig, Sinv, detS, alpha, *_ = _textbook(p)
+    sigma_z = 0.9
+    D = sigma_z ** 2 + Sig[2, 2]
+    h, dz = 0.25, 0.5
+    total = 0.0
+    for z in np.arange(-12.0, 12.0 + 1e-9, dz):
+        sl = dict(z=float(z), sigma_z=sigma_z, x0=0.0, y0=0.0, dx=h, dy=h, width=128, height=128)
+        mass = focus.render(p, [sl], exact=True, conv_exact=True)[0].numpy().sum() * h * h
+        ref = alpha * (2 * math.pi) ** 1.5 * math.sqrt(detS) * sigma_z / math.sqrt(D) * math.exp(-0.5 * z * z / D)
+        assert abs(mass - ref) <= 1e-10 * alpha * (2 * math.pi) ** 1.5 * math.sqrt(detS)
+        total += mass * dz
+    ref_total = math.sqrt(2 * math.pi) * sigma_z * alpha * (2 * math.pi) ** 1.5 * math.sqrt(detS)
+    assert abs(total - ref_total) <= 1e-9 * ref_total
+    sl = dict(z=0.0, sigma_z=0.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=32, height=32)
+    assert not focus.render(p, [sl], exact=True, conv_exact=True)[0].numpy().any()
+    g = focus.grad(p, [sl], [np.ones((32, 32))], exact=True, conv_exact=True)
+    assert np.isfinite(g).all() and not g.any()
+
+
 # ----------------------------------------------------------------------------- assembly
 def _brute(p, sl, exact):
     """Pure-Python per-pixel sum; membership from the binary32 records, values per Gaussian."""

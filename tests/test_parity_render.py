@@ -144,6 +144,29 @@ def test_forward_exact_mode_matches_brute_force(gp):
     assert err <= FWD_TOL
 
 
+@pytest.mark.parametrize("case", ["tiny", "sigma_mix", "offset_grid"])
+def test_forward_exact_convolution(gp, case):
+    from paper_2603_20611_amd import binding as B
+    _say(f"exact convolution {case}")
+    if case == "tiny":
+        p, slices, _ = synth.tiny(2)
+    else:
+        p = synth.gaussians_uniform(400, (70, 45, 12), np.log(1.4), 0.45, seed=23)
+        if case == "sigma_mix":
+            slices = [dict(z=3.0, sigma_z=0.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=70, height=45),
+                      dict(z=5.5, sigma_z=0.8, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=70, height=45),
+                      dict(z=8.0, sigma_z=math.inf, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=70, height=45)]
+        else:
+            slices = [dict(z=5.0, sigma_z=0.7, x0=-3.25, y0=4.5, dx=0.8, dy=1.3, width=81, height=33)]
+    opts = B.default_opts(flags=B.GP_FLAG_CONV_EXACT)
+    params, ws, imgs = _render_gpu(gp, p, slices, opts)
+    _check_bins(ws, p, slices)
+    ref = [x.numpy() for x in focus.render(p, slices, conv_exact=True)]
+    err, mx = _fwd_err(imgs, ref)
+    _say(f"exact convolution {case}: rel err {err:.3e} (max {mx:.3f})")
+    assert err <= FWD_TOL
+
+
 def test_forward_non_finite_and_empty(gp):
     _say("non-finite parameters and empty set")
     p = synth.gaussians_uniform(300, (64, 64, 10), np.log(1.5), 0.3, seed=7)
@@ -219,19 +242,20 @@ def _grad_check(g_gpu, g_ref):
     return worst
 
 
-def _backward_case(gp, p, slices, seed=0):
-    from paper_2603_20611_amd import render
+def _backward_case(gp, p, slices, seed=0, conv_exact=False):
+    from paper_2603_20611_amd import binding as B, render
+    opts = B.default_opts(flags=B.GP_FLAG_CONV_EXACT if conv_exact else 0)
     params = _gpu_params(p)
     ws = render.Workspace()
-    render.render(params, slices, ws=ws, n=p.shape[1])
+    render.render(params, slices, opts, ws=ws, n=p.shape[1])
     rng = np.random.default_rng(seed)
     w = [rng.standard_normal((int(s["height"]), int(s["width"]))) for s in slices]
     gflat = torch.from_numpy(np.concatenate([x.ravel() for x in w]).astype(np.float32)).cuda()
-    grad = render.render_backward(params, slices, gflat, ws, n=p.shape[1])
+    grad = render.render_backward(params, slices, gflat, ws, opts, n=p.shape[1])
     torch.cuda.synchronize()
     g_gpu = grad.cpu().numpy().astype(np.float64)[:, :p.shape[1]]
     w64 = [x.astype(np.float32).astype(np.float64) for x in w]
-    g_ref = focus.grad(p, slices, w64)
+    g_ref = focus.grad(p, slices, w64, conv_exact=conv_exact)
     return g_gpu, g_ref, (params, ws, gflat)
 
 
@@ -260,6 +284,23 @@ def test_backward_edge_cases(gp, case):
     g_gpu, g_ref, _ = _backward_case(gp, p, slices, seed=3)
     worst = _grad_check(g_gpu, g_ref)
     _say(f"{case} worst per block {worst}")
+    assert max(worst.values()) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("case", ["tiny", "sigma_inf", "offset_grid"])
+def test_backward_exact_convolution(gp, case):
+    _say(f"backward, exact convolution {case}")
+    if case == "tiny":
+        p, slices, _ = synth.tiny(3)
+    else:
+        p = synth.gaussians_uniform(300, (64, 48, 10), np.log(1.4), 0.4, seed=33)
+        if case == "sigma_inf":
+            slices = synth.axial_slices(2, 64, 48, math.inf, z0=3.3, dz=4.0)
+        else:
+            slices = [dict(z=5.0, sigma_z=0.7, x0=-3.25, y0=4.5, dx=0.8, dy=1.3, width=81, height=33)]
+    g_gpu, g_ref, _ = _backward_case(gp, p, slices, seed=4, conv_exact=True)
+    worst = _grad_check(g_gpu, g_ref)
+    _say(f"exact convolution {case} worst per block {worst}")
     assert max(worst.values()) <= GRAD_TOL
 
 
