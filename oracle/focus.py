@@ -10,9 +10,11 @@ What is followed, step by step:
   * Gaussian parameterisation G = (mu, s, q, alpha), Sigma = R S S^T R^T with
     S = diag(mod * s), R = quatToMatrix(q)  (Sec. 3; supplement, "Derivation
     of Forward rendering process", first three equations);
-  * slice camera: axial slice at depth z, R_c = I, t = (0, 0, -z), so
-    mu_c = mu + t and Sigma_c = Sigma  (supplement, "Derivation of Forward
-    rendering process", camera transform);
+  * slice camera: mu_c = R_c mu + t, Sigma_c = R_c Sigma R_c^T (supplement,
+    "Derivation of Forward rendering process", camera transform), the slice
+    being the plane z_c = z of that frame; an axial slice has R_c = I, t = 0
+    (so mu_c = mu - z e3 relative to the plane), an oblique slice carries its
+    pose (R_c row-major, t) under the key "pose";
   * axial re-parameterisation Sigma_e^-1 = Sigma_c^-1 + e3 e3^T / sigma_z^2,
     mu_e = Sigma_e Sigma_c^-1 mu_c  (Sec. 4.2, Focus Gaussian equation);
   * opacity modulation opacity_r = exp(-1/2 (mu_c^T Sigma_c^-1 mu_c -
@@ -83,17 +85,23 @@ def activate(params, scale_mod=1.0):
 # --------------------------------------------------------------------------- #
 # Focus Gaussian on one axial slice
 # --------------------------------------------------------------------------- #
-def focus(mu, Sigma, alpha, z, sigma_z, conv_exact=False):
-    """Per-Gaussian Focus-Gaussian quantities on the slice at depth z.
+def focus(mu, Sigma, alpha, z, sigma_z, conv_exact=False, pose=None):
+    """Per-Gaussian Focus-Gaussian quantities on the slice z_c = z.
 
+    pose: None (axial, R_c = I, t = 0) or 12 numbers (R_c row-major, t).
     Returns dict with mu2d [n,2], Sigma2d [n,2,2], opacity_r [n], alpha_t [n]
     (and the 3-D mu_e, Sigma_e).
     """
     n = mu.shape[0]
     e3 = torch.tensor([0.0, 0.0, 1.0], dtype=F64)
-    t = torch.tensor([0.0, 0.0, -float(z)], dtype=F64)
-    mu_c = mu + t                                   # R_c = I
-    Sigma_c = Sigma
+    if pose is None:
+        Rc, t = torch.eye(3, dtype=F64), torch.zeros(3, dtype=F64)
+    else:
+        pz = torch.as_tensor(np.asarray(pose, dtype=np.float32).astype(np.float64).reshape(-1))
+        Rc, t = pz[0:9].reshape(3, 3), pz[9:12]
+    # camera frame, measured from the imaging plane z_c = z
+    mu_c = mu @ Rc.T + t - float(z) * e3
+    Sigma_c = Rc @ Sigma @ Rc.T
     Sc_inv = torch.linalg.inv(Sigma_c)
     sz = float(sigma_z)
     if sz > 0.0:
@@ -161,7 +169,7 @@ def render_slice(params, params32, sl, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.B
     uniq, inv = np.unique(gidx, return_inverse=True)
     u = torch.from_numpy(uniq)
     mu, Sigma, alpha = activate(params[:, u], scale_mod)
-    f = focus(mu, Sigma, alpha, sl["z"], sl["sigma_z"], conv_exact)
+    f = focus(mu, Sigma, alpha, sl["z"], sl["sigma_z"], conv_exact, sl.get("pose"))
     inv_t = torch.from_numpy(inv)
     Sinv = torch.linalg.inv(f["Sigma2d"])[inv_t]          # [K,2,2]
     m2 = f["mu2d"][inv_t]                                 # [K,2]
@@ -215,7 +223,7 @@ def render_pixels(params, sl, px, py, q_cut=spec32.Q_CUT_DEFAULT, bbox=spec32.BB
         if members.size == 0:
             continue
         mu, Sigma, alpha = activate(p64[:, torch.from_numpy(members)], scale_mod)
-        f = focus(mu, Sigma, alpha, sl["z"], sl["sigma_z"], conv_exact)
+        f = focus(mu, Sigma, alpha, sl["z"], sl["sigma_z"], conv_exact, sl.get("pose"))
         X = sl["x0"] + (x + 0.5) * sl["dx"]
         Y = sl["y0"] + (y + 0.5) * sl["dy"]
         d = torch.tensor([X, Y], dtype=F64)[None, :] - f["mu2d"]

@@ -25,7 +25,15 @@ Readings of the paper taken here:
     (default q_cut = 2 ln 255, i.e. opacity_r >= 1/255);
   * footprint: the axis-aligned box of the k-sigma ellipse of Sigma_2d (k = 3),
     converted to 16x16 tiles of the slice's pixel grid and clamped to the grid;
-  * pixel (px, py) of a slice has centre (x0 + (px + 1/2) dx, y0 + (py + 1/2) dy).
+  * pixel (px, py) of a slice has centre (x0 + (px + 1/2) dx, y0 + (py + 1/2) dy);
+  * oblique slices (the general camera of the supplement's forward derivation,
+    mu_c = R_c mu + t, Sigma_c = R_c Sigma R_c^T): a slice may carry a pose
+    (R_c row-major, t), and then samples the plane z_c = z of the camera frame.
+    In binary32, R' = R_c R_q entry by entry as (R_c[i][0] R_q[0][j] +
+    R_c[i][1] R_q[1][j]) + R_c[i][2] R_q[2][j], the covariance and adjugate
+    entries are the quadratic forms below with R' in place of R_q, and
+    mu_c[i] = ((R_c[i][0] mu_x + R_c[i][1] mu_y) + R_c[i][2] mu_z) + t[i].  The
+    identity pose reproduces the axial slice bit for bit.
 
 The exponential needed for s = exp(l) is not correctly rounded on any machine, so
 the specification defines its own: Cody-Waite range reduction with the two-part
@@ -82,6 +90,13 @@ def _cov32(ls, q, scale_mod):
          [two * (xy + wz), one - two * (xx + zz), two * (yz - wx)],
          [two * (xz - wy), two * (yz + wx), one - two * (xx + yy)]]
     v0, v1, v2 = s0 * s0, s1 * s1, s2 * s2
+    out = _forms(R, v0, v1, v2)
+    out.update(n2=n2, R=R, v=(v0, v1, v2))
+    return out
+
+
+def _forms(R, v0, v1, v2):
+    """Covariance R diag(v) R^T and adjugate R diag(v1 v2, v0 v2, v0 v1) R^T entries."""
     P0, P1, P2 = v1 * v2, v0 * v2, v0 * v1
 
     def quad(a, b, w0, w1, w2):
@@ -90,13 +105,29 @@ def _cov32(ls, q, scale_mod):
                 + (R[a][2] * R[b][2]) * w2)
 
     return dict(
-        n2=n2,
         sxx=quad(0, 0, v0, v1, v2), sxy=quad(0, 1, v0, v1, v2), sxz=quad(0, 2, v0, v1, v2),
         syy=quad(1, 1, v0, v1, v2), syz=quad(1, 2, v0, v1, v2), szz=quad(2, 2, v0, v1, v2),
         adj00=quad(0, 0, P0, P1, P2), adj01=quad(0, 1, P0, P1, P2),
         adj11=quad(1, 1, P0, P1, P2), adj22=quad(2, 2, P0, P1, P2),
         detS=(v0 * v1) * v2,
     )
+
+
+def pose32(act, pose):
+    """activate32 output seen from a posed slice's camera frame (binary32).
+
+    pose: 12 numbers, R_c row-major then t."""
+    pose = np.asarray(pose, dtype=np.float64).astype(f32).reshape(-1)
+    Rc = pose[0:9].reshape(3, 3)
+    t = pose[9:12]
+    R = act["R"]
+    Rp = [[(Rc[i][0] * R[0][j] + Rc[i][1] * R[1][j]) + Rc[i][2] * R[2][j] for j in range(3)] for i in range(3)]
+    out = dict(act)
+    out.update(_forms(Rp, *act["v"]))
+    mu = (act["mux"], act["muy"], act["muz"])
+    m = [((Rc[i][0] * mu[0] + Rc[i][1] * mu[1]) + Rc[i][2] * mu[2]) + t[i] for i in range(3)]
+    out.update(mux=m[0], muy=m[1], muz=m[2], R=Rp)
+    return out
 
 
 def activate32(params, scale_mod=1.0):
@@ -181,7 +212,7 @@ def bins(params, slices, q_cut=Q_CUT_DEFAULT, bbox=BBOX_DEFAULT, scale_mod=1.0, 
             for t in range(ntx * nty):
                 keys.append(((nbins + t) << 32) + idx.astype(np.int64))
         else:
-            r = slice_records32(act, sl, q_cut, bbox)
+            r = slice_records32(pose32(act, sl["pose"]) if sl.get("pose") is not None else act, sl, q_cut, bbox)
             idx = np.nonzero(r["member"])[0]
             wx = (r["tx1"][idx] - r["tx0"][idx] + 1).astype(np.int64)
             wy = (r["ty1"][idx] - r["ty0"][idx] + 1).astype(np.int64)

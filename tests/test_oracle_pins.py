@@ -238,6 +238,94 @@ def test_exact_convolution_mass_and_zero_width():
     assert np.isfinite(g).all() and not g.any()
 
 
+# ----------------------------------------------------------------------------- oblique slices
+def test_identity_pose_is_the_axial_slice():
+    p = synth.gaussians_uniform(800, (48, 48, 16), np.log(1.4), 0.4, seed=16)
+    ax = synth.axial_slices(3, 48, 40, 1.2, z0=3.0, dz=4.5)
+    ident = np.concatenate([np.eye(3).reshape(-1), np.zeros(3)]).astype(np.float32)
+    po = [dict(s, pose=ident) for s in ax]
+    k0, r0 = spec32.bins(p, ax)
+    k1, r1 = spec32.bins(p, po)
+    assert np.array_equal(k0, k1) and np.array_equal(r0, r1)
+    for a, b in zip(focus.render(p, ax), focus.render(p, po)):
+        assert torch.equal(a, b)
+
+
+def _quat_mul(a, b):
+    aw, ax, ay, az = a
+    bw, bx, by, bz = b
+    return np.array([aw * bw - ax * bx - ay * by - az * bz, aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx, aw * bz + ax * by - ay * bx + az * bw])
+
+
+@pytest.mark.parametrize("sigma_z", [0.0, 1.5, math.inf])
+@pytest.mark.parametrize("kind", ["axis_cycle", "generic"])
+def test_pose_is_a_rigid_motion_of_the_set(sigma_z, kind):
+    """Rendering the set through a slice pose (R_c, t) equals rendering, on the axial slice,
+    the set moved by that rigid motion (mu' = R_c mu + t, rotation R_c R(q), i.e. q' = q_c q
+    with scipy's quaternion of R_c).  The axis cycle is a rotation exactly representable in
+    binary32 (equal to rounding); a generic rotation rounded to binary32 is orthonormal
+    only to ~1e-7, which bounds the agreement."""
+    p = synth.gaussians_uniform(120, (40, 40, 16), np.log(1.5), 0.3, seed=17).astype(np.float64)
+    if kind == "axis_cycle":
+        pose = np.array([0, 1, 0, 0, 0, 1, 1, 0, 0, 3.0, -2.0, 1.5], np.float64)
+    else:
+        pose = _pose(5, t=(3.0, -2.0, 1.5)).astype(np.float64)
+    Rc, t = pose[0:9].reshape(3, 3), pose[9:12]
+    x, y, z, w = Rotation.from_matrix(Rc).as_quat()
+    qc = np.array([w, x, y, z])
+    moved = p.copy()
+    moved[0:3] = Rc @ p[0:3] + t[:, None]
+    for i in range(p.shape[1]):
+        moved[6:10, i] = _quat_mul(qc, p[6:10, i] / np.linalg.norm(p[6:10, i]))
+    base = dict(z=6.0, sigma_z=sigma_z, x0=-20.0, y0=-20.0, dx=1.0, dy=1.0, width=48, height=48)
+    a = focus.render(torch.from_numpy(p), [dict(base, pose=pose)], exact=True)[0].numpy()
+    b = focus.render(torch.from_numpy(moved), [base], exact=True)[0].numpy()
+    rtol = 1e-9 if kind == "axis_cycle" else 2e-5
+    np.testing.assert_allclose(a, b, rtol=rtol, atol=rtol * 1e-3 * b.max())
+    assert b.max() > 0
+
+
+@pytest.mark.parametrize("sigma_z", [0.7, 2.0])
+@pytest.mark.parametrize("kind", ["axis_cycle", "generic"])
+def test_oblique_slice_matches_convolution_integral(sigma_z, kind):
+    """I(p) on the plane z_c = z of pose (R_c, t): the integral of h(t') g(x(t')) dt' along the
+    world line x(t') = R_c^T ((X, Y, z + t') - t), divided by sqrt(2 pi det Sigma_e) with
+    det Sigma_e = det Sigma sigma_z^2 / (sigma_z^2 + n^T Sigma n), n the plane's world normal.
+    A generic rotation rounded to binary32 is orthonormal only to ~1e-7, which perturbs the
+    exponent relatively by that much (the bound used)."""
+    rng = np.random.default_rng(18)
+    if kind == "axis_cycle":
+        R0 = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    else:
+        R0 = Rotation.random(random_state=7).as_matrix()
+    tol = 1e-10 if kind == "axis_cycle" else 2e-6
+    # the box centre (12, 12, 4) goes to the camera origin
+    pose = np.concatenate([R0.reshape(-1), -R0 @ np.array([12.0, 12.0, 4.0])]).astype(np.float32)
+    Rc, tv = pose[0:9].reshape(3, 3).astype(np.float64), pose[9:12].astype(np.float64)
+    n = Rc[2]
+    for _ in range(3):
+        p = _rand_gaussian(rng, box=(24, 24, 8))
+        mu, Sig, Sinv, detS, alpha, *_ = _textbook(p)
+        z = float(rng.uniform(-1, 1)) + float(n @ mu + tv[2])
+        sl = dict(z=z, sigma_z=sigma_z, x0=-20.0, y0=-20.0, dx=1.0, dy=1.0, width=40, height=40, pose=pose)
+        img = focus.render(p, [sl], exact=True)[0].numpy()
+        det_e = detS * sigma_z ** 2 / (sigma_z ** 2 + n @ Sig @ n)
+        c = Rc @ mu + tv   # the Gaussian's centre in the camera frame, to pick pixels near it
+        assert -20 < c[0] < 20 and -20 < c[1] < 20
+        for px, py in [(int(c[0] + 20), int(c[1] + 20)), (3, 5), (22, 17), (30, 28)]:
+            X, Y = -20.0 + px + 0.5, -20.0 + py + 0.5
+            def f(tt):
+                x = Rc.T @ (np.array([X, Y, z + tt]) - tv)
+                d = x - mu
+                return math.exp(-tt * tt / (2 * sigma_z ** 2)) * alpha * math.exp(-0.5 * d @ Sinv @ d)
+            val, _ = integrate.quad(f, -60, 60, epsabs=0, epsrel=1e-13, limit=400)
+            ref = val / math.sqrt(2 * math.pi * det_e)
+            # a relative perturbation of the pose perturbs the exponent in proportion to it
+            bound = tol * abs(ref) * (1.0 + abs(math.log(max(abs(ref), 1e-300) / alpha)))
+            assert abs(img[py, px] - ref) <= bound + 1e-300
+
+
 # ----------------------------------------------------------------------------- assembly
 def _brute(p, sl, exact):
     """Pure-Python per-pixel sum; membership from the binary32 records, values per Gaussian."""
@@ -293,16 +381,29 @@ def test_render_is_linear_in_the_gaussian_set():
         np.testing.assert_allclose(f.numpy(), (x + y).numpy(), rtol=1e-12, atol=1e-13)
 
 
-def test_spec32_membership_tracks_float64_geometry():
+def _pose(seed, t=(0.0, 0.0, 0.0)):
+    R = Rotation.random(random_state=seed).as_matrix()
+    return np.concatenate([R.reshape(-1), np.asarray(t, np.float64)]).astype(np.float32)
+
+
+@pytest.mark.parametrize("posed", [False, True])
+def test_spec32_membership_tracks_float64_geometry(posed):
     """The binary32 axial test matches the paper's opacity-modulation Mahalanobis change,
     and each binary32 rectangle is the tile cover of the float64 3-sigma box except where
-    that box lies within rounding distance of a tile edge."""
+    that box lies within rounding distance of a tile edge (also for an oblique slice, whose
+    float64 geometry comes from the camera transform of the forward derivation)."""
     p = synth.gaussians_uniform(3000, (64, 64, 32), np.log(1.5), 0.4, seed=10)
     sl = dict(z=13.5, sigma_z=1.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=64, height=64)
     act = spec32.activate32(p)
+    if posed:
+        # a tilted plane through the middle of the box: a rotation about its centre
+        R = Rotation.random(random_state=3).as_matrix()
+        t = np.array([32.0, 32.0, 13.5]) - R @ np.array([32.0, 32.0, 16.0])
+        sl["pose"] = np.concatenate([R.reshape(-1), t]).astype(np.float32)
+        act = spec32.pose32(act, sl["pose"])
     rec = spec32.slice_records32(act, sl)
     mu, Sig, alpha = focus.activate(torch.from_numpy(p.astype(np.float64)))
-    f = focus.focus(mu, Sig, alpha, sl["z"], sl["sigma_z"])
+    f = focus.focus(mu, Sig, alpha, sl["z"], sl["sigma_z"], pose=sl.get("pose"))
     qd = f["qdiff"].numpy()
     q_cut = float(spec32.Q_CUT_DEFAULT)
     clear = np.abs(qd - q_cut) > 1e-4 * q_cut
@@ -322,7 +423,7 @@ def test_spec32_membership_tracks_float64_geometry():
         t1 = np.clip(np.floor(hi), 0, 3).astype(int)
         assert (rec["tx0"][i], rec["ty0"][i], rec["tx1"][i], rec["ty1"][i]) == (t0[0], t0[1], t1[0], t1[1])
         checked += 1
-    assert checked > 500
+    assert checked > 300
 
 
 def test_bins_keys_and_ranges_layout():
