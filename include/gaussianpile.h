@@ -168,6 +168,25 @@ gp_status gp_render_backward(gp_workspace* ws, const gp_gaussians* g, const gp_s
                              int32_t n_slices, const gp_render_opts* opts, const float* d_grad_out,
                              float* d_grad, int64_t grad_stride, void* stream);
 
+/* Oblique slices: gp_render_slices / gp_render_backward with a camera pose per
+ * slice (supplement, "Derivation of Forward rendering process": each slice's
+ * view matrix [R_c | t] maps mu_c = R_c mu + t, Sigma_c = R_c Sigma R_c^T).
+ * h_poses: host array [n_slices][12] float32, R_c row-major then t (the caller
+ * keeps ownership; it is copied before the call returns).  R_c must be a
+ * rotation (|R_c R_c^T - I| <= 1e-4 entrywise, det > 0), else GP_EINVAL.  Slice
+ * k then samples the plane z_c = z of its camera frame, with pixel centres at
+ * (x_c, y_c) = (x0 + (px + 1/2) dx, y0 + (py + 1/2) dy); the identity pose is
+ * the axial slice (and gives bit-identical bins and images).  Membership stays
+ * binary32-exact: R_c R_q and mu_c are formed in a fixed order (documented with
+ * the binning specification).  h_poses = NULL is the axial call.  The backward
+ * must get the same poses as its forward (else GP_ESTATE). */
+gp_status gp_render_slices_posed(gp_workspace* ws, const gp_gaussians* g, const gp_slice* h_slices,
+                                 const float* h_poses, int32_t n_slices, const gp_render_opts* opts,
+                                 float* d_out, void* stream);
+gp_status gp_render_backward_posed(gp_workspace* ws, const gp_gaussians* g, const gp_slice* h_slices,
+                                   const float* h_poses, int32_t n_slices, const gp_render_opts* opts,
+                                   const float* d_grad_out, float* d_grad, int64_t grad_stride, void* stream);
+
 /* L1 term of the loss (Sec. 4.3, loss function): d_grad[j] = scale * sign(d_image[j] -
  * d_target[j]) with sign(0) = 0, and *d_loss += scale * sum_j |d_image[j] -
  * d_target[j]| (d_loss may be NULL).  scale is normally 1 / n.

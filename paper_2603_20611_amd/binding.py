@@ -101,6 +101,10 @@ _SIGS = {
                                      C.POINTER(RenderOpts), _P, _P]),
     "gp_render_backward": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(Slice), C.c_int32,
                                        C.POINTER(RenderOpts), _P, _P, C.c_int64, _P]),
+    "gp_render_slices_posed": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(Slice), C.POINTER(C.c_float),
+                                           C.c_int32, C.POINTER(RenderOpts), _P, _P]),
+    "gp_render_backward_posed": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(Slice), C.POINTER(C.c_float),
+                                             C.c_int32, C.POINTER(RenderOpts), _P, _P, C.c_int64, _P]),
     "gp_l1_loss_grad": (C.c_int32, [_P, _P, C.c_int64, C.c_float, _P, _P, _P]),
     "gp_adam_step": (C.c_int32, [_P, _P, _P, _P, C.c_int64, C.c_int64, C.POINTER(AdamCfg), _P]),
     "gp_workspace_set_timing": (C.c_int32, [_P, C.c_int32]),
@@ -152,6 +156,18 @@ def check(status):
     if status != GP_OK:
         raise GpError(status, load().gp_last_error().decode())
     return status
+
+
+def make_poses(slices):
+    """Host array [n][12] (R_c row-major, t) of the slices' "pose" entries, identity where a
+    slice has none; None if no slice has a pose (axial batch)."""
+    if not any(s.get("pose") is not None for s in slices):
+        return None
+    flat = []
+    for s in slices:
+        p = s.get("pose")
+        flat.extend([float(x) for x in (p if p is not None else (1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0))])
+    return (C.c_float * len(flat))(*flat)
 
 
 def default_opts(**kw):

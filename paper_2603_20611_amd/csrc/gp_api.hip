@@ -64,6 +64,8 @@ gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups, int64
     const int64_t cap = n_slices + 64;
     GP_HIP(dev_alloc(&ws->d_slices, cap));
     GP_HIP(host_alloc(&ws->h_slices, cap));
+    GP_HIP(dev_alloc(&ws->d_poses, 12 * cap));
+    GP_HIP(host_alloc(&ws->h_poses, 12 * cap));
     ws->slice_cap = cap;
   }
   if (n_groups > ws->group_cap) {
@@ -231,7 +233,7 @@ static gp_status check_opts(const gp_render_opts* o) {
 // each) into the workspace's pinned staging.  outs[k] (if given) is where slice
 // k's image goes; otherwise images are packed back to back from out_base.
 gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_slice* hs, int ns, float* out_base,
-                      float* const* outs, BatchPlan* plan) {
+                      float* const* outs, BatchPlan* plan, const float* poses) {
   int64_t nbins = 0, total_gauss = 0;
   for (int k = 0; k < ns; ++k)
     nbins += (int64_t)((hs[k].width + kTile - 1) / kTile) * ((hs[k].height + kTile - 1) / kTile);
@@ -268,12 +270,16 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
     bool sorted = true;
     for (int k = G.k0 + 1; k < G.k1 && sorted; ++k)
       sorted = hs[k].z >= hs[k - 1].z && hs[k].sigma_z == hs[G.k0].sigma_z;
-    G.flags = sorted ? kGroupSortedZ : 0;
+    G.flags = sorted && !poses ? kGroupSortedZ : 0;
     G.zlo = INFINITY; G.zhi = -INFINITY; G.sz2max = 0.f; G.pad = 0.f;
     for (int k = G.k0; k < G.k1; ++k) {
       G.zlo = std::min(G.zlo, hs[k].z);
       G.zhi = std::max(G.zhi, hs[k].z);
       G.sz2max = std::max(G.sz2max, hs[k].sigma_z * hs[k].sigma_z);
+    }
+    if (poses) {   // depths are in each slice's own frame: no world-depth shortcut
+      G.zlo = -INFINITY;
+      G.zhi = INFINITY;
     }
     for (int k = G.k0; k < G.k1; ++k) ws->h_slices[k].group = g;
     gb += (groups[g].g->n + 63) / 64 * 64;
@@ -289,12 +295,16 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
   ws->h_hdr->tiles_per_slice = tps;
   plan->ns = ns; plan->ng = ng; plan->nbins = nbins; plan->total_gauss = total_gauss; plan->npix = off;
   plan->attr_dtype = ng > 0 ? groups[0].g->attr_dtype : GP_F32;
+  plan->posed = poses ? 1 : 0;
+  if (poses) std::memcpy(ws->h_poses, poses, sizeof(float) * 12 * (size_t)ns);
   return GP_OK;
 }
 
 gp_status upload_batch(Workspace* ws, const BatchPlan& p, hipStream_t s) {
   GP_HIP(hipMemcpyAsync(ws->d_hdr, ws->h_hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s));
   if (p.ns > 0) GP_HIP(hipMemcpyAsync(ws->d_slices, ws->h_slices, sizeof(SliceDev) * p.ns, hipMemcpyHostToDevice, s));
+  if (p.ns > 0 && p.posed)
+    GP_HIP(hipMemcpyAsync(ws->d_poses, ws->h_poses, sizeof(float) * 12 * p.ns, hipMemcpyHostToDevice, s));
   if (p.ng > 0) GP_HIP(hipMemcpyAsync(ws->d_groups, ws->h_groups, sizeof(GroupDev) * p.ng, hipMemcpyHostToDevice, s));
   GP_HIP(hipEventRecord(ws->upload_done, s));
   ws->last_stream = s;
@@ -402,13 +412,13 @@ gp_status workspace_new(Workspace** out, int64_t max_records, int64_t max_instan
 void workspace_free(Workspace* ws) {
   if (!ws) return;
   (void)wait_ws(ws);
-  void* dev[] = {ws->d_slices, ws->d_groups, ws->d_hdr, ws->d_work, ws->d_ctr, ws->d_bin_lo, ws->d_bin_hi,
+  void* dev[] = {ws->d_slices, ws->d_poses, ws->d_groups, ws->d_hdr, ws->d_work, ws->d_ctr, ws->d_bin_lo, ws->d_bin_hi,
                  ws->d_rec_pay, ws->d_rec_meta, ws->d_g_rbase, ws->d_g_nrec, ws->d_g_ninst, ws->d_g_krange,
                  ws->d_wave_cnt, ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, ws->d_hist,
                  ws->d_scan_part, ws->d_moments, ws->d_ssim, ws->d_vox_rec, ws->d_vox_box, ws->d_vox_mom};
   for (void* p : dev)
     if (p) (void)hipFree(p);
-  void* host[] = {ws->h_slices, ws->h_groups, ws->h_hdr, ws->h_ctr};
+  void* host[] = {ws->h_slices, ws->h_poses, ws->h_groups, ws->h_hdr, ws->h_ctr};
   for (void* p : host)
     if (p) (void)hipHostFree(p);
   (void)resolve_timings(ws);
@@ -471,8 +481,42 @@ gp_status gp_workspace_check(gp_workspace* w, int64_t* records, int64_t* instanc
   return GP_OK;
 }
 
-gp_status gp_render_slices(gp_workspace* w, const gp_gaussians* g, const gp_slice* hs, int32_t ns,
-                           const gp_render_opts* o, float* out, void* stream) {
+// Camera poses of posed slices: finite, R_c a rotation (orthonormal to 1e-4,
+// determinant > 0).
+static gp_status check_poses(const float* poses, int ns) {
+  for (int k = 0; k < ns; ++k) {
+    const float* p = poses + 12 * (size_t)k;
+    char buf[160];
+    for (int i = 0; i < 12; ++i)
+      if (!std::isfinite(p[i])) {
+        snprintf(buf, sizeof buf, "pose %d: non-finite entry", k);
+        return einval(buf);
+      }
+    double worst = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double d = 0.0;
+        for (int i = 0; i < 3; ++i) d += (double)p[3 * r + i] * p[3 * c + i];
+        worst = std::max(worst, std::fabs(d - (r == c ? 1.0 : 0.0)));
+      }
+    const double det = (double)p[0] * ((double)p[4] * p[8] - (double)p[5] * p[7]) -
+                       (double)p[1] * ((double)p[3] * p[8] - (double)p[5] * p[6]) +
+                       (double)p[2] * ((double)p[3] * p[7] - (double)p[4] * p[6]);
+    if (worst > 1e-4 || !(det > 0.0)) {
+      snprintf(buf, sizeof buf, "pose %d: R_c must be a rotation (|R R^T - I| = %.2e, det = %.3f)", k, worst, det);
+      return einval(buf);
+    }
+  }
+  return GP_OK;
+}
+
+static uint64_t slices_hash(const gp_slice* hs, const float* poses, int ns, const gp_render_opts* o) {
+  uint64_t h = hash_bytes(hs, sizeof(gp_slice) * (size_t)ns, hash_bytes(o, sizeof(*o)));
+  return poses ? hash_bytes(poses, sizeof(float) * 12 * (size_t)ns, h ^ 0x9e3779b97f4a7c15ull) : h;
+}
+
+gp_status gp_render_slices_posed(gp_workspace* w, const gp_gaussians* g, const gp_slice* hs, const float* poses,
+                                 int32_t ns, const gp_render_opts* o, float* out, void* stream) {
   if (!w) return einval("render: NULL workspace");
   Workspace* ws = reinterpret_cast<Workspace*>(w);
   gp_status st = check_gaussians(g);
@@ -481,6 +525,7 @@ gp_status gp_render_slices(gp_workspace* w, const gp_gaussians* g, const gp_slic
   if (ns < 0 || (ns > 0 && (!hs || !out))) return einval("render: bad slices/out");
   for (int k = 0; k < ns; ++k)
     if ((st = check_slice(hs[k], k)) != GP_OK) return st;
+  if (poses && (st = check_poses(poses, ns)) != GP_OK) return st;
   GP_HIP(hipSetDevice(ws->device));
   ws->have_forward = false;
   ws->vox_have = false;
@@ -488,9 +533,10 @@ gp_status gp_render_slices(gp_workspace* w, const gp_gaussians* g, const gp_slic
   hipStream_t s = static_cast<hipStream_t>(stream);
   GroupIn grp{g, 0, ns};
   BatchPlan plan{};
-  if ((st = stage_batch(ws, &grp, 1, hs, ns, out, nullptr, &plan)) != GP_OK) return st;
+  if ((st = stage_batch(ws, &grp, 1, hs, ns, out, nullptr, &plan, poses)) != GP_OK) return st;
   if ((st = upload_batch(ws, plan, s)) != GP_OK) return st;
-  const LaunchDims d{plan.total_gauss, plan.nbins, emit_width_for(ns)};
+  LaunchDims d{plan.total_gauss, plan.nbins, emit_width_for(ns)};
+  d.posed = poses ? 1 : 0;
   if ((st = enqueue_forward(ws, make_render_const(o, g->attr_dtype, ws), d, s)) != GP_OK) return st;
   ws->have_forward = true;
   ws->fwd_means = g->means;
@@ -500,13 +546,19 @@ gp_status gp_render_slices(gp_workspace* w, const gp_gaussians* g, const gp_slic
   ws->fwd_nslices = ns;
   ws->fwd_nbins = (int32_t)plan.nbins;
   ws->fwd_gauss = plan.total_gauss;
-  ws->fwd_slice_hash = hash_bytes(hs, sizeof(gp_slice) * (size_t)ns, hash_bytes(o, sizeof(*o)));
+  ws->fwd_posed = d.posed;
+  ws->fwd_slice_hash = slices_hash(hs, poses, ns, o);
   return GP_OK;
 }
 
-gp_status gp_render_backward(gp_workspace* w, const gp_gaussians* g, const gp_slice* hs, int32_t ns,
-                             const gp_render_opts* o, const float* grad_out, float* grad, int64_t grad_stride,
-                             void* stream) {
+gp_status gp_render_slices(gp_workspace* w, const gp_gaussians* g, const gp_slice* hs, int32_t ns,
+                           const gp_render_opts* o, float* out, void* stream) {
+  return gp_render_slices_posed(w, g, hs, nullptr, ns, o, out, stream);
+}
+
+gp_status gp_render_backward_posed(gp_workspace* w, const gp_gaussians* g, const gp_slice* hs, const float* poses,
+                                   int32_t ns, const gp_render_opts* o, const float* grad_out, float* grad,
+                                   int64_t grad_stride, void* stream) {
   if (!w) return einval("backward: NULL workspace");
   Workspace* ws = reinterpret_cast<Workspace*>(w);
   gp_status st = check_gaussians(g);
@@ -516,20 +568,27 @@ gp_status gp_render_backward(gp_workspace* w, const gp_gaussians* g, const gp_sl
   if (g->attr_dtype == GP_QM) return einval("backward: coded (GP_QM) Gaussians are render-only");
   if (ns < 0 || (ns > 0 && (!hs || !grad_out || !grad))) return einval("backward: bad arguments");
   if (!ws->have_forward || ws->fwd_means != g->means || ws->fwd_attrs != g->attrs || ws->fwd_n != g->n ||
-      ws->fwd_stride != g->stride || ws->fwd_nslices != ns ||
-      ws->fwd_slice_hash != hash_bytes(hs, sizeof(gp_slice) * (size_t)ns, hash_bytes(o, sizeof(*o)))) {
+      ws->fwd_stride != g->stride || ws->fwd_nslices != ns || ws->fwd_posed != (poses ? 1 : 0) ||
+      ws->fwd_slice_hash != slices_hash(hs, poses, ns, o)) {
     set_error("backward: the workspace does not hold the forward of these Gaussians and slices");
     return GP_ESTATE;
   }
   if (ns == 0 || g->n == 0) return GP_OK;
   GP_HIP(hipSetDevice(ws->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const LaunchDims d{ws->fwd_gauss, ws->fwd_nbins};
+  LaunchDims d{ws->fwd_gauss, ws->fwd_nbins};
+  d.posed = ws->fwd_posed;
   GP_HIP(timed(ws, GP_STAGE_RASTER_BWD, s, [&] { return launch_raster_bwd(ws->fwd_rc, *ws, grad_out, d, s); }));
   GP_HIP(timed(ws, GP_STAGE_PREPROCESS_BWD, s,
                [&] { return launch_preprocess_bwd(ws->fwd_rc, *ws, grad, grad_stride, d, s); }));
   ws->last_stream = s;
   return GP_OK;
+}
+
+gp_status gp_render_backward(gp_workspace* w, const gp_gaussians* g, const gp_slice* hs, int32_t ns,
+                             const gp_render_opts* o, const float* grad_out, float* grad, int64_t grad_stride,
+                             void* stream) {
+  return gp_render_backward_posed(w, g, hs, nullptr, ns, o, grad_out, grad, grad_stride, stream);
 }
 
 gp_status gp_l1_loss_grad(const float* img, const float* tgt, int64_t n, float scale, float* grad, float* loss,

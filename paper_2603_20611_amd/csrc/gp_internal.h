@@ -44,6 +44,9 @@ struct SliceDev {
   float* out;          // where the forward writes the slice's image
   int64_t pad;
 };
+// Camera poses of a posed batch live in their own array ([n_slices][12]: R_c
+// row-major, then t), so the slice descriptors stay small (they are read for
+// every (Gaussian, slice) pair and should stay in the L1 cache).
 
 // Sizes of one batch, read by the kernels from device memory so that a launch
 // sequence can be captured once and replayed for batches of any size up to the
@@ -99,6 +102,7 @@ struct LaunchDims {
   int64_t gauss;        // flattened Gaussians to cover (multiple of 64)
   int64_t bins;         // bins to cover (also fixes the sort's key width)
   int32_t emit_width = 1;   // lanes per Gaussian in the emit (1, 2, 4, 8 or 16)
+  int32_t posed = 0;        // the slices carry camera poses
 };
 // Emit width for groups of at most `slices` slices each.
 inline int32_t emit_width_for(int64_t slices) {
@@ -157,6 +161,7 @@ struct Workspace {
 
   // device buffers
   SliceDev* d_slices = nullptr;
+  float* d_poses = nullptr;         // [slice_cap][12]
   GroupDev* d_groups = nullptr;
   BatchHdr* d_hdr = nullptr;
   uint32_t* d_work = nullptr;       // kWorkCount work counters
@@ -195,6 +200,7 @@ struct Workspace {
 
   // pinned staging for uploads / readbacks
   SliceDev* h_slices = nullptr;
+  float* h_poses = nullptr;
   GroupDev* h_groups = nullptr;
   BatchHdr* h_hdr = nullptr;
   uint32_t* h_ctr = nullptr;
@@ -206,6 +212,7 @@ struct Workspace {
   const void* fwd_attrs = nullptr;
   int64_t fwd_n = 0, fwd_stride = 0;
   int32_t fwd_nslices = 0, fwd_nbins = 0;
+  int32_t fwd_posed = 0;
   int64_t fwd_gauss = 0;
   uint64_t fwd_slice_hash = 0;
   RenderConst fwd_rc{};
@@ -244,13 +251,14 @@ struct BatchPlan {
   int32_t ns, ng;
   int64_t nbins, total_gauss, npix;
   int32_t attr_dtype;
+  int32_t posed;
 };
 hipError_t wait_ws(Workspace* ws);
 gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups, int64_t n_bins, int64_t n_gauss);
 gp_status reserve_lists(Workspace* ws, int64_t rec_cap, int64_t inst_cap);
 gp_status reserve_sort(Workspace* ws, int bits);
 gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_slice* hs, int ns, float* out_base,
-                      float* const* outs, BatchPlan* plan);
+                      float* const* outs, BatchPlan* plan, const float* poses = nullptr);
 gp_status upload_batch(Workspace* ws, const BatchPlan& p, hipStream_t s);
 RenderConst make_render_const(const gp_render_opts* o, int attr_dtype, const Workspace* ws);
 gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hipStream_t s);

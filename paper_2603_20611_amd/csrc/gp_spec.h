@@ -66,6 +66,8 @@ __device__ __forceinline__ float quad3(const float (&R)[3][3], int a, int b, flo
   return ((R[a][0] * R[b][0]) * w0 + (R[a][1] * R[b][1]) * w1) + (R[a][2] * R[b][2]) * w2;
 }
 
+__device__ __forceinline__ void spec_forms(SpecCov& c);
+
 __device__ __forceinline__ void spec_cov(float l0, float l1, float l2, float qw, float qx, float qy,
                                          float qz, float mod, SpecCov& c) {
 #pragma clang fp contract(off)
@@ -88,6 +90,13 @@ __device__ __forceinline__ void spec_cov(float l0, float l1, float l2, float qw,
   c.R[2][0] = 2.0f * (xz - wy);
   c.R[2][1] = 2.0f * (yz + wx);
   c.R[2][2] = 1.0f - 2.0f * (xx + yy);
+  spec_forms(c);
+}
+
+// Covariance R diag(v) R^T and adjugate entries R diag(v1 v2, v0 v2, v0 v1) R^T
+// of c.R and c's scales (v_i = s_i^2).
+__device__ __forceinline__ void spec_forms(SpecCov& c) {
+#pragma clang fp contract(off)
   const float v0 = c.s0 * c.s0, v1 = c.s1 * c.s1, v2 = c.s2 * c.s2;
   const float P0 = v1 * v2, P1 = v0 * v2, P2 = v0 * v1;
   c.sxx = quad3(c.R, 0, 0, v0, v1, v2);
@@ -101,6 +110,26 @@ __device__ __forceinline__ void spec_cov(float l0, float l1, float l2, float qw,
   c.a11 = quad3(c.R, 1, 1, P0, P1, P2);
   c.a22 = quad3(c.R, 2, 2, P0, P1, P2);
   c.detS = (v0 * v1) * v2;
+}
+
+// The Gaussian seen from a posed slice's camera frame (supplement, forward
+// derivation: mu_c = R_c mu + t, Sigma_c = R_c Sigma R_c^T), pose = R_c
+// row-major then t: the rotation becomes R_c R (entry by entry, left to
+// right), covariance and adjugate follow from it as in spec_cov, and the mean
+// is ((R_c[i][0] mu_x + R_c[i][1] mu_y) + R_c[i][2] mu_z) + t[i].  The identity
+// pose reproduces c and mu bit for bit.
+__device__ __forceinline__ void spec_pose(const SpecCov& c, const float* mu, const float* pose, SpecCov& o,
+                                          float* mo) {
+#pragma clang fp contract(off)
+  o = c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      o.R[i][j] = (pose[3 * i] * c.R[0][j] + pose[3 * i + 1] * c.R[1][j]) + pose[3 * i + 2] * c.R[2][j];
+    mo[i] = ((pose[3 * i] * mu[0] + pose[3 * i + 1] * mu[1]) + pose[3 * i + 2] * mu[2]) + pose[9 + i];
+  }
+  spec_forms(o);
 }
 
 // Axial quantities of one (Gaussian, slice) pair.

@@ -42,9 +42,10 @@ struct BwdPreArgs {
   int32_t* st_count;
   float* st_max_radius;
   int64_t st_n;
+  const float* poses;       // [n_slices][12] of a posed batch
 };
 
-template <int DT>
+template <int DT, bool POSED>
 __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, int t) {
   const uint32_t nrec = a.g_nrec[t];
   if (nrec == 0) return;
@@ -82,20 +83,26 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
       const float4 m1 = a.moments[2 * (size_t)(meta.ibase + s) + 1];
       M0 += m0.x; Mx += m0.y; My += m0.z; Mxx += m0.w; Mxy += m1.x; Myy += m1.y;
     }
-    // forward quantities of this (Gaussian, slice) pair
-    const SpecAxial ax = spec_axial(p[2], c.szz, sl.z, sl.sigma_z);
+    // forward quantities of this (Gaussian, slice) pair, in the slice's camera
+    // frame (the world frame for axial batches)
+    SpecCov cpose;
+    float mpose[3];
+    if (POSED) spec_pose(c, p, a.poses + 12 * meta.slice, cpose, mpose);
+    const SpecCov& cv = POSED ? cpose : c;
+    const float* mv = POSED ? mpose : p;
+    const SpecAxial ax = spec_axial(mv[2], cv.szz, sl.z, sl.sigma_z);
     const float invD = 1.0f / ax.D;
-    const float w = 1.0f / (1.0f + c.szz / ax.s2);
-    const float A = w * c.sxx + c.a11 * invD;
-    const float C = w * c.syy + c.a00 * invD;
-    const float B = w * c.sxy - c.a01 * invD;
-    const float u = c.sxz * invD, v = c.syz * invD;
-    const float det = w * c.a22 + c.detS * invD;
+    const float w = 1.0f / (1.0f + cv.szz / ax.s2);
+    const float A = w * cv.sxx + cv.a11 * invD;
+    const float C = w * cv.syy + cv.a00 * invD;
+    const float B = w * cv.sxy - cv.a01 * invD;
+    const float u = cv.sxz * invD, v = cv.syz * invD;
+    const float det = w * cv.a22 + cv.detS * invD;
     if (!(det > 0.0f) || !isfinite(det)) continue;
     const float rho = expf(-0.5f * ax.q);
     // exact convolution integral: alpha~ carries f = sqrt(2 pi det Sigma w)
     const bool conv = (a.rc.flags & GP_FLAG_CONV_EXACT) != 0;
-    const float f = conv ? sqrtf(6.28318530717958648f * c.detS * w) : 1.0f;
+    const float f = conv ? sqrtf(6.28318530717958648f * cv.detS * w) : 1.0f;
     const float sq = sqrtf(det) / f;
     const float at = alpha * rho / sq;
     const float inv_det = 1.0f / det;
@@ -122,27 +129,59 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
     galpha += g_at * rho / sq;
     const float g_rho = g_at * alpha / sq;
     const float g_q = -0.5f * rho * g_rho;
+    // Focus Gaussian -> camera-frame Sigma_c, mu_c
+    const float g_u = -m * g_m2x, g_v = -m * g_m2y;
+    float lzz = u * u * gA + u * v * gB + v * v * gC - (u * g_u + v * g_v) * invD - g_q * m * m * invD * invD;
     // d ln f = (1/2) (d ln det Sigma + d ln w), d ln det Sigma / d l_i = 2,
     // d ln w / d Sigma_zz = -1 / D
     if (conv) {
       gls += g_at * at;
-      gzz += -0.5f * g_at * at * invD;
+      lzz += -0.5f * g_at * at * invD;
     }
-    // Focus Gaussian -> Sigma, mu
-    const float g_u = -m * g_m2x, g_v = -m * g_m2y;
-    gxx += gA;
-    gxy += gB;
-    gyy += gC;
-    gxz += -2.f * u * gA - v * gB + g_u * invD;
-    gyz += -2.f * v * gC - u * gB + g_v * invD;
-    gzz += u * u * gA + u * v * gB + v * v * gC - (u * g_u + v * g_v) * invD - g_q * m * m * invD * invD;
-    gmx += g_m2x;
-    gmy += g_m2y;
+    const float lxx = gA, lxy = gB, lyy = gC;
+    const float lxz = -2.f * u * gA - v * gB + g_u * invD;
+    const float lyz = -2.f * v * gC - u * gB + g_v * invD;
+    const float lmx = g_m2x, lmy = g_m2y;
+    const float lmz = -(u * g_m2x + v * g_m2y) + 2.f * g_q * m * invD;
+    if (POSED) {
+      // back to the world frame: dL/dSigma = R_c^T G R_c (symmetric G with the
+      // off-diagonal gradients halved), dL/dmu = R_c^T dL/dmu_c
+      const float* Rc = a.poses + 12 * meta.slice;
+      const float G[3][3] = {{lxx, 0.5f * lxy, 0.5f * lxz}, {0.5f * lxy, lyy, 0.5f * lyz}, {0.5f * lxz, 0.5f * lyz, lzz}};
+      float T[3][3];   // G R_c
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) T[i][jj] = G[i][0] * Rc[jj] + G[i][1] * Rc[3 + jj] + G[i][2] * Rc[6 + jj];
+      float W[3][3];   // R_c^T T
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int jj = i; jj < 3; ++jj) W[i][jj] = Rc[i] * T[0][jj] + Rc[3 + i] * T[1][jj] + Rc[6 + i] * T[2][jj];
+      gxx += W[0][0];
+      gyy += W[1][1];
+      gzz += W[2][2];
+      gxy += 2.f * W[0][1];
+      gxz += 2.f * W[0][2];
+      gyz += 2.f * W[1][2];
+      gmx += Rc[0] * lmx + Rc[3] * lmy + Rc[6] * lmz;
+      gmy += Rc[1] * lmx + Rc[4] * lmy + Rc[7] * lmz;
+      gmz += Rc[2] * lmx + Rc[5] * lmy + Rc[8] * lmz;
+    } else {
+      gxx += lxx;
+      gxy += lxy;
+      gyy += lyy;
+      gxz += lxz;
+      gyz += lyz;
+      gzz += lzz;
+      gmx += lmx;
+      gmy += lmy;
+      gmz += lmz;
+    }
     // densification statistics in pixel units
     st_norm += sqrtf((g_m2x * ddx) * (g_m2x * ddx) + (g_m2y * ddy) * (g_m2y * ddy));
     st_rad = fmaxf(st_rad, a.rc.bbox * fmaxf(sqrtf(A) / ddx, sqrtf(C) / ddy));
     st_cnt += 1;
-    gmz += -(u * g_m2x + v * g_m2y) + 2.f * g_q * m * invD;
   }
 
   // Sigma = M M^T with M = R diag(s): dL/dM = 2 Gs M, Gs symmetric
@@ -195,11 +234,23 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
   }
 }
 
-template <int DT>
+template <int DT, bool POSED>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < total; t += gridDim.x * 256) backward_one<DT>(a, n_groups, t);
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < total; t += gridDim.x * 256)
+    backward_one<DT, POSED>(a, n_groups, t);
+}
+
+template <bool POSED>
+hipError_t launch_bwd_p(const BwdPreArgs& a, int attr_dtype, unsigned blocks, hipStream_t s) {
+  switch (attr_dtype) {
+    case GP_BF16: k_preprocess_bwd<GP_BF16, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case GP_F16: k_preprocess_bwd<GP_F16, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case GP_Q16: k_preprocess_bwd<GP_Q16, POSED><<<blocks, 256, 0, s>>>(a); break;
+    default: k_preprocess_bwd<GP_F32, POSED><<<blocks, 256, 0, s>>>(a); break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -221,16 +272,12 @@ hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, flo
                ws.st_grad_norm,
                ws.st_count,
                ws.st_max_radius,
-               ws.st_n};
+               ws.st_n,
+               ws.d_poses};
   int64_t blocks = (d.gauss + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  switch (rc.attr_dtype) {
-    case GP_BF16: k_preprocess_bwd<GP_BF16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    case GP_F16: k_preprocess_bwd<GP_F16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    case GP_Q16: k_preprocess_bwd<GP_Q16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    default: k_preprocess_bwd<GP_F32><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-  }
-  return hipGetLastError();
+  return d.posed ? launch_bwd_p<true>(a, rc.attr_dtype, (unsigned)blocks, s)
+                 : launch_bwd_p<false>(a, rc.attr_dtype, (unsigned)blocks, s);
 }
 
 }  // namespace gp

@@ -69,6 +69,7 @@ struct PreArgs {
   uint32_t* inst_key;   // bin of every instance slot
   uint32_t* inst_val;   // record of every instance slot
   uint32_t sentinel_bin;
+  const float* poses;   // [n_slices][12] of a posed batch
 };
 
 __device__ __forceinline__ bool kept_on(const PreArgs& a, float muz, float szz, int k) {
@@ -165,13 +166,15 @@ __device__ __forceinline__ void activate(const PreArgs& a, Loaded& L) {
   L.ok = L.ok && (L.c.n2 > 0.0f);
 }
 
-// Footprint of (Gaussian, slice k); false if the pair is culled or off-grid.
-__device__ __forceinline__ bool footprint(const PreArgs& a, const Loaded& L, int k, SpecAxial& ax, SpecRect& rect) {
+// Footprint of (Gaussian, slice k) from its camera-frame view (cv, mv); false
+// if the pair is culled or off-grid.
+__device__ __forceinline__ bool footprint(const PreArgs& a, const SpecCov& cv, const float* mv, int k,
+                                          SpecAxial& ax, SpecRect& rect) {
   const SliceDev& sl = a.slices[k];
   const bool exact = (a.rc.flags & GP_FLAG_EXACT) != 0;
-  ax = spec_axial(L.p[2], L.c.szz, sl.z, sl.sigma_z);
+  ax = spec_axial(mv[2], cv.szz, sl.z, sl.sigma_z);
   if (!exact && !(ax.q <= a.rc.q_cut)) return false;
-  const bool vis = spec_rect(L.c, L.p[0], L.p[1], ax, sl.x0, sl.y0, sl.dx, sl.dy, sl.ntx, sl.nty, a.rc.bbox, rect);
+  const bool vis = spec_rect(cv, mv[0], mv[1], ax, sl.x0, sl.y0, sl.dx, sl.dy, sl.ntx, sl.nty, a.rc.bbox, rect);
   if (exact) {
     rect.tx0 = 0; rect.tx1 = sl.ntx - 1; rect.ty0 = 0; rect.ty1 = sl.nty - 1;
     return true;
@@ -194,23 +197,30 @@ __device__ __forceinline__ bool far_from_group(const PreArgs& a, const GroupDev&
   return d * d > a.rc.q_cut * (G.sz2max + smax * smax) * 1.001f;
 }
 
-template <int DT>
+template <int DT, bool POSED>
 __device__ __forceinline__ void count_one(const PreArgs& a, int n_groups, int t) {
   Loaded L;
   load_params<DT>(a, n_groups, t, L);
-  if (L.ok && far_from_group(a, L.G, L.p)) L.ok = false;   // culled on every slice
+  // the world-depth shortcuts hold for axial slices only
+  if (!POSED && L.ok && far_from_group(a, L.G, L.p)) L.ok = false;   // culled on every slice
   else activate(a, L);
   int kb = L.G.k0, ke = L.G.k1;
   if (!L.ok) {
     ke = kb;
-  } else if (!(a.rc.flags & GP_FLAG_EXACT) && (L.G.flags & kGroupSortedZ)) {
+  } else if (!POSED && !(a.rc.flags & GP_FLAG_EXACT) && (L.G.flags & kGroupSortedZ)) {
     kept_range(a, L.G, L.p[2], L.c.szz, &kb, &ke);
   }
   uint32_t nrec = 0, ninst = 0;
   for (int k = kb; k < ke; ++k) {
     SpecAxial ax;
     SpecRect rect;
-    if (!footprint(a, L, k, ax, rect)) continue;
+    // the Gaussian in the slice's camera frame (the world frame for axial batches)
+    SpecCov cv;
+    float mv[3];
+    if (POSED) spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
+    const SpecCov& cr = POSED ? cv : L.c;
+    const float* mr = POSED ? mv : L.p;
+    if (!footprint(a, cr, mr, k, ax, rect)) continue;
     nrec += 1u;
     ninst += (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
   }
@@ -229,14 +239,16 @@ __device__ __forceinline__ void count_one(const PreArgs& a, int n_groups, int t)
 
 // Image quantities of a kept (Gaussian, slice) pair (binary32; not part of the
 // membership specification).
-__device__ __forceinline__ void make_record(const Loaded& L, const SliceDev& sl, const SpecAxial& ax,
-                                            const SpecRect& rect, int k, uint32_t ibase, uint32_t flags,
-                                            RecPay& pay, RecMeta& meta) {
-  const SpecCov& c = L.c;
+__device__ __forceinline__ void make_record(const SpecCov& c, float alpha, const SliceDev& sl,
+                                            const SpecAxial& ax, const SpecRect& rect, int k, uint32_t ibase,
+                                            uint32_t flags, RecPay& pay, RecMeta& meta) {
+  // a fixed operation order (no contraction), so that equal inputs give equal
+  // records in every instantiation of the emit
+#pragma clang fp contract(off)
   const float B = rect.w * c.sxy - c.a01 * rect.invD;
   const float det = rect.w * c.a22 + c.detS * rect.invD;
   const float rho = expf(-0.5f * ax.q);
-  float at = L.p[10] * rho / sqrtf(det);
+  float at = alpha * rho / sqrtf(det);
   // exact convolution integral: times sqrt(2 pi det Sigma_e), det Sigma_e = det Sigma w
   if (flags & GP_FLAG_CONV_EXACT) at *= sqrtf(kTwoPi * c.detS * rect.w);
   const float inv_det = 1.0f / det;
@@ -270,7 +282,7 @@ __device__ __forceinline__ void make_record(const Loaded& L, const SliceDev& sl,
 // per Gaussian and many slices per Gaussian, every lane would stream to its own
 // region and L2 would evict partly written lines.)  W = 1 is the one-lane
 // form, used when each Gaussian has at most one slice.
-template <int DT, int W>
+template <int DT, int W, bool POSED>
 __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0) {
   const int lane = threadIdx.x & 63;
   const int t = t0 + lane;
@@ -315,7 +327,12 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0
       const int k = c0 + li;
       SpecAxial ax;
       SpecRect rect;
-      const bool kept = k < ke && footprint(a, L, k, ax, rect);
+      SpecCov cv;
+      float mv[3];
+      if (POSED && k < ke) spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
+      const SpecCov& cr = POSED ? cv : L.c;
+      const float* mr = POSED ? mv : L.p;
+      const bool kept = k < ke && footprint(a, cr, mr, k, ax, rect);
       const uint32_t nt = kept ? (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1)) : 0u;
       uint32_t rpos = 0u, ipos = 0u, rtot = 1u, itot = nt;
       if (W > 1) {
@@ -338,7 +355,7 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0
         uint32_t slot = inst_run + ipos;
         RecPay pay;
         RecMeta meta;
-        make_record(L, sl, ax, rect, k, slot, a.rc.flags, pay, meta);
+        make_record(cr, L.p[10], sl, ax, rect, k, slot, a.rc.flags, pay, meta);
         a.rec_pay[rid] = pay;
         a.rec_meta[rid] = meta;
         for (int ty = rect.ty0; ty <= rect.ty1; ++ty) {
@@ -361,32 +378,57 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0
 
 // Grid-stride over whole wavefronts of flattened Gaussians, so that a launch
 // sized for the workspace capacity serves any batch (sizes from the header).
-template <int DT>
+template <int DT, bool POSED>
 __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   const int stride = gridDim.x * 256;
-  for (int t = blockIdx.x * 256 + threadIdx.x; (t & ~63) < total; t += stride) count_one<DT>(a, n_groups, t);
+  for (int t = blockIdx.x * 256 + threadIdx.x; (t & ~63) < total; t += stride)
+    count_one<DT, POSED>(a, n_groups, t);
 }
 
-template <int DT, int W>
+template <int DT, int W, bool POSED>
 __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   const int stride = gridDim.x * 256;
-  for (int t0 = blockIdx.x * 256 + (threadIdx.x & ~63); t0 < total; t0 += stride) emit_wave<DT, W>(a, n_groups, t0);
+  for (int t0 = blockIdx.x * 256 + (threadIdx.x & ~63); t0 < total; t0 += stride)
+    emit_wave<DT, W, POSED>(a, n_groups, t0);
 }
 
-template <int DT>
+template <int DT, bool POSED>
 hipError_t launch_emit_dt(const PreArgs& a, int width, unsigned blocks, hipStream_t s) {
   switch (width) {
-    case 16: k_pre_emit<DT, 16><<<blocks, 256, 0, s>>>(a); break;
-    case 8: k_pre_emit<DT, 8><<<blocks, 256, 0, s>>>(a); break;
-    case 4: k_pre_emit<DT, 4><<<blocks, 256, 0, s>>>(a); break;
-    case 2: k_pre_emit<DT, 2><<<blocks, 256, 0, s>>>(a); break;
-    default: k_pre_emit<DT, 1><<<blocks, 256, 0, s>>>(a); break;
+    case 16: k_pre_emit<DT, 16, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case 8: k_pre_emit<DT, 8, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case 4: k_pre_emit<DT, 4, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case 2: k_pre_emit<DT, 2, POSED><<<blocks, 256, 0, s>>>(a); break;
+    default: k_pre_emit<DT, 1, POSED><<<blocks, 256, 0, s>>>(a); break;
   }
   return hipGetLastError();
+}
+
+template <bool POSED>
+hipError_t launch_count_p(const PreArgs& a, int attr_dtype, unsigned blocks, hipStream_t s) {
+  switch (attr_dtype) {
+    case GP_BF16: k_pre_count<GP_BF16, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case GP_F16: k_pre_count<GP_F16, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case GP_Q16: k_pre_count<GP_Q16, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case GP_QM: k_pre_count<GP_QM, POSED><<<blocks, 256, 0, s>>>(a); break;
+    default: k_pre_count<GP_F32, POSED><<<blocks, 256, 0, s>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+template <bool POSED>
+hipError_t launch_emit_p(const PreArgs& a, int attr_dtype, int width, unsigned blocks, hipStream_t s) {
+  switch (attr_dtype) {
+    case GP_BF16: return launch_emit_dt<GP_BF16, POSED>(a, width, blocks, s);
+    case GP_F16: return launch_emit_dt<GP_F16, POSED>(a, width, blocks, s);
+    case GP_Q16: return launch_emit_dt<GP_Q16, POSED>(a, width, blocks, s);
+    case GP_QM: return launch_emit_dt<GP_QM, POSED>(a, width, blocks, s);
+    default: return launch_emit_dt<GP_F32, POSED>(a, width, blocks, s);
+  }
 }
 
 }  // namespace
@@ -409,7 +451,7 @@ hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDi
 static PreArgs pre_args(const RenderConst& rc, const Workspace& ws, uint32_t sentinel_bin) {
   return PreArgs{rc, ws.d_hdr, ws.d_groups, ws.d_slices, ws.d_ctr, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase,
                  ws.d_g_nrec, ws.d_g_ninst, ws.d_g_krange, ws.d_wave_cnt, ws.d_inst_key, ws.d_inst_val,
-                 sentinel_bin};
+                 sentinel_bin, ws.d_poses};
 }
 
 hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s) {
@@ -417,14 +459,8 @@ hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const La
   const PreArgs a = pre_args(rc, ws, 0u);
   int64_t blocks = (d.gauss + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  switch (rc.attr_dtype) {
-    case GP_BF16: k_pre_count<GP_BF16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    case GP_F16: k_pre_count<GP_F16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    case GP_Q16: k_pre_count<GP_Q16><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    case GP_QM: k_pre_count<GP_QM><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-    default: k_pre_count<GP_F32><<<(unsigned)blocks, 256, 0, s>>>(a); break;
-  }
-  return hipGetLastError();
+  return d.posed ? launch_count_p<true>(a, rc.attr_dtype, (unsigned)blocks, s)
+                 : launch_count_p<false>(a, rc.attr_dtype, (unsigned)blocks, s);
 }
 
 hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, uint32_t sentinel_bin,
@@ -433,13 +469,8 @@ hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const Lau
   const PreArgs a = pre_args(rc, ws, sentinel_bin);
   int64_t blocks = (d.gauss + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  switch (rc.attr_dtype) {
-    case GP_BF16: return launch_emit_dt<GP_BF16>(a, d.emit_width, (unsigned)blocks, s);
-    case GP_F16: return launch_emit_dt<GP_F16>(a, d.emit_width, (unsigned)blocks, s);
-    case GP_Q16: return launch_emit_dt<GP_Q16>(a, d.emit_width, (unsigned)blocks, s);
-    case GP_QM: return launch_emit_dt<GP_QM>(a, d.emit_width, (unsigned)blocks, s);
-    default: return launch_emit_dt<GP_F32>(a, d.emit_width, (unsigned)blocks, s);
-  }
+  return d.posed ? launch_emit_p<true>(a, rc.attr_dtype, d.emit_width, (unsigned)blocks, s)
+                 : launch_emit_p<false>(a, rc.attr_dtype, d.emit_width, (unsigned)blocks, s);
 }
 
 }  // namespace gp

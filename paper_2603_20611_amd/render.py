@@ -114,7 +114,12 @@ def render(params, slices, opts=None, ws=None, out=None, n=None, attrs=None, att
     if out is None:
         out = torch.empty(slice_pixels(slices), device=params.device, dtype=torch.float32)
     g = gaussians_struct(params, n, attrs, attr_dtype)
-    B.check(lib.gp_render_slices(ws.handle, C.byref(g), sl, len(slices), C.byref(opts), _ptr(out), _stream()))
+    poses = B.make_poses(slices)
+    if poses is None:
+        B.check(lib.gp_render_slices(ws.handle, C.byref(g), sl, len(slices), C.byref(opts), _ptr(out), _stream()))
+    else:
+        B.check(lib.gp_render_slices_posed(ws.handle, C.byref(g), sl, poses, len(slices), C.byref(opts), _ptr(out),
+                                           _stream()))
     return out
 
 
@@ -125,8 +130,13 @@ def render_backward(params, slices, grad_out, ws, opts=None, grad=None, n=None):
     if grad is None:
         grad = torch.zeros_like(params)
     g = gaussians_struct(params, n)
-    B.check(lib.gp_render_backward(ws.handle, C.byref(g), sl, len(slices), C.byref(opts),
-                                   _ptr(grad_out.contiguous()), _ptr(grad), grad.shape[1], _stream()))
+    poses = B.make_poses(slices)
+    if poses is None:
+        B.check(lib.gp_render_backward(ws.handle, C.byref(g), sl, len(slices), C.byref(opts),
+                                       _ptr(grad_out.contiguous()), _ptr(grad), grad.shape[1], _stream()))
+    else:
+        B.check(lib.gp_render_backward_posed(ws.handle, C.byref(g), sl, poses, len(slices), C.byref(opts),
+                                             _ptr(grad_out.contiguous()), _ptr(grad), grad.shape[1], _stream()))
     return grad
 
 
