@@ -25,8 +25,6 @@
 namespace gp {
 namespace {
 
-constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kTwoPi = 6.28318530717958648f;
 
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
@@ -237,29 +235,81 @@ __device__ __forceinline__ void count_one(const PreArgs& a, int n_groups, int t)
   if ((t & 63) == 0) a.wave_cnt[t >> 6] = make_uint2(sr, si);
 }
 
-// Image quantities of a kept (Gaussian, slice) pair (binary32; not part of the
-// membership specification).
-__device__ __forceinline__ void make_record(const SpecCov& c, float alpha, const SliceDev& sl,
-                                            const SpecAxial& ax, const SpecRect& rect, int k, uint32_t ibase,
-                                            uint32_t flags, RecPay& pay, RecMeta& meta) {
+// Float64 covariance of a Gaussian from its binary32 parameters (rotation of
+// the quaternion normalised in float64; the scales are the specification's
+// binary32 exp, whose error moves an eigenvalue, not the conditioning), as
+// Sigma = v1 I + (v0 - v1) r0 r0^T + (v2 - v1) r2 r2^T with r0, r2 the first
+// and last columns of R.  out: xx, xy, xz, yy, yz, zz.
+__device__ __forceinline__ void cov_f64(const float* p, float mod, double* out) {
+#pragma clang fp contract(off)
+  const double qw = p[6], qx = p[7], qy = p[8], qz = p[9];
+  const double rn = 1.0 / sqrt(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+  const double w = qw * rn, x = qx * rn, y = qy * rn, z = qz * rn;
+  const float s0 = exp_spec(p[3]) * mod, s1 = exp_spec(p[4]) * mod, s2 = exp_spec(p[5]) * mod;
+  const double v0 = (double)s0 * (double)s0, v1 = (double)s1 * (double)s1, v2 = (double)s2 * (double)s2;
+  const double r0[3] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y)};
+  const double r2[3] = {2.0 * (x * z + w * y), 2.0 * (y * z - w * x), 1.0 - 2.0 * (x * x + y * y)};
+  const double d0 = v0 - v1, d2 = v2 - v1;
+  out[0] = (v1 + d0 * r0[0] * r0[0]) + d2 * r2[0] * r2[0];
+  out[1] = d0 * r0[0] * r0[1] + d2 * r2[0] * r2[1];
+  out[2] = d0 * r0[0] * r0[2] + d2 * r2[0] * r2[2];
+  out[3] = (v1 + d0 * r0[1] * r0[1]) + d2 * r2[1] * r2[1];
+  out[4] = d0 * r0[1] * r0[2] + d2 * r2[1] * r2[2];
+  out[5] = (v1 + d0 * r0[2] * r0[2]) + d2 * r2[2] * r2[2];
+}
+
+// Image quantities of a kept (Gaussian, slice) pair, not part of the membership
+// specification: computed in float64 from the Gaussian's float64 covariance
+// (cov, world frame) and binary32 mean and intensity, rounded once.  A thin,
+// elongated Gaussian makes Sigma_2d ill-conditioned, and its conic taken from
+// binary32 covariance entries would be off by ~1e-5 of the record's peak; the
+// pixel-space mean at large pixel coordinates likewise.  pose: the slice's
+// camera pose (Sigma_c = R_c Sigma R_c^T, mu_c = R_c mu + t) or nullptr.
+__device__ __forceinline__ void make_record(const double* cov, const float* p, const SpecCov& c, const float* pose,
+                                            const SliceDev& sl, int k, uint32_t ibase, uint32_t flags,
+                                            const SpecRect& rect, RecPay& pay, RecMeta& meta) {
   // a fixed operation order (no contraction), so that equal inputs give equal
   // records in every instantiation of the emit
 #pragma clang fp contract(off)
-  const float B = rect.w * c.sxy - c.a01 * rect.invD;
-  const float det = rect.w * c.a22 + c.detS * rect.invD;
-  const float rho = expf(-0.5f * ax.q);
-  float at = alpha * rho / sqrtf(det);
+  double mu[3] = {p[0], p[1], p[2]};
+  double sxx = cov[0], sxy = cov[1], sxz = cov[2], syy = cov[3], syz = cov[4], szz = cov[5];
+  if (pose) {
+    const double S[3][3] = {{sxx, sxy, sxz}, {sxy, syy, syz}, {sxz, syz, szz}};
+    double T[3][3], mc[3];   // T = R_c Sigma
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        T[i][j] = ((double)pose[3 * i] * S[0][j] + (double)pose[3 * i + 1] * S[1][j]) + (double)pose[3 * i + 2] * S[2][j];
+      mc[i] = (((double)pose[3 * i] * mu[0] + (double)pose[3 * i + 1] * mu[1]) + (double)pose[3 * i + 2] * mu[2]) +
+              (double)pose[9 + i];
+    }
+    auto E = [&](int i, int j) {
+      return (T[i][0] * (double)pose[3 * j] + T[i][1] * (double)pose[3 * j + 1]) + T[i][2] * (double)pose[3 * j + 2];
+    };
+    sxx = E(0, 0); sxy = E(0, 1); sxz = E(0, 2); syy = E(1, 1); syz = E(1, 2); szz = E(2, 2);
+    mu[0] = mc[0]; mu[1] = mc[1]; mu[2] = mc[2];
+  }
+  const double v0 = (double)c.s0 * (double)c.s0, v1 = (double)c.s1 * (double)c.s1, v2 = (double)c.s2 * (double)c.s2;
+  const double s2 = (double)sl.sigma_z * (double)sl.sigma_z;
+  const double invD = 1.0 / (s2 + szz);          // 0 for sigma_z = inf
+  const double u = sxz * invD, v = syz * invD;
+  const double A = sxx - u * sxz, B = sxy - u * syz, C = syy - v * syz;
+  const double det = A * C - B * B;
+  const double m = mu[2] - (double)sl.z;
+  const float rho = expf(-0.5f * (float)(m * m * invD));
+  float at = p[10] * rho / sqrtf((float)det);
   // exact convolution integral: times sqrt(2 pi det Sigma_e), det Sigma_e = det Sigma w
-  if (flags & GP_FLAG_CONV_EXACT) at *= sqrtf(kTwoPi * c.detS * rect.w);
-  const float inv_det = 1.0f / det;
-  const float ca = rect.C * inv_det, cb = -B * inv_det, cc = rect.A * inv_det;
-  pay.x = (rect.mx - sl.x0) / sl.dx - 0.5f;
-  pay.y = (rect.my - sl.y0) / sl.dy - 0.5f;
-  pay.a = -0.5f * kLog2e * ca * sl.dx * sl.dx;
-  pay.b = -kLog2e * cb * sl.dx * sl.dy;
-  pay.c = -0.5f * kLog2e * cc * sl.dy * sl.dy;
+  if (flags & GP_FLAG_CONV_EXACT) at *= sqrtf((float)(6.283185307179586 * ((v0 * v1) * v2) / (1.0 + szz / s2)));
+  const double inv_det = 1.0 / det;
+  const double L2 = 1.4426950408889634;
+  pay.x = (float)((((mu[0] - u * m) - (double)sl.x0) / (double)sl.dx) - 0.5);
+  pay.y = (float)((((mu[1] - v * m) - (double)sl.y0) / (double)sl.dy) - 0.5);
+  pay.a = (float)(-0.5 * L2 * C * inv_det * (double)sl.dx * (double)sl.dx);
+  pay.b = (float)(L2 * B * inv_det * (double)sl.dx * (double)sl.dy);
+  pay.c = (float)(-0.5 * L2 * A * inv_det * (double)sl.dy * (double)sl.dy);
   pay.w = at;
-  const bool good = det > 0.0f && isfinite(at) && isfinite(pay.x) && isfinite(pay.y) && isfinite(pay.a) &&
+  const bool good = det > 0.0 && isfinite(at) && isfinite(pay.x) && isfinite(pay.y) && isfinite(pay.a) &&
                     isfinite(pay.b) && isfinite(pay.c);
   if (!good) pay.x = pay.y = pay.a = pay.b = pay.c = pay.w = 0.0f;
   const bool smooth = pay.a >= kSmoothA && fabsf(pay.b) <= kSmoothB;
@@ -283,10 +333,20 @@ __device__ __forceinline__ void make_record(const SpecCov& c, float alpha, const
 // region and L2 would evict partly written lines.)  W = 1 is the one-lane
 // form, used when each Gaussian has at most one slice.
 template <int DT, int W, bool POSED>
-__device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0) {
+__device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0, double (*cov64)[64][6]) {
   const int lane = threadIdx.x & 63;
+  const int wave = (threadIdx.x >> 6) & 3;
   const int t = t0 + lane;
   uint32_t nrec = a.g_nrec[t];
+  // each lane: the float64 covariance of its own Gaussian, once for all its records
+  if (nrec > 0u) {
+    Loaded Lq;
+    load_params<DT>(a, n_groups, t, Lq);
+    cov_f64(Lq.p, a.rc.scale_mod, cov64[wave][lane]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const uint32_t ninst = a.g_ninst[t];
   uint32_t pr = nrec, pi = ninst;
 #pragma unroll
@@ -355,7 +415,8 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0
         uint32_t slot = inst_run + ipos;
         RecPay pay;
         RecMeta meta;
-        make_record(cr, L.p[10], sl, ax, rect, k, slot, a.rc.flags, pay, meta);
+        make_record(cov64[wave][gi], L.p, L.c, POSED ? a.poses + 12 * k : nullptr, sl, k, slot, a.rc.flags, rect,
+                    pay, meta);
         a.rec_pay[rid] = pay;
         a.rec_meta[rid] = meta;
         for (int ty = rect.ty0; ty <= rect.ty1; ++ty) {
@@ -392,8 +453,14 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   const int stride = gridDim.x * 256;
-  for (int t0 = blockIdx.x * 256 + (threadIdx.x & ~63); t0 < total; t0 += stride)
-    emit_wave<DT, W, POSED>(a, n_groups, t0);
+  __shared__ double cov64[4][64][6];
+  for (int t0 = blockIdx.x * 256 + (threadIdx.x & ~63); t0 < total; t0 += stride) {
+    emit_wave<DT, W, POSED>(a, n_groups, t0, cov64);
+    // the wavefront's slots are rewritten by its next round
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 template <int DT, bool POSED>

@@ -79,6 +79,79 @@ __device__ __forceinline__ float mul0(float x, float y) {
 
 
 
+// One step of a half-wavefront: record (r0, r1) over the lane's 2 x 4 pixels
+// whose first pixel is (fx0, fy0), added to acc (rows 0, 1 in acc[0..3], acc[4..7]).
+__device__ __forceinline__ void raster_step(const float4 r0, const float4 r1, float fx0, float fy0,
+                                            float (&acc)[8]) {
+  const float d0 = fx0 - r0.x;
+  const float dy0 = fy0 - r0.y;
+  const float by0 = r0.w * dy0;
+  const float cy0 = r1.x * dy0 * dy0;
+  const float p00 = fmaf(fmaf(r0.z, d0, by0), d0, cy0);
+  float e00, e01, e02, e03, e10, e11, e12, e13;
+  // both records of the step must allow the row recurrence (uniform branch);
+  // the record's g is negative where it does not
+  if (__builtin_amdgcn_read_exec() == __builtin_amdgcn_ballot_w64(r1.z > 0.0f)) {
+    // second row's exponent: p(d0, dy0 + 1) = p00 + b d0 + c (2 dy0 + 1)
+    const float p10 = fmaf(r0.w, d0, fmaf(r1.x, fmaf(2.0f, dy0, 1.0f), p00));
+    const float t = fmaf(d0, 2.0f, 1.0f);
+    e00 = __builtin_amdgcn_exp2f(p00);
+    e10 = __builtin_amdgcn_exp2f(p10);
+    float q0 = __builtin_amdgcn_exp2f(fmaf(r0.z, t, by0));
+    float q1 = q0 * r1.w;
+    e01 = mul0(e00, q0);
+    e11 = mul0(e10, q1);
+    q0 *= r1.z;
+    q1 *= r1.z;
+    e02 = mul0(e01, q0);
+    e12 = mul0(e11, q1);
+    q0 *= r1.z;
+    q1 *= r1.z;
+    e03 = mul0(e02, q0);
+    e13 = mul0(e12, q1);
+  } else {
+    const float dy1 = dy0 + 1.0f;
+    const float by1 = r0.w * dy1, cy1 = r1.x * dy1 * dy1;
+    const float d1 = d0 + 1.0f, d2 = d0 + 2.0f, d3 = d0 + 3.0f;
+    e00 = __builtin_amdgcn_exp2f(p00);
+    e01 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d1, by0), d1, cy0));
+    e02 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d2, by0), d2, cy0));
+    e03 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d3, by0), d3, cy0));
+    e10 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d0, by1), d0, cy1));
+    e11 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d1, by1), d1, cy1));
+    e12 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d2, by1), d2, cy1));
+    e13 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d3, by1), d3, cy1));
+  }
+  const float w = r1.y;
+  acc[0] = fmaf(w, e00, acc[0]);
+  acc[1] = fmaf(w, e01, acc[1]);
+  acc[2] = fmaf(w, e02, acc[2]);
+  acc[3] = fmaf(w, e03, acc[3]);
+  acc[4] = fmaf(w, e10, acc[4]);
+  acc[5] = fmaf(w, e11, acc[5]);
+  acc[6] = fmaf(w, e12, acc[6]);
+  acc[7] = fmaf(w, e13, acc[7]);
+}
+
+// The two rows of a lane's pixels, clipped to the slice.
+__device__ __forceinline__ void store_pixels(const SliceDev& sl, int px0, int py0, const float (&acc)[8]) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int py = py0 + r;
+    if (py >= sl.height) continue;
+    float* o = sl.out + (int64_t)py * sl.width;
+    const float* v = acc + 4 * r;
+    if (px0 + 3 < sl.width && (reinterpret_cast<uintptr_t>(o + px0) & 15) == 0) {
+      *reinterpret_cast<float4*>(o + px0) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+      if (px0 < sl.width) o[px0] = v[0];
+      if (px0 + 1 < sl.width) o[px0 + 1] = v[1];
+      if (px0 + 2 < sl.width) o[px0 + 2] = v[2];
+      if (px0 + 3 < sl.width) o[px0 + 3] = v[3];
+    }
+  }
+}
+
 __device__ __forceinline__ int slice_of(const FwdArgs& a, int n_slices, int tps, int bin) {
   return tps > 0 ? bin / tps : slice_of_bin(a.slices, n_slices, bin);
 }
@@ -197,54 +270,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
         const float4 r0 = buf0[j + half];
         const float4 r1 = buf1[j + half];   // j + 1 may be a zero slot: w = 0
         asm volatile("" :: "v"(r1.z), "v"(r1.w));   // one 16-byte LDS read for r1
-        const float d0 = fx0 - r0.x;
-        const float dy0 = fy0 - r0.y;
-        const float by0 = r0.w * dy0;
-        const float cy0 = r1.x * dy0 * dy0;
-        const float p00 = fmaf(fmaf(r0.z, d0, by0), d0, cy0);
-        float e00, e01, e02, e03, e10, e11, e12, e13;
-        // both records of the step must allow the row recurrence (uniform branch);
-        // the record's g is negative where it does not
-        if (__builtin_amdgcn_read_exec() == __builtin_amdgcn_ballot_w64(r1.z > 0.0f)) {
-          // second row's exponent: p(d0, dy0 + 1) = p00 + b d0 + c (2 dy0 + 1)
-          const float p10 = fmaf(r0.w, d0, fmaf(r1.x, fmaf(2.0f, dy0, 1.0f), p00));
-          const float t = fmaf(d0, 2.0f, 1.0f);
-          e00 = __builtin_amdgcn_exp2f(p00);
-          e10 = __builtin_amdgcn_exp2f(p10);
-          float q0 = __builtin_amdgcn_exp2f(fmaf(r0.z, t, by0));
-          float q1 = q0 * r1.w;
-          e01 = mul0(e00, q0);
-          e11 = mul0(e10, q1);
-          q0 *= r1.z;
-          q1 *= r1.z;
-          e02 = mul0(e01, q0);
-          e12 = mul0(e11, q1);
-          q0 *= r1.z;
-          q1 *= r1.z;
-          e03 = mul0(e02, q0);
-          e13 = mul0(e12, q1);
-        } else {
-          const float dy1 = dy0 + 1.0f;
-          const float by1 = r0.w * dy1, cy1 = r1.x * dy1 * dy1;
-          const float d1 = d0 + 1.0f, d2 = d0 + 2.0f, d3 = d0 + 3.0f;
-          e00 = __builtin_amdgcn_exp2f(p00);
-          e01 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d1, by0), d1, cy0));
-          e02 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d2, by0), d2, cy0));
-          e03 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d3, by0), d3, cy0));
-          e10 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d0, by1), d0, cy1));
-          e11 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d1, by1), d1, cy1));
-          e12 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d2, by1), d2, cy1));
-          e13 = __builtin_amdgcn_exp2f(fmaf(fmaf(r0.z, d3, by1), d3, cy1));
-        }
-        const float w = r1.y;
-        acc[0] = fmaf(w, e00, acc[0]);
-        acc[1] = fmaf(w, e01, acc[1]);
-        acc[2] = fmaf(w, e02, acc[2]);
-        acc[3] = fmaf(w, e03, acc[3]);
-        acc[4] = fmaf(w, e10, acc[4]);
-        acc[5] = fmaf(w, e11, acc[5]);
-        acc[6] = fmaf(w, e12, acc[6]);
-        acc[7] = fmaf(w, e13, acc[7]);
+        raster_step(r0, r1, fx0, fy0, acc);
       }
       if (stage < 3) advance();
       __syncthreads();
@@ -254,23 +280,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     // the two halves hold partial sums of the same pixels
 #pragma unroll
     for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
-    if (half == 0) {
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const int py = py0 + r;
-        if (py >= sl.height) continue;
-        float* o = sl.out + (int64_t)py * sl.width;
-        const float* v = acc + 4 * r;
-        if (px0 + 3 < sl.width && (reinterpret_cast<uintptr_t>(o + px0) & 15) == 0) {
-          *reinterpret_cast<float4*>(o + px0) = make_float4(v[0], v[1], v[2], v[3]);
-        } else {
-          if (px0 < sl.width) o[px0] = v[0];
-          if (px0 + 1 < sl.width) o[px0 + 1] = v[1];
-          if (px0 + 2 < sl.width) o[px0 + 2] = v[2];
-          if (px0 + 3 < sl.width) o[px0 + 3] = v[3];
-        }
-      }
-    }
+    if (half == 0) store_pixels(sl, px0, py0, acc);
     // the next tile becomes the current one
     item = nitem;
     rem = nrem;
@@ -281,6 +291,92 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     n1 = m1;
     rid_next = nrid2;
     if (item >= 0 && took) ticket = wave_take(counter);
+  }
+}
+
+// Small batches (at most kSplitMaxBins bins): one 256-lane workgroup per tile,
+// its four wavefronts taking every fourth batch of the list, so that a batch of
+// a few slices still fills the chip (a wavefront per tile would leave most
+// SIMDs with one or two wavefronts to hide latency).  The four partial images
+// are added in a fixed order through LDS (deterministic).
+constexpr int kSplitMaxBins = 4096;
+
+__global__ __launch_bounds__(256) void k_raster_fwd_split(FwdArgs a) {
+  __shared__ float4 buf0[4][64];
+  __shared__ float4 buf1[4][64];
+  __shared__ float part[3][kTilePix];
+  const int bin = blockIdx.x;
+  if (bin >= a.hdr->n_bins) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int half = lane >> 5, m = lane & 31;
+  const int row0 = (m >> 2) * 2, col0 = (m & 3) * 4;
+  const int k = slice_of(a, a.hdr->n_slices, a.hdr->tiles_per_slice, bin);
+  const SliceDev sl = a.slices[k];
+  const int tile = bin - sl.tile_base;
+  const int px0 = (tile % sl.ntx) * kTile + col0;
+  const int py0 = (tile / sl.ntx) * kTile + row0;
+  const float fx0 = (float)px0, fy0 = (float)py0;
+  const uint32_t start = a.bin_lo[bin], end = a.bin_hi[bin];
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 pad4 = make_float4(0.f, 0.f, 1.f, 0.f);   // w = 0, smooth
+  float acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+  // this wavefront's batches: start + 64 (wave + 4 i)
+  uint32_t base = start + 64u * wave;
+  float4 n0 = zero4, n1 = pad4;
+  if (base + lane < end) {
+    const float4* src = reinterpret_cast<const float4*>(a.rec_pay + a.list[base + lane]);
+    n0 = src[0];
+    n1 = src[1];
+  }
+  uint32_t rid_next = (base + 256 + lane < end) ? a.list[base + 256 + lane] : 0u;
+  for (; base < end; base += 256) {
+    buf0[wave][lane] = n0;
+    buf1[wave][lane] = n1;
+    // the wavefront's own LDS slots: ordering within the wavefront suffices
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int cnt = __builtin_amdgcn_readfirstlane((int)min(64u, end - base));
+    const uint32_t nb = base + 256;
+    n0 = zero4;
+    n1 = pad4;
+    if (nb + lane < end) {
+      const float4* src = reinterpret_cast<const float4*>(a.rec_pay + rid_next);
+      n0 = src[0];
+      n1 = src[1];
+    }
+    if (nb + 256 + lane < end) rid_next = a.list[nb + 256 + lane];
+    for (int j = 0; j < cnt; j += 2) {
+      const float4 r0 = buf0[wave][j + half];
+      const float4 r1 = buf1[wave][j + half];   // j + 1 may be a zero slot: w = 0
+      asm volatile("" :: "v"(r1.z), "v"(r1.w));   // one 16-byte LDS read for r1
+      raster_step(r0, r1, fx0, fy0, acc);
+    }
+    // all reads of this batch before the slots are overwritten
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
+  const int p0 = row0 * kTile + col0;
+  if (wave > 0 && half == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      part[wave - 1][p0 + i] = acc[i];
+      part[wave - 1][p0 + kTile + i] = acc[4 + i];
+    }
+  }
+  __syncthreads();
+  if (wave == 0 && half == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      acc[i] = ((acc[i] + part[0][p0 + i]) + part[1][p0 + i]) + part[2][p0 + i];
+      acc[4 + i] = ((acc[4 + i] + part[0][p0 + kTile + i]) + part[1][p0 + kTile + i]) + part[2][p0 + kTile + i];
+    }
+    store_pixels(sl, px0, py0, acc);
   }
 }
 
@@ -384,6 +480,11 @@ hipError_t launch_raster_fwd(const RenderConst& rc, const Workspace& ws, const L
   (void)rc;
   if (d.bins <= 0) return hipSuccess;
   FwdArgs a{ws.d_hdr, ws.d_slices, ws.d_bin_lo, ws.d_bin_hi, ws.d_list, ws.d_rec_pay, ws.d_work};
+  if (d.bins <= kSplitMaxBins) {
+    // d.bins bounds the batch's bins (the header holds the exact count)
+    k_raster_fwd_split<<<(unsigned)d.bins, 256, 0, s>>>(a);
+    return hipGetLastError();
+  }
   const int64_t blocks = d.bins < 8192 ? d.bins : 8192;
   k_raster_fwd<<<(unsigned)blocks, 64, 0, s>>>(a);
   return hipGetLastError();

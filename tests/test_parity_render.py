@@ -131,6 +131,24 @@ def test_forward_edge_cases(gp, case):
     assert err <= FWD_TOL
 
 
+@pytest.mark.parametrize("case", ["split", "queue", "slice_groups"])
+def test_forward_work_schedules(gp, case):
+    """The three raster schedules: a workgroup of four wavefronts per tile (at most
+    4096 bins), one wavefront per tile from the work queue, and one wavefront per tile
+    position over three consecutive slices (at least 24,576 bins; 100 slices leave a
+    last group of one)."""
+    _say(f"schedule {case}")
+    n_slices = {"split": 16, "queue": 20, "slice_groups": 100}[case]
+    p = synth.gaussians_uniform(6000, (256.0, 256.0, float(n_slices)), np.log(1.5), 0.4, seed=24)
+    slices = synth.axial_slices(n_slices, 256, 256, 1.0, z0=0.5, dz=1.0)
+    params, ws, imgs = _render_gpu(gp, p, slices)
+    _check_bins(ws, p, slices)
+    ref = [x.numpy() for x in focus.render(p, slices)]
+    err, mx = _fwd_err(imgs, ref)
+    _say(f"{case}: rel err {err:.3e} (max {mx:.3f})")
+    assert err <= FWD_TOL
+
+
 def test_forward_exact_mode_matches_brute_force(gp):
     from paper_2603_20611_amd import binding as B
     _say("exact mode")
