@@ -393,7 +393,9 @@ struct BwdArgs {
   uint32_t* work;
 };
 
-// 256 lanes per tile, tiles pulled from an atomic work counter.
+// 256 lanes per tile, tiles pulled from an atomic work counter; each lane sums
+// the six moments of a list entry over a quarter of the tile's upstream
+// gradient, staged in LDS.
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   __shared__ float G[kTilePix];
   __shared__ int s_item;
@@ -423,52 +425,73 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     }
     __syncthreads();
     const float fx0 = (float)(tx * kTile), fy0 = (float)(ty * kTile);
-    for (uint32_t cb = start + wave * 64; cb < end; cb += 256) {
-      const uint32_t idx = cb + lane;
-      if (idx >= end) continue;
-      const uint32_t rid = a.list[idx];
-      const float4* src = reinterpret_cast<const float4*>(a.rec_pay + rid);
-      const float4 r0 = src[0];
-      const float4 r1 = src[1];
-      const RecMeta meta = a.rec_meta[rid];
-      const float ca = r0.z, cb2 = r0.w, cc = r1.x;
-      float dx[kTile];
-#pragma unroll
-      for (int c = 0; c < kTile; ++c) dx[c] = (fx0 - r0.x) + (float)c;
+    // work units: a list entry's four-row quarter of the tile (4 lanes per
+    // entry), so that a tile with a few more entries than lanes costs a quarter
+    // round more, not a whole round
+    const uint32_t units = 4u * (end - start);
+    for (uint32_t u0 = (uint32_t)wave * 64u; u0 < units; u0 += 256u) {
+      const uint32_t u = u0 + (uint32_t)lane;
+      const bool valid = u < units;
+      const uint32_t e = u >> 2, rq = u & 3u;
       float M0 = 0.f, Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
-      for (int row = 0; row < kTile; ++row) {
-        const float dy = (fy0 + (float)row) - r0.y;
-        const float by = cb2 * dy;
-        const float cy = cc * dy * dy;
-        const float4* grow = reinterpret_cast<const float4*>(G + row * kTile);
-        float s0 = 0.f, sx = 0.f, sxx = 0.f;
+      uint32_t rid = 0u;
+      if (valid) {
+        rid = a.list[start + e];
+        const float4* src = reinterpret_cast<const float4*>(a.rec_pay + rid);
+        const float4 r0 = src[0];
+        const float4 r1 = src[1];
+        const float ca = r0.z, cb2 = r0.w, cc = r1.x;
+        float dx[kTile];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 g4 = grow[q];
-          const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+        for (int c = 0; c < kTile; ++c) dx[c] = (fx0 - r0.x) + (float)c;
+        for (int rr = 0; rr < 4; ++rr) {
+          const int row = 4 * (int)rq + rr;
+          const float dy = (fy0 + (float)row) - r0.y;
+          const float by = cb2 * dy;
+          const float cy = cc * dy * dy;
+          const float4* grow = reinterpret_cast<const float4*>(G + row * kTile);
+          float s0 = 0.f, sx = 0.f, sxx = 0.f;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const float d = dx[4 * q + c];
-            const float p = fmaf(fmaf(ca, d, by), d, cy);
-            const float we = gv[c] * __builtin_amdgcn_exp2f(p);
-            const float wd = we * d;
-            s0 += we;
-            sx += wd;
-            sxx = fmaf(wd, d, sxx);
+          for (int q = 0; q < 4; ++q) {
+            const float4 g4 = grow[q];
+            const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const float d = dx[4 * q + c];
+              const float p = fmaf(fmaf(ca, d, by), d, cy);
+              const float we = gv[c] * __builtin_amdgcn_exp2f(p);
+              const float wd = we * d;
+              s0 += we;
+              sx += wd;
+              sxx = fmaf(wd, d, sxx);
+            }
           }
+          M0 += s0;
+          Mx += sx;
+          Mxx += sxx;
+          My = fmaf(dy, s0, My);
+          Mxy = fmaf(dy, sx, Mxy);
+          Myy = fmaf(dy * dy, s0, Myy);
         }
-        M0 += s0;
-        Mx += sx;
-        Mxx += sxx;
-        My = fmaf(dy, s0, My);
-        Mxy = fmaf(dy, sx, Mxy);
-        Myy = fmaf(dy * dy, s0, Myy);
       }
-      // the record's instance slot of this tile (footprint enumerated row-major)
-      const uint32_t tx0 = meta.rx & 0xFFFFu, tx1 = meta.rx >> 16, ty0 = meta.ry & 0xFFFFu;
-      const uint32_t slot = meta.ibase + ((uint32_t)ty - ty0) * (tx1 - tx0 + 1u) + ((uint32_t)tx - tx0);
-      a.moments[2 * (size_t)slot] = make_float4(M0, Mx, My, Mxx);
-      a.moments[2 * (size_t)slot + 1] = make_float4(Mxy, Myy, 0.f, 0.f);
+      // the entry's four quarters, added in a fixed order
+#pragma unroll
+      for (int o = 1; o <= 2; o <<= 1) {
+        M0 += __shfl_xor(M0, o, 64);
+        Mx += __shfl_xor(Mx, o, 64);
+        My += __shfl_xor(My, o, 64);
+        Mxx += __shfl_xor(Mxx, o, 64);
+        Mxy += __shfl_xor(Mxy, o, 64);
+        Myy += __shfl_xor(Myy, o, 64);
+      }
+      if (valid && rq == 0u) {
+        // the record's instance slot of this tile (footprint enumerated row-major)
+        const RecMeta meta = a.rec_meta[rid];
+        const uint32_t tx0 = meta.rx & 0xFFFFu, tx1 = meta.rx >> 16, ty0 = meta.ry & 0xFFFFu;
+        const uint32_t slot = meta.ibase + ((uint32_t)ty - ty0) * (tx1 - tx0 + 1u) + ((uint32_t)tx - tx0);
+        a.moments[2 * (size_t)slot] = make_float4(M0, Mx, My, Mxx);
+        a.moments[2 * (size_t)slot + 1] = make_float4(Mxy, Myy, 0.f, 0.f);
+      }
     }
     __syncthreads();   // G[] is reused by the next tile
   }
