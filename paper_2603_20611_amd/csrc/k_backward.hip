@@ -234,12 +234,38 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
   }
 }
 
+// A workgroup takes 2048 Gaussians at a time, gathers those with records (a
+// batch of a few slices reaches a small fraction of a large set) into LDS and
+// gives them to its 256 lanes, so that lanes do not idle on Gaussians without
+// records.  Each Gaussian still has exactly one writer; the order in which a
+// workgroup visits its Gaussians does not change any result.
+constexpr int kBwdChunk = 2048;
+
 template <int DT, bool POSED>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
+  __shared__ int s_list[kBwdChunk];
+  __shared__ int s_n;
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < total; t += gridDim.x * 256)
-    backward_one<DT, POSED>(a, n_groups, t);
+  const int lane = threadIdx.x & 63;
+  for (int base = blockIdx.x * kBwdChunk; base < total; base += gridDim.x * kBwdChunk) {
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kBwdChunk / 256; ++i) {
+      const int t = base + i * 256 + threadIdx.x;
+      const bool active = t < total && a.g_nrec[t] > 0u;
+      const uint64_t m = __ballot(active);
+      int wbase = 0;
+      if (lane == 0 && m) wbase = atomicAdd(&s_n, __popcll(m));
+      wbase = __shfl(wbase, 0, 64);
+      if (active) s_list[wbase + __popcll(m & ((1ull << lane) - 1ull))] = t;
+    }
+    __syncthreads();
+    const int n = s_n;
+    for (int j = threadIdx.x; j < n; j += 256) backward_one<DT, POSED>(a, n_groups, s_list[j]);
+    __syncthreads();   // s_list and s_n are rewritten by the next chunk
+  }
 }
 
 template <bool POSED>
@@ -274,7 +300,7 @@ hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, flo
                ws.st_max_radius,
                ws.st_n,
                ws.d_poses};
-  int64_t blocks = (d.gauss + 255) / 256;
+  int64_t blocks = (d.gauss + kBwdChunk - 1) / kBwdChunk;
   if (blocks > 16384) blocks = 16384;
   return d.posed ? launch_bwd_p<true>(a, rc.attr_dtype, (unsigned)blocks, s)
                  : launch_bwd_p<false>(a, rc.attr_dtype, (unsigned)blocks, s);
