@@ -68,6 +68,7 @@ struct PreArgs {
   uint32_t* inst_val;   // record of every instance slot
   uint32_t sentinel_bin;
   const float* poses;   // [n_slices][12] of a posed batch
+  int emit_chunk;       // Gaussians per workgroup round of the emit
 };
 
 __device__ __forceinline__ bool kept_on(const PreArgs& a, float muz, float szz, int k) {
@@ -321,32 +322,18 @@ __device__ __forceinline__ void make_record(const double* cov, const float* p, c
   meta.slice = (uint32_t)k;
 }
 
-// Emit of the 64 consecutive Gaussians t0 .. t0 + 63 by one wavefront.
+// Slots of the 64 consecutive Gaussians t0 .. t0 + 63 of one wavefront.
 //
 // Record and instance slots come from an exclusive scan over the wavefront
 // (plus the wavefront's base), so the wavefront's output is one contiguous
-// range of records and one of instances.  W lanes cooperate on one Gaussian:
-// lane i of the group takes slices kb + i, kb + i + W, ... of its kept window,
-// and the group's kept slices are compacted with a ballot, so consecutive
-// lanes write consecutive records and adjacent instance runs.  (With one lane
-// per Gaussian and many slices per Gaussian, every lane would stream to its own
-// region and L2 would evict partly written lines.)  W = 1 is the one-lane
-// form, used when each Gaussian has at most one slice.
-template <int DT, int W, bool POSED>
-__device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0, double (*cov64)[64][6]) {
+// range of records and one of instances, in Gaussian order: g_rbase and
+// g_ninst (overwritten with the instance base) receive them.  Gaussians that
+// have records are appended to the workgroup's list in LDS (in any order:
+// every output position is fixed by the scan).
+__device__ __forceinline__ void slots_wave(const PreArgs& a, int t0, int* list, int* n_list) {
   const int lane = threadIdx.x & 63;
-  const int wave = (threadIdx.x >> 6) & 3;
   const int t = t0 + lane;
   uint32_t nrec = a.g_nrec[t];
-  // each lane: the float64 covariance of its own Gaussian, once for all its records
-  if (nrec > 0u) {
-    Loaded Lq;
-    load_params<DT>(a, n_groups, t, Lq);
-    cov_f64(Lq.p, a.rc.scale_mod, cov64[wave][lane]);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const uint32_t ninst = a.g_ninst[t];
   uint32_t pr = nrec, pi = ninst;
 #pragma unroll
@@ -358,6 +345,7 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0
   const uint32_t rbase = wb.x + pr - nrec, ibase = wb.y + pi - ninst;
   const bool fits = (uint64_t)rbase + nrec <= a.rc.rec_cap && (uint64_t)ibase + ninst <= a.rc.inst_cap;
   a.g_rbase[t] = rbase;
+  a.g_ninst[t] = ibase;
   if (!fits) {
     // overflow: this Gaussian's slots inside the capacity stay unused and are
     // marked so that no later kernel reads them
@@ -367,19 +355,52 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0
     for (uint32_t s = ibase; s < ibase + ninst && s < a.rc.inst_cap; ++s) a.inst_key[s] = a.sentinel_bin;
     nrec = 0u;
   }
-  const uint32_t krange = a.g_krange[t];
+  const uint64_t m = __ballot(nrec > 0u);
+  int base = 0;
+  if (lane == 0 && m) base = atomicAdd(n_list, __popcll(m));
+  base = __shfl(base, 0, 64);
+  if (nrec > 0u) list[base + __popcll(m & ((1ull << lane) - 1ull))] = t;
+}
+
+// Emit of 64 consecutive entries j0 .. j0 + 63 of the workgroup's list of
+// Gaussians with records, by one wavefront: W lanes cooperate on one Gaussian.  Lane i of the group takes
+// slices kb + i, kb + i + W, ... of its kept window, and the group's kept slices
+// are compacted with a ballot, so consecutive lanes write consecutive records
+// and adjacent instance runs.  (With one lane per Gaussian and many slices per
+// Gaussian, every lane would stream to its own region and L2 would evict
+// partly written lines.)  W = 1 is the one-lane form, used when each Gaussian
+// has at most one slice.  Each lane first computes the float64 covariance of
+// its own entry's Gaussian into LDS, once for all of its records.
+template <int DT, int W, bool POSED>
+__device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const int* list, uint32_t j0,
+                                          uint32_t n_active, double (*cov64)[6]) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t j = j0 + (uint32_t)lane;
+  const int t = j < n_active ? list[j] : 0;
+  uint32_t rbase = 0u, ibase = 0u, krange = 0u;
+  if (j < n_active) {
+    rbase = a.g_rbase[t];
+    ibase = a.g_ninst[t];
+    krange = a.g_krange[t];
+    Loaded Lq;
+    load_params<DT>(a, n_groups, t, Lq);
+    cov_f64(Lq.p, a.rc.scale_mod, cov64[lane]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int sub = lane / W, li = lane % W;
   for (int it = 0; it < W; ++it) {
-    // 64 / W groups per round, W rounds: Gaussian gi of the 64.  Every lane
-    // takes part in the exchanges; divergence starts after them.
+    // 64 / W groups per round, W rounds: entry gi of the 64.  Every lane takes
+    // part in the exchanges; divergence starts after them.
     const int gi = it * (64 / W) + sub;
-    const uint32_t g_nrec = __shfl(nrec, gi, 64);
+    const int tg = __shfl(t, gi, 64);
     const uint32_t g_rb = __shfl(rbase, gi, 64);
     const uint32_t g_ib = __shfl(ibase, gi, 64);
     const uint32_t g_kr = __shfl(krange, gi, 64);
-    if (g_nrec == 0u) continue;
+    if (j0 + (uint32_t)gi >= n_active) continue;
     Loaded L;
-    load_params<DT>(a, n_groups, t0 + gi, L);
+    load_params<DT>(a, n_groups, tg, L);
     activate(a, L);
     const int kb = (int)(g_kr & 0xFFFFu), ke = (int)(g_kr >> 16);
     uint32_t rec_run = g_rb, inst_run = g_ib;
@@ -415,7 +436,7 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0
         uint32_t slot = inst_run + ipos;
         RecPay pay;
         RecMeta meta;
-        make_record(cov64[wave][gi], L.p, L.c, POSED ? a.poses + 12 * k : nullptr, sl, k, slot, a.rc.flags, rect,
+        make_record(cov64[gi], L.p, L.c, POSED ? a.poses + 12 * k : nullptr, sl, k, slot, a.rc.flags, rect,
                     pay, meta);
         a.rec_pay[rid] = pay;
         a.rec_meta[rid] = meta;
@@ -435,6 +456,10 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, int t0
       }
     }
   }
+  // the wavefront's LDS slots are rewritten by its next round
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Grid-stride over whole wavefronts of flattened Gaussians, so that a launch
@@ -448,18 +473,51 @@ __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
     count_one<DT, POSED>(a, n_groups, t);
 }
 
+// A workgroup takes `chunk` consecutive Gaussians at a time (a multiple of 256,
+// at most kEmitChunk): their slots (wavefront scans), then the emit of those
+// that have records, 64 per wavefront.  A batch of a few slices reaches a small
+// fraction of a large set, and without the gathering most lanes would idle on
+// Gaussians without records; a deep stack reaches nearly all of them and takes
+// 256 at a time (one wavefront's worth each, the most parallel form).
+constexpr int kEmitChunk = 2048;
+
 template <int DT, int W, bool POSED>
 __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
+  __shared__ int list[kEmitChunk];
+  __shared__ int n_list;
+  __shared__ double cov64[4][64][6];
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
-  const int stride = gridDim.x * 256;
-  __shared__ double cov64[4][64][6];
-  for (int t0 = blockIdx.x * 256 + (threadIdx.x & ~63); t0 < total; t0 += stride) {
-    emit_wave<DT, W, POSED>(a, n_groups, t0, cov64);
-    // the wavefront's slots are rewritten by its next round
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int wave = threadIdx.x >> 6;
+  const int chunk = a.emit_chunk;
+  if (chunk == 256) {
+    // one wavefront's 64 Gaussians at a time, synchronised within the wavefront only
+    __shared__ int n_w[4];
+    int* wl = list + wave * 64;
+    const int lane = threadIdx.x & 63;
+    for (int t0 = blockIdx.x * 256 + wave * 64; t0 < total; t0 += gridDim.x * 256) {
+      if (lane == 0) n_w[wave] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      slots_wave(a, t0, wl, &n_w[wave]);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane(n_w[wave]);
+      if (n > 0u) emit_wave<DT, W, POSED>(a, n_groups, wl, 0u, n, cov64[wave]);
+    }
+    return;
+  }
+  for (int base = blockIdx.x * chunk; base < total; base += gridDim.x * chunk) {
+    if (threadIdx.x == 0) n_list = 0;
+    __syncthreads();
+    for (int t0 = base + wave * 64; t0 < min(base + chunk, total); t0 += 256) slots_wave(a, t0, list, &n_list);
+    __syncthreads();
+    const uint32_t n = (uint32_t)n_list;
+    for (uint32_t j0 = (uint32_t)wave * 64u; j0 < n; j0 += 256u)
+      emit_wave<DT, W, POSED>(a, n_groups, list, j0, n, cov64[wave]);
+    __syncthreads();   // list and n_list are rewritten by the next chunk
   }
 }
 
@@ -518,7 +576,7 @@ hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDi
 static PreArgs pre_args(const RenderConst& rc, const Workspace& ws, uint32_t sentinel_bin) {
   return PreArgs{rc, ws.d_hdr, ws.d_groups, ws.d_slices, ws.d_ctr, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase,
                  ws.d_g_nrec, ws.d_g_ninst, ws.d_g_krange, ws.d_wave_cnt, ws.d_inst_key, ws.d_inst_val,
-                 sentinel_bin, ws.d_poses};
+                 sentinel_bin, ws.d_poses, 256};
 }
 
 hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s) {
@@ -533,8 +591,10 @@ hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const La
 hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, uint32_t sentinel_bin,
                            hipStream_t s) {
   if (d.gauss <= 0) return hipSuccess;
-  const PreArgs a = pre_args(rc, ws, sentinel_bin);
-  int64_t blocks = (d.gauss + 255) / 256;
+  PreArgs a = pre_args(rc, ws, sentinel_bin);
+  // few slices per Gaussian set (narrow emit): most Gaussians have no record
+  a.emit_chunk = d.emit_width >= 16 ? 256 : kEmitChunk;
+  int64_t blocks = (d.gauss + a.emit_chunk - 1) / a.emit_chunk;
   if (blocks > 16384) blocks = 16384;
   return d.posed ? launch_emit_p<true>(a, rc.attr_dtype, d.emit_width, (unsigned)blocks, s)
                  : launch_emit_p<false>(a, rc.attr_dtype, d.emit_width, (unsigned)blocks, s);
