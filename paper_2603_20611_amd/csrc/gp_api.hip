@@ -610,16 +610,17 @@ gp_status gp_l1_dssim_loss_grad(gp_workspace* w, const float* img, const float* 
   if (!img || !tgt || !grad) return einval("l1_dssim: NULL array");
   Workspace* ws = reinterpret_cast<Workspace*>(w);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (3 * npix > ws->ssim_cap) {
+  const int64_t need = ssim_scratch(n_slices, width, height);
+  if (need > ws->ssim_cap) {
     GP_HIP(hipStreamSynchronize(s));
     GP_HIP(wait_ws(ws));
-    hipError_t e = dev_alloc(&ws->d_ssim, 3 * npix);
+    hipError_t e = dev_alloc(&ws->d_ssim, need);
     if (e != hipSuccess) {
       ws->ssim_cap = 0;
       set_error("l1_dssim: cannot allocate scratch");
       return GP_ENOMEM;
     }
-    ws->ssim_cap = 3 * npix;
+    ws->ssim_cap = need;
   }
   GP_HIP(launch_ssim_loss(img, tgt, n_slices, width, height, (double)lambda, ws->d_ssim, grad, loss, s));
   return GP_OK;

@@ -339,6 +339,8 @@ hipError_t launch_densify(const float* p, const float* m, const float* v, int64_
 // k_optim.hip
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, int64_t stride,
                        const gp_adam_cfg& c, hipStream_t s);
+// Scratch (float64 elements) of launch_ssim_loss: coefficient maps and per-block sums.
+int64_t ssim_scratch(int n_slices, int width, int height);
 hipError_t launch_ssim_loss(const float* x, const float* y, int n_slices, int width, int height, double lam,
                             double* maps, float* grad, float* loss, hipStream_t s);
 hipError_t launch_l1(const float* img, const float* tgt, int64_t n, float scale, float* grad,

@@ -31,6 +31,7 @@ struct SsimArgs {
   const float* x;       // [S][H][W] rendered slices
   const float* y;       // [S][H][W] targets
   double* maps;         // [3][S][H][W] coefficient maps
+  double* part;         // [2][blocks]: per-block sums of the two loss terms
   float* grad;          // [S][H][W] dL/dI (written)
   float* loss;          // [2]: += L1 term, += D-SSIM term
   int W, H;
@@ -117,9 +118,29 @@ __global__ __launch_bounds__(256) void k_ssim_stats(SsimArgs a) {
   const double t1 = block_sum(part_l1, red);
   __syncthreads();
   const double t2 = block_sum(part_d, red);
-  if (threadIdx.x == 0 && a.loss) {
-    atomicAdd(&a.loss[0], (float)(t1 * a.inv_n));
-    atomicAdd(&a.loss[1], (float)(t2 * a.inv_n));
+  if (threadIdx.x == 0) {
+    const int64_t bid = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    a.part[2 * bid] = t1;
+    a.part[2 * bid + 1] = t2;
+  }
+}
+
+// The two loss terms from the per-block sums, in a fixed order (one writer:
+// deterministic, and no contended atomics).
+__global__ __launch_bounds__(256) void k_ssim_loss_sum(const double* __restrict__ part, int64_t nblocks,
+                                                       double inv_n, float* __restrict__ loss) {
+  __shared__ double red[4];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += 256) {
+    s1 += part[2 * b];
+    s2 += part[2 * b + 1];
+  }
+  const double t1 = block_sum(s1, red);
+  __syncthreads();
+  const double t2 = block_sum(s2, red);
+  if (threadIdx.x == 0) {
+    loss[0] += (float)(t1 * inv_n);
+    loss[1] += (float)(t2 * inv_n);
   }
 }
 
@@ -172,12 +193,18 @@ __global__ __launch_bounds__(256) void k_ssim_grad(SsimArgs a) {
 
 }  // namespace
 
+int64_t ssim_scratch(int n_slices, int width, int height) {
+  const int64_t blocks = (int64_t)((width + kSW - 1) / kSW) * ((height + kSH - 1) / kSH) * n_slices;
+  return 3 * (int64_t)n_slices * width * height + 2 * blocks;
+}
+
 hipError_t launch_ssim_loss(const float* x, const float* y, int n_slices, int width, int height, double lam,
                             double* maps, float* grad, float* loss, hipStream_t s) {
   SsimArgs a{};
   a.x = x;
   a.y = y;
   a.maps = maps;
+  a.part = maps + 3 * (int64_t)n_slices * width * height;
   a.grad = grad;
   a.loss = loss;
   a.W = width;
@@ -197,6 +224,9 @@ hipError_t launch_ssim_loss(const float* x, const float* y, int n_slices, int wi
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_ssim_grad<<<grid, 256, 0, s>>>(a);
+  e = hipGetLastError();
+  if (e != hipSuccess || !loss) return e;
+  k_ssim_loss_sum<<<1, 256, 0, s>>>(a.part, (int64_t)grid.x * grid.y * grid.z, a.inv_n, loss);
   return hipGetLastError();
 }
 
