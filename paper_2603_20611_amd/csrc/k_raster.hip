@@ -390,27 +390,19 @@ struct BwdArgs {
   const RecMeta* rec_meta;
   const float* grad_out;
   float4* moments;
-  uint32_t* work;
 };
 
-// 256 lanes per tile, tiles pulled from an atomic work counter; each lane sums
+// 256 lanes per tile, tiles assigned round-robin (the tiles of a batch cost
+// about the same, and every workgroup taking a ticket from one counter at the
+// start of a small batch serialised on it: 30 % of this kernel); each lane sums
 // the six moments of a list entry over a quarter of the tile's upstream
 // gradient, staged in LDS.
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   __shared__ float G[kTilePix];
-  __shared__ int s_item;
   const int n_bins = a.hdr->n_bins;
   const int n_slices = a.hdr->n_slices;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      const uint32_t c = atomicAdd(&a.work[kWorkRasterBwd], 1u);
-      s_item = c < (uint32_t)n_bins ? (int)c : -1;
-    }
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();   // s_item is rewritten by the next iteration
-    if (item < 0) break;
+  for (int item = blockIdx.x; item < n_bins; item += gridDim.x) {
     const int bin = item;
     const uint32_t start = a.bin_lo[bin], end = a.bin_hi[bin];
     if (start == end) continue;
@@ -517,10 +509,8 @@ hipError_t launch_raster_bwd(const RenderConst& rc, const Workspace& ws, const f
                              const LaunchDims& d, hipStream_t s) {
   (void)rc;
   if (d.bins <= 0) return hipSuccess;
-  hipError_t e = launch_fill_u32(ws.d_work + kWorkRasterBwd, 0u, 1, s);
-  if (e != hipSuccess) return e;
   BwdArgs a{ws.d_hdr, ws.d_slices, ws.d_bin_lo, ws.d_bin_hi, ws.d_list, ws.d_rec_pay, ws.d_rec_meta, grad_out,
-            ws.d_moments, ws.d_work};
+            ws.d_moments};
   const int64_t blocks = d.bins < 2048 ? d.bins : 2048;
   k_raster_bwd<<<(unsigned)blocks, 256, 0, s>>>(a);
   return hipGetLastError();
