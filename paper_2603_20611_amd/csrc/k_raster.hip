@@ -157,7 +157,10 @@ __device__ __forceinline__ int slice_of(const FwdArgs& a, int n_slices, int tps,
 }
 
 // One 64-lane workgroup per work item (a tile, or a tile position over a
-// slice group), items taken from a shared counter.  Two software pipelines
+// slice group), items taken from a shared counter; each workgroup's first two
+// items are fixed (its index and index + grid size), since every workgroup
+// taking its first tickets at once serialised on the counter (12 % of the
+// kernel on the 400-slice stack).  Two software pipelines
 // hide the memory latency: within a tile, record ids are
 // loaded two batches ahead and records one batch ahead; across tiles, the next
 // tile is fetched one step per batch of the current one (its queue ticket is
@@ -193,7 +196,9 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
 
   // the first tile, fetched without overlap
   int rem = 0;
-  int item = first_bin(wave_take(counter), rem);
+  // the first two items of every workgroup are fixed; the counter hands out the rest
+  const uint32_t fixed = 2u * gridDim.x;
+  int item = first_bin(blockIdx.x, rem);
   if (item < 0) return;
   uint32_t start = a.bin_lo[item], end = a.bin_hi[item];
   int k = slice_of(a, n_slices, tps, item);
@@ -204,7 +209,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     n1 = src[1];
   }
   uint32_t rid_next = (start + 64 + lane < end) ? a.list[start + 64 + lane] : 0u;
-  uint32_t ticket = wave_take(counter);
+  uint32_t ticket = blockIdx.x + gridDim.x;
 
   while (item >= 0) {
     const int bin = item;
@@ -290,7 +295,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     n0 = m0;
     n1 = m1;
     rid_next = nrid2;
-    if (item >= 0 && took) ticket = wave_take(counter);
+    if (item >= 0 && took) ticket = wave_take(counter) + fixed;
   }
 }
 

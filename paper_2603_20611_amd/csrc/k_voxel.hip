@@ -176,14 +176,16 @@ __device__ __forceinline__ void vox_tile_xyz(const VoxArgs& a, int tile, int* tx
 }
 
 // One wavefront per tile; lane (lx, ly) owns the column of 8 voxels along z.
+// Each workgroup's first tile is its own index; the shared counter hands out
+// the rest (every workgroup taking a ticket at once serialised on it).
 __global__ __launch_bounds__(64) void k_vox_fwd(VoxArgs a) {
   __shared__ float4 b0[64], b1[64], b2[64];
   const int lane = threadIdx.x;
   const int lx = lane & 7, ly = lane >> 3;
   uint32_t* counter = a.work + kWorkRasterFwd;
-  uint32_t t0 = wave_take(counter);
+  const uint32_t t0 = blockIdx.x;
   for (int tile = t0 < (uint32_t)a.n_tiles ? (int)t0 : -1; tile >= 0;) {
-    const uint32_t ticket = wave_take(counter);   // resolved after this tile
+    const uint32_t ticket = wave_take(counter) + gridDim.x;   // resolved after this tile
     int tx, ty, tz;
     vox_tile_xyz(a, tile, &tx, &ty, &tz);
     const float fx = (float)(tx * kVT + lx), fy = (float)(ty * kVT + ly), fz0 = (float)(tz * kVT);
@@ -233,16 +235,11 @@ __global__ __launch_bounds__(256) void k_vox_bwd(VoxArgs a) {
   __shared__ float G[kVTVox];
   __shared__ int s_item;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (threadIdx.x == 0) {
-    const uint32_t c = atomicAdd(&a.work[kWorkRasterBwd], 1u);
-    s_item = c < (uint32_t)a.n_tiles ? (int)c : -1;
-  }
-  __syncthreads();
-  int tile = s_item;
-  __syncthreads();   // s_item is rewritten at the end of the first tile
+  // the first tile is the workgroup's own index; the counter hands out the rest
+  int tile = blockIdx.x < (unsigned)a.n_tiles ? (int)blockIdx.x : -1;
   while (tile >= 0) {
     uint32_t ticket = 0u;
-    if (threadIdx.x == 0) ticket = atomicAdd(&a.work[kWorkRasterBwd], 1u);
+    if (threadIdx.x == 0) ticket = atomicAdd(&a.work[kWorkRasterBwd], 1u) + gridDim.x;
     const uint32_t start = a.tile_lo[tile], end = a.tile_hi[tile];
     if (start != end) {
     int tx, ty, tz;
