@@ -4,13 +4,13 @@
 // (slots come from a scan, not from atomics).  A stable sort by bin therefore
 // leaves each tile list in Gaussian-index order, the unique order the oracle
 // also uses, without any per-list sort.  One pass of the sort:
-//   hist:    each block counts the digits of its 4096-element tile (LDS atomics;
+//   hist:    each block counts the digits of its 8192-element tile (LDS atomics;
 //            counts only, so their order does not matter);
 //   scan:    exclusive scan of the digit-major [digit][block] count matrix;
-//   scatter: each block re-reads its tile in 256-element chunks and gives every
-//            element its stable rank among equal digits: within a wavefront by
-//            matching digits bit by bit with ballots, across the block's four
-//            wavefronts through per-digit counts in LDS.
+//   scatter: each block re-reads its tile and gives every element its stable
+//            rank among equal digits: within a wavefront by matching digits
+//            bit by bit with ballots, across the block's eight wavefronts
+//            through per-digit counts in LDS.
 // Element counts are read from the device, so launches sized for a capacity
 // serve any batch (graph replay).
 #include "gp_internal.h"
@@ -136,10 +136,19 @@ int64_t scan_parts_needed(int64_t max_n) { return (max_n + kScanTile - 1) / kSca
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int kSortTile = 4096;    // elements per block
-constexpr int kSortChunk = 256;    // elements per block step (one per thread)
+constexpr int kSortThreads = 512;                         // threads per block
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kPerWave = 1024;                            // elements per wavefront
+constexpr int kSortTile = kSortWaves * kPerWave;          // elements per block
 constexpr int kMaxDigitBits = 9;
 constexpr int kMaxDigits = 1 << kMaxDigitBits;
+constexpr int kDigPerThread = kMaxDigits / kSortThreads;  // 1 or 2
+
+// LDS slot of a digit's counter: the low three bits are xor-ed with bits 6-8,
+// so that digits 64 or 256 apart (the same tile on slices of the other
+// parity, four tile rows down) fall in different banks.
+__device__ __forceinline__ uint32_t dslot(uint32_t d) { return d ^ ((d >> 6) & 7u); }
+
 
 struct RadixArgs {
   const uint32_t* key_in;
@@ -152,25 +161,31 @@ struct RadixArgs {
   int nblocks, shift, bits;
 };
 
-__global__ __launch_bounds__(256) void k_radix_hist(RadixArgs a) {
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(RadixArgs a) {
   __shared__ uint32_t h[kMaxDigits];
   const int R = 1 << a.bits;
-  for (int i = threadIdx.x; i < R; i += 256) h[i] = 0u;
+  for (int i = threadIdx.x; i < R; i += kSortThreads) h[i] = 0u;
   __syncthreads();
   const uint32_t n = min(*a.count, a.cap);
   const uint32_t tile = blockIdx.x;
   const uint32_t base = tile * kSortTile;
   // all loads first (independent, in flight together), then the counting
-  constexpr int kPer = kSortTile / 256;
+  constexpr int kPer = kSortTile / kSortThreads;
   uint32_t kv[kPer];
+  const bool full = base + kSortTile <= n;
+  if (full) {
 #pragma unroll
-  for (int c = 0; c < kPer; ++c) {
-    const uint32_t j = base + c * 256 + threadIdx.x;
-    kv[c] = j < n ? a.key_in[j] : 0u;
+    for (int c = 0; c < kPer; ++c) kv[c] = a.key_in[base + c * kSortThreads + threadIdx.x];
+  } else {
+#pragma unroll
+    for (int c = 0; c < kPer; ++c) {
+      const uint32_t j = base + c * kSortThreads + threadIdx.x;
+      kv[c] = j < n ? a.key_in[j] : 0u;
+    }
   }
 #pragma unroll
   for (int c = 0; c < kPer; ++c) {
-    const uint32_t j = base + c * 256 + threadIdx.x;
+    const uint32_t j = base + c * kSortThreads + threadIdx.x;
     if (j < n) {
       const uint32_t d = (kv[c] >> a.shift) & (R - 1);
       // runs of equal digits are common (the high digit of consecutive pairs
@@ -178,14 +193,14 @@ __global__ __launch_bounds__(256) void k_radix_hist(RadixArgs a) {
       const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
       const uint64_t act = __builtin_amdgcn_read_exec();
       if (__builtin_amdgcn_ballot_w64(d == d0) == act) {
-        if (__lane_id() == (uint32_t)__builtin_ctzll(act)) atomicAdd(&h[d0], (uint32_t)__popcll(act));
+        if (__lane_id() == (uint32_t)__builtin_ctzll(act)) atomicAdd(&h[dslot(d0)], (uint32_t)__popcll(act));
       } else {
-        atomicAdd(&h[d], 1u);
+        atomicAdd(&h[dslot(d)], 1u);
       }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < R; i += 256) a.hist[(size_t)i * a.nblocks + tile] = h[i];
+  for (int i = threadIdx.x; i < R; i += kSortThreads) a.hist[(size_t)i * a.nblocks + tile] = h[dslot(i)];
 }
 
 // Scatter of one tile: the tile is first sorted stably by digit into LDS, then
@@ -194,110 +209,165 @@ __global__ __launch_bounds__(256) void k_radix_hist(RadixArgs a) {
 // on its own cache line.
 //
 // Wavefront w owns elements 1024 w .. 1024 w + 1023 of the tile (16 chunks of
-// 64).  Each wavefront counts its digits; one block-wide scan turns the counts
-// into the first local position of every (digit, wavefront); each wavefront
-// then ranks its chunks on its own (lanes with equal digits matched by
-// ballots, a per-wavefront running count per digit in LDS), with no
-// workgroup barrier between chunks.
-__global__ __launch_bounds__(256) void k_radix_scatter(RadixArgs a) {
-  constexpr int kPerWave = kSortTile / 4;        // elements per wavefront
+// 64).  Each wavefront matches the digits of each chunk (lanes with equal
+// digits found bit by bit with ballots); the lowest lane of each distinct
+// digit adds the chunk's count to the wavefront's counter in LDS and gets back
+// the digit's count in the earlier chunks, so every element knows its offset
+// within its (digit, wavefront) run.  One block-wide scan turns the counts
+// into the first local position of every (digit, wavefront), and the elements
+// go to their places with no further synchronisation.  Every global load
+// (elements and the block's digit offsets) is issued before the first wait;
+// the digit width is a template parameter so that the matching unrolls; LDS
+// is 80 KB, two blocks per CU.
+template <int BITS>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RadixArgs a) {
   constexpr int kChunks = kPerWave / 64;         // chunks per wavefront
+  constexpr int R = 1 << BITS;
   __shared__ uint32_t sk[kSortTile], sv[kSortTile];
-  __shared__ uint32_t wrun[4][kMaxDigits];       // per-wavefront digit counts, then running positions
-  __shared__ uint32_t loc[kMaxDigits];           // local run start of each digit (exclusive scan)
-  __shared__ uint32_t glob[kMaxDigits];          // global start of this tile's run of each digit
-  __shared__ uint32_t part[256];
-  const int R = 1 << a.bits;
+  __shared__ uint32_t wrun[kSortWaves][kMaxDigits];   // per-wavefront digit counts, then running positions
+  uint32_t* const wtot = sk;                     // the wavefront totals of the scan (before sk is used)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t n = min(*a.count, a.cap);
   const uint32_t tile = blockIdx.x;
   const uint32_t base = tile * kSortTile;
   if (base >= n) return;   // whole block past the end (uniform)
   const uint32_t tn = min((uint32_t)kSortTile, n - base);
-  for (int i = threadIdx.x; i < R; i += 256) {
-    glob[i] = a.hist[(size_t)i * a.nblocks + tile];
-    wrun[0][i] = wrun[1][i] = wrun[2][i] = wrun[3][i] = 0u;
-  }
-  __syncthreads();
-  // load (element 1024 w + 64 c + lane in register c) and count digits per wavefront
+  const bool full = tn == (uint32_t)kSortTile;
+  // every global load of the block is issued before anything waits on one
   uint32_t key[kChunks], val[kChunks];
+  if (full) {
 #pragma unroll
-  for (int c = 0; c < kChunks; ++c) {
-    const uint32_t j = (uint32_t)(wave * kPerWave + c * 64 + lane);
-    key[c] = j < tn ? a.key_in[base + j] : 0u;
-    val[c] = j < tn ? a.val_in[base + j] : 0u;
-  }
-#pragma unroll
-  for (int c = 0; c < kChunks; ++c) {
-    const uint32_t j = (uint32_t)(wave * kPerWave + c * 64 + lane);
-    if (j < tn) atomicAdd(&wrun[wave][(key[c] >> a.shift) & (R - 1)], 1u);
-  }
-  __syncthreads();
-  // exclusive scan over digits of the tile's counts (two digits per thread),
-  // then the first position of each (digit, wavefront)
-  {
-    const int i0 = 2 * threadIdx.x;
-    uint32_t c0 = 0u, c1 = 0u;
-    if (i0 < R) c0 = wrun[0][i0] + wrun[1][i0] + wrun[2][i0] + wrun[3][i0];
-    if (i0 + 1 < R) c1 = wrun[0][i0 + 1] + wrun[1][i0 + 1] + wrun[2][i0 + 1] + wrun[3][i0 + 1];
-    const uint32_t v = c0 + c1;
-    part[threadIdx.x] = v;
-    __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-      const uint32_t o = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
-      __syncthreads();
-      part[threadIdx.x] += o;
-      __syncthreads();
+    for (int c = 0; c < kChunks; ++c) {
+      const uint32_t j = (uint32_t)(wave * kPerWave + c * 64 + lane);
+      key[c] = a.key_in[base + j];
+      val[c] = a.val_in[base + j];
     }
-    const uint32_t excl = part[threadIdx.x] - v;
+  } else {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = i0 + h;
-      if (i >= R) continue;
-      uint32_t p = h == 0 ? excl : excl + c0;
-      loc[i] = p;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const uint32_t cnt = wrun[w][i];
-        wrun[w][i] = p;
-        p += cnt;
-      }
+    for (int c = 0; c < kChunks; ++c) {
+      const uint32_t j = (uint32_t)(wave * kPerWave + c * 64 + lane);
+      key[c] = j < tn ? a.key_in[base + j] : 0u;
+      val[c] = j < tn ? a.val_in[base + j] : 0u;
     }
   }
+  uint32_t g[kDigPerThread];
+#pragma unroll
+  for (int h = 0; h < kDigPerThread; ++h) {
+    const int i = kDigPerThread * threadIdx.x + h;
+    g[h] = i < R ? a.hist[(size_t)i * a.nblocks + tile] : 0u;
+  }
+  for (int i = threadIdx.x; i < R; i += kSortThreads)
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) wrun[w][i] = 0u;
   __syncthreads();
-  // stable ranks within each wavefront, chunk by chunk
+  // lanes with the same digit: for every bit, the ballot of that bit, or its
+  // complement where the lane's bit is 0.  The lowest lane of each distinct
+  // digit of a chunk adds the chunk's count to the wavefront's counter; the
+  // value it returns (the digit's count in the wavefront's earlier chunks)
+  // plus a lane's rank among its equals is the lane's offset within the
+  // wavefront's run of that digit (10 bits, three chunks per register).
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  constexpr int kPacked = (kChunks + 2) / 3;
+  uint32_t pk[kPacked];
+#pragma unroll
+  for (int q = 0; q < kPacked; ++q) pk[q] = 0u;
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
     const bool valid = (uint32_t)(wave * kPerWave + c * 64 + lane) < tn;
     const uint32_t digit = valid ? (key[c] >> a.shift) & (R - 1) : 0u;
-    uint64_t same = __ballot(valid);
-    for (int b = 0; b < a.bits; ++b) {
-      const uint64_t bb = __ballot((digit >> b) & 1u);
-      same &= ((digit >> b) & 1u) ? bb : ~bb;
+    const uint64_t vb = __ballot(valid);
+    uint32_t same_lo = (uint32_t)vb, same_hi = (uint32_t)(vb >> 32);
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+      const int32_t mt = (int32_t)(digit << (31 - b)) >> 31;   // -1 where the lane's bit is set
+      const uint64_t bb = __builtin_amdgcn_ballot_w64(mt != 0);
+      same_lo &= ~((uint32_t)bb ^ (uint32_t)mt);
+      same_hi &= ~((uint32_t)(bb >> 32) ^ (uint32_t)mt);
     }
+    const uint64_t same = ((uint64_t)same_hi << 32) | same_lo;
     const uint32_t rank = (uint32_t)__popcll(same & lt_mask);
-    uint32_t p = 0u;
+    uint32_t old = 0u;
+    if (valid && rank == 0u) old = atomicAdd(&wrun[wave][dslot(digit)], (uint32_t)__popcll(same));
+    const int leader = valid ? __builtin_ctzll(same) : lane;
+    const uint32_t off = __shfl(old, leader, 64) + rank;
+    pk[c / 3] |= (off & 1023u) << (10 * (c % 3));
+  }
+  __syncthreads();
+  // exclusive scan over digits of the tile's counts: thread t owns digits
+  // kDigPerThread t ...; a shuffle scan within each wavefront, then the totals
+  // of the wavefronts before it
+  uint32_t gofs[kDigPerThread];
+  {
+    uint32_t cw[kDigPerThread][kSortWaves], c[kDigPerThread];
+    uint32_t v = 0u;
+#pragma unroll
+    for (int h = 0; h < kDigPerThread; ++h) {
+      const int i = kDigPerThread * threadIdx.x + h;
+      c[h] = 0u;
+#pragma unroll
+      for (int w = 0; w < kSortWaves; ++w) {
+        cw[h][w] = i < R ? wrun[w][dslot(i)] : 0u;
+        c[h] += cw[h][w];
+      }
+      v += c[h];
+    }
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t u = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += u;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    uint32_t p = inc - v;
+    for (int w = 0; w < wave; ++w) p += wtot[w];
+#pragma unroll
+    for (int h = 0; h < kDigPerThread; ++h) {
+      const int i = kDigPerThread * threadIdx.x + h;
+      gofs[h] = g[h] - p;
+      if (i < R) {
+        uint32_t q = p;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+          wrun[w][dslot(i)] = q;
+          q += cw[h][w];
+        }
+      }
+      p += c[h];
+    }
+  }
+  __syncthreads();
+  // every element to its place in the tile's local order: the start of its
+  // (digit, wavefront) run plus its offset in it
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    const bool valid = (uint32_t)(wave * kPerWave + c * 64 + lane) < tn;
     if (valid) {
-      p = wrun[wave][digit] + rank;
+      const uint32_t slot = dslot((key[c] >> a.shift) & (R - 1));
+      const uint32_t p = wrun[wave][slot] + ((pk[c / 3] >> (10 * (c % 3))) & 1023u);
       sk[p] = key[c];
       sv[p] = val[c];
     }
-    // all lanes have read the running position before its leader advances it
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (valid && rank == 0) wrun[wave][digit] += (uint32_t)__popcll(same);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // the running positions are done with: their first row now holds the offsets
+  uint32_t* const go = wrun[0];
+#pragma unroll
+  for (int h = 0; h < kDigPerThread; ++h) {
+    const int i = kDigPerThread * threadIdx.x + h;
+    if (i < R) go[dslot(i)] = gofs[h];
   }
   __syncthreads();
   // write out in local order: runs of one digit go to consecutive addresses
-  for (uint32_t p = threadIdx.x; p < tn; p += 256) {
-    const uint32_t k = sk[p];
-    const uint32_t d = (k >> a.shift) & (R - 1);
-    const uint32_t dst = glob[d] + (p - loc[d]);
-    a.key_out[dst] = k;
-    a.val_out[dst] = sv[p];
+#pragma unroll
+  for (int c = 0; c < kSortTile / kSortThreads; ++c) {
+    const uint32_t p = c * kSortThreads + threadIdx.x;
+    if (p < tn) {
+      const uint32_t k = sk[p];
+      const uint32_t dst = go[dslot((k >> a.shift) & (R - 1))] + p;
+      a.key_out[dst] = k;
+      a.val_out[dst] = sv[p];
+    }
   }
 }
 
@@ -370,10 +440,20 @@ hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
     const int shift = p * db;
     const int pb = std::min(db, bits - shift);
     RadixArgs a{ki, vi, ko, vo, hist, d_count, (uint32_t)cap, nblocks, shift, pb};
-    k_radix_hist<<<nblocks, 256, 0, s>>>(a);
+    k_radix_hist<<<nblocks, kSortThreads, 0, s>>>(a);
     hipError_t e = launch_scan_u32(hist, hist, nullptr, ((int64_t)1 << pb) * nblocks, scan_part, nullptr, s);
     if (e != hipSuccess) return e;
-    k_radix_scatter<<<nblocks, 256, 0, s>>>(a);
+    switch (pb) {
+      case 1: k_radix_scatter<1><<<nblocks, kSortThreads, 0, s>>>(a); break;
+      case 2: k_radix_scatter<2><<<nblocks, kSortThreads, 0, s>>>(a); break;
+      case 3: k_radix_scatter<3><<<nblocks, kSortThreads, 0, s>>>(a); break;
+      case 4: k_radix_scatter<4><<<nblocks, kSortThreads, 0, s>>>(a); break;
+      case 5: k_radix_scatter<5><<<nblocks, kSortThreads, 0, s>>>(a); break;
+      case 6: k_radix_scatter<6><<<nblocks, kSortThreads, 0, s>>>(a); break;
+      case 7: k_radix_scatter<7><<<nblocks, kSortThreads, 0, s>>>(a); break;
+      case 8: k_radix_scatter<8><<<nblocks, kSortThreads, 0, s>>>(a); break;
+      default: k_radix_scatter<9><<<nblocks, kSortThreads, 0, s>>>(a); break;
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     std::swap(ki, ko);
