@@ -6,7 +6,8 @@
 // also uses, without any per-list sort.  One pass of the sort:
 //   hist:    each block counts the digits of its 8192-element tile (LDS atomics;
 //            counts only, so their order does not matter);
-//   scan:    exclusive scan of the digit-major [digit][block] count matrix;
+//   scan:    exclusive scan of every digit's row of the [digit][block] count
+//            matrix, and the rows' totals (the scatter scans those);
 //   scatter: each block re-reads its tile and gives every element its stable
 //            rank among equal digits: within a wavefront by matching digits
 //            bit by bit with ballots, across the block's eight wavefronts
@@ -156,6 +157,7 @@ struct RadixArgs {
   uint32_t* key_out;
   uint32_t* val_out;
   uint32_t* hist;         // [digits][nblocks]
+  const uint32_t* rowtot; // [digits] row totals of hist
   const uint32_t* count;  // element count (device)
   uint32_t cap;           // element capacity
   int nblocks, shift, bits;
@@ -250,11 +252,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RadixArgs a) {
       val[c] = j < tn ? a.val_in[base + j] : 0u;
     }
   }
-  uint32_t g[kDigPerThread];
+  // the digits' offsets for this tile and row totals wait in the tail of sk
+  // (unused until the ranking) rather than in registers through the counting
+  uint32_t* const sg = sk + kSortTile - 2 * kMaxDigits;
+  uint32_t* const srt = sk + kSortTile - kMaxDigits;
 #pragma unroll
   for (int h = 0; h < kDigPerThread; ++h) {
     const int i = kDigPerThread * threadIdx.x + h;
-    g[h] = i < R ? a.hist[(size_t)i * a.nblocks + tile] : 0u;
+    sg[i] = i < R ? a.hist[(size_t)i * a.nblocks + tile] : 0u;
+    srt[i] = i < R ? a.rowtot[i] : 0u;
   }
   for (int i = threadIdx.x; i < R; i += kSortThreads)
 #pragma unroll
@@ -293,13 +299,21 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RadixArgs a) {
     pk[c / 3] |= (off & 1023u) << (10 * (c % 3));
   }
   __syncthreads();
-  // exclusive scan over digits of the tile's counts: thread t owns digits
-  // kDigPerThread t ...; a shuffle scan within each wavefront, then the totals
-  // of the wavefronts before it
+  // exclusive scans over digits of the tile's counts and of the digits' totals
+  // (thread t owns digits kDigPerThread t ...): a shuffle scan within each
+  // wavefront, then the totals of the wavefronts before it.  A digit's global
+  // start for this tile is the total of the smaller digits plus the digit's
+  // count in the earlier tiles (its row of the count matrix, scanned).
   uint32_t gofs[kDigPerThread];
   {
     uint32_t cw[kDigPerThread][kSortWaves], c[kDigPerThread];
-    uint32_t v = 0u;
+    uint32_t v = 0u, vr = 0u, g[kDigPerThread], rt[kDigPerThread];
+#pragma unroll
+    for (int h = 0; h < kDigPerThread; ++h) {
+      g[h] = sg[kDigPerThread * threadIdx.x + h];
+      rt[h] = srt[kDigPerThread * threadIdx.x + h];
+      vr += rt[h];
+    }
 #pragma unroll
     for (int h = 0; h < kDigPerThread; ++h) {
       const int i = kDigPerThread * threadIdx.x + h;
@@ -311,20 +325,30 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RadixArgs a) {
       }
       v += c[h];
     }
-    uint32_t inc = v;
+    uint32_t inc = v, incr = vr;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t u = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += u;
+      const uint32_t u = __shfl_up(inc, d, 64), ur = __shfl_up(incr, d, 64);
+      if (lane >= d) {
+        inc += u;
+        incr += ur;
+      }
     }
-    if (lane == 63) wtot[wave] = inc;
+    if (lane == 63) {
+      wtot[wave] = inc;
+      wtot[kSortWaves + wave] = incr;
+    }
     __syncthreads();
-    uint32_t p = inc - v;
-    for (int w = 0; w < wave; ++w) p += wtot[w];
+    uint32_t p = inc - v, pr = incr - vr;
+    for (int w = 0; w < wave; ++w) {
+      p += wtot[w];
+      pr += wtot[kSortWaves + w];
+    }
 #pragma unroll
     for (int h = 0; h < kDigPerThread; ++h) {
       const int i = kDigPerThread * threadIdx.x + h;
-      gofs[h] = g[h] - p;
+      gofs[h] = g[h] + pr - p;
+      pr += rt[h];
       if (i < R) {
         uint32_t q = p;
 #pragma unroll
@@ -369,6 +393,63 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RadixArgs a) {
       a.val_out[dst] = sv[p];
     }
   }
+}
+
+// Exclusive scan of every digit's row of the [digit][block] count matrix, in
+// place, and the row's total (one block per digit).  The scatter adds the
+// totals of the smaller digits itself.  The row passes through LDS in chunks
+// of 4096 entries (unrolled, coalesced loads and stores); thread t scans
+// entries 16 t .. 16 t + 15 of a chunk.
+__global__ __launch_bounds__(256) void k_hist_rowscan(uint32_t* __restrict__ hist, int nblocks,
+                                                      uint32_t* __restrict__ rowtot) {
+  constexpr int kChunk = 4096, kPer = kChunk / 256;
+  __shared__ uint32_t buf[kChunk];
+  __shared__ uint32_t wsum[4];
+  uint32_t* row = hist + (size_t)blockIdx.x * nblocks;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t carry = 0u;
+  for (int c0 = 0; c0 < nblocks; c0 += kChunk) {
+    const int m = min(kChunk, nblocks - c0);
+    uint32_t ld[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int jj = k * 256 + (int)threadIdx.x;
+      ld[k] = jj < m ? row[c0 + jj] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) buf[k * 256 + threadIdx.x] = ld[k];
+    __syncthreads();
+    uint32_t v[kPer], sum = 0u;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      v[k] = buf[kPer * threadIdx.x + k];
+      sum += v[k];
+    }
+    uint32_t inc = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t u = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += u;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t run = carry + inc - sum;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      buf[kPer * threadIdx.x + k] = run;
+      run += v[k];
+    }
+    carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int jj = k * 256 + (int)threadIdx.x;
+      if (jj < m) row[c0 + jj] = buf[jj];
+    }
+    __syncthreads();   // buf and wsum are rewritten by the next chunk
+  }
+  if (threadIdx.x == 0) rowtot[blockIdx.x] = carry;
 }
 
 // Bin ranges from the sorted keys: [lo, hi) of every non-empty bin (the reset
@@ -420,7 +501,7 @@ int64_t radix_hist_entries(int bits, int64_t cap) {
   const int passes = radix_passes(bits);
   if (passes == 0) return 1;
   const int db = (bits + passes - 1) / passes;
-  return ((int64_t)1 << db) * ((cap + kSortTile - 1) / kSortTile);
+  return ((int64_t)1 << db) * ((cap + kSortTile - 1) / kSortTile) + kMaxDigits;   // matrix, row totals
 }
 
 // Stable sort of `count` (device) pairs by the low `bits` bits of the key.
@@ -439,10 +520,10 @@ hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
   for (int p = 0; p < passes; ++p) {
     const int shift = p * db;
     const int pb = std::min(db, bits - shift);
-    RadixArgs a{ki, vi, ko, vo, hist, d_count, (uint32_t)cap, nblocks, shift, pb};
+    uint32_t* rowtot = hist + ((size_t)1 << db) * nblocks;
+    RadixArgs a{ki, vi, ko, vo, hist, rowtot, d_count, (uint32_t)cap, nblocks, shift, pb};
     k_radix_hist<<<nblocks, kSortThreads, 0, s>>>(a);
-    hipError_t e = launch_scan_u32(hist, hist, nullptr, ((int64_t)1 << pb) * nblocks, scan_part, nullptr, s);
-    if (e != hipSuccess) return e;
+    k_hist_rowscan<<<1 << pb, 256, 0, s>>>(hist, nblocks, rowtot);
     switch (pb) {
       case 1: k_radix_scatter<1><<<nblocks, kSortThreads, 0, s>>>(a); break;
       case 2: k_radix_scatter<2><<<nblocks, kSortThreads, 0, s>>>(a); break;
@@ -454,7 +535,7 @@ hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
       case 8: k_radix_scatter<8><<<nblocks, kSortThreads, 0, s>>>(a); break;
       default: k_radix_scatter<9><<<nblocks, kSortThreads, 0, s>>>(a); break;
     }
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     std::swap(ki, ko);
     std::swap(vi, vo);
