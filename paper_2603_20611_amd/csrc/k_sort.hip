@@ -31,6 +31,10 @@ __device__ __forceinline__ uint2 add2(uint2 a, uint2 b) { return make_uint2(a.x 
 __device__ __forceinline__ uint32_t add2(uint32_t a, uint32_t b) { return a + b; }
 __device__ __forceinline__ uint2 sub2(uint2 a, uint2 b) { return make_uint2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ uint32_t sub2(uint32_t a, uint32_t b) { return a - b; }
+__device__ __forceinline__ uint2 shfl_up2(uint2 v, int d) {
+  return make_uint2(__shfl_up(v.x, d, 64), __shfl_up(v.y, d, 64));
+}
+__device__ __forceinline__ uint32_t shfl_up2(uint32_t v, int d) { return __shfl_up(v, d, 64); }
 
 // Block-wide inclusive scan of one value per thread (256 threads).
 template <typename T>
@@ -84,8 +88,8 @@ __global__ __launch_bounds__(256) void k_scan_parts(T* __restrict__ part, int np
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_scan_down(const T* __restrict__ in, const int32_t* __restrict__ n_ptr,
-                                                   int64_t n_fixed, const T* __restrict__ part, T* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_scan_down(const T* in, const int32_t* __restrict__ n_ptr, int64_t n_fixed,
+                                                   const T* __restrict__ part, T* out) {
   __shared__ T sh[256];
   const int64_t n = n_ptr ? *n_ptr : n_fixed;
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -105,15 +109,59 @@ __global__ __launch_bounds__(256) void k_scan_down(const T* __restrict__ in, con
   }
 }
 
+// Exclusive scan of up to kSmallScan values by one block: thread t takes 8
+// consecutive values (one 64-byte run, so each wavefront's loads are
+// contiguous), then a shuffle scan per wavefront and the wavefront totals.
+// in and out may be the same array: every value is read before the barrier.
+constexpr int kSmallScan = 8192;
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_single(const T* in, const int32_t* __restrict__ n_ptr, int64_t n_fixed,
+                                                      T* out, T* __restrict__ total) {
+  constexpr int kPer = kSmallScan / 1024;
+  __shared__ T wsum[16];
+  const int64_t n = n_ptr ? *n_ptr : n_fixed;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j0 = (int64_t)threadIdx.x * kPer;
+  T v[kPer];
+  T sum = zero_of<T>();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    v[k] = j0 + k < n ? in[j0 + k] : zero_of<T>();
+    sum = add2(sum, v[k]);
+  }
+  T inc = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T u = shfl_up2(inc, d);
+    if (lane >= d) inc = add2(inc, u);
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  T run = sub2(inc, sum);
+  for (int w = 0; w < wave; ++w) run = add2(run, wsum[w]);
+  if (threadIdx.x == 1023 && total) *total = add2(run, sum);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (j0 + k < n) out[j0 + k] = run;
+    run = add2(run, v[k]);
+  }
+}
+
 }  // namespace
 
 // Exclusive scan of n values (n on the host, or *d_n on the device when given;
-// the launch covers max_n).  part must hold ceil(max_n / 2048) values.
+// the launch covers max_n).  part must hold ceil(max_n / 2048) values (unused
+// when max_n fits one block).
 template <typename T>
 static hipError_t scan_impl(const T* in, T* out, const int32_t* d_n, int64_t max_n, T* part, T* total,
                             hipStream_t s) {
   const int64_t nb = (max_n + kScanTile - 1) / kScanTile;
   if (nb <= 0) return hipSuccess;
+  if (max_n <= kSmallScan) {
+    k_scan_single<T><<<1, 1024, 0, s>>>(in, d_n, max_n, out, total);
+    return hipGetLastError();
+  }
   k_scan_reduce<T><<<(unsigned)nb, 256, 0, s>>>(in, d_n, max_n, part);
   k_scan_parts<T><<<1, 256, 0, s>>>(part, (int)nb, total);
   k_scan_down<T><<<(unsigned)nb, 256, 0, s>>>(in, d_n, max_n, part, out);
@@ -169,7 +217,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(RadixArgs a) {
   for (int i = threadIdx.x; i < R; i += kSortThreads) h[i] = 0u;
   __syncthreads();
   const uint32_t n = min(*a.count, a.cap);
-  const uint32_t tile = blockIdx.x;
+  // consecutive tiles on one XCD (workgroups go to the eight XCDs in turn):
+  // their counts share cache lines of the [digit][tile] matrix, which then
+  // merge in that XCD's L2 instead of being written partially by eight
+  const uint32_t per = (a.nblocks + 7) / 8;
+  const uint32_t tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= (uint32_t)a.nblocks) return;
   const uint32_t base = tile * kSortTile;
   // all loads first (independent, in flight together), then the counting
   constexpr int kPer = kSortTile / kSortThreads;
@@ -522,7 +575,7 @@ hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
     const int pb = std::min(db, bits - shift);
     uint32_t* rowtot = hist + ((size_t)1 << db) * nblocks;
     RadixArgs a{ki, vi, ko, vo, hist, rowtot, d_count, (uint32_t)cap, nblocks, shift, pb};
-    k_radix_hist<<<nblocks, kSortThreads, 0, s>>>(a);
+    k_radix_hist<<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a);
     k_hist_rowscan<<<1 << pb, 256, 0, s>>>(hist, nblocks, rowtot);
     switch (pb) {
       case 1: k_radix_scatter<1><<<nblocks, kSortThreads, 0, s>>>(a); break;
