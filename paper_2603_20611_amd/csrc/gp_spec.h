@@ -154,24 +154,41 @@ struct SpecRect {
   int tx0, tx1, ty0, ty1;
 };
 
-__device__ __forceinline__ bool spec_rect(const SpecCov& c, float mux, float muy, const SpecAxial& ax,
-                                          float x0, float y0, float dx, float dy, int ntx, int nty,
-                                          float bbox, SpecRect& r) {
+// The part of the footprint that depends on the slice only through sigma_z
+// (through s2 and D): equal for every slice of one sigma_z, so a loop over
+// slices may reuse it (the same operations on the same operands).
+struct SpecSigma {
+  float invD, w, A, C, u, v, rx, ry;
+};
+__device__ __forceinline__ SpecSigma spec_sigma(const SpecCov& c, const SpecAxial& ax, float bbox) {
 #pragma clang fp contract(off)
-  r.invD = 1.0f / ax.D;
-  r.w = 1.0f / (1.0f + c.szz / ax.s2);
-  r.A = r.w * c.sxx + c.a11 * r.invD;
-  r.C = r.w * c.syy + c.a00 * r.invD;
-  r.u = c.sxz * r.invD;
-  r.v = c.syz * r.invD;
+  SpecSigma g;
+  g.invD = 1.0f / ax.D;
+  g.w = 1.0f / (1.0f + c.szz / ax.s2);
+  g.A = g.w * c.sxx + c.a11 * g.invD;
+  g.C = g.w * c.syy + c.a00 * g.invD;
+  g.u = c.sxz * g.invD;
+  g.v = c.syz * g.invD;
+  g.rx = bbox * sqrtf(g.A);
+  g.ry = bbox * sqrtf(g.C);
+  return g;
+}
+__device__ __forceinline__ bool spec_rect_from(const SpecSigma& g, float mux, float muy, const SpecAxial& ax,
+                                               float x0, float y0, float dx, float dy, int ntx, int nty,
+                                               SpecRect& r) {
+#pragma clang fp contract(off)
+  r.invD = g.invD;
+  r.w = g.w;
+  r.A = g.A;
+  r.C = g.C;
+  r.u = g.u;
+  r.v = g.v;
   r.mx = mux - r.u * ax.m;
   r.my = muy - r.v * ax.m;
-  const float rx = bbox * sqrtf(r.A);
-  const float ry = bbox * sqrtf(r.C);
-  const float xl = floorf((((r.mx - rx) - x0) / dx) * 0.0625f);
-  const float xh = floorf((((r.mx + rx) - x0) / dx) * 0.0625f);
-  const float yl = floorf((((r.my - ry) - y0) / dy) * 0.0625f);
-  const float yh = floorf((((r.my + ry) - y0) / dy) * 0.0625f);
+  const float xl = floorf((((r.mx - g.rx) - x0) / dx) * 0.0625f);
+  const float xh = floorf((((r.mx + g.rx) - x0) / dx) * 0.0625f);
+  const float yl = floorf((((r.my - g.ry) - y0) / dy) * 0.0625f);
+  const float yh = floorf((((r.my + g.ry) - y0) / dy) * 0.0625f);
   const float fx = (float)(ntx - 1), fy = (float)(nty - 1);
   const bool vis = (xh >= 0.0f) && (xl <= fx) && (yh >= 0.0f) && (yl <= fy);
   if (!vis) return false;
@@ -180,6 +197,11 @@ __device__ __forceinline__ bool spec_rect(const SpecCov& c, float mux, float muy
   r.ty0 = (int)fmaxf(yl, 0.0f);
   r.ty1 = (int)fminf(yh, fy);
   return true;
+}
+__device__ __forceinline__ bool spec_rect(const SpecCov& c, float mux, float muy, const SpecAxial& ax,
+                                          float x0, float y0, float dx, float dy, int ntx, int nty,
+                                          float bbox, SpecRect& r) {
+  return spec_rect_from(spec_sigma(c, ax, bbox), mux, muy, ax, x0, y0, dx, dy, ntx, nty, r);
 }
 
 }  // namespace gp

@@ -181,6 +181,30 @@ __device__ __forceinline__ bool footprint(const PreArgs& a, const SpecCov& cv, c
   return vis;
 }
 
+// footprint() of an axial slice (the world-frame covariance c for every
+// slice) with the sigma_z part reused from the previous slice of the same
+// sigma_z (g, valid for the bits `key` of sigma_z^2 once `have`).
+__device__ __forceinline__ bool footprint_axial(const PreArgs& a, const SpecCov& c, const float* mv, int k,
+                                                SpecAxial& ax, SpecRect& rect, SpecSigma& g, uint32_t& key,
+                                                bool& have) {
+  const SliceDev& sl = a.slices[k];
+  const bool exact = (a.rc.flags & GP_FLAG_EXACT) != 0;
+  ax = spec_axial(mv[2], c.szz, sl.z, sl.sigma_z);
+  if (!exact && !(ax.q <= a.rc.q_cut)) return false;
+  const uint32_t kb = __float_as_uint(ax.s2);
+  if (!have || kb != key) {
+    g = spec_sigma(c, ax, a.rc.bbox);
+    key = kb;
+    have = true;
+  }
+  const bool vis = spec_rect_from(g, mv[0], mv[1], ax, sl.x0, sl.y0, sl.dx, sl.dy, sl.ntx, sl.nty, rect);
+  if (exact) {
+    rect.tx0 = 0; rect.tx1 = sl.ntx - 1; rect.ty0 = 0; rect.ty1 = sl.nty - 1;
+    return true;
+  }
+  return vis;
+}
+
 // Conservative axial pre-test on the raw parameters: true only if no slice of
 // the group can keep the Gaussian.  Sigma_zz <= max_i s_i^2, so with d the
 // distance of mu_z from the group's depth range, d^2 > q_cut (sigma_z,max^2 +
@@ -210,16 +234,21 @@ __device__ __forceinline__ void count_one(const PreArgs& a, int n_groups, int t)
     kept_range(a, L.G, L.p[2], L.c.szz, &kb, &ke);
   }
   uint32_t nrec = 0, ninst = 0;
+  SpecSigma sg;
+  uint32_t sg_key = 0u;
+  bool sg_have = false;
   for (int k = kb; k < ke; ++k) {
     SpecAxial ax;
     SpecRect rect;
-    // the Gaussian in the slice's camera frame (the world frame for axial batches)
-    SpecCov cv;
-    float mv[3];
-    if (POSED) spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
-    const SpecCov& cr = POSED ? cv : L.c;
-    const float* mr = POSED ? mv : L.p;
-    if (!footprint(a, cr, mr, k, ax, rect)) continue;
+    if (POSED) {
+      // the Gaussian in the slice's camera frame
+      SpecCov cv;
+      float mv[3];
+      spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
+      if (!footprint(a, cv, mv, k, ax, rect)) continue;
+    } else if (!footprint_axial(a, L.c, L.p, k, ax, rect, sg, sg_key, sg_have)) {
+      continue;
+    }
     nrec += 1u;
     ninst += (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
   }
