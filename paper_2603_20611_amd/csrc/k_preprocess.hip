@@ -71,37 +71,42 @@ struct PreArgs {
   int emit_chunk;       // Gaussians per workgroup round of the emit
 };
 
-__device__ __forceinline__ bool kept_on(const PreArgs& a, float muz, float szz, int k) {
-  const SpecAxial ax = spec_axial(muz, szz, a.slices[k].z, a.slices[k].sigma_z);
+// (z, sigma_z) of slice k: from the workgroup's LDS copy when there is one
+__device__ __forceinline__ float2 slice_zs(const PreArgs& a, const float2* zs, int k) {
+  return zs ? zs[k] : make_float2(a.slices[k].z, a.slices[k].sigma_z);
+}
+__device__ __forceinline__ bool kept_on(const PreArgs& a, const float2* zs, float muz, float szz, int k) {
+  const float2 v = slice_zs(a, zs, k);
+  const SpecAxial ax = spec_axial(muz, szz, v.x, v.y);
   return ax.q <= a.rc.q_cut;
 }
 
 // Kept slices [*kb, *ke) of a Gaussian in a z-sorted, single-sigma_z group.
-__device__ __forceinline__ void kept_range(const PreArgs& a, const GroupDev& G, float muz, float szz, int* kb,
-                                           int* ke) {
+__device__ __forceinline__ void kept_range(const PreArgs& a, const float2* zs, const GroupDev& G, float muz,
+                                           float szz, int* kb, int* ke) {
   // last slice with z <= mu_z (or k0 - 1)
   int lo = G.k0, hi = G.k1 - 1, ks = G.k0 - 1;
   while (lo <= hi) {
     const int mid = (lo + hi) >> 1;
-    if (a.slices[mid].z <= muz) { ks = mid; lo = mid + 1; } else { hi = mid - 1; }
+    if (slice_zs(a, zs, mid).x <= muz) { ks = mid; lo = mid + 1; } else { hi = mid - 1; }
   }
   // the smallest q is at ks or ks + 1
   int kmin = -1;
-  if (ks >= G.k0 && kept_on(a, muz, szz, ks)) kmin = ks;
-  else if (ks + 1 < G.k1 && kept_on(a, muz, szz, ks + 1)) kmin = ks + 1;
+  if (ks >= G.k0 && kept_on(a, zs, muz, szz, ks)) kmin = ks;
+  else if (ks + 1 < G.k1 && kept_on(a, zs, muz, szz, ks + 1)) kmin = ks + 1;
   if (kmin < 0) { *kb = *ke = G.k0; return; }
   // first kept slice in [k0, kmin] (q non-increasing there)
   lo = G.k0; hi = kmin;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (kept_on(a, muz, szz, mid)) hi = mid; else lo = mid + 1;
+    if (kept_on(a, zs, muz, szz, mid)) hi = mid; else lo = mid + 1;
   }
   *kb = lo;
   // last kept slice in [kmin, k1) (q non-decreasing there)
   lo = kmin; hi = G.k1 - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (kept_on(a, muz, szz, mid)) lo = mid; else hi = mid - 1;
+    if (kept_on(a, zs, muz, szz, mid)) lo = mid; else hi = mid - 1;
   }
   *ke = lo + 1;
 }
@@ -181,13 +186,21 @@ __device__ __forceinline__ bool footprint(const PreArgs& a, const SpecCov& cv, c
   return vis;
 }
 
+// The slice fields the footprint reads, loaded into registers.
+struct SliceGeo {
+  float z, sigma_z, x0, y0, dx, dy;
+  int32_t ntx, nty;
+};
+__device__ __forceinline__ SliceGeo slice_geo(const SliceDev& sl) {
+  return SliceGeo{sl.z, sl.sigma_z, sl.x0, sl.y0, sl.dx, sl.dy, sl.ntx, sl.nty};
+}
+
 // footprint() of an axial slice (the world-frame covariance c for every
 // slice) with the sigma_z part reused from the previous slice of the same
 // sigma_z (g, valid for the bits `key` of sigma_z^2 once `have`).
-__device__ __forceinline__ bool footprint_axial(const PreArgs& a, const SpecCov& c, const float* mv, int k,
-                                                SpecAxial& ax, SpecRect& rect, SpecSigma& g, uint32_t& key,
-                                                bool& have) {
-  const SliceDev& sl = a.slices[k];
+__device__ __forceinline__ bool footprint_axial(const PreArgs& a, const SpecCov& c, const float* mv,
+                                                const SliceGeo& sl, SpecAxial& ax, SpecRect& rect, SpecSigma& g,
+                                                uint32_t& key, bool& have) {
   const bool exact = (a.rc.flags & GP_FLAG_EXACT) != 0;
   ax = spec_axial(mv[2], c.szz, sl.z, sl.sigma_z);
   if (!exact && !(ax.q <= a.rc.q_cut)) return false;
@@ -221,7 +234,7 @@ __device__ __forceinline__ bool far_from_group(const PreArgs& a, const GroupDev&
 }
 
 template <int DT, bool POSED>
-__device__ __forceinline__ void count_one(const PreArgs& a, int n_groups, int t) {
+__device__ __forceinline__ void count_one(const PreArgs& a, const float2* zs, int n_groups, int t) {
   Loaded L;
   load_params<DT>(a, n_groups, t, L);
   // the world-depth shortcuts hold for axial slices only
@@ -231,26 +244,39 @@ __device__ __forceinline__ void count_one(const PreArgs& a, int n_groups, int t)
   if (!L.ok) {
     ke = kb;
   } else if (!POSED && !(a.rc.flags & GP_FLAG_EXACT) && (L.G.flags & kGroupSortedZ)) {
-    kept_range(a, L.G, L.p[2], L.c.szz, &kb, &ke);
+    kept_range(a, zs, L.G, L.p[2], L.c.szz, &kb, &ke);
   }
   uint32_t nrec = 0, ninst = 0;
-  SpecSigma sg;
-  uint32_t sg_key = 0u;
-  bool sg_have = false;
-  for (int k = kb; k < ke; ++k) {
-    SpecAxial ax;
-    SpecRect rect;
-    if (POSED) {
+  if constexpr (POSED) {
+    for (int k = kb; k < ke; ++k) {
       // the Gaussian in the slice's camera frame
+      SpecAxial ax;
+      SpecRect rect;
       SpecCov cv;
       float mv[3];
       spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
       if (!footprint(a, cv, mv, k, ax, rect)) continue;
-    } else if (!footprint_axial(a, L.c, L.p, k, ax, rect, sg, sg_key, sg_have)) {
-      continue;
+      nrec += 1u;
+      ninst += (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
     }
-    nrec += 1u;
-    ninst += (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
+  } else {
+    // the next slice's fields are in flight while this slice is tested
+    SpecSigma sg;
+    uint32_t sg_key = 0u;
+    bool sg_have = false;
+    SliceGeo cur{};
+    if (kb < ke) cur = slice_geo(a.slices[kb]);
+    for (int k = kb; k < ke; ++k) {
+      SliceGeo nxt = cur;
+      if (k + 1 < ke) nxt = slice_geo(a.slices[k + 1]);
+      SpecAxial ax;
+      SpecRect rect;
+      if (footprint_axial(a, L.c, L.p, cur, ax, rect, sg, sg_key, sg_have)) {
+        nrec += 1u;
+        ninst += (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
+      }
+      cur = nxt;
+    }
   }
   a.g_nrec[t] = nrec;
   a.g_ninst[t] = ninst;
@@ -493,13 +519,26 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
 
 // Grid-stride over whole wavefronts of flattened Gaussians, so that a launch
 // sized for the workspace capacity serves any batch (sizes from the header).
+// The binary searches over slice depths read (z, sigma_z) from an LDS copy
+// when the batch has at most kZsLds slices (a chain of dependent loads that
+// otherwise goes to the cache hierarchy at every step).
+constexpr int kZsLds = 2048;
+
 template <int DT, bool POSED>
 __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
+  __shared__ float2 zs_lds[POSED ? 1 : kZsLds];
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
+  const int n_slices = a.hdr->n_slices;
+  const float2* zs = nullptr;
+  if (!POSED && n_slices <= kZsLds) {
+    for (int i = threadIdx.x; i < n_slices; i += 256) zs_lds[i] = make_float2(a.slices[i].z, a.slices[i].sigma_z);
+    __syncthreads();
+    zs = zs_lds;
+  }
   const int stride = gridDim.x * 256;
   for (int t = blockIdx.x * 256 + threadIdx.x; (t & ~63) < total; t += stride)
-    count_one<DT, POSED>(a, n_groups, t);
+    count_one<DT, POSED>(a, zs, n_groups, t);
 }
 
 // A workgroup takes `chunk` consecutive Gaussians at a time (a multiple of 256,
