@@ -426,9 +426,15 @@ __device__ __forceinline__ void slots_wave(const PreArgs& a, int t0, int* list, 
 // partly written lines.)  W = 1 is the one-lane form, used when each Gaussian
 // has at most one slice.  Each lane first computes the float64 covariance of
 // its own entry's Gaussian into LDS, once for all of its records.
+// What the emit of an axial batch needs of an activated Gaussian: the mean,
+// the intensity and the covariance terms of the footprint and the record.
+struct EmitGauss {
+  float mx, my, mz, inten, s0, s1, s2, sxx, syy, szz, sxz, syz, a00, a11;
+};
+
 template <int DT, int W, bool POSED>
 __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const int* list, uint32_t j0,
-                                          uint32_t n_active, double (*cov64)[6]) {
+                                          uint32_t n_active, double (*cov64)[6], EmitGauss* eg) {
   const int lane = threadIdx.x & 63;
   const uint32_t j = j0 + (uint32_t)lane;
   const int t = j < n_active ? list[j] : 0;
@@ -440,6 +446,12 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
     Loaded Lq;
     load_params<DT>(a, n_groups, t, Lq);
     cov_f64(Lq.p, a.rc.scale_mod, cov64[lane]);
+    if (!POSED) {
+      activate(a, Lq);
+      const SpecCov& c = Lq.c;
+      eg[lane] = EmitGauss{Lq.p[0], Lq.p[1], Lq.p[2], Lq.p[10], c.s0, c.s1, c.s2, c.sxx, c.syy, c.szz,
+                           c.sxz, c.syz, c.a00, c.a11};
+    }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -455,8 +467,31 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
     const uint32_t g_kr = __shfl(krange, gi, 64);
     if (j0 + (uint32_t)gi >= n_active) continue;
     Loaded L;
-    load_params<DT>(a, n_groups, tg, L);
-    activate(a, L);
+    if constexpr (POSED) {
+      load_params<DT>(a, n_groups, tg, L);
+      activate(a, L);
+    } else {
+      // the group's Gaussian as its entry's lane activated it (the same values)
+      (void)tg;
+      const EmitGauss e = eg[gi];
+#pragma unroll
+      for (int r = 0; r < 11; ++r) L.p[r] = 0.0f;
+      L.p[0] = e.mx;
+      L.p[1] = e.my;
+      L.p[2] = e.mz;
+      L.p[10] = e.inten;
+      L.c = SpecCov{};
+      L.c.s0 = e.s0;
+      L.c.s1 = e.s1;
+      L.c.s2 = e.s2;
+      L.c.sxx = e.sxx;
+      L.c.syy = e.syy;
+      L.c.szz = e.szz;
+      L.c.sxz = e.sxz;
+      L.c.syz = e.syz;
+      L.c.a00 = e.a00;
+      L.c.a11 = e.a11;
+    }
     const int kb = (int)(g_kr & 0xFFFFu), ke = (int)(g_kr >> 16);
     uint32_t rec_run = g_rb, inst_run = g_ib;
     for (int c0 = kb; c0 < ke; c0 += W) {
@@ -554,6 +589,7 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   __shared__ int list[kEmitChunk];
   __shared__ int n_list;
   __shared__ double cov64[4][64][6];
+  __shared__ EmitGauss egs[4][POSED ? 1 : 64];
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   const int wave = threadIdx.x >> 6;
@@ -573,7 +609,7 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane(n_w[wave]);
-      if (n > 0u) emit_wave<DT, W, POSED>(a, n_groups, wl, 0u, n, cov64[wave]);
+      if (n > 0u) emit_wave<DT, W, POSED>(a, n_groups, wl, 0u, n, cov64[wave], egs[wave]);
     }
     return;
   }
@@ -584,7 +620,7 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
     __syncthreads();
     const uint32_t n = (uint32_t)n_list;
     for (uint32_t j0 = (uint32_t)wave * 64u; j0 < n; j0 += 256u)
-      emit_wave<DT, W, POSED>(a, n_groups, list, j0, n, cov64[wave]);
+      emit_wave<DT, W, POSED>(a, n_groups, list, j0, n, cov64[wave], egs[wave]);
     __syncthreads();   // list and n_list are rewritten by the next chunk
   }
 }
