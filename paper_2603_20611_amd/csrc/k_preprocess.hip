@@ -427,10 +427,38 @@ __device__ __forceinline__ void slots_wave(const PreArgs& a, int t0, int* list, 
 // has at most one slice.  Each lane first computes the float64 covariance of
 // its own entry's Gaussian into LDS, once for all of its records.
 // What the emit of an axial batch needs of an activated Gaussian: the mean,
-// the intensity and the covariance terms of the footprint and the record.
+// the intensity, the scales and Sigma_zz, and the sigma_z part of its
+// footprint for the sigma_z of its first kept slice (key: the bits of that
+// sigma_z^2).
 struct EmitGauss {
-  float mx, my, mz, inten, s0, s1, s2, sxx, syy, szz, sxz, syz, a00, a11;
+  float mx, my, mz, inten, s0, s1, s2, szz;
+  uint32_t key;
+  SpecSigma g;
 };
+
+// footprint() of an axial slice for the emit: the stored sigma_z part when the
+// slice's sigma_z^2 is the key's, else computed from the reloaded Gaussian t.
+template <int DT>
+__device__ __forceinline__ bool footprint_emit(const PreArgs& a, int n_groups, int t, const EmitGauss& e, int k,
+                                               SpecAxial& ax, SpecRect& rect) {
+  const SliceDev& sl = a.slices[k];
+  const bool exact = (a.rc.flags & GP_FLAG_EXACT) != 0;
+  ax = spec_axial(e.mz, e.szz, sl.z, sl.sigma_z);
+  if (!exact && !(ax.q <= a.rc.q_cut)) return false;
+  SpecSigma g = e.g;
+  if (__float_as_uint(ax.s2) != e.key) {
+    Loaded L;
+    load_params<DT>(a, n_groups, t, L);
+    activate(a, L);
+    g = spec_sigma(L.c, ax, a.rc.bbox);
+  }
+  const bool vis = spec_rect_from(g, e.mx, e.my, ax, sl.x0, sl.y0, sl.dx, sl.dy, sl.ntx, sl.nty, rect);
+  if (exact) {
+    rect.tx0 = 0; rect.tx1 = sl.ntx - 1; rect.ty0 = 0; rect.ty1 = sl.nty - 1;
+    return true;
+  }
+  return vis;
+}
 
 template <int DT, int W, bool POSED>
 __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const int* list, uint32_t j0,
@@ -449,8 +477,10 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
     if (!POSED) {
       activate(a, Lq);
       const SpecCov& c = Lq.c;
-      eg[lane] = EmitGauss{Lq.p[0], Lq.p[1], Lq.p[2], Lq.p[10], c.s0, c.s1, c.s2, c.sxx, c.syy, c.szz,
-                           c.sxz, c.syz, c.a00, c.a11};
+      const SliceDev& s0 = a.slices[krange & 0xFFFFu];   // the first kept slice
+      const SpecAxial ax0 = spec_axial(Lq.p[2], c.szz, s0.z, s0.sigma_z);
+      eg[lane] = EmitGauss{Lq.p[0], Lq.p[1], Lq.p[2], Lq.p[10], c.s0, c.s1, c.s2, c.szz,
+                           __float_as_uint(ax0.s2), spec_sigma(c, ax0, a.rc.bbox)};
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -467,13 +497,13 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
     const uint32_t g_kr = __shfl(krange, gi, 64);
     if (j0 + (uint32_t)gi >= n_active) continue;
     Loaded L;
+    EmitGauss e{};
     if constexpr (POSED) {
       load_params<DT>(a, n_groups, tg, L);
       activate(a, L);
     } else {
       // the group's Gaussian as its entry's lane activated it (the same values)
-      (void)tg;
-      const EmitGauss e = eg[gi];
+      e = eg[gi];
 #pragma unroll
       for (int r = 0; r < 11; ++r) L.p[r] = 0.0f;
       L.p[0] = e.mx;
@@ -484,13 +514,7 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
       L.c.s0 = e.s0;
       L.c.s1 = e.s1;
       L.c.s2 = e.s2;
-      L.c.sxx = e.sxx;
-      L.c.syy = e.syy;
       L.c.szz = e.szz;
-      L.c.sxz = e.sxz;
-      L.c.syz = e.syz;
-      L.c.a00 = e.a00;
-      L.c.a11 = e.a11;
     }
     const int kb = (int)(g_kr & 0xFFFFu), ke = (int)(g_kr >> 16);
     uint32_t rec_run = g_rb, inst_run = g_ib;
@@ -500,10 +524,15 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
       SpecRect rect;
       SpecCov cv;
       float mv[3];
-      if (POSED && k < ke) spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
-      const SpecCov& cr = POSED ? cv : L.c;
-      const float* mr = POSED ? mv : L.p;
-      const bool kept = k < ke && footprint(a, cr, mr, k, ax, rect);
+      bool kept = false;
+      if constexpr (POSED) {
+        if (k < ke) {
+          spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
+          kept = footprint(a, cv, mv, k, ax, rect);
+        }
+      } else {
+        kept = k < ke && footprint_emit<DT>(a, n_groups, tg, e, k, ax, rect);
+      }
       const uint32_t nt = kept ? (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1)) : 0u;
       uint32_t rpos = 0u, ipos = 0u, rtot = 1u, itot = nt;
       if (W > 1) {
