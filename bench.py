@@ -192,6 +192,57 @@ def voxel_leg(params, dev, steps=10):
             "backward_ms": round(1e3 * t_b, 4)}
 
 
+def extras_leg(params, slices, dev, steps=5):
+    """The rows the forward line does not time, on the same 500k Gaussians: the
+    codec (encoding the set, and the 400-slice stack rendered from the coded
+    set), an oblique batch (64 slices of 256 x 256 tilted by 30 degrees about x
+    through the volume's centre, 1 apart along their normal) and one densify /
+    prune pass over the whole set with synthetic statistics."""
+    import torch
+    from paper_2603_20611_amd import render
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    n = params.shape[1]
+    res = {}
+    hold = {}
+    t_enc = timed(lambda: hold.__setitem__("c", render.encode(params)))
+    codes, header, _ = hold["c"]
+    ws = render.Workspace()
+    img = torch.empty(len(slices) * RES * RES, device=dev)
+    t_qm = timed(lambda: render.render_coded(codes, header, n, slices, ws=ws, out=img))
+    res["codec"] = {"encode_ms": round(1e3 * t_enc, 4), "coded_forward_ms": round(1e3 * t_qm, 4),
+                    "coded_mpix_per_s": round(len(slices) * RES * RES / t_qm / 1e6, 1), "bytes_per_gaussian": 22}
+    c, s_ = np.cos(np.radians(30.0)), np.sin(np.radians(30.0))
+    R = np.array([[1.0, 0.0, 0.0], [0.0, c, -s_], [0.0, s_, c]])
+    centre = np.array([RES / 2.0, RES / 2.0, N_SLICES / 2.0])
+    pose = np.concatenate([R.reshape(-1), -R @ centre]).astype(np.float32)
+    obl = [dict(z=float(k) + 0.5, sigma_z=SIGMA_Z, x0=-RES / 2.0, y0=-RES / 2.0, dx=1.0, dy=1.0, width=RES,
+                height=RES, pose=pose) for k in range(-32, 32)]
+    ws_o = render.Workspace()
+    img_o = torch.empty(len(obl) * RES * RES, device=dev)
+    t_ob = timed(lambda: render.render(params, obl, ws=ws_o, out=img_o))
+    res["oblique"] = {"slices": len(obl), "tilt_deg": 30.0, "forward_ms": round(1e3 * t_ob, 4),
+                      "mpix_per_s": round(len(obl) * RES * RES / t_ob / 1e6, 1)}
+    rng = np.random.default_rng(11)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    cnt = torch.from_numpy(rng.integers(0, 12, n).astype(np.int32)).to(dev)
+    gn = torch.from_numpy((np.where(rng.uniform(size=n) < 0.1, 2e-4, 1e-5) * cnt.cpu().numpy()).astype(np.float32)).to(dev)
+    rad = torch.from_numpy(rng.uniform(0.5, 30.0, n).astype(np.float32)).to(dev)
+    noise = torch.from_numpy(rng.normal(size=(6, n)).astype(np.float32)).to(dev)
+    t_dp = timed(lambda: hold.__setitem__("d", render.densify_prune(params, m, v, gn, cnt, rad, noise)))
+    res["densify_prune"] = {"gaussians_in": n, "gaussians_out": int(hold["d"][3]), "ms": round(1e3 * t_dp, 4)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,6 +396,9 @@ def main():
     log("voxeliser")
     result["voxelize"] = voxel_leg(params, dev)
     log(f"voxelize: {result['voxelize']}")
+    log("codec, oblique batch, densify / prune")
+    result.update(extras_leg(params, slices, dev))
+    log(f"codec: {result['codec']}; oblique: {result['oblique']}; densify_prune: {result['densify_prune']}")
     if not args.no_serving:
         result["serving"] = serving_leg(dev, args.serving_requests)
     if not args.no_cpu:
