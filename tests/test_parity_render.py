@@ -149,6 +149,49 @@ def test_forward_work_schedules(gp, case):
     assert err <= FWD_TOL
 
 
+def test_full_size_sampled(gp):
+    """The benchmark's workload at full size (500k Gaussians, 400 slices of 256 x 256,
+    sigma_z = 3) in its launch configuration (a fixed workspace sized by one counted
+    render, then renders without host synchronisation): the tile lists of four slices
+    (the two ends among them) bit-exact, and sampled pixels of those slices, the
+    brightest included, against the oracle evaluated pixel by pixel."""
+    from paper_2603_20611_amd import render
+    _say("full size: 500k Gaussians, 400 slices of 256 x 256")
+    p = synth.ultrasound_hidden(500_000, seed=1)
+    slices = synth.ultrasound_slices(400, 256, 3.0)
+    params = torch.from_numpy(p).cuda().contiguous()
+    out = torch.empty(400 * 256 * 256, device="cuda")
+    ws_a = render.Workspace()
+    render.render(params, slices, ws=ws_a, out=out)
+    rec, inst, _ = ws_a.check()
+    del ws_a
+    ws = render.Workspace(capacity=(int(rec * 1.3) + 4096, int(inst * 1.3) + 16384))
+    for _ in range(2):
+        render.render(params, slices, ws=ws, out=out)
+    torch.cuda.synchronize()
+    img = out.cpu().numpy().astype(np.float64).reshape(400, 256, 256)
+    keys, _ = ws.export_bins(400 * 256, inst + 16)
+    assert keys.size == inst
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for k in (0, 137, 263, 399):
+        # tile lists of slice k: (tile, Gaussian) in the oracle's order
+        mine = keys[(keys >> 32) // 256 == k]
+        gidx, tile = focus.slice_instances(p, slices[k])
+        assert np.array_equal((mine >> 32) - 256 * k, tile), f"slice {k}: tile lists differ"
+        assert np.array_equal(mine & 0xFFFFFFFF, gidx), f"slice {k}: tile lists differ"
+        # pixels: 24 at random and the slice's brightest, relative to the oracle's value there
+        iy, ix = np.unravel_index(int(np.argmax(img[k])), (256, 256))
+        px = np.concatenate([rng.integers(0, 256, 24), [ix]])
+        py = np.concatenate([rng.integers(0, 256, 24), [iy]])
+        ref = focus.render_pixels(p, slices[k], px, py)
+        scale = max(abs(float(ref[-1])), 1e-30)
+        err = float(np.abs(img[k, py, px] - ref).max()) / scale
+        worst = max(worst, err)
+        _say(f"slice {k}: {mine.size} list entries bit-exact, sampled rel err {err:.3e}")
+    assert worst <= FWD_TOL
+
+
 def test_forward_exact_mode_matches_brute_force(gp):
     from paper_2603_20611_amd import binding as B
     _say("exact mode")
