@@ -210,13 +210,22 @@ def extras_leg(params, slices, dev, steps=5):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    def fixed_ws(draw):
+        # as in the forward leg: a workspace sized by one counted render, so
+        # that the timed renders run without host synchronisation
+        ws_a = render.Workspace()
+        draw(ws_a)
+        rec, inst, _ = ws_a.check()
+        del ws_a
+        return render.Workspace(capacity=(int(rec * 1.3) + 4096, int(inst * 1.3) + 16384))
+
     n = params.shape[1]
     res = {}
     hold = {}
     t_enc = timed(lambda: hold.__setitem__("c", render.encode(params)))
     codes, header, _ = hold["c"]
-    ws = render.Workspace()
     img = torch.empty(len(slices) * RES * RES, device=dev)
+    ws = fixed_ws(lambda w: render.render_coded(codes, header, n, slices, ws=w, out=img))
     t_qm = timed(lambda: render.render_coded(codes, header, n, slices, ws=ws, out=img))
     res["codec"] = {"encode_ms": round(1e3 * t_enc, 4), "coded_forward_ms": round(1e3 * t_qm, 4),
                     "coded_mpix_per_s": round(len(slices) * RES * RES / t_qm / 1e6, 1), "bytes_per_gaussian": 22}
@@ -226,8 +235,8 @@ def extras_leg(params, slices, dev, steps=5):
     pose = np.concatenate([R.reshape(-1), -R @ centre]).astype(np.float32)
     obl = [dict(z=float(k) + 0.5, sigma_z=SIGMA_Z, x0=-RES / 2.0, y0=-RES / 2.0, dx=1.0, dy=1.0, width=RES,
                 height=RES, pose=pose) for k in range(-32, 32)]
-    ws_o = render.Workspace()
     img_o = torch.empty(len(obl) * RES * RES, device=dev)
+    ws_o = fixed_ws(lambda w: render.render(params, obl, ws=w, out=img_o))
     t_ob = timed(lambda: render.render(params, obl, ws=ws_o, out=img_o))
     res["oblique"] = {"slices": len(obl), "tilt_deg": 30.0, "forward_ms": round(1e3 * t_ob, 4),
                       "mpix_per_s": round(len(obl) * RES * RES / t_ob / 1e6, 1)}
