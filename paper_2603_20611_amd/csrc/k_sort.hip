@@ -283,7 +283,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RadixArgs a) {
   uint32_t* const wtot = sk;                     // the wavefront totals of the scan (before sk is used)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t n = min(*a.count, a.cap);
-  const uint32_t tile = blockIdx.x;
+  // consecutive tiles on one XCD, as in the histogram: a digit's runs of
+  // adjacent tiles are adjacent in the output, and their shared lines then
+  // merge in that XCD's L2
+  const uint32_t per = (a.nblocks + 7) / 8;
+  const uint32_t tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= (uint32_t)a.nblocks) return;
   const uint32_t base = tile * kSortTile;
   if (base >= n) return;   // whole block past the end (uniform)
   const uint32_t tn = min((uint32_t)kSortTile, n - base);
@@ -578,15 +583,15 @@ hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
     k_radix_hist<<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a);
     k_hist_rowscan<<<1 << pb, 256, 0, s>>>(hist, nblocks, rowtot);
     switch (pb) {
-      case 1: k_radix_scatter<1><<<nblocks, kSortThreads, 0, s>>>(a); break;
-      case 2: k_radix_scatter<2><<<nblocks, kSortThreads, 0, s>>>(a); break;
-      case 3: k_radix_scatter<3><<<nblocks, kSortThreads, 0, s>>>(a); break;
-      case 4: k_radix_scatter<4><<<nblocks, kSortThreads, 0, s>>>(a); break;
-      case 5: k_radix_scatter<5><<<nblocks, kSortThreads, 0, s>>>(a); break;
-      case 6: k_radix_scatter<6><<<nblocks, kSortThreads, 0, s>>>(a); break;
-      case 7: k_radix_scatter<7><<<nblocks, kSortThreads, 0, s>>>(a); break;
-      case 8: k_radix_scatter<8><<<nblocks, kSortThreads, 0, s>>>(a); break;
-      default: k_radix_scatter<9><<<nblocks, kSortThreads, 0, s>>>(a); break;
+      case 1: k_radix_scatter<1><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
+      case 2: k_radix_scatter<2><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
+      case 3: k_radix_scatter<3><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
+      case 4: k_radix_scatter<4><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
+      case 5: k_radix_scatter<5><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
+      case 6: k_radix_scatter<6><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
+      case 7: k_radix_scatter<7><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
+      case 8: k_radix_scatter<8><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
+      default: k_radix_scatter<9><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
