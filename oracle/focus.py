@@ -290,9 +290,11 @@ def l1_grad(image, target):
 GROUP_ROWS = {"mean": (0, 3), "log_scale": (3, 6), "quat": (6, 10), "alpha": (10, 11)}
 
 
-def adam_step(params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15):
+def adam_step(params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, clamp_alpha=False):
     """One Adam update of [11, N] arrays in float64; lr: dict group -> learning rate.
 
+    clamp_alpha: afterwards project the intensity row onto alpha >= 0 (the
+    intensity is used linearly, and a negative one has no physical meaning).
     Returns (params, m, v) as new float64 arrays."""
     p = np.asarray(params, np.float64).copy()
     g = np.asarray(grads, np.float64)
@@ -302,4 +304,6 @@ def adam_step(params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15):
     vhat = v / (1.0 - beta2 ** step)
     for name, (r0, r1) in GROUP_ROWS.items():
         p[r0:r1] -= lr[name] * mhat[r0:r1] / (np.sqrt(vhat[r0:r1]) + eps)
+    if clamp_alpha:
+        p[10] = np.maximum(p[10], 0.0)
     return p, m, v

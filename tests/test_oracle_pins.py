@@ -511,3 +511,73 @@ def test_l1_grad_sign_convention():
     I = np.array([1.0, 2.0, 3.0, 4.0])
     T = np.array([0.5, 2.0, 3.5, 4.0])
     np.testing.assert_array_equal(focus.l1_grad(I, T), np.array([1.0, 0.0, -1.0, 0.0]) / 4)
+
+
+def test_adam_two_steps_closed_form():
+    """Two steps with different gradients g1, g2 from a zero state.  Bias
+    correction makes the second step's estimates plain weighted means:
+        m2 / (1 - b1^2) = (b1 g1 + g2) / (1 + b1),
+        v2 / (1 - b2^2) = (b2 g1^2 + g2^2) / (1 + b2),
+    so with g1 = 1, g2 = 3 the second update is -lr (39/19) / sqrt(9.999/1.999).
+    Swapping b1 and b2 gives -lr 2.0005 / sqrt(9.9/1.9) instead (0.876 lr vs
+    0.918 lr), and a dropped bias correction or a v built from g instead of g^2
+    moves it further."""
+    lr = dict(mean=0.5, log_scale=0.25, quat=0.125, alpha=1.0)
+    rows = np.concatenate([[lr["mean"]] * 3, [lr["log_scale"]] * 3, [lr["quat"]] * 4, [lr["alpha"]]])
+    p0 = np.linspace(-1.0, 1.0, 11)[:, None]
+    z = np.zeros_like(p0)
+    p1, m, v = focus.adam_step(p0, np.ones_like(p0), z, z, lr, 1)
+    p2, _, _ = focus.adam_step(p1, 3.0 * np.ones_like(p0), m, v, lr, 2)
+    step2 = (39.0 / 19.0) / math.sqrt(9.999 / 1.999)
+    np.testing.assert_allclose(p1 - p0, -rows[:, None], rtol=1e-12)
+    np.testing.assert_allclose(p2 - p1, -rows[:, None] * step2, rtol=1e-12)
+    swapped = 2.0005 / math.sqrt(9.9 / 1.9)
+    assert abs(step2 - swapped) > 0.04
+
+
+def test_adam_alpha_projection():
+    rng = np.random.default_rng(15)
+    p = rng.standard_normal((11, 40))
+    p[10] = np.linspace(-0.02, 0.02, 40)
+    g = rng.standard_normal((11, 40))
+    lr = dict(mean=1e-3, log_scale=1e-3, quat=1e-3, alpha=5e-2)
+    z = np.zeros_like(p)
+    a, ma, va = focus.adam_step(p, g, z, z, lr, 1)
+    b, mb, vb = focus.adam_step(p, g, z, z, lr, 1, clamp_alpha=True)
+    np.testing.assert_array_equal(b[:10], a[:10])
+    np.testing.assert_array_equal(b[10], np.where(a[10] < 0.0, 0.0, a[10]))
+    assert (a[10] < 0).any() and (a[10] > 0).any()
+    np.testing.assert_array_equal(ma, mb)
+    np.testing.assert_array_equal(va, vb)
+
+
+@pytest.mark.parametrize("case", ["offset", "ragged"])
+def test_render_pixels_matches_render_slice(case):
+    """The per-pixel evaluation used at full size equals the whole-slice oracle
+    (itself pinned by brute force) at every pixel, tile edges and the ragged
+    border included."""
+    p = synth.gaussians_uniform(150, (40.0, 30.0, 8.0), np.log(1.4), 0.4, seed=61)
+    if case == "offset":
+        sl = dict(z=4.2, sigma_z=1.3, x0=-3.25, y0=2.5, dx=0.8, dy=1.1, width=45, height=27)
+    else:
+        sl = dict(z=3.1, sigma_z=0.6, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=37, height=19)
+    full = focus.render(p, [sl])[0].numpy()
+    py, px = np.meshgrid(np.arange(sl["height"]), np.arange(sl["width"]), indexing="ij")
+    vals = focus.render_pixels(p, sl, px.ravel(), py.ravel()).reshape(full.shape)
+    assert np.abs(full).max() > 0.1
+    np.testing.assert_allclose(vals, full, rtol=1e-12, atol=1e-14 * np.abs(full).max())
+
+
+def test_grad_of_gaussians_matches_full_gradient():
+    """Gradient columns of a chosen subset (unsorted indices) equal those
+    columns of the full gradient, which is pinned by central differences."""
+    p = synth.gaussians_uniform(120, (40.0, 32.0, 8.0), np.log(1.4), 0.4, seed=62)
+    slices = [dict(z=2.5, sigma_z=1.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=40, height=32),
+              dict(z=5.5, sigma_z=2.0, x0=1.5, y0=-2.0, dx=0.9, dy=1.2, width=41, height=29)]
+    rng = np.random.default_rng(63)
+    w = [rng.standard_normal((s["height"], s["width"])) for s in slices]
+    full = focus.grad(p, slices, w)
+    idx = np.array([77, 3, 118, 40, 9, 64, 25])
+    sub = focus.grad_of_gaussians(p, slices, w, idx)
+    assert np.abs(full[:, idx]).max() > 0
+    np.testing.assert_allclose(sub, full[:, idx], rtol=1e-10, atol=1e-12 * np.abs(full).max())
