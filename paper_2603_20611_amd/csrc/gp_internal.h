@@ -116,15 +116,18 @@ inline int32_t emit_width_for(int64_t slices) {
 enum { kCtrRecords = 0, kCtrInstances = 1, kCtrOverflow = 2, kCtrCount = 4 };
 
 // Record payload in pixel space, 32 bytes, gathered by the rasterisers:
-//   x, y = mean in pixel-index units; a, b, c = exponent coefficients of
-//   exp2(a dx^2 + b dx dy + c dy^2); w = alpha~; for records inside the row
-//   recurrence's range (a >= kSmoothA, |b| <= kSmoothB) g = 2^(2a), the
-//   change of the per-pixel ratio along a row, and h = 2^b, its change from
-//   one row to the next; g = -1 and h = 0 mark the other records.
+//   the mean in pixel-index units as ax + xr, ay + yr, with the anchors ax, ay
+//   the nearest integers (exact in binary32) and xr, yr the remainders
+//   (|xr|, |yr| <= 1/2), so that the rasterisers form offsets from a tile
+//   origin as (origin - anchor) - remainder without the rounding a binary32
+//   mean of a large coordinate would carry; a, b, c = exponent coefficients of
+//   exp2(a dx^2 + b dx dy + c dy^2); w = alpha~.
 struct alignas(16) RecPay {
-  float x, y, a, b;
-  float c, w, g, h;
+  float xr, yr, a, b;
+  float c, w, ax, ay;
 };
+// Records with a >= kSmoothA and |b| <= kSmoothB take the forward raster's row
+// recurrence.
 constexpr float kSmoothA = -4.0f;
 constexpr float kSmoothB = 16.0f;
 

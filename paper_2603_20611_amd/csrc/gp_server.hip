@@ -84,12 +84,22 @@ struct Volume {
   float s_lateral_mean = 0.f;  // mean of each Gaussian's largest scale
 };
 
+// Where a volume's resident planes are.  Copied into each request when it is
+// taken into a batch (under the server lock), so that launching the batch never
+// reads the volume table, which gp_server_add_volume may grow meanwhile.
+struct VolView {
+  const void* means = nullptr;
+  const void* attrs = nullptr;
+  int64_t n = 0, stride = 0;
+};
+
 struct Request {
   uint64_t ticket;
   gp_request r;
   float* out;
   double t_submit;
   bool solo;       // render alone (after an overflow)
+  VolView vol{};   // set by take_batch
 };
 
 struct TicketState {
@@ -159,6 +169,27 @@ double est_instances(const Server* sv, const gp_request& r, double records) {
   return records * per * sv->tiles_factor;
 }
 
+// The slot's forward launch sequence at the server's capacity, captured once
+// when the server is created: the kernels read the batch's sizes from the
+// descriptors uploaded before each replay.  Capturing then, in the creating
+// thread, keeps any capture away from the time when other threads issue work
+// (a capture in progress makes work on the legacy stream fail).
+gp_status capture_slot(Server* sv, Slot* sl) {
+  hipGraph_t graph = nullptr;
+  GP_HIP(hipStreamBeginCapture(sl->stream, hipStreamCaptureModeThreadLocal));
+  const gp_status st = enqueue_forward(sl->ws, sv->rc, sv->cap_dims, sl->stream);
+  hipError_t e = hipStreamEndCapture(sl->stream, &graph);
+  if (st != GP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&sl->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return GP_OK;
+}
+
 void on_batch_done(void* p) {
   Slot* sl = static_cast<Slot*>(p);
   Server* sv = sl->sv;
@@ -184,8 +215,8 @@ gp_status launch_batch(Server* sv, Slot* sl) {
     const gp_request& r = reqs[k].r;
     hs[k] = gp_slice{r.z, r.sigma_z, r.x0, r.y0, r.dx, r.dy, r.width, r.height};
     outs[k] = reqs[k].out;
-    if (groups.empty() || sets.back().means != sv->vols[r.volume_id].means) {
-      const Volume& v = sv->vols[r.volume_id];
+    if (groups.empty() || sets.back().means != reqs[k].vol.means) {
+      const VolView& v = reqs[k].vol;
       sets.push_back(gp_gaussians{v.means, v.attrs, v.n, v.stride,
                                   sv->cfg.attr_dtype == GP_QM ? GP_QM : GP_F32, sv->cfg.attr_dtype});
       groups.push_back(GroupIn{nullptr, (int32_t)k, (int32_t)k + 1});
@@ -200,17 +231,6 @@ gp_status launch_batch(Server* sv, Slot* sl) {
   if (st != GP_OK) return st;
   if ((st = upload_batch(ws, plan, sl->stream)) != GP_OK) return st;
   if (sv->cfg.use_graphs) {
-    if (!sl->exec) {
-      hipGraph_t graph = nullptr;
-      GP_HIP(hipStreamBeginCapture(sl->stream, hipStreamCaptureModeThreadLocal));
-      st = enqueue_forward(ws, sv->rc, sv->cap_dims, sl->stream);
-      hipError_t e = hipStreamEndCapture(sl->stream, &graph);
-      if (st != GP_OK) return st;
-      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-      e = hipGraphInstantiate(&sl->exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    }
     GP_HIP(hipGraphLaunch(sl->exec, sl->stream));
   } else {
     if ((st = enqueue_forward(ws, sv->rc, LaunchDims{plan.total_gauss, plan.nbins}, sl->stream)) != GP_OK)
@@ -272,6 +292,8 @@ bool take_batch(Server* sv, Slot* sl) {
     recs += add_r;
     if (new_vol) vols_in.push_back(r.r.volume_id);
     sl->reqs.push_back(r);
+    const Volume& v = sv->vols[r.r.volume_id];
+    sl->reqs.back().vol = VolView{v.means, v.attrs, v.n, v.stride};
     const bool solo = r.solo;
     sv->queue.pop_front();
     if (solo) break;
@@ -420,6 +442,14 @@ gp_status gp_server_create(gp_server** out, const gp_server_cfg* cfg) {
     }
   }
   sv->rc = make_render_const(&cfg->opts, cfg->attr_dtype, sv->slots[0]->ws);
+  if (cfg->use_graphs) {
+    for (Slot* sl : sv->slots) {
+      if ((st = capture_slot(sv, sl)) != GP_OK) {
+        free_server(sv);
+        return st;
+      }
+    }
+  }
   sv->sched = std::thread(scheduler, sv);
   *out = reinterpret_cast<gp_server*>(sv);
   return GP_OK;

@@ -359,18 +359,20 @@ __device__ __forceinline__ void make_record(const double* cov, const float* p, c
   if (flags & GP_FLAG_CONV_EXACT) at *= sqrtf((float)(6.283185307179586 * ((v0 * v1) * v2) / (1.0 + szz / s2)));
   const double inv_det = 1.0 / det;
   const double L2 = 1.4426950408889634;
-  pay.x = (float)((((mu[0] - u * m) - (double)sl.x0) / (double)sl.dx) - 0.5);
-  pay.y = (float)((((mu[1] - v * m) - (double)sl.y0) / (double)sl.dy) - 0.5);
+  // pixel-index mean as a binary32 anchor (nearest integer) plus remainder
+  const double px = (((mu[0] - u * m) - (double)sl.x0) / (double)sl.dx) - 0.5;
+  const double py = (((mu[1] - v * m) - (double)sl.y0) / (double)sl.dy) - 0.5;
+  pay.ax = (float)rint(px);
+  pay.ay = (float)rint(py);
+  pay.xr = (float)(px - (double)pay.ax);
+  pay.yr = (float)(py - (double)pay.ay);
   pay.a = (float)(-0.5 * L2 * C * inv_det * (double)sl.dx * (double)sl.dx);
   pay.b = (float)(L2 * B * inv_det * (double)sl.dx * (double)sl.dy);
   pay.c = (float)(-0.5 * L2 * A * inv_det * (double)sl.dy * (double)sl.dy);
   pay.w = at;
-  const bool good = det > 0.0 && isfinite(at) && isfinite(pay.x) && isfinite(pay.y) && isfinite(pay.a) &&
-                    isfinite(pay.b) && isfinite(pay.c);
-  if (!good) pay.x = pay.y = pay.a = pay.b = pay.c = pay.w = 0.0f;
-  const bool smooth = pay.a >= kSmoothA && fabsf(pay.b) <= kSmoothB;
-  pay.g = smooth ? exp2f(2.0f * pay.a) : -1.0f;
-  pay.h = smooth ? exp2f(pay.b) : 0.0f;
+  const bool good = det > 0.0 && isfinite(at) && isfinite(pay.ax) && isfinite(pay.ay) && isfinite(pay.xr) &&
+                    isfinite(pay.yr) && isfinite(pay.a) && isfinite(pay.b) && isfinite(pay.c);
+  if (!good) pay.xr = pay.yr = pay.ax = pay.ay = pay.a = pay.b = pay.c = pay.w = 0.0f;
   meta.ibase = ibase;
   meta.rx = (uint32_t)rect.tx0 | ((uint32_t)rect.tx1 << 16);
   meta.ry = (uint32_t)rect.ty0 | ((uint32_t)rect.ty1 << 16);

@@ -4,7 +4,11 @@
 //
 // Records arrive in pixel space: with dx, dy the offsets of the pixel index
 // from the record's mean, a contribution is w * exp2(a dx^2 + b dx dy + c dy^2)
-// (the exponent coefficients carry -1/2 log2(e) and the pixel pitch).
+// (the exponent coefficients carry -1/2 log2(e) and the pixel pitch).  The mean
+// is stored as an integer anchor plus a remainder; a tile forms each record's
+// offset from its own origin once, as (origin - anchor) - remainder, which is
+// exact up to one rounding of a number no larger than the footprint, so pixel
+// offsets keep their precision on grids of any size.
 //
 // Forward: one 64-lane wavefront per 16x16 tile.  The two half-wavefronts
 // take two records at a time, and lane m of a half owns the 2 x 4 pixels of
@@ -70,6 +74,18 @@ struct FwdArgs {
 constexpr int kSliceGroup = 3;
 constexpr int kGroupMinBins = 3 * 8192;
 
+// A record as a tile's sweep reads it: the mean's offset from the tile origin
+// (ox0, oy0), the exponent coefficients a, b, c and the intensity w, and for
+// records inside the row recurrence's range g = 2^(2a), the change of the
+// per-pixel ratio along a row, and h = 2^b, its change from one row to the
+// next (g = -1, h = 0 mark the other records).  A zero record stages to w = 0.
+__device__ __forceinline__ void stage_record(const float4 r0, const float4 r1, float ox0, float oy0, float4& s0,
+                                             float4& s1) {
+  const bool smooth = r0.z >= kSmoothA && fabsf(r0.w) <= kSmoothB;
+  s0 = make_float4((ox0 - r1.z) - r0.x, (oy0 - r1.w) - r0.y, r0.z, r0.w);
+  s1 = make_float4(r1.x, r1.y, smooth ? exp2f(2.0f * r0.z) : -1.0f, smooth ? exp2f(r0.w) : 0.0f);
+}
+
 // Product with 0 * anything = 0 (also 0 * inf).
 __device__ __forceinline__ float mul0(float x, float y) {
   float r;
@@ -79,12 +95,13 @@ __device__ __forceinline__ float mul0(float x, float y) {
 
 
 
-// One step of a half-wavefront: record (r0, r1) over the lane's 2 x 4 pixels
-// whose first pixel is (fx0, fy0), added to acc (rows 0, 1 in acc[0..3], acc[4..7]).
+// One step of a half-wavefront: staged record (r0, r1) over the lane's 2 x 4
+// pixels whose first pixel is (fx0, fy0) from the tile origin, added to acc
+// (rows 0, 1 in acc[0..3], acc[4..7]).
 __device__ __forceinline__ void raster_step(const float4 r0, const float4 r1, float fx0, float fy0,
                                             float (&acc)[8]) {
-  const float d0 = fx0 - r0.x;
-  const float dy0 = fy0 - r0.y;
+  const float d0 = fx0 + r0.x;
+  const float dy0 = fy0 + r0.y;
   const float by0 = r0.w * dy0;
   const float cy0 = r1.x * dy0 * dy0;
   const float p00 = fmaf(fmaf(r0.z, d0, by0), d0, cy0);
@@ -180,7 +197,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   const int row0 = (m >> 2) * 2;
   const int col0 = (m & 3) * 4;
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4 pad4 = make_float4(0.f, 0.f, 1.f, 0.f);   // w = 0, smooth
+  const float fx0 = (float)col0, fy0 = (float)row0;
   uint32_t* counter = a.work + kWorkRasterFwd;
   // work items (queue tickets) -> first bin; rem = further slices of the item
   const int sg = (tps > 0 && n_bins >= kGroupMinBins) ? kSliceGroup : 1;
@@ -202,7 +219,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   if (item < 0) return;
   uint32_t start = a.bin_lo[item], end = a.bin_hi[item];
   int k = slice_of(a, n_slices, tps, item);
-  float4 n0 = zero4, n1 = pad4;
+  float4 n0 = zero4, n1 = zero4;
   if (start + lane < end) {
     const float4* src = reinterpret_cast<const float4*>(a.rec_pay + a.list[start + lane]);
     n0 = src[0];
@@ -218,7 +235,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     const int tx = tile % sl.ntx, ty = tile / sl.ntx;
     const int px0 = tx * kTile + col0;
     const int py0 = ty * kTile + row0;
-    const float fx0 = (float)px0, fy0 = (float)py0;
+    const float ox0 = (float)(tx * kTile), oy0 = (float)(ty * kTile);
     float acc[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) acc[i] = 0.f;
@@ -227,7 +244,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     int nitem = -1, nk = 0, stage = 0, nrem = 0;
     bool took = false;
     uint32_t ns = 0u, ne = 0u, nrid = 0u, nrid2 = 0u;
-    float4 m0 = zero4, m1 = pad4;
+    float4 m0 = zero4, m1 = zero4;
     auto advance = [&]() {
       if (stage == 0) {
         if (rem > 0) {
@@ -258,13 +275,17 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     };
 
     for (uint32_t base = start; base < end; base += 64) {
-      buf0[lane] = n0;
-      buf1[lane] = n1;   // slots past the end hold zeros (w = 0)
+      {
+        float4 s0, s1;
+        stage_record(n0, n1, ox0, oy0, s0, s1);
+        buf0[lane] = s0;
+        buf1[lane] = s1;   // slots past the end hold zero records (w = 0)
+      }
       __syncthreads();
       const int cnt = __builtin_amdgcn_readfirstlane((int)min(64u, end - base));
       const uint32_t nb = base + 64;
       n0 = zero4;
-      n1 = pad4;
+      n1 = zero4;
       if (nb + lane < end) {
         const float4* src = reinterpret_cast<const float4*>(a.rec_pay + rid_next);
         n0 = src[0];
@@ -320,16 +341,16 @@ __global__ __launch_bounds__(256) void k_raster_fwd_split(FwdArgs a) {
   const int tile = bin - sl.tile_base;
   const int px0 = (tile % sl.ntx) * kTile + col0;
   const int py0 = (tile / sl.ntx) * kTile + row0;
-  const float fx0 = (float)px0, fy0 = (float)py0;
+  const float ox0 = (float)(px0 - col0), oy0 = (float)(py0 - row0);
+  const float fx0 = (float)col0, fy0 = (float)row0;
   const uint32_t start = a.bin_lo[bin], end = a.bin_hi[bin];
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4 pad4 = make_float4(0.f, 0.f, 1.f, 0.f);   // w = 0, smooth
   float acc[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) acc[i] = 0.f;
   // this wavefront's batches: start + 64 (wave + 4 i)
   uint32_t base = start + 64u * wave;
-  float4 n0 = zero4, n1 = pad4;
+  float4 n0 = zero4, n1 = zero4;
   if (base + lane < end) {
     const float4* src = reinterpret_cast<const float4*>(a.rec_pay + a.list[base + lane]);
     n0 = src[0];
@@ -337,8 +358,12 @@ __global__ __launch_bounds__(256) void k_raster_fwd_split(FwdArgs a) {
   }
   uint32_t rid_next = (base + 256 + lane < end) ? a.list[base + 256 + lane] : 0u;
   for (; base < end; base += 256) {
-    buf0[wave][lane] = n0;
-    buf1[wave][lane] = n1;
+    {
+      float4 s0, s1;
+      stage_record(n0, n1, ox0, oy0, s0, s1);
+      buf0[wave][lane] = s0;
+      buf1[wave][lane] = s1;
+    }
     // the wavefront's own LDS slots: ordering within the wavefront suffices
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -346,7 +371,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd_split(FwdArgs a) {
     const int cnt = __builtin_amdgcn_readfirstlane((int)min(64u, end - base));
     const uint32_t nb = base + 256;
     n0 = zero4;
-    n1 = pad4;
+    n1 = zero4;
     if (nb + lane < end) {
       const float4* src = reinterpret_cast<const float4*>(a.rec_pay + rid_next);
       n0 = src[0];
@@ -438,12 +463,14 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
         const float4 r0 = src[0];
         const float4 r1 = src[1];
         const float ca = r0.z, cb2 = r0.w, cc = r1.x;
+        // offsets of the tile origin from the mean: (origin - anchor) - remainder
+        const float ox = (fx0 - r1.z) - r0.x, oy = (fy0 - r1.w) - r0.y;
         float dx[kTile];
 #pragma unroll
-        for (int c = 0; c < kTile; ++c) dx[c] = (fx0 - r0.x) + (float)c;
+        for (int c = 0; c < kTile; ++c) dx[c] = ox + (float)c;
         for (int rr = 0; rr < 4; ++rr) {
           const int row = 4 * (int)rq + rr;
-          const float dy = (fy0 + (float)row) - r0.y;
+          const float dy = oy + (float)row;
           const float by = cb2 * dy;
           const float cy = cc * dy * dy;
           const float4* grow = reinterpret_cast<const float4*>(G + row * kTile);

@@ -216,3 +216,119 @@ def test_errors_budget_and_shutdown(gp):
     assert first is None or first.status == 0
     sv.close()      # cancels what is queued, waits for what runs
     torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------- benchmark configuration
+BENCH_SERVER = dict(max_gaussians=64 << 20, max_records=24 << 20, max_instances=48 << 20, max_bins=64 * 4096,
+                    max_batch=64, slots=3, use_graphs=1)
+
+
+def test_bench_config_mixed_grids(gp):
+    """The server as the benchmark configures it (262,144-bin batches, captured
+    graphs, three slots, GP_Q16 storage) on volumes of the serving workload's
+    generator (sizes log-uniform in [20k, 1M], 512 x 512 x 128 extent) and requests
+    for 256^2, 512^2 and 1024^2 grids over that extent.  Batches of more than 4,096
+    bins over mixed grids take the work-queue raster with a per-bin slice search.
+    Sampled pixels of every image (its brightest included) are checked against the
+    oracle on the dequantised parameters (1e-5) and on the float32 masters (2e-3),
+    and one request rendered alone equals its image in the mix bit for bit."""
+    from paper_2603_20611_amd import binding as B, serve
+    _say("benchmark server configuration, mixed 256/512/1024 grids")
+    vols = synth.serving_volumes(5, 20_000, 1_000_000, (512.0, 512.0, 128.0), seed=5)
+    reqs = synth.serving_requests(30, len(vols), depth=128.0, extent=512.0, seed=6)
+    sv = serve.Server(**BENCH_SERVER)
+    for v in vols:
+        sv.add_volume(torch.from_numpy(v).cuda().contiguous())
+    outs, tickets = [], []
+    for r in reqs:
+        o = torch.empty(r["res"] * r["res"], device="cuda")
+        outs.append(o)
+        tickets.append(sv.submit(r["volume"], r["z"], r["sigma_z"], o, r["res"], r["res"], dx=r["dx"], dy=r["dx"]))
+    res = [sv.poll(t, timeout_us=60_000_000) for t in tickets]
+    torch.cuda.synchronize()
+    assert all(x.status == 0 for x in res)
+    # the batches that ran: bins and grids per batch
+    by_batch = {}
+    for r, x in zip(reqs, res):
+        by_batch.setdefault(x.batch_id, []).append(r["res"])
+    bins = {b: sum(((g + 15) // 16) ** 2 for g in grids) for b, grids in by_batch.items()}
+    mixed_big = [b for b, grids in by_batch.items() if bins[b] > 4096 and len(set(grids)) > 1]
+    _say(f"{len(by_batch)} batches, sizes {sorted(len(g) for g in by_batch.values())}, "
+         f"{len(mixed_big)} with > 4096 bins over mixed grids")
+    assert mixed_big, "no batch took the work-queue raster over mixed grids"
+    imgs = [o.cpu().numpy().astype(np.float64).reshape(r["res"], r["res"]) for o, r in zip(outs, reqs)]
+    rng = np.random.default_rng(7)
+    worst_k, worst_m = 0.0, 0.0
+    for img, r in zip(imgs, reqs):
+        p = vols[r["volume"]]
+        sl = dict(z=r["z"], sigma_z=r["sigma_z"], x0=0.0, y0=0.0, dx=r["dx"], dy=r["dx"], width=r["res"],
+                  height=r["res"])
+        iy, ix = np.unravel_index(int(np.argmax(img)), img.shape)
+        px = np.concatenate([rng.integers(0, r["res"], 24), [ix, r["res"] - 1]])
+        py = np.concatenate([rng.integers(0, r["res"], 24), [iy, r["res"] - 1]])
+        ref_q = focus.render_pixels(_dequant(p, B.GP_Q16), sl, px, py)
+        ref_m = focus.render_pixels(p, sl, px, py)
+        got = img[py, px]
+        worst_k = max(worst_k, float(np.abs(got - ref_q).max()) / max(abs(float(ref_q[-2])), 1e-30))
+        worst_m = max(worst_m, float(np.abs(got - ref_m).max()) / max(abs(float(ref_m[-2])), 1e-30))
+    _say(f"kernel arithmetic {worst_k:.2e}, vs float32 masters {worst_m:.2e}")
+    assert worst_k <= 1e-5
+    assert worst_m <= 2e-3
+    # one request of a mixed batch, alone
+    j = next(i for i, x in enumerate(res) if x.batch_id in mixed_big)
+    r = reqs[j]
+    o = torch.empty(r["res"] * r["res"], device="cuda")
+    x = sv.poll(sv.submit(r["volume"], r["z"], r["sigma_z"], o, r["res"], r["res"], dx=r["dx"], dy=r["dx"]),
+                timeout_us=60_000_000)
+    torch.cuda.synchronize()
+    assert x.status == 0 and x.batch_size == 1
+    assert np.array_equal(o.cpu().numpy().astype(np.float64).reshape(r["res"], r["res"]), imgs[j])
+    sv.close()
+
+
+def test_volumes_added_while_serving(gp):
+    """Volumes added from another thread while requests are admitted and launched:
+    every request completes and matches the image it renders on a quiet server."""
+    import threading
+    from paper_2603_20611_amd import serve
+    _say("volumes added while serving")
+    vols = _volumes([3000, 4000, 5000, 6000, 7000, 8000, 9000, 10000], seed=70)
+    sv = serve.Server(max_gaussians=1 << 20, max_records=1 << 20, max_instances=4 << 20, max_bins=64 * 64,
+                      max_batch=16, slots=3)
+    first = sv.add_volume(torch.from_numpy(vols[0]).cuda().contiguous())
+    tens = [torch.from_numpy(v).cuda().contiguous() for v in vols[1:]]
+    torch.cuda.synchronize()
+    ids = [first]
+
+    def adder():
+        for t in tens:
+            ids.append(sv.add_volume(t))
+
+    th = threading.Thread(target=adder)
+    th.start()
+    outs, tickets, used = [], [], []
+    rng = np.random.default_rng(71)
+    for i in range(200):
+        vid = ids[int(rng.integers(0, len(ids)))]     # only volumes already added
+        o = torch.empty(64 * 64, device="cuda")
+        z = float(rng.uniform(0, EXTENT[2]))
+        outs.append(o)
+        used.append((vid, z))
+        tickets.append(sv.submit(vid, z, 1.0, o, 64, 64, dx=2.0, dy=2.0))
+    th.join()
+    res = [sv.poll(t, timeout_us=60_000_000) for t in tickets]
+    torch.cuda.synchronize()
+    assert all(x.status == 0 for x in res)
+    assert sv.stats().volumes == len(vols)
+    quiet = serve.Server(max_gaussians=1 << 20, max_records=1 << 20, max_instances=4 << 20, max_bins=64 * 64,
+                         max_batch=16, slots=3)
+    order = {vid: k for k, vid in enumerate(ids)}
+    qids = [quiet.add_volume(torch.from_numpy(v).cuda().contiguous()) for v in vols]
+    for j in (0, 57, 123, 199):
+        vid, z = used[j]
+        o = torch.empty(64 * 64, device="cuda")
+        x = quiet.poll(quiet.submit(qids[order[vid]], z, 1.0, o, 64, 64, dx=2.0, dy=2.0), timeout_us=30_000_000)
+        torch.cuda.synchronize()
+        assert x.status == 0 and torch.equal(o, outs[j])
+    quiet.close()
+    sv.close()
