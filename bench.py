@@ -6,21 +6,33 @@ uniform in 256 x 256 x 400), 400 axial slices of 256 x 256 pixels, sigma_z = 3.
 The target stack is rendered once from a separate hidden set of 500,000
 Gaussians and multiplied by Rayleigh(1) speckle.
 
-Timed phases (each K steps after W warm-up steps, bracketed by a device
-synchronisation on both sides):
-  forward   one step = the whole 400-slice stack rendered in one launch sequence
-            (activation, axial cull, projection, tile-key emission, radix sort,
-            additive rasterisation).  `value` = rendered megapixels per second.
-  train     one step = one reconstruction iteration on a batch of 8 consecutive
-            slices at a random depth: forward, L1 + 0.2 D-SSIM loss gradient, backward,
+Timed phases (bracketed by a device synchronisation on both sides):
+  forward   K steps after W warm-up steps; one step = the whole 400-slice stack
+            rendered in one launch sequence (activation, axial cull,
+            projection, tile-key emission, radix sort, additive
+            rasterisation).  `value` = rendered megapixels per second.
+  train     reconstruction iterations on batches of 8 consecutive slices at a
+            random depth: forward, L1 + 0.2 D-SSIM loss gradient, backward,
             fused Adam (learning rates decayed exponentially to 0.1x over
             30,000 iterations).  Reported as fwd_bwd_iter_per_s.
+  voxel, extras   the voxeliser; the codec, an oblique batch, densify / prune.
+  serving   the batched server against one launch per request, swept over
+            offered Poisson rates, compared at equal p99.
+  recon     the microscopy-shaped reconstruction (200k Gaussians fitted to a
+            noisy 512 x 512 x 128 stack, batches of 8 slices): iterations per
+            second, loss and PSNR along the run with densify / prune.
+  contention  2M Gaussians fitted to a 1024 x 1024 x 256 stack in batches of 16
+            slices beside the server at 500 requests/s of 512 x 512 slices:
+            iterations per second and serving p99, alone and together.
 
 The dominant kernel (additive rasterisation of the forward) is timed with HIP
-events recorded by the library on the stream it launches on; its roofline is
-the VALU + transcendental issue rate of the chip (4 (pixel, Gaussian) pairs per
-clock per SIMD, derived below).  The CPU
-oracle is timed on 64 slices of 256 x 256 of the same workload.
+events recorded by the library on the stream it launches on (the only events in
+the timed forward loop); its roofline is the chip's fp32 vector rate, 157.3
+TFLOP/s, against the method's 11 flops per (pixel, Gaussian) pair.  The
+training loop is timed without events; a separate pass of the same iterations
+times every call and stage and prices each against its own roofline
+(algorithmic flops or HBM bytes).  The CPU oracle is timed on the host's cores
+before the GPU is touched: one thread, and a pool of one process per core.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -43,12 +55,22 @@ RES = 256
 SIGMA_Z = 3.0
 TRAIN_BATCH = 8
 LAMBDA_SSIM = 0.2   # weight of the D-SSIM term of the loss
-# raster roofline: per (pixel, Gaussian) pair the method needs one exp2 and four
-# fp32 VALU operations (offset, two FMAs of the quadratic form, accumulate).
-# gfx950 issues 32 fp32 lanes/clk/SIMD (157.3 TFLOP/s fp32 over 1024 SIMDs at
-# 2.4 GHz) and transcendentals at a quarter of that rate: 4*2 + 8 = 16 SIMD
-# cycles per 64 pairs -> 4 pairs/clk/SIMD.
-PEAK_PAIRS_PER_S = 1024 * 2.4e9 * 4.0
+# MI355X published peaks: fp32 vector 157.3 TFLOP/s (1024 SIMDs x 2.4 GHz x 32
+# lanes x 2 flops of an FMA), fp64 vector 78.6 TFLOP/s, HBM3E 8 TB/s.
+PEAK_FP32 = 157.3e12
+PEAK_FP64 = 78.6e12
+PEAK_HBM = 8.0e12
+# algorithmic work per (pixel, Gaussian) pair of the tile lists: two subtractions
+# for the offset, three multiplies and two FMAs for the quadratic form with the
+# conic pre-scaled by -1/2 log2(e) (9 flops), one FMA to accumulate (2 flops):
+# 11 flops and one exp2; the backward recomputes the pair (9 flops and the exp2)
+# and accumulates the six moments of the upstream gradient (22 flops): 31 flops.
+FLOP_PAIR_FWD = 11.0
+FLOP_PAIR_BWD = 31.0
+# the issue model of the forward raster kernel (a model, not the roofline): per
+# 64 pairs 4 VALU operations at 2 cycles and one exp2 at 8 cycles per wave64,
+# 16 SIMD cycles, 4 pairs per clock per SIMD
+PAIR_ISSUE_MODEL = 1024 * 2.4e9 * 4.0
 
 
 def measured_traffic(kernel):
@@ -75,45 +97,239 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(params_np, slices):
-    """The oracle, as it stands, on 64 slices of the workload."""
+_CPU = {}   # inputs of the pool workers (inherited through fork)
+
+
+def _cpu_init():
+    import torch
+    torch.set_num_threads(1)
+
+
+def _cpu_slice(k):
+    from oracle import focus
+    focus.render(_CPU["params"], [_CPU["slices"][k]])
+    return k
+
+
+def _host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return len(os.sched_getaffinity(0)), model
+
+
+def cpu_baseline(learn, slices):
+    """The oracle, as it stands, on the host's cores (run before the GPU is touched,
+    so that the pool can fork): one thread, and a pool of one single-threaded
+    process per core (at most 16) over slices.  Timed: slices of the benchmark's
+    workload (500k Gaussians, 256 x 256, sigma_z = 3), the tiny workload's 32 slices
+    (2,000 Gaussians, 64 x 64) forward and forward + backward, and one 512 x 512
+    slice of the microscopy-shaped learnable set (200k Gaussians, sigma_z = 2)."""
+    import multiprocessing as mp
     import torch
     from oracle import focus
-    sample = slices[N_SLICES // 2 - 32:N_SLICES // 2 + 32]
+    from paper_2603_20611_amd import synth
+
+    nproc, model = _host_cpu()
+    workers = max(1, min(nproc, 16))
+    threads0 = torch.get_num_threads()
+    torch.set_num_threads(1)
+    px = RES * RES
+    mid = N_SLICES // 2
     t0 = time.perf_counter()
-    imgs = focus.render(params_np, sample)
-    dt = time.perf_counter() - t0
-    del imgs
-    px = sum(s["width"] * s["height"] for s in sample)
-    return {"value": round(px / dt / 1e6, 4), "unit": "Mpix/s", "cores": int(torch.get_num_threads()),
-            "kind": "oracle",
-            "sample": f"{len(sample)} consecutive {RES}x{RES} slices (z={sample[0]['z']}..{sample[-1]['z']}) of the "
-                      f"{N_GAUSS}-Gaussian workload, float64 oracle, {dt:.1f} s"}
+    focus.render(learn, slices[mid:mid + 2])
+    t_single = time.perf_counter() - t0
+    single_mpix = 2 * px / t_single / 1e6
+    _CPU.update(params=learn, slices=slices)
+    n_pool = 2 * workers
+    ks = list(range(mid - n_pool // 2, mid - n_pool // 2 + n_pool))
+    with mp.get_context("fork").Pool(workers, initializer=_cpu_init) as pool:
+        t0 = time.perf_counter()
+        pool.map(_cpu_slice, ks, chunksize=1)
+        t_pool = time.perf_counter() - t0
+    pool_mpix = n_pool * px / t_pool / 1e6
+    p1, s1, tp1 = synth.tiny(0)
+    t0 = time.perf_counter()
+    target = focus.render(tp1, s1)
+    imgs = focus.render(p1, s1)
+    t_fwd1 = (time.perf_counter() - t0) / 2
+    t0 = time.perf_counter()
+    imgs = focus.render(p1, s1)
+    w = [focus.l1_grad(i.numpy(), t.numpy()) for i, t in zip(imgs, target)]
+    focus.grad(p1, s1, w)
+    t_fb1 = time.perf_counter() - t0
+    pm = synth.microscopy_learnable(200_000)
+    sm = synth.axial_slices(1, 512, 512, 2.0, z0=64.5)
+    t0 = time.perf_counter()
+    focus.render(pm, sm)
+    t_m = time.perf_counter() - t0
+    torch.set_num_threads(threads0)
+    _CPU.clear()
+    return {"value": round(pool_mpix, 4), "unit": "Mpix/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n_pool} slices of 256x256 (z={slices[ks[0]]['z']}..{slices[ks[-1]]['z']}) of the "
+                      f"500000-Gaussian workload over a pool of {workers} single-threaded processes, "
+                      f"float64 oracle, {t_pool:.1f} s",
+            "host": {"nproc": nproc, "cpu_model": model},
+            "single_thread_mpix_per_s": round(single_mpix, 4),
+            "tiny_32x64x64": {"forward_s": round(t_fwd1, 3), "forward_backward_s": round(t_fb1, 3),
+                              "threads": 1},
+            "microscopy_512x512_slice_s": round(t_m, 3)}
 
 
-def serving_leg(dev, n_requests, seed=3):
+def recon_microscopy_leg(dev, iters=1500, timed=200, log_every=250):
+    """Microscopy-shaped reconstruction (plain float32): a hidden set of 300k
+    filaments and blobs in 512 x 512 x 128 renders the target, 128 light-sheet
+    slices at sigma_z = 2 with Poisson (200 photons) and Gaussian (0.01) noise;
+    200k learnable Gaussians (means uniform, log-scale ln 1.5, intensities
+    U(0, 0.1)) are fitted with batches of 8 random slices.  Reported: iterations
+    per second over `timed` iterations without a densify pass, then the loss and
+    PSNR (against the noise-free stack) along `iters` iterations with densify /
+    prune every 100 from iteration 500."""
+    import torch
+    from paper_2603_20611_amd import render, synth, train
+    hidden = synth.microscopy_hidden(300_000, seed=20)
+    slices = synth.axial_slices(128, 512, 512, 2.0)
+    ws = render.Workspace()
+    clean = render.render(torch.from_numpy(hidden).to(dev).contiguous(), slices, ws=ws)
+    del ws
+    noisy = torch.from_numpy(synth.photon_noise(clean.cpu().numpy(), seed=22)).to(dev)
+    rec = train.Reconstruction(synth.microscopy_learnable(200_000, seed=21), noisy, slices, batch=8, seed=23)
+    psnr0 = rec.psnr(clean)
+    for _ in range(20):
+        rec.step()
+    t_it = train.timed_iterations(rec, timed)
+    rec.take_loss()
+    t0 = time.perf_counter()
+    rec.run(iters - rec.it, log_every=log_every)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    psnr1 = rec.psnr(clean)
+    out = {"gaussians_init": 200_000, "gaussians_final": rec.n, "batch_slices": 8, "resolution": 512,
+           "iter_per_s": round(1.0 / t_it, 1), "ms_per_iter": round(1e3 * t_it, 4),
+           "iterations": rec.it, "run_s_with_densify": round(t_run, 3),
+           "psnr_clean_db": [round(psnr0, 3), round(psnr1, 3)],
+           "history": [dict(iter=i, l1=round(a, 6), dssim=round(b, 6), gaussians=n) for i, a, b, n in rec.history]}
+    log(f"microscopy reconstruction: {out}")
+    return out
+
+
+def _open_loop(sv, reqs, outs, t_start=None):
+    """Submits requests at their arrival times (seconds from t_start), then waits
+    for all; returns latencies (ms) and batch sizes."""
+    t0 = time.perf_counter() if t_start is None else t_start
+    tickets = []
+    for r, o in zip(reqs, outs):
+        delay = t0 + r["t"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(sv.submit(r["volume"], r["z"], r["sigma_z"], o, r["res"], r["res"], dx=r["dx"], dy=r["dx"]))
+    res = [sv.poll(t, -1) for t in tickets]
+    wall = time.perf_counter() - t0
+    assert all(x.status == 0 for x in res), "serving request failed"
+    return (np.array([x.latency_ms for x in res]), np.array([x.batch_size for x in res]), wall)
+
+
+def contention_leg(dev, vols, seconds=3.0, iters_alone=30, rate=500.0):
+    """Large reconstruction beside serving: 2M learnable Gaussians fitted to a
+    1024 x 1024 x 256 microscopy-shaped target (the microscopy generator at the
+    same density as the 512 x 512 x 128 workload: 2.4M hidden Gaussians), float32
+    forward + backward + Adam on batches of 16 slices on one stream, while the
+    batched server renders 512 x 512 slices of the 64 resident serving volumes
+    requested at `rate` per second (Poisson) on its own streams.  Reported:
+    reconstruction iterations per second and serving p50 / p99, each alone and
+    both together."""
+    import threading
+    import torch
+    from paper_2603_20611_amd import render, serve, synth, train
+    box = (1024.0, 1024.0, 256.0)
+    hidden = torch.from_numpy(synth.microscopy_hidden(2_400_000, box=box, seed=30)).to(dev).contiguous()
+    slices = synth.axial_slices(256, 1024, 1024, 2.0)
+    clean = torch.empty(256 * 1024 * 1024, device=dev)
+    ws = render.Workspace()
+    for k in range(0, 256, 32):
+        render.render(hidden, slices[k:k + 32], ws=ws, out=clean[k * 1024 * 1024:(k + 32) * 1024 * 1024])
+    del ws, hidden
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(33)
+    noisy = synth.photon_noise_torch(clean, gen)
+    del clean
+    rec = train.Reconstruction(synth.microscopy_learnable(2_000_000, box=box, seed=31), noisy, slices, batch=16,
+                               densify_every=0, seed=32, grow_room=1.0)
+    for _ in range(3):
+        rec.step()
+    t_alone = train.timed_iterations(rec, iters_alone)
+    sv = serve.Server(max_gaussians=64 << 20, max_records=24 << 20, max_instances=48 << 20, max_bins=64 * 4096,
+                      max_batch=64, slots=3, use_graphs=1)
+    for v in vols:
+        t = torch.from_numpy(v).to(dev).contiguous()
+        sv.add_volume(t)
+        del t
+    n_req = int(rate * seconds)
+    reqs = synth.serving_requests(n_req, len(vols), depth=128.0, extent=512.0, seed=34, rate=rate,
+                                  resolutions=(512,))
+    outs = [torch.empty(512 * 512, device=dev) for _ in reqs]
+    torch.cuda.synchronize()
+    _open_loop(sv, reqs[:8], outs[:8], t_start=time.perf_counter() - 1e3)     # warm-up, graph capture
+    lat_a, bs_a, _ = _open_loop(sv, reqs, outs)
+    # both: the submitter in a thread, iterations on this thread until it is done
+    box_ = {}
+    th = threading.Thread(target=lambda: box_.__setitem__("r", _open_loop(sv, reqs, outs)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th.start()
+    n_it = 0
+    while th.is_alive():
+        rec.step()
+        n_it += 1
+        if n_it % 8 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    t_mix = time.perf_counter() - t0
+    th.join()
+    rec.ws.check()
+    lat_m, bs_m, _ = box_["r"]
+    sv.close()
+    pct = lambda x, q: round(float(np.percentile(x, q)), 3)
+    out = {"gaussians": 2_000_000, "target": [1024, 1024, 256], "batch_slices": 16, "serving_rate_req_per_s": rate,
+           "serving_resolution": 512, "requests": n_req,
+           "alone": {"iter_per_s": round(1.0 / t_alone, 2), "serving_p50_ms": pct(lat_a, 50),
+                     "serving_p99_ms": pct(lat_a, 99), "serving_mean_batch": round(float(bs_a.mean()), 2)},
+           "mixed": {"iter_per_s": round(n_it / t_mix, 2), "iterations": n_it, "serving_p50_ms": pct(lat_m, 50),
+                     "serving_p99_ms": pct(lat_m, 99), "serving_mean_batch": round(float(bs_m.mean()), 2)}}
+    log(f"contention: {out}")
+    del rec, noisy
+    torch.cuda.synchronize()
+    return out
+
+
+def serving_leg(dev, vols, seconds=1.5, rates_batched=(2000, 4000, 8000, 16000, 24000, 32000),
+                rates_plain=(1000, 2000, 4000, 6000, 8000), saturation_requests=2000):
     """Serving workload: 64 resident volumes (log-uniform 20k..1M Gaussians, the
-    microscopy generator in a 512x512x128 extent), Poisson requests at 2,000/s
-    for slices at z ~ U(0, 128), resolution in {256^2, 512^2, 1024^2}, sigma_z
-    in {0.5, 1, 2, 3}.  The batched server (continuous batching, graph replay,
-    3 slots) is compared with one launch per request (max_batch 1, 1 slot, no
-    graphs) at the same offered load and in a closed loop (all requests queued
-    at once: saturation throughput)."""
+    microscopy generator in a 512x512x128 extent, GP_Q16 storage), open-loop
+    Poisson requests for slices at z ~ U(0, 128), resolution uniform in {256^2,
+    512^2, 1024^2}, sigma_z uniform in {0.5, 1, 2, 3}.  The batched server
+    (continuous batching, graph replay, 3 slots) and one launch per request
+    (max_batch 1, 1 slot, no graphs) are each swept over offered rates,
+    `seconds` of arrivals per rate, up to the first rate a system cannot keep up
+    with; then each runs a closed loop (all requests queued at once).  The
+    comparison at equal p99: the plain renderer's knee (its highest rate kept up
+    with) fixes the p99; the batched server's highest rate kept up with at no
+    larger p99 over that knee rate is the speed-up."""
     import torch
     from paper_2603_20611_amd import serve, synth
-
-    vols = synth.serving_volumes(64, 20_000, 1_000_000, (512.0, 512.0, 128.0), seed=seed)
-    reqs = synth.serving_requests(n_requests, len(vols), depth=128.0, extent=512.0, seed=seed, rate=2000.0)
     total_g = sum(v.shape[1] for v in vols)
-    log(f"serving: {len(vols)} volumes, {total_g} Gaussians, {len(reqs)} requests")
-    outs = [torch.empty(r["res"] * r["res"], device=dev) for r in reqs]
-    systems = {
-        "batched": dict(max_batch=64, slots=3, use_graphs=1),
-        "plain": dict(max_batch=1, slots=1, use_graphs=0),
-    }
-    result = {"volumes": len(vols), "gaussians": int(total_g), "requests": len(reqs), "offered_req_per_s": 2000.0,
+    pool = {r: [torch.empty(r * r, device=dev) for _ in range(1024)] for r in (256, 512, 1024)}
+    systems = {"batched": (dict(max_batch=64, slots=3, use_graphs=1), rates_batched),
+               "plain": (dict(max_batch=1, slots=1, use_graphs=0), rates_plain)}
+    result = {"volumes": len(vols), "gaussians": int(total_g), "seconds_per_rate": seconds,
               "attr_storage": "q16 (fp16 log-scales and intensity, int16 unit quaternion)"}
-    for name, cfg in systems.items():
+    pct = lambda x, q: round(float(np.percentile(x, q)), 3)
+    for name, (cfg, rates) in systems.items():
         sv = serve.Server(max_gaussians=64 << 20, max_records=24 << 20, max_instances=48 << 20,
                           max_bins=64 * 4096, **cfg)
         for v in vols:
@@ -121,44 +337,48 @@ def serving_leg(dev, n_requests, seed=3):
             sv.add_volume(t)
             del t
         torch.cuda.synchronize()
+        counter = [0]
 
-        def submit(r, o):
-            return sv.submit(r["volume"], r["z"], r["sigma_z"], o, r["res"], r["res"], dx=r["dx"], dy=r["dx"])
+        def outs_for(reqs):
+            o = []
+            for r in reqs:
+                lst = pool[r["res"]]
+                o.append(lst[counter[0] % len(lst)])
+                counter[0] += 1
+            return o
 
-        # warm-up (graph capture, first launches)
-        for r, o in zip(reqs[:8], outs[:8]):
-            sv.poll(submit(r, o), -1)
-        # open loop at the offered rate
-        t0 = time.perf_counter()
-        tickets = []
-        for r, o in zip(reqs, outs):
-            delay = t0 + r["t"] - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            tickets.append(submit(r, o))
-        res = [sv.poll(t, -1) for t in tickets]
-        wall = time.perf_counter() - t0
-        lat = np.array([x.latency_ms for x in res])
-        bs = np.array([x.batch_size for x in res])
-        # closed loop: everything queued at once
-        t1 = time.perf_counter()
-        tickets = [submit(r, o) for r, o in zip(reqs, outs)]
-        res2 = [sv.poll(t, -1) for t in tickets]
-        wall2 = time.perf_counter() - t1
-        lat2 = np.array([x.latency_ms for x in res2])
-        ok = all(x.status == 0 for x in res + res2)
+        warm = synth.serving_requests(16, len(vols), seed=99, rate=1e6)
+        _open_loop(sv, warm, outs_for(warm))
+        sweep = []
+        for k, rate in enumerate(rates):
+            reqs = synth.serving_requests(int(rate * seconds), len(vols), depth=128.0, extent=512.0,
+                                          seed=100 + k, rate=float(rate))
+            lat, bs, wall = _open_loop(sv, reqs, outs_for(reqs))
+            done_rate = len(reqs) / wall
+            kept = done_rate >= 0.95 * rate
+            sweep.append({"offered_req_per_s": rate, "slices_per_s": round(done_rate, 1), "p50_ms": pct(lat, 50),
+                          "p99_ms": pct(lat, 99), "mean_batch": round(float(bs.mean()), 2), "kept_up": kept})
+            log(f"serving {name} @ {rate}/s: {sweep[-1]}")
+            if not kept:
+                break
+        sat = synth.serving_requests(saturation_requests, len(vols), seed=3, rate=1e9)
+        lat2, bs2, wall2 = _open_loop(sv, sat, outs_for(sat))
         st = sv.stats()
-        result[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
-                        "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                        "slices_per_s": round(len(reqs) / wall, 1),
-                        "mean_batch": round(float(bs.mean()), 2),
-                        "saturated_slices_per_s": round(len(reqs) / wall2, 1),
-                        "saturated_p50_ms": round(float(np.percentile(lat2, 50)), 3),
-                        "saturated_p99_ms": round(float(np.percentile(lat2, 99)), 3),
-                        "all_ok": bool(ok), "retries": int(st.retries)}
-        log(f"serving {name}: {result[name]}")
+        result[name] = {"sweep": sweep, "saturated_slices_per_s": round(len(sat) / wall2, 1),
+                        "saturated_p50_ms": pct(lat2, 50), "saturated_p99_ms": pct(lat2, 99),
+                        "saturated_mean_batch": round(float(bs2.mean()), 2), "retries": int(st.retries)}
         sv.close()
         torch.cuda.synchronize()
+    plain_ok = [s for s in result["plain"]["sweep"] if s["kept_up"]]
+    if plain_ok:
+        knee = plain_ok[-1]
+        ok = [s for s in result["batched"]["sweep"] if s["kept_up"] and s["p99_ms"] <= knee["p99_ms"]]
+        best = ok[-1]["offered_req_per_s"] if ok else None
+        result["equal_p99"] = {"plain_knee_req_per_s": knee["offered_req_per_s"], "p99_ms": knee["p99_ms"],
+                               "batched_req_per_s": best,
+                               "speedup": round(best / knee["offered_req_per_s"], 2) if best else None,
+                               "batched_sweep_capped": bool(ok and ok[-1] is result["batched"]["sweep"][-1]
+                                                            and result["batched"]["sweep"][-1]["kept_up"])}
     result["saturated_speedup"] = round(result["batched"]["saturated_slices_per_s"]
                                         / result["plain"]["saturated_slices_per_s"], 2)
     return result
@@ -252,6 +472,38 @@ def extras_leg(params, slices, dev, steps=5):
     return res
 
 
+def stage_bytes(stage, n, rec, inst, npix, passes):
+    """Algorithmic HBM bytes of one launch of a stage: parameters 44 B per
+    Gaussian; records 48 B written; (bin, record) pairs 8 B written; per radix
+    pass 4 B read by the histogram and 8 B read + 8 B written by the scatter per
+    pair, 4 B per pair for the ranges; the raster gathers 24 B of record per list
+    entry and writes 4 B per pixel; the backward's moments are 24 B per entry."""
+    if stage == "preprocess":
+        return n * (44 + 8)
+    if stage == "emit":
+        return n * 44 + rec * 48 + inst * 8
+    if stage == "sort":
+        return inst * (passes * 20 + 4)
+    if stage == "raster_fwd":
+        return inst * 24 + npix * 4
+    if stage == "raster_bwd":
+        return inst * 24 + npix * 4 + inst * 24
+    if stage == "preprocess_bwd":
+        return n * 44 + rec * 48 + inst * 24 + n * 44
+    raise KeyError(stage)
+
+
+def stage_roofline_s(stage, n, rec, inst, npix, passes):
+    """max(flop term, byte term) of a stage at the chip's peaks."""
+    t_b = stage_bytes(stage, n, rec, inst, npix, passes) / PEAK_HBM
+    pairs = 256.0 * inst
+    if stage == "raster_fwd":
+        return max(t_b, FLOP_PAIR_FWD * pairs / PEAK_FP32)
+    if stage == "raster_bwd":
+        return max(t_b, FLOP_PAIR_BWD * pairs / PEAK_FP32)
+    return t_b
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,7 +512,9 @@ def main():
     ap.add_argument("--train-steps", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-seconds", type=float, default=1.5, help="seconds of arrivals per offered rate")
+    ap.add_argument("--legs", default="forward,train,voxel,extras,serving,recon,contention",
+                    help="comma-separated legs to run (forward always runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (calibrates HBM byte counters)")
     ap.add_argument("--forward-only", action="store_true", help="time the forward phase only")
@@ -268,9 +522,25 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build"}))
         sys.exit(2)
+    legs = set(args.legs.split(","))
+    if args.forward_only:
+        legs = set()
+    if args.no_serving:
+        legs.discard("serving")
+
+    from paper_2603_20611_amd import synth
+
+    log("generating workload")
+    learn = synth.ultrasound_hidden(N_GAUSS, seed=1)
+    slices = synth.ultrasound_slices(N_SLICES, RES, SIGMA_Z)
+    cpu = None
+    if not args.no_cpu and not args.forward_only:
+        log("timing the CPU oracle (before the GPU is touched)")
+        cpu = cpu_baseline(learn, slices)
+        log(f"cpu: {cpu}")
 
     import torch
-    from paper_2603_20611_amd import binding as B, render, synth
+    from paper_2603_20611_amd import binding as B, render
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -281,20 +551,15 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {a.numel() * 4} bytes read and written")
         del a, b
-    log("generating workload")
-    learn = synth.ultrasound_hidden(N_GAUSS, seed=1)
-    hidden = synth.ultrasound_hidden(N_GAUSS, seed=0)
-    slices = synth.ultrasound_slices(N_SLICES, RES, SIGMA_Z)
     params = torch.from_numpy(learn).to(dev).contiguous()
-    hidden_t = torch.from_numpy(hidden).to(dev).contiguous()
 
     # target stack: render the hidden set, apply speckle (input data, made once)
-    if not args.forward_only:
+    if "train" in legs:
+        hidden_t = torch.from_numpy(synth.ultrasound_hidden(N_GAUSS, seed=0)).to(dev).contiguous()
         ws_t = render.Workspace()
         target = render.render(hidden_t, slices, ws=ws_t)
         target *= torch.from_numpy(synth.speckle(target.numel(), seed=2)).to(dev)
-        del ws_t
-    del hidden_t
+        del ws_t, hidden_t
     torch.cuda.synchronize()
 
     # size a fixed workspace from one counted render, then render without host syncs
@@ -306,72 +571,44 @@ def main():
     ws = render.Workspace(capacity=(int(rec * 1.3) + 4096, int(inst * 1.3) + 16384))
     log(f"records={rec} instances={inst} bins={bins}")
 
-    # ---------------- forward phase
+    # ---------------- forward phase: events around the raster kernel only
     for _ in range(args.warmup):
         render.render(params, slices, ws=ws, out=out)
     torch.cuda.synchronize()
-    ws.set_timing(True)
+    ws.set_timing(True, stages=("raster_fwd",))
     t0 = time.perf_counter()
     for _ in range(args.steps):
         render.render(params, slices, ws=ws, out=out)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    raster = ws.timings()["raster_fwd"]
+    ws.check()
+    # stage breakdown: the same steps again with every stage bracketed
+    ws.set_timing(True)
+    for _ in range(args.steps):
+        render.render(params, slices, ws=ws, out=out)
     st = ws.timings()
     ws.set_timing(False)
     ws.check()
     fwd_ms = 1e3 * t_fwd / args.steps
     mpix = N_SLICES * RES * RES * args.steps / t_fwd / 1e6
-    raster_ms = st["raster_fwd"][0] / max(st["raster_fwd"][1], 1)
+    raster_ms = raster[0] / max(raster[1], 1)
     pairs = 256.0 * inst
-    achieved = pairs / (raster_ms * 1e-3)
-    log(f"forward: {fwd_ms:.3f} ms/step, {mpix:.0f} Mpix/s; stages (ms/launch): "
-        + ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in st.items() if v[1]))
+    flops = FLOP_PAIR_FWD * pairs / (raster_ms * 1e-3)
+    log(f"forward: {fwd_ms:.3f} ms/step, {mpix:.0f} Mpix/s; raster {raster_ms:.4f} ms = {flops / 1e12:.1f} TFLOP/s; "
+        "stages (ms/launch): " + ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in st.items() if v[1]))
+    stage_ms = {k: round(v_[0] / max(v_[1], 1), 4) for k, v_ in st.items() if v_[1]}
+    passes = 2
+    fwd_stages = {}
+    for k, ms in stage_ms.items():
+        rt = stage_roofline_s(k, N_GAUSS, rec, inst, N_SLICES * RES * RES, passes)
+        fwd_stages[k] = {"ms": ms, "roofline_ms": round(1e3 * rt, 4), "frac": round(rt / (ms * 1e-3), 4)}
 
     if args.forward_only:
         print(json.dumps({"forward_ms": round(fwd_ms, 4), "mpix_per_s": round(mpix, 1),
-                          "stage_ms": {k: round(v_[0] / max(v_[1], 1), 4) for k, v_ in st.items() if v_[1]},
+                          "raster_ms": round(raster_ms, 4), "stage_ms": stage_ms,
                           "records": rec, "instances": inst}), flush=True)
         return
-
-    # ---------------- training phase
-    n_train = args.train_steps or max(args.steps * 5, 50)
-    grad = torch.zeros_like(params)
-    m = torch.zeros_like(params)
-    v = torch.zeros_like(params)
-    img = torch.empty(TRAIN_BATCH * RES * RES, device=dev)
-    gimg = torch.empty_like(img)
-    loss = torch.zeros(2, device=dev)
-    rng = np.random.default_rng(7)
-    starts = rng.integers(0, N_SLICES - TRAIN_BATCH + 1, size=n_train + args.warmup)
-    batches = [slices[int(k):int(k) + TRAIN_BATCH] for k in starts]
-    opts = B.default_opts()
-    ws_tr = render.Workspace(capacity=(int(rec * TRAIN_BATCH / N_SLICES * 3) + 65536,
-                                       int(inst * TRAIN_BATCH / N_SLICES * 3) + 262144))
-    lr0 = np.array([6e-4, 2e-3, 1e-3, 2e-2])
-    total_iters = 30000
-
-    def train_step(it, batch, k0):
-        render.render(params, batch, opts, ws_tr, out=img)
-        tgt = target[k0 * RES * RES:(k0 + TRAIN_BATCH) * RES * RES]
-        render.l1_dssim_loss_grad(img, tgt, TRAIN_BATCH, RES, RES, ws_tr, lam=LAMBDA_SSIM, grad=gimg, loss=loss)
-        render.render_backward(params, batch, gimg, ws_tr, opts, grad=grad)
-        lr = lr0 * 0.1 ** (it / total_iters)
-        render.adam_step(params, grad, m, v, it + 1, lr, flags=B.GP_ADAM_ZERO_GRAD | B.GP_ADAM_CLAMP_ALPHA)
-
-    for i in range(args.warmup):
-        train_step(i, batches[i], int(starts[i]))
-    torch.cuda.synchronize()
-    ws_tr.set_timing(True)
-    t0 = time.perf_counter()
-    for i in range(args.warmup, args.warmup + n_train):
-        train_step(i, batches[i], int(starts[i]))
-    torch.cuda.synchronize()
-    t_tr = time.perf_counter() - t0
-    st_tr = ws_tr.timings()
-    ws_tr.check()
-    it_s = n_train / t_tr
-    log(f"train: {1e3 * t_tr / n_train:.3f} ms/iter ({it_s:.0f} it/s); stages (ms/launch): "
-        + ", ".join(f"{k}={v_[0] / max(v_[1], 1):.3f}" for k, v_ in st_tr.items() if v_[1]))
 
     result = {
         "metric": "Mpix/s fwd & fwd+bwd iter/s @500k Gaussians; serving p50/p99 ms vs plain",
@@ -390,30 +627,142 @@ def main():
                                "sigma_z=3, whole stack per forward step",
                    "gaussians": N_GAUSS, "slices": N_SLICES, "resolution": RES, "sigma_z": SIGMA_Z,
                    "train_batch_slices": TRAIN_BATCH},
-        "fwd_bwd_iter_per_s": round(it_s, 1),
-        "fwd_bwd_ms_per_iter": round(1e3 * t_tr / n_train, 4),
-        "train_steps": n_train,
-        "stage_ms": {k: round(v_[0] / max(v_[1], 1), 4) for k, v_ in st.items() if v_[1]},
-        "train_stage_ms": {k: round(v_[0] / max(v_[1], 1), 4) for k, v_ in st_tr.items() if v_[1]},
         "records": rec, "instances": inst, "pairs_per_step": int(pairs),
-        "roofline": {"bound": "alu", "kernel": "k_raster_fwd", "achieved": round(achieved / 1e9, 1),
-                     "peak": round(PEAK_PAIRS_PER_S / 1e9, 1), "unit": "Gpair/s",
-                     "frac": round(achieved / PEAK_PAIRS_PER_S, 4), "traffic": measured_traffic("k_raster_fwd"),
+        "roofline": {"bound": "alu", "kernel": "k_raster_fwd", "achieved": round(flops / 1e12, 2),
+                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": round(flops / PEAK_FP32, 4),
+                     "traffic": measured_traffic("k_raster_fwd"),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel_ms": round(raster_ms, 4)},
+                     "flop_per_pair": FLOP_PAIR_FWD, "pairs_per_launch": int(pairs),
+                     "kernel_ms": round(raster_ms, 4),
+                     "issue_model": {"achieved_gpair_per_s": round(pairs / (raster_ms * 1e-3) / 1e9, 1),
+                                     "model_gpair_per_s": round(PAIR_ISSUE_MODEL / 1e9, 1),
+                                     "frac": round(pairs / (raster_ms * 1e-3) / PAIR_ISSUE_MODEL, 4)}},
+        "forward_stages": fwd_stages,
     }
-    log("voxeliser")
-    result["voxelize"] = voxel_leg(params, dev)
-    log(f"voxelize: {result['voxelize']}")
-    log("codec, oblique batch, densify / prune")
-    result.update(extras_leg(params, slices, dev))
-    log(f"codec: {result['codec']}; oblique: {result['oblique']}; densify_prune: {result['densify_prune']}")
-    if not args.no_serving:
-        result["serving"] = serving_leg(dev, args.serving_requests)
-    if not args.no_cpu:
-        log("timing the CPU oracle on 64 slices")
-        result["cpu_baseline"] = cpu_baseline(learn, slices)
+
+    if "train" in legs:
+        result.update(train_leg(args, params, slices, target, rec, inst, dev))
+    if "voxel" in legs:
+        log("voxeliser")
+        result["voxelize"] = voxel_leg(params, dev)
+        log(f"voxelize: {result['voxelize']}")
+    if "extras" in legs:
+        log("codec, oblique batch, densify / prune")
+        result.update(extras_leg(params, slices, dev))
+        log(f"codec: {result['codec']}; oblique: {result['oblique']}; densify_prune: {result['densify_prune']}")
+    vols = None
+    if "serving" in legs or "contention" in legs:
+        vols = synth.serving_volumes(64, 20_000, 1_000_000, (512.0, 512.0, 128.0), seed=3)
+        log(f"serving: {len(vols)} volumes, {sum(v.shape[1] for v in vols)} Gaussians")
+    if "serving" in legs:
+        result["serving"] = serving_leg(dev, vols, seconds=args.serving_seconds)
+    if "recon" in legs:
+        log("microscopy-shaped reconstruction (200k Gaussians, 512 x 512 x 128)")
+        result["reconstruction_microscopy"] = recon_microscopy_leg(dev)
+    if "contention" in legs:
+        log("large reconstruction (2M Gaussians, 1024 x 1024 x 256) beside serving")
+        result["reconstruction_with_serving"] = contention_leg(dev, vols)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
+
+
+def train_leg(args, params, slices, target, rec, inst, dev):
+    """Reconstruction iterations on batches of 8 consecutive slices: forward, L1 +
+    0.2 D-SSIM loss gradient, backward, fused Adam (intensity projection, gradient
+    reset).  Timed without events; then the same number of iterations again with
+    every call and stage bracketed by events, each priced against its roofline."""
+    import torch
+    from paper_2603_20611_amd import binding as B, render
+
+    n_train = args.train_steps or max(args.steps * 5, 50)
+    n = params.shape[1]
+    grad = torch.zeros_like(params)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    npix = TRAIN_BATCH * RES * RES
+    img = torch.empty(npix, device=dev)
+    gimg = torch.empty_like(img)
+    loss = torch.zeros(2, device=dev)
+    rng = np.random.default_rng(7)
+    total = args.warmup + 2 * n_train
+    starts = rng.integers(0, N_SLICES - TRAIN_BATCH + 1, size=total)
+    batches = [slices[int(k):int(k) + TRAIN_BATCH] for k in starts]
+    opts = B.default_opts()
+    ws_tr = render.Workspace(capacity=(int(rec * TRAIN_BATCH / N_SLICES * 3) + 65536,
+                                       int(inst * TRAIN_BATCH / N_SLICES * 3) + 262144))
+    lr0 = np.array([6e-4, 2e-3, 1e-3, 2e-2])
+    total_iters = 30000
+    flags = B.GP_ADAM_ZERO_GRAD | B.GP_ADAM_CLAMP_ALPHA
+
+    def train_step(it, ev=None):
+        batch, k0 = batches[it], int(starts[it])
+        tgt = target[k0 * RES * RES:(k0 + TRAIN_BATCH) * RES * RES]
+        lr = lr0 * 0.1 ** (it / total_iters)
+        calls = (lambda: render.render(params, batch, opts, ws_tr, out=img),
+                 lambda: render.l1_dssim_loss_grad(img, tgt, TRAIN_BATCH, RES, RES, ws_tr, lam=LAMBDA_SSIM,
+                                                   grad=gimg, loss=loss),
+                 lambda: render.render_backward(params, batch, gimg, ws_tr, opts, grad=grad),
+                 lambda: render.adam_step(params, grad, m, v, it + 1, lr, flags=flags))
+        for j, call in enumerate(calls):
+            if ev is not None:
+                ev[j][0].record()
+            call()
+            if ev is not None:
+                ev[j][1].record()
+
+    for i in range(args.warmup):
+        train_step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + n_train):
+        train_step(i)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter() - t0
+    ws_tr.check()
+    it_s = n_train / t_tr
+    # breakdown pass: events around each call (torch's current stream, on which the
+    # library launches) and the library's stage events
+    names = ("render", "loss", "backward", "adam")
+    call_ms = {k: 0.0 for k in names}
+    ws_tr.set_timing(True)
+    recs = insts = 0
+    for i in range(args.warmup + n_train, total):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in names]
+        train_step(i, ev)
+        torch.cuda.synchronize()
+        for k, (a, b) in zip(names, ev):
+            call_ms[k] += a.elapsed_time(b)
+        r_, i_, _ = ws_tr.check()
+        recs += r_
+        insts += i_
+    st = ws_tr.timings()
+    ws_tr.set_timing(False)
+    call_ms = {k: round(v_ / n_train, 4) for k, v_ in call_ms.items()}
+    stage_ms = {k: round(v_[0] / max(v_[1], 1), 4) for k, v_ in st.items() if v_[1]}
+    rec_b, inst_b = recs / n_train, insts / n_train
+    stages = {}
+    roof_total = 0.0
+    for k, ms in stage_ms.items():
+        rt = stage_roofline_s(k, n, rec_b, inst_b, npix, 2)
+        roof_total += rt
+        stages[k] = {"ms": ms, "roofline_ms": round(1e3 * rt, 4), "frac": round(rt / (ms * 1e-3), 4)}
+    # loss: image, target read and gradient written (12 B per pixel) plus the D-SSIM
+    # statistics (32 B written and read back per pixel); Adam: 28 B per parameter element
+    loss_rt = npix * (12 + 64) / PEAK_HBM
+    adam_rt = n * 11 * 28 / PEAK_HBM
+    roof_total += loss_rt + adam_rt
+    stages["loss"] = {"ms": call_ms["loss"], "roofline_ms": round(1e3 * loss_rt, 4),
+                      "frac": round(loss_rt / (call_ms["loss"] * 1e-3), 4)}
+    stages["adam"] = {"ms": call_ms["adam"], "roofline_ms": round(1e3 * adam_rt, 4),
+                      "frac": round(adam_rt / (call_ms["adam"] * 1e-3), 4)}
+    it_ms = 1e3 * t_tr / n_train
+    log(f"train: {it_ms:.3f} ms/iter ({it_s:.0f} it/s); calls (ms): {call_ms}; stages: {stages}")
+    return {"fwd_bwd_iter_per_s": round(it_s, 1), "fwd_bwd_ms_per_iter": round(it_ms, 4), "train_steps": n_train,
+            "train_call_ms": call_ms, "train_stages": stages,
+            "train_roofline": {"roofline_ms_per_iter": round(1e3 * roof_total, 4),
+                               "frac": round(roof_total / (it_ms * 1e-3), 4),
+                               "records_per_iter": int(rec_b), "instances_per_iter": int(inst_b)}}
 
 
 if __name__ == "__main__":

@@ -411,12 +411,14 @@ gp_status gp_server_stats_get(gp_server* sv, gp_server_stats* st);
  * batches on the GPU, frees everything.  NULL is accepted. */
 gp_status gp_server_destroy(gp_server* sv);
 
-/* Per-stage kernel timing of a workspace, for measurement.  While enabled, each
- * stage of a render or backward on this workspace is bracketed by HIP events
- * recorded on the call's stream (no host synchronisation is added);
- * gp_workspace_timings synchronises, resolves the pending events and returns,
- * per stage, the summed milliseconds and the number of launches since timing
- * was enabled.  Enabling resets the sums.  Errors: GP_EINVAL, GP_EHIP. */
+/* Per-stage kernel timing of a workspace, for measurement.  `enable` is a mask
+ * of stages, bit (1 << GP_STAGE_x) for stage x (GP_TIMING_ALL for every stage,
+ * 0 to switch timing off).  Each selected stage of a render or backward on this
+ * workspace is bracketed by HIP events recorded on the call's stream (no host
+ * synchronisation is added); gp_workspace_timings synchronises, resolves the
+ * pending events and returns, per stage, the summed milliseconds and the number
+ * of launches since timing was set.  Setting resets the sums.  Errors:
+ * GP_EINVAL, GP_EHIP. */
 #define GP_STAGE_PREPROCESS      0   /* activation, axial cull, counts, slot scan   */
 #define GP_STAGE_EMIT            1   /* records and (bin, record) pairs             */
 #define GP_STAGE_SORT            2   /* stable radix sort by bin, bin ranges        */
@@ -424,6 +426,7 @@ gp_status gp_server_destroy(gp_server* sv);
 #define GP_STAGE_RASTER_BWD      4   /* per-entry moments of the upstream gradient */
 #define GP_STAGE_PREPROCESS_BWD  5   /* chain rule to the Gaussian parameters       */
 #define GP_N_STAGES              6
+#define GP_TIMING_ALL            ((1 << GP_N_STAGES) - 1)
 gp_status gp_workspace_set_timing(gp_workspace* ws, int32_t enable);
 gp_status gp_workspace_timings(gp_workspace* ws, double* h_ms, int64_t* h_counts, int32_t n_stages);
 

@@ -159,10 +159,11 @@ static hipEvent_t take_event(Workspace* ws) {
   return e;
 }
 
-// Runs f (which enqueues one stage on s); with timing on, brackets it by events.
+// Runs f (which enqueues one stage on s); with the stage's timing bit set,
+// brackets it by events.
 template <typename F>
 static hipError_t timed(Workspace* ws, int stage, hipStream_t s, F&& f) {
-  if (!ws->timing) return f();
+  if (!((ws->timing >> stage) & 1u)) return f();
   hipEvent_t a = take_event(ws), b = take_event(ws);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, s);
@@ -647,7 +648,7 @@ gp_status gp_workspace_set_timing(gp_workspace* w, int32_t enable) {
     ws->stage_ms[i] = 0.0;
     ws->stage_n[i] = 0;
   }
-  ws->timing = enable != 0;
+  ws->timing = (uint32_t)enable & ((1u << GP_N_STAGES) - 1u);
   return GP_OK;
 }
 

@@ -227,8 +227,8 @@ struct Workspace {
   float* st_max_radius = nullptr;
   int64_t st_n = 0;
 
-  // optional per-stage timing (events recorded around each stage)
-  bool timing = false;
+  // optional per-stage timing (events recorded around the stages whose bit is set)
+  uint32_t timing = 0;
   struct TimedLaunch { int stage; hipEvent_t start, stop; };
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> event_pool;

@@ -45,8 +45,14 @@ class Workspace:
         B.check(B.load().gp_workspace_check(self._h, C.byref(r), C.byref(i), C.byref(b)))
         return r.value, i.value, b.value
 
-    def set_timing(self, enable=True):
-        B.check(B.load().gp_workspace_set_timing(self._h, 1 if enable else 0))
+    def set_timing(self, enable=True, stages=None):
+        """Per-stage event timing on (all stages, or the named ones in `stages`) or off."""
+        mask = 0
+        if enable:
+            names = B.STAGES if stages is None else stages
+            for name in names:
+                mask |= 1 << B.STAGES.index(name)
+        B.check(B.load().gp_workspace_set_timing(self._h, mask))
 
     def timings(self):
         """{stage: (milliseconds summed, launches)} since timing was enabled (synchronises)."""

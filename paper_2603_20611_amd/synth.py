@@ -127,6 +127,15 @@ def photon_noise(image, seed, photons=200.0, read_std=0.01):
     return (rng.poisson(lam) / photons + rng.normal(0.0, read_std, lam.shape)).astype(np.float32)
 
 
+def photon_noise_torch(image, generator, photons=200.0, read_std=0.01):
+    """photon_noise on the device (large stacks): Poisson(photons I) / photons +
+    N(0, read_std^2), drawn from a seeded torch generator."""
+    import torch
+    lam = image.clamp(min=0.0) * photons
+    out = torch.poisson(lam, generator=generator) / photons
+    return out + read_std * torch.randn(out.shape, device=out.device, generator=generator)
+
+
 def serving_volumes(n_volumes=64, n_min=20_000, n_max=1_000_000, box=(512.0, 512.0, 128.0), seed=3):
     """Resident volumes for the serving workload: sizes log-uniform in [n_min, n_max]."""
     rng = np.random.default_rng(seed)
