@@ -209,6 +209,26 @@ gp_status gp_l1_dssim_loss_grad(gp_workspace* ws, const float* d_image, const fl
                                 int32_t width, int32_t height, float lambda, float* d_grad, float* d_loss,
                                 void* stream);
 
+/* gp_l1_dssim_loss_grad without a workspace and without allocating, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving or training loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results as gp_l1_dssim_loss_grad; its scratch (coefficient maps
+ * and per-block sums, float64) lives in a static device array of 6,422,528
+ * elements (51.4 MB) that every GPU the library runs on holds until the process
+ * ends.  A call needs 3 * n_slices * width * height + 2 * n_slices *
+ * ceil(width / 32) * ceil(height / 16) elements: up to 2^21 pixels of slices
+ * whose sides are multiples of 32 and 16 (e.g. 8 slices of 512 x 512 or 32 of
+ * 256 x 256).  Larger requests return GP_EINVAL before anything is launched.
+ * All calls on one GPU share that array, which keeps the last call's contents
+ * (nothing in it needs clearing: every element read is first written by the
+ * same call); calls whose executions overlap on one GPU (other streams, other
+ * threads) race on it and must be serialised by the caller.  The first call on
+ * a device looks up the array's address there (no allocation).
+ * Errors: GP_EINVAL (as gp_l1_dssim_loss_grad, or too large), GP_EHIP. */
+gp_status gp_l1_dssim_loss_grad_noalloc(const float* d_image, const float* d_target, int32_t n_slices,
+                                        int32_t width, int32_t height, float lambda, float* d_grad,
+                                        float* d_loss, void* stream);
+
 /* Adam (Kingma & Ba, Algorithm 1; the optimiser named in Sec. 5.1) on float32
  * planes [11][stride] in place: for every element
  *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2

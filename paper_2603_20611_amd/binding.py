@@ -114,6 +114,7 @@ _SIGS = {
     "gp_voxelize_backward": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(VolumeGrid), C.POINTER(RenderOpts),
                                          _P, _P, C.c_int64, _P]),
     "gp_l1_dssim_loss_grad": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_float, _P, _P, _P]),
+    "gp_l1_dssim_loss_grad_noalloc": (C.c_int32, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_float, _P, _P, _P]),
     "gp_densify_default_cfg": (C.c_int32, [C.POINTER(DensifyCfg)]),
     "gp_workspace_set_densify_stats": (C.c_int32, [_P, _P, _P, _P, C.c_int64]),
     "gp_densify_prune": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P, _P, _P, C.POINTER(DensifyCfg),

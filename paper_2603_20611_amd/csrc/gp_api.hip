@@ -627,6 +627,25 @@ gp_status gp_l1_dssim_loss_grad(gp_workspace* w, const float* img, const float* 
   return GP_OK;
 }
 
+gp_status gp_l1_dssim_loss_grad_noalloc(const float* img, const float* tgt, int32_t n_slices, int32_t width,
+                                        int32_t height, float lambda, float* grad, float* loss, void* stream) {
+  if (n_slices < 0 || width < 0 || height < 0 || n_slices > 65535)
+    return einval("l1_dssim_noalloc: bad sizes");
+  if (!(lambda >= 0.f) || !std::isfinite(lambda)) return einval("l1_dssim_noalloc: lambda must be finite and >= 0");
+  const int64_t npix = (int64_t)n_slices * width * height;
+  if (npix == 0) return GP_OK;
+  if (!img || !tgt || !grad) return einval("l1_dssim_noalloc: NULL array");
+  const int64_t need = ssim_scratch(n_slices, width, height);
+  if (need > ssim_noalloc_capacity())
+    return einval("l1_dssim_noalloc: slices need " + std::to_string(need) + " float64 scratch elements, more than the " +
+                  std::to_string(ssim_noalloc_capacity()) + " of the static scratch");
+  double* scratch = nullptr;
+  GP_HIP(ssim_noalloc_scratch(&scratch));
+  GP_HIP(launch_ssim_loss(img, tgt, n_slices, width, height, (double)lambda, scratch, grad, loss,
+                          static_cast<hipStream_t>(stream)));
+  return GP_OK;
+}
+
 gp_status gp_adam_step(float* p, float* g, float* m, float* v, int64_t n, int64_t stride, const gp_adam_cfg* c,
                        void* stream) {
   if (!c) return einval("adam: NULL cfg");

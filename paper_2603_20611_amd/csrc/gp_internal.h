@@ -343,6 +343,10 @@ hipError_t launch_densify(const float* p, const float* m, const float* v, int64_
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, int64_t stride,
                        const gp_adam_cfg& c, hipStream_t s);
 // Scratch (float64 elements) of launch_ssim_loss: coefficient maps and per-block sums.
+// ssim_noalloc_scratch: the device address, on the current device, of the
+// library's static scratch of ssim_noalloc_capacity() elements (looked up once per device).
+int64_t ssim_noalloc_capacity();
+hipError_t ssim_noalloc_scratch(double** out);
 int64_t ssim_scratch(int n_slices, int width, int height);
 hipError_t launch_ssim_loss(const float* x, const float* y, int n_slices, int width, int height, double lam,
                             double* maps, float* grad, float* loss, hipStream_t s);

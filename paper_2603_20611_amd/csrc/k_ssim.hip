@@ -20,6 +20,8 @@
 // Both compute in float64: the moments form of the variances (E[x^2] - mx^2)
 // and the sum mx-term + 2 I x2-term cancel to a few bits in smooth regions,
 // and the whole loss costs about 300 flops per pixel, far from any bound.
+#include <mutex>
+
 #include "gp_internal.h"
 
 namespace gp {
@@ -191,7 +193,39 @@ __global__ __launch_bounds__(256) void k_ssim_grad(SsimArgs a) {
   }
 }
 
+// Scratch of the allocation-free loss entry point: the coefficient maps of up to
+// 2^21 pixels and the per-block sums, held by every GPU the library runs on
+// until the process ends.  Host code never passes the array's name to a kernel
+// (on the host it is only a stand-in): its device address is looked up once per
+// device, with that device current, and that address is used instead.
+constexpr int64_t kNoAllocScratchDoubles = 3ll * (1ll << 21) + (1ll << 17);
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
 }  // namespace
+
+int64_t ssim_noalloc_capacity() { return kNoAllocScratchDoubles; }
+
+hipError_t ssim_noalloc_scratch(double** out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
 
 int64_t ssim_scratch(int n_slices, int width, int height) {
   const int64_t blocks = (int64_t)((width + kSW - 1) / kSW) * ((height + kSH - 1) / kSH) * n_slices;

@@ -187,6 +187,16 @@ def l1_dssim_loss_grad(image, target, n_slices, width, height, ws, lam=0.2, grad
     return grad
 
 
+def l1_dssim_loss_grad_noalloc(image, target, n_slices, width, height, lam=0.2, grad=None, loss=None):
+    """As l1_dssim_loss_grad, through the library's allocation-free entry point (its
+    scratch is a static device array shared by all calls on the GPU)."""
+    if grad is None:
+        grad = torch.empty_like(image)
+    B.check(B.load().gp_l1_dssim_loss_grad_noalloc(_ptr(image), _ptr(target), int(n_slices), int(width),
+                                                    int(height), float(lam), _ptr(grad), _ptr(loss), _stream()))
+    return grad
+
+
 def adam_step(params, grad, m, v, step, lr, betas=(0.9, 0.999), eps=1e-15, n=None, flags=0):
     """lr: (mean, log_scale, quat, alpha) learning rates."""
     lib = B.load()

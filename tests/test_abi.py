@@ -57,3 +57,10 @@ def test_host_side_validation_without_gpu():
     assert b"step" in lib.gp_last_error()
     assert lib.gp_l1_loss_grad(None, None, -1, 1.0, None, None, None) == B.GP_EINVAL
     assert lib.gp_render_slices(None, None, None, 0, None, None, None) == B.GP_EINVAL
+    # the allocation-free loss refuses a batch beyond its static scratch before any device call
+    fake = ctypes.c_void_p(256)
+    assert lib.gp_l1_dssim_loss_grad_noalloc(fake, fake, 9, 512, 512, ctypes.c_float(0.2), fake, None,
+                                             None) == B.GP_EINVAL
+    assert b"static scratch" in lib.gp_last_error()
+    assert lib.gp_l1_dssim_loss_grad_noalloc(fake, fake, -1, 512, 512, ctypes.c_float(0.2), fake, None,
+                                             None) == B.GP_EINVAL
