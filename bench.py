@@ -219,15 +219,29 @@ def recon_microscopy_leg(dev, iters=1500, timed=200, log_every=250):
 
 
 def _open_loop(sv, reqs, outs, t_start=None):
-    """Submits requests at their arrival times (seconds from t_start), then waits
-    for all; returns latencies (ms) and batch sizes."""
+    """Open-loop arrivals: every request due by now is queued in one call, stamped
+    with its scheduled arrival time (so that a late submission still counts its
+    wait); then all are waited for.  Returns latencies (ms) and batch sizes, and
+    the wall time from the first arrival to the last completion."""
     t0 = time.perf_counter() if t_start is None else t_start
+    off = sv.clock_ms() - 1e3 * time.perf_counter()       # server clock minus ours (ms)
     tickets = []
-    for r, o in zip(reqs, outs):
-        delay = t0 + r["t"] - time.perf_counter()
-        if delay > 0:
-            time.sleep(delay)
-        tickets.append(sv.submit(r["volume"], r["z"], r["sigma_z"], o, r["res"], r["res"], dx=r["dx"], dy=r["dx"]))
+    i, n = 0, len(reqs)
+    while i < n:
+        now = time.perf_counter()
+        j = i
+        while j < n and t0 + reqs[j]["t"] <= now:
+            j += 1
+        if j == i:
+            wait = t0 + reqs[i]["t"] - now
+            if wait > 3e-4:
+                time.sleep(wait - 2e-4)
+            continue
+        batch = reqs[i:j]
+        tickets += sv.submit_many(
+            [dict(volume=r["volume"], z=r["z"], sigma_z=r["sigma_z"], width=r["res"], height=r["res"], dx=r["dx"],
+                  dy=r["dx"]) for r in batch], outs[i:j], [1e3 * (t0 + r["t"]) + off for r in batch])
+        i = j
     res = [sv.poll(t, -1) for t in tickets]
     wall = time.perf_counter() - t0
     assert all(x.status == 0 for x in res), "serving request failed"
@@ -307,8 +321,8 @@ def contention_leg(dev, vols, seconds=3.0, iters_alone=30, rate=500.0):
     return out
 
 
-def serving_leg(dev, vols, seconds=1.5, rates_batched=(2000, 4000, 8000, 16000, 24000, 32000),
-                rates_plain=(1000, 2000, 4000, 6000, 8000), saturation_requests=2000):
+def serving_leg(dev, vols, seconds=1.5, rates_batched=(2000, 4000, 8000, 16000, 24000, 28000, 32000, 40000),
+                rates_plain=(1000, 2000, 4000, 6000, 7000, 8000), saturation_requests=2000):
     """Serving workload: 64 resident volumes (log-uniform 20k..1M Gaussians, the
     microscopy generator in a 512x512x128 extent, GP_Q16 storage), open-loop
     Poisson requests for slices at z ~ U(0, 128), resolution uniform in {256^2,

@@ -418,6 +418,18 @@ gp_status gp_server_add_volume(gp_server* sv, const gp_gaussians* g, int32_t* vo
  * volume, bad grid, NULL), GP_ECANCELED (server shutting down). */
 gp_status gp_serve_submit(gp_server* sv, const gp_request* req, float* d_out, uint64_t* ticket);
 
+/* Queues n requests at once (one lock, one scheduler wake-up): request i
+ * renders into d_outs[i] and receives tickets[i].  t_arrival_ms, if not NULL,
+ * gives each request's arrival time on the server's clock (gp_clock_ms), from
+ * which its latency is measured (a front end that receives requests in bursts
+ * keeps their true waiting time); NULL stamps them now.  All requests are
+ * checked before any is queued.  Errors: as gp_serve_submit (nothing queued). */
+gp_status gp_serve_submit_many(gp_server* sv, const gp_request* reqs, float* const* d_outs,
+                               const double* t_arrival_ms, int32_t n, uint64_t* tickets);
+
+/* The server's clock: milliseconds of a steady (monotonic) clock. */
+double gp_clock_ms(void);
+
 /* Waits up to timeout_us (0: do not wait, < 0: forever) for a ticket.
  * Returns GP_OK and fills *res when the request finished (res->status tells
  * how), GP_EAGAIN if it is still pending, GP_EINVAL for an unknown ticket.

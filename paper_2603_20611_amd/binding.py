@@ -123,6 +123,9 @@ _SIGS = {
     "gp_server_create": (C.c_int32, [C.POINTER(_P), C.POINTER(ServerCfg)]),
     "gp_server_add_volume": (C.c_int32, [_P, C.POINTER(Gaussians), C.POINTER(C.c_int32)]),
     "gp_serve_submit": (C.c_int32, [_P, C.POINTER(Request), _P, C.POINTER(C.c_uint64)]),
+    "gp_serve_submit_many": (C.c_int32, [_P, C.POINTER(Request), C.POINTER(_P), C.POINTER(C.c_double), C.c_int32,
+                                         C.POINTER(C.c_uint64)]),
+    "gp_clock_ms": (C.c_double, []),
     "gp_serve_poll": (C.c_int32, [_P, C.c_uint64, C.c_int32, C.POINTER(ServeResult)]),
     "gp_server_stats_get": (C.c_int32, [_P, C.POINTER(ServerStats)]),
     "gp_server_destroy": (C.c_int32, [_P]),

@@ -57,23 +57,51 @@ hipError_t wait_ws(Workspace* ws) {
   return hipStreamSynchronize(static_cast<hipStream_t>(ws->last_stream));
 }
 
+// The descriptor block for slice_cap slices and group_cap groups: header at 0,
+// then slices, groups, poses (256-byte aligned parts).
+static hipError_t layout_desc(Workspace* ws, int64_t slice_cap, int64_t group_cap) {
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t off_s = up(sizeof(BatchHdr));
+  const size_t off_g = off_s + up(sizeof(SliceDev) * (size_t)slice_cap);
+  const size_t off_p = off_g + up(sizeof(GroupDev) * (size_t)group_cap);
+  const size_t bytes = off_p + up(sizeof(float) * 12 * (size_t)slice_cap);
+  if (ws->d_desc) {
+    hipError_t e = hipFree(ws->d_desc);
+    ws->d_desc = nullptr;
+    if (e != hipSuccess) return e;
+  }
+  if (ws->h_desc) {
+    hipError_t e = hipHostFree(ws->h_desc);
+    ws->h_desc = nullptr;
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipMalloc(&ws->d_desc, bytes);
+  if (e == hipSuccess) e = hipHostMalloc(&ws->h_desc, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) return e;
+  std::memset(ws->h_desc, 0, bytes);
+  char* d = static_cast<char*>(ws->d_desc);
+  char* h = static_cast<char*>(ws->h_desc);
+  ws->d_hdr = reinterpret_cast<BatchHdr*>(d);
+  ws->h_hdr = reinterpret_cast<BatchHdr*>(h);
+  ws->d_slices = reinterpret_cast<SliceDev*>(d + off_s);
+  ws->h_slices = reinterpret_cast<SliceDev*>(h + off_s);
+  ws->d_groups = reinterpret_cast<GroupDev*>(d + off_g);
+  ws->h_groups = reinterpret_cast<GroupDev*>(h + off_g);
+  ws->d_poses = reinterpret_cast<float*>(d + off_p);
+  ws->h_poses = reinterpret_cast<float*>(h + off_p);
+  ws->desc_off_groups = off_g;
+  ws->desc_off_poses = off_p;
+  ws->slice_cap = slice_cap;
+  ws->group_cap = group_cap;
+  return hipSuccess;
+}
+
 gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups, int64_t n_bins,
                                int64_t n_gauss) {
-  if (n_slices > ws->slice_cap) {
+  if (n_slices > ws->slice_cap || n_groups > ws->group_cap) {
     GP_HIP(wait_ws(ws));
-    const int64_t cap = n_slices + 64;
-    GP_HIP(dev_alloc(&ws->d_slices, cap));
-    GP_HIP(host_alloc(&ws->h_slices, cap));
-    GP_HIP(dev_alloc(&ws->d_poses, 12 * cap));
-    GP_HIP(host_alloc(&ws->h_poses, 12 * cap));
-    ws->slice_cap = cap;
-  }
-  if (n_groups > ws->group_cap) {
-    GP_HIP(wait_ws(ws));
-    const int64_t cap = n_groups + 8;
-    GP_HIP(dev_alloc(&ws->d_groups, cap));
-    GP_HIP(host_alloc(&ws->h_groups, cap));
-    ws->group_cap = cap;
+    GP_HIP(layout_desc(ws, std::max<int64_t>(ws->slice_cap, n_slices > ws->slice_cap ? n_slices + 64 : 0),
+                       std::max<int64_t>(ws->group_cap, n_groups > ws->group_cap ? n_groups + 8 : 0)));
   }
   if (n_bins > ws->bin_cap) {
     GP_HIP(wait_ws(ws));
@@ -302,11 +330,10 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
 }
 
 gp_status upload_batch(Workspace* ws, const BatchPlan& p, hipStream_t s) {
-  GP_HIP(hipMemcpyAsync(ws->d_hdr, ws->h_hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s));
-  if (p.ns > 0) GP_HIP(hipMemcpyAsync(ws->d_slices, ws->h_slices, sizeof(SliceDev) * p.ns, hipMemcpyHostToDevice, s));
-  if (p.ns > 0 && p.posed)
-    GP_HIP(hipMemcpyAsync(ws->d_poses, ws->h_poses, sizeof(float) * 12 * p.ns, hipMemcpyHostToDevice, s));
-  if (p.ng > 0) GP_HIP(hipMemcpyAsync(ws->d_groups, ws->h_groups, sizeof(GroupDev) * p.ng, hipMemcpyHostToDevice, s));
+  // one copy: the header, the slices, the groups and (posed batches) the poses
+  const size_t bytes = p.ns > 0 && p.posed ? ws->desc_off_poses + sizeof(float) * 12 * (size_t)p.ns
+                                           : ws->desc_off_groups + sizeof(GroupDev) * (size_t)p.ng;
+  GP_HIP(hipMemcpyAsync(ws->d_desc, ws->h_desc, bytes, hipMemcpyHostToDevice, s));
   GP_HIP(hipEventRecord(ws->upload_done, s));
   ws->last_stream = s;
   return GP_OK;
@@ -324,7 +351,11 @@ RenderConst make_render_const(const gp_render_opts* o, int attr_dtype, const Wor
 //   reset -> count -> wavefront scan -> (automatic sizing: read the counts,
 //   grow) -> emit -> radix sort by bin -> bin ranges -> rasterise.
 // With fixed capacities nothing synchronises, so the sequence can be captured.
-gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hipStream_t s) {
+// rec_limit / inst_limit (> 0) lower the capacities the launch may fill (and
+// the sort's extent) below the workspace's: a batch that needs more reports
+// an overflow.
+gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hipStream_t s, int64_t rec_limit,
+                          int64_t inst_limit) {
   if (ws->auto_size && (ws->rec_cap == 0 || ws->inst_cap == 0)) {
     // first use: a generous guess, corrected after the first count
     const int64_t guess_rec = std::max<int64_t>(1 << 16, d.gauss / 4);
@@ -356,18 +387,19 @@ gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hi
       if (st != GP_OK) return st;
     }
   }
-  rc.rec_cap = (uint32_t)ws->rec_cap;
-  rc.inst_cap = (uint32_t)ws->inst_cap;
+  const int64_t rcap = rec_limit > 0 ? std::min<int64_t>(rec_limit, ws->rec_cap) : ws->rec_cap;
+  const int64_t icap = inst_limit > 0 ? std::min<int64_t>(inst_limit, ws->inst_cap) : ws->inst_cap;
+  rc.rec_cap = (uint32_t)rcap;
+  rc.inst_cap = (uint32_t)icap;
   const uint32_t sentinel = (uint32_t)((1ll << bits) - 1);
   const uint32_t* d_count = ws->d_ctr + kCtrInstances;
   GP_HIP(timed(ws, GP_STAGE_EMIT, s, [&] { return launch_pre_emit(rc, *ws, d, sentinel, s); }));
   GP_HIP(timed(ws, GP_STAGE_SORT, s, [&] {
-    const int64_t n_sort = ws->auto_size ? std::min<int64_t>(ws->last_instances, ws->inst_cap) : ws->inst_cap;
+    const int64_t n_sort = ws->auto_size ? std::min<int64_t>(ws->last_instances, icap) : icap;
     hipError_t e = launch_radix_sort(ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, d_count,
                                      std::max<int64_t>(n_sort, 1), bits, ws->d_hist,
                                      reinterpret_cast<uint32_t*>(ws->d_scan_part), s, &ws->d_list_key, &ws->d_list);
-    if (e == hipSuccess)
-      e = launch_bin_ranges(ws->d_hdr, ws->d_list_key, d_count, ws->inst_cap, ws->d_bin_lo, ws->d_bin_hi, s);
+    if (e == hipSuccess) e = launch_bin_ranges(ws->d_hdr, ws->d_list_key, d_count, icap, ws->d_bin_lo, ws->d_bin_hi, s);
     return e;
   }));
   GP_HIP(timed(ws, GP_STAGE_RASTER_FWD, s, [&] { return launch_raster_fwd(rc, *ws, d, s); }));
@@ -391,9 +423,8 @@ gp_status workspace_new(Workspace** out, int64_t max_records, int64_t max_instan
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->d_ctr), sizeof(uint32_t) * kCtrCount);
   if (e == hipSuccess) e = hipMemset(ws->d_ctr, 0, sizeof(uint32_t) * kCtrCount);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->d_work), sizeof(uint32_t) * kWorkCount);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->d_hdr), sizeof(BatchHdr));
+  if (e == hipSuccess) e = layout_desc(ws, 0, 0);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_ctr), sizeof(uint32_t) * kCtrCount, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_hdr), sizeof(BatchHdr), hipHostMallocDefault);
   if (e != hipSuccess) {
     workspace_free(ws);
     return hip_fail(e, "workspace_create");
@@ -413,13 +444,13 @@ gp_status workspace_new(Workspace** out, int64_t max_records, int64_t max_instan
 void workspace_free(Workspace* ws) {
   if (!ws) return;
   (void)wait_ws(ws);
-  void* dev[] = {ws->d_slices, ws->d_poses, ws->d_groups, ws->d_hdr, ws->d_work, ws->d_ctr, ws->d_bin_lo, ws->d_bin_hi,
+  void* dev[] = {ws->d_desc, ws->d_work, ws->d_ctr, ws->d_bin_lo, ws->d_bin_hi,
                  ws->d_rec_pay, ws->d_rec_meta, ws->d_g_rbase, ws->d_g_nrec, ws->d_g_ninst, ws->d_g_krange,
                  ws->d_wave_cnt, ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, ws->d_hist,
                  ws->d_scan_part, ws->d_moments, ws->d_ssim, ws->d_vox_rec, ws->d_vox_box, ws->d_vox_mom};
   for (void* p : dev)
     if (p) (void)hipFree(p);
-  void* host[] = {ws->h_slices, ws->h_poses, ws->h_groups, ws->h_hdr, ws->h_ctr};
+  void* host[] = {ws->h_desc, ws->h_ctr};
   for (void* p : host)
     if (p) (void)hipHostFree(p);
   (void)resolve_timings(ws);

@@ -162,6 +162,13 @@ struct Workspace {
   // capacities (elements)
   int64_t rec_cap = 0, inst_cap = 0, bin_cap = 0, slice_cap = 0, group_cap = 0, gauss_cap = 0;
 
+  // batch descriptors: header, slices, groups and poses in one block (device
+  // and pinned host copies of the same layout), so that a batch is uploaded by
+  // one copy; the pointers below point into it
+  void* d_desc = nullptr;
+  void* h_desc = nullptr;
+  size_t desc_off_groups = 0, desc_off_poses = 0;
+
   // device buffers
   SliceDev* d_slices = nullptr;
   float* d_poses = nullptr;         // [slice_cap][12]
@@ -264,7 +271,8 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
                       float* const* outs, BatchPlan* plan, const float* poses = nullptr);
 gp_status upload_batch(Workspace* ws, const BatchPlan& p, hipStream_t s);
 RenderConst make_render_const(const gp_render_opts* o, int attr_dtype, const Workspace* ws);
-gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hipStream_t s);
+gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hipStream_t s, int64_t rec_limit = 0,
+                          int64_t inst_limit = 0);
 gp_status check_gaussians_pub(const gp_gaussians* g);
 gp_status check_slice_pub(const gp_slice& sl, int k);
 gp_status check_opts_pub(const gp_render_opts* o);

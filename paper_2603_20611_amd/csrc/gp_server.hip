@@ -109,13 +109,27 @@ struct TicketState {
 
 struct Server;
 
+// Launch capacities of a batch: flattened Gaussians and bins the launch grids
+// cover, records and tile-list entries it may fill.  Each slot has one
+// captured graph per bucket and a batch replays the smallest whose capacities
+// cover it (empty workgroups of a launch sized for the largest batch cost
+// time at light load); a batch that still overflows a smaller bucket reruns
+// in the largest.
+struct Bucket {
+  int64_t gauss, bins, rec, inst;
+};
+constexpr int kMaxBuckets = 3;
+
 struct Slot {
   Server* sv = nullptr;
   Workspace* ws = nullptr;
   hipStream_t stream = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec[kMaxBuckets] = {};
   std::vector<Request> reqs;
   bool busy = false, finished = false;
+  bool rerun = false;         // overflowed a smaller bucket: replay the largest
+  int bucket = 0;
+  double est_rec = 0.0, est_inst = 0.0;   // admission estimates of the batch
   int64_t batch_id = 0;
   double t_done = 0.0;
 };
@@ -138,6 +152,7 @@ struct Server {
   gp_server_stats stats{};
   RenderConst rc{};
   LaunchDims cap_dims{};
+  std::vector<Bucket> buckets;      // ascending; the last is the full capacity
 };
 
 int64_t tiles_of(const gp_request& r) {
@@ -174,19 +189,54 @@ double est_instances(const Server* sv, const gp_request& r, double records) {
 // descriptors uploaded before each replay.  Capturing then, in the creating
 // thread, keeps any capture away from the time when other threads issue work
 // (a capture in progress makes work on the legacy stream fail).
+void on_batch_done(void* p);
+
 gp_status capture_slot(Server* sv, Slot* sl) {
-  hipGraph_t graph = nullptr;
-  GP_HIP(hipStreamBeginCapture(sl->stream, hipStreamCaptureModeThreadLocal));
-  const gp_status st = enqueue_forward(sl->ws, sv->rc, sv->cap_dims, sl->stream);
-  hipError_t e = hipStreamEndCapture(sl->stream, &graph);
-  if (st != GP_OK) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return st;
+  for (size_t b = 0; b < sv->buckets.size(); ++b) {
+    const Bucket& k = sv->buckets[b];
+    hipGraph_t graph = nullptr;
+    GP_HIP(hipStreamBeginCapture(sl->stream, hipStreamCaptureModeThreadLocal));
+    const gp_status st = enqueue_forward(sl->ws, sv->rc, LaunchDims{k.gauss, k.bins}, sl->stream, k.rec, k.inst);
+    hipError_t e = hipStreamEndCapture(sl->stream, &graph);
+    if (st != GP_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&sl->exec[b], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
   }
-  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&sl->exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return GP_OK;
+}
+
+// The smallest bucket that covers the batch (its exact Gaussians and bins, its
+// estimated records and entries with a margin).
+int pick_bucket(const Server* sv, const BatchPlan& plan, double est_rec, double est_inst) {
+  const int last = (int)sv->buckets.size() - 1;
+  for (int b = 0; b < last; ++b) {
+    const Bucket& k = sv->buckets[b];
+    if (plan.total_gauss <= k.gauss && plan.nbins <= k.bins && 1.5 * est_rec <= (double)k.rec &&
+        1.5 * est_inst <= (double)k.inst)
+      return b;
+  }
+  return last;
+}
+
+// Launches the slot's batch (descriptors already uploaded) in bucket b.
+gp_status launch_bucket(Server* sv, Slot* sl, const BatchPlan* plan, int b) {
+  Workspace* ws = sl->ws;
+  sl->bucket = b;
+  const Bucket& k = sv->buckets[b];
+  if (sv->cfg.use_graphs) {
+    GP_HIP(hipGraphLaunch(sl->exec[b], sl->stream));
+  } else {
+    const LaunchDims d = plan ? LaunchDims{plan->total_gauss, plan->nbins} : LaunchDims{k.gauss, k.bins};
+    const gp_status st = enqueue_forward(ws, sv->rc, d, sl->stream, k.rec, k.inst);
+    if (st != GP_OK) return st;
+  }
+  GP_HIP(hipMemcpyAsync(ws->h_ctr, ws->d_ctr, sizeof(uint32_t) * kCtrCount, hipMemcpyDeviceToHost, sl->stream));
+  GP_HIP(hipLaunchHostFunc(sl->stream, on_batch_done, sl));
   return GP_OK;
 }
 
@@ -230,20 +280,19 @@ gp_status launch_batch(Server* sv, Slot* sl) {
                              outs.data(), &plan);
   if (st != GP_OK) return st;
   if ((st = upload_batch(ws, plan, sl->stream)) != GP_OK) return st;
-  if (sv->cfg.use_graphs) {
-    GP_HIP(hipGraphLaunch(sl->exec, sl->stream));
-  } else {
-    if ((st = enqueue_forward(ws, sv->rc, LaunchDims{plan.total_gauss, plan.nbins}, sl->stream)) != GP_OK)
-      return st;
-  }
-  GP_HIP(hipMemcpyAsync(ws->h_ctr, ws->d_ctr, sizeof(uint32_t) * kCtrCount, hipMemcpyDeviceToHost, sl->stream));
-  GP_HIP(hipLaunchHostFunc(sl->stream, on_batch_done, sl));
-  return GP_OK;
+  return launch_bucket(sv, sl, &plan, pick_bucket(sv, plan, sl->est_rec, sl->est_inst));
 }
 
-// Called with the lock held: completes a finished slot's requests.
-void retire(Server* sv, Slot* sl) {
+// Called with the lock held: completes a finished slot's requests.  Returns
+// true if the batch overflowed a smaller bucket and must be replayed in the
+// largest (the slot stays busy).
+bool retire(Server* sv, Slot* sl) {
   const bool overflow = sl->ws->h_ctr[kCtrOverflow] != 0;
+  if (overflow && sl->bucket + 1 < (int)sv->buckets.size()) {
+    sl->finished = false;
+    sl->rerun = true;
+    return true;
+  }
   if (overflow && sl->reqs.size() > 1) {
     // re-run each request alone, at the head of the queue, in the original order
     sv->tiles_factor *= 1.5;
@@ -267,6 +316,7 @@ void retire(Server* sv, Slot* sl) {
   sl->reqs.clear();
   sl->busy = false;
   sl->finished = false;
+  return false;
 }
 
 // Takes a batch from the head of the queue (lock held).  Returns false if empty.
@@ -275,6 +325,7 @@ bool take_batch(Server* sv, Slot* sl) {
   int64_t bins = 0, gauss = 0;
   double inst = 0.0, recs = 0.0;
   std::vector<int32_t> vols_in;
+  sl->est_rec = sl->est_inst = 0.0;
   while (!sv->queue.empty() && (int)sl->reqs.size() < sv->cfg.max_batch) {
     const Request& r = sv->queue.front();
     if (r.solo && !sl->reqs.empty()) break;
@@ -298,6 +349,8 @@ bool take_batch(Server* sv, Slot* sl) {
     sv->queue.pop_front();
     if (solo) break;
   }
+  sl->est_rec = recs;
+  sl->est_inst = inst;
   return true;
 }
 
@@ -306,13 +359,33 @@ void scheduler(Server* sv) {
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
     bool progressed = false;
+    std::vector<Slot*> reruns;
     for (Slot* sl : sv->slots) {
       if (sl->busy && sl->finished) {
-        retire(sv, sl);
-        progressed = true;
+        if (retire(sv, sl)) reruns.push_back(sl);
+        else progressed = true;
       }
     }
     if (progressed) sv->cv_done.notify_all();
+    for (Slot* sl : reruns) {
+      sl->rerun = false;
+      sv->stats.retries += (int64_t)sl->reqs.size();
+      lk.unlock();
+      const gp_status st = launch_bucket(sv, sl, nullptr, (int)sv->buckets.size() - 1);
+      lk.lock();
+      if (st != GP_OK) {
+        for (const Request& r : sl->reqs) {
+          TicketState& t = sv->tickets[r.ticket];
+          t.done = true;
+          t.res.status = st;
+          t.res.batch_id = sl->batch_id;
+          sv->stats.completed += 1;
+        }
+        sl->reqs.clear();
+        sl->busy = false;
+        sv->cv_done.notify_all();
+      }
+    }
     if (sv->stop) {
       bool any_busy = false;
       for (Slot* sl : sv->slots) any_busy = any_busy || sl->busy;
@@ -359,7 +432,8 @@ void scheduler(Server* sv) {
 void free_server(Server* sv) {
   for (Slot* sl : sv->slots) {
     if (sl->stream) (void)hipStreamSynchronize(sl->stream);
-    if (sl->exec) (void)hipGraphExecDestroy(sl->exec);
+    for (hipGraphExec_t x : sl->exec)
+      if (x) (void)hipGraphExecDestroy(x);
     if (sl->ws) workspace_free(sl->ws);
     if (sl->stream) (void)hipStreamDestroy(sl->stream);
     delete sl;
@@ -421,6 +495,20 @@ gp_status gp_server_create(gp_server** out, const gp_server_cfg* cfg) {
   }
   sv->cfg = *cfg;
   sv->cap_dims = LaunchDims{(cfg->max_gaussians + 63) / 64 * 64 + 64ll * cfg->max_batch, cfg->max_bins};
+  {
+    const Bucket full{sv->cap_dims.gauss, sv->cap_dims.bins, cfg->max_records, cfg->max_instances};
+    const Bucket cand[2] = {{1ll << 21, 16384, 1ll << 21, 1ll << 22}, {1ll << 23, 65536, 1ll << 23, 1ll << 24}};
+    for (const Bucket& c : cand) {
+      const Bucket b{std::min(c.gauss, full.gauss), std::min(c.bins, full.bins), std::min(c.rec, full.rec),
+                     std::min(c.inst, full.inst)};
+      const bool smaller = b.gauss < full.gauss || b.bins < full.bins || b.rec < full.rec || b.inst < full.inst;
+      const bool grows = sv->buckets.empty() || b.gauss > sv->buckets.back().gauss ||
+                         b.bins > sv->buckets.back().bins || b.rec > sv->buckets.back().rec ||
+                         b.inst > sv->buckets.back().inst;
+      if (smaller && grows) sv->buckets.push_back(b);
+    }
+    sv->buckets.push_back(full);
+  }
   for (int i = 0; i < cfg->slots; ++i) {
     Slot* sl = new (std::nothrow) Slot();
     if (!sl) {
@@ -434,7 +522,9 @@ gp_status gp_server_create(gp_server** out, const gp_server_cfg* cfg) {
     if (st == GP_OK) sl->ws->overflow_per_forward = true;
     // descriptor buffers sized for the largest batch so captured graphs stay valid
     if (st == GP_OK) st = reserve_small(sl->ws, cfg->max_batch, cfg->max_batch, cfg->max_bins, sv->cap_dims.gauss);
-    if (st == GP_OK) st = reserve_sort(sl->ws, key_bits(cfg->max_bins));
+    // sort scratch for every bucket's key width (fewer bits can mean wider digits)
+    for (const Bucket& b : sv->buckets)
+      if (st == GP_OK) st = reserve_sort(sl->ws, key_bits(b.bins));
     hipError_t e = st == GP_OK ? hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) : hipSuccess;
     if (st != GP_OK || e != hipSuccess) {
       free_server(sv);
@@ -551,38 +641,62 @@ gp_status gp_server_add_volume(gp_server* s, const gp_gaussians* g, int32_t* vol
   return GP_OK;
 }
 
-gp_status gp_serve_submit(gp_server* s, const gp_request* req, float* out, uint64_t* ticket) {
-  if (!s || !req || !out || !ticket) {
-    set_error("submit: NULL");
+gp_status gp_serve_submit_many(gp_server* s, const gp_request* reqs, float* const* outs, const double* t_arrival,
+                               int32_t n, uint64_t* tickets) {
+  if (!s || n < 0 || (n > 0 && (!reqs || !outs || !tickets))) {
+    set_error("submit: NULL or n < 0");
     return GP_EINVAL;
   }
   Server* sv = reinterpret_cast<Server*>(s);
-  const gp_slice sl{req->z, req->sigma_z, req->x0, req->y0, req->dx, req->dy, req->width, req->height};
-  gp_status st = check_slice_pub(sl, 0);
-  if (st != GP_OK) return st;
-  if (tiles_of(*req) > sv->cfg.max_bins) {
-    set_error("submit: request has more tiles than a batch may hold");
-    return GP_EINVAL;
+  for (int32_t i = 0; i < n; ++i) {
+    const gp_request* req = reqs + i;
+    if (!outs[i]) {
+      set_error("submit: NULL output");
+      return GP_EINVAL;
+    }
+    const gp_slice sl{req->z, req->sigma_z, req->x0, req->y0, req->dx, req->dy, req->width, req->height};
+    gp_status st = check_slice_pub(sl, 0);
+    if (st != GP_OK) return st;
+    if (tiles_of(*req) > sv->cfg.max_bins) {
+      set_error("submit: request has more tiles than a batch may hold");
+      return GP_EINVAL;
+    }
   }
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (req->volume_id < 0 || req->volume_id >= (int32_t)sv->vols.size()) {
-      set_error("submit: unknown volume");
-      return GP_EINVAL;
+    for (int32_t i = 0; i < n; ++i) {
+      if (reqs[i].volume_id < 0 || reqs[i].volume_id >= (int32_t)sv->vols.size()) {
+        set_error("submit: unknown volume");
+        return GP_EINVAL;
+      }
     }
     if (sv->stop) {
       set_error("submit: server is shutting down");
       return GP_ECANCELED;
     }
-    const uint64_t t = sv->next_ticket++;
-    sv->tickets.emplace(t, TicketState{});
-    sv->queue.push_back(Request{t, *req, out, now_ms(), false});
-    sv->stats.submitted += 1;
-    *ticket = t;
+    const double now = now_ms();
+    for (int32_t i = 0; i < n; ++i) {
+      const uint64_t t = sv->next_ticket++;
+      sv->tickets.emplace(t, TicketState{});
+      sv->queue.push_back(Request{t, reqs[i], outs[i], t_arrival ? t_arrival[i] : now, false});
+      tickets[i] = t;
+    }
+    sv->stats.submitted += n;
   }
-  sv->cv.notify_all();
+  if (n > 0) sv->cv.notify_all();
   return GP_OK;
 }
+
+gp_status gp_serve_submit(gp_server* s, const gp_request* req, float* out, uint64_t* ticket) {
+  if (!s || !req || !out || !ticket) {
+    set_error("submit: NULL");
+    return GP_EINVAL;
+  }
+  float* outs[1] = {out};
+  return gp_serve_submit_many(s, req, outs, nullptr, 1, ticket);
+}
+
+double gp_clock_ms(void) { return now_ms(); }
 
 gp_status gp_serve_poll(gp_server* s, uint64_t ticket, int32_t timeout_us, gp_serve_result* res) {
   if (!s || !res) {

@@ -233,13 +233,11 @@ __device__ __forceinline__ bool far_from_group(const PreArgs& a, const GroupDev&
   return d * d > a.rc.q_cut * (G.sz2max + smax * smax) * 1.001f;
 }
 
-template <int DT, bool POSED>
-__device__ __forceinline__ void count_one(const PreArgs& a, const float2* zs, int n_groups, int t) {
-  Loaded L;
-  load_params<DT>(a, n_groups, t, L);
-  // the world-depth shortcuts hold for axial slices only
-  if (!POSED && L.ok && far_from_group(a, L.G, L.p)) L.ok = false;   // culled on every slice
-  else activate(a, L);
+// Records and list entries of Gaussian L on its slices (L loaded; L.ok false
+// for a Gaussian culled on every slice); *kr receives its kept slice range.
+template <bool POSED>
+__device__ __forceinline__ void count_slices(const PreArgs& a, const float2* zs, Loaded& L, uint32_t* nrec_out,
+                                             uint32_t* ninst_out, uint32_t* kr) {
   int kb = L.G.k0, ke = L.G.k1;
   if (!L.ok) {
     ke = kb;
@@ -278,10 +276,16 @@ __device__ __forceinline__ void count_one(const PreArgs& a, const float2* zs, in
       cur = nxt;
     }
   }
+  *nrec_out = nrec;
+  *ninst_out = ninst;
+  *kr = (uint32_t)kb | ((uint32_t)ke << 16);
+}
+
+// Per-Gaussian outputs of the count and the wavefront's sums (whole wavefronts).
+__device__ __forceinline__ void count_store(const PreArgs& a, int t, uint32_t nrec, uint32_t ninst, uint32_t kr) {
   a.g_nrec[t] = nrec;
   a.g_ninst[t] = ninst;
-  a.g_krange[t] = (uint32_t)kb | ((uint32_t)ke << 16);
-  // wavefront sums
+  a.g_krange[t] = kr;
   uint32_t sr = nrec, si = ninst;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
@@ -289,6 +293,18 @@ __device__ __forceinline__ void count_one(const PreArgs& a, const float2* zs, in
     si += __shfl_xor(si, o, 64);
   }
   if ((t & 63) == 0) a.wave_cnt[t >> 6] = make_uint2(sr, si);
+}
+
+template <int DT, bool POSED>
+__device__ __forceinline__ void count_one(const PreArgs& a, const float2* zs, int n_groups, int t) {
+  Loaded L;
+  load_params<DT>(a, n_groups, t, L);
+  // the world-depth shortcuts hold for axial slices only
+  if (!POSED && L.ok && far_from_group(a, L.G, L.p)) L.ok = false;   // culled on every slice
+  else activate(a, L);
+  uint32_t nrec, ninst, kr;
+  count_slices<POSED>(a, zs, L, &nrec, &ninst, &kr);
+  count_store(a, t, nrec, ninst, kr);
 }
 
 // Float64 covariance of a Gaussian from its binary32 parameters (rotation of
@@ -590,9 +606,23 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
 // otherwise goes to the cache hierarchy at every step).
 constexpr int kZsLds = 2048;
 
-template <int DT, bool POSED>
+// Gaussians per workgroup round of the compacting count.
+constexpr int kCountChunk = 512;
+
+// COMPACT (axial batches of few slices per group, where most Gaussians are far
+// from every slice): a workgroup first tests a chunk of kCountChunk Gaussians
+// against the group's depth range and lists the near ones in LDS, then gives
+// one lane to each listed Gaussian for the covariance and footprints.  Without
+// the list, the few near Gaussians of every wavefront kept the whole
+// wavefront on the long path (the count of an 8-slice batch of 500k
+// Gaussians was bound by that divergence).
+template <int DT, bool POSED, bool COMPACT>
 __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
   __shared__ float2 zs_lds[POSED ? 1 : kZsLds];
+  __shared__ int s_list[COMPACT ? kCountChunk : 1];
+  __shared__ uint32_t s_nrec[COMPACT ? kCountChunk : 1], s_ninst[COMPACT ? kCountChunk : 1];
+  __shared__ uint32_t s_kr[COMPACT ? kCountChunk : 1];
+  __shared__ int s_n;
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   const int n_slices = a.hdr->n_slices;
@@ -602,9 +632,41 @@ __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
     __syncthreads();
     zs = zs_lds;
   }
-  const int stride = gridDim.x * 256;
-  for (int t = blockIdx.x * 256 + threadIdx.x; (t & ~63) < total; t += stride)
-    count_one<DT, POSED>(a, zs, n_groups, t);
+  if constexpr (!COMPACT) {
+    const int stride = gridDim.x * 256;
+    for (int t = blockIdx.x * 256 + threadIdx.x; (t & ~63) < total; t += stride)
+      count_one<DT, POSED>(a, zs, n_groups, t);
+  } else {
+    for (int base = blockIdx.x * kCountChunk; base < total; base += gridDim.x * kCountChunk) {
+      if (threadIdx.x == 0) s_n = 0;
+      __syncthreads();
+      for (int i = threadIdx.x; i < kCountChunk; i += 256) {
+        Loaded L;
+        load_params<DT>(a, n_groups, base + i, L);
+        const bool near = L.ok && !far_from_group(a, L.G, L.p);
+        s_nrec[i] = 0u;
+        s_ninst[i] = 0u;
+        s_kr[i] = (uint32_t)L.G.k0 | ((uint32_t)L.G.k0 << 16);
+        if (near) s_list[atomicAdd(&s_n, 1)] = i;
+      }
+      __syncthreads();
+      const int n = s_n;
+      for (int j = threadIdx.x; j < n; j += 256) {
+        const int i = s_list[j];
+        Loaded L;
+        load_params<DT>(a, n_groups, base + i, L);
+        activate(a, L);
+        count_slices<POSED>(a, zs, L, &s_nrec[i], &s_ninst[i], &s_kr[i]);
+      }
+      __syncthreads();
+      // whole wavefronts (chunk and base are multiples of 64; total is too)
+      for (int i = threadIdx.x; i < kCountChunk; i += 256) {
+        const int t = base + i;
+        if ((t & ~63) < total) count_store(a, t, s_nrec[i], s_ninst[i], s_kr[i]);
+      }
+      __syncthreads();   // the LDS arrays are rewritten by the next chunk
+    }
+  }
 }
 
 // A workgroup takes `chunk` consecutive Gaussians at a time (a multiple of 256,
@@ -668,14 +730,14 @@ hipError_t launch_emit_dt(const PreArgs& a, int width, unsigned blocks, hipStrea
   return hipGetLastError();
 }
 
-template <bool POSED>
+template <bool POSED, bool COMPACT>
 hipError_t launch_count_p(const PreArgs& a, int attr_dtype, unsigned blocks, hipStream_t s) {
   switch (attr_dtype) {
-    case GP_BF16: k_pre_count<GP_BF16, POSED><<<blocks, 256, 0, s>>>(a); break;
-    case GP_F16: k_pre_count<GP_F16, POSED><<<blocks, 256, 0, s>>>(a); break;
-    case GP_Q16: k_pre_count<GP_Q16, POSED><<<blocks, 256, 0, s>>>(a); break;
-    case GP_QM: k_pre_count<GP_QM, POSED><<<blocks, 256, 0, s>>>(a); break;
-    default: k_pre_count<GP_F32, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case GP_BF16: k_pre_count<GP_BF16, POSED, COMPACT><<<blocks, 256, 0, s>>>(a); break;
+    case GP_F16: k_pre_count<GP_F16, POSED, COMPACT><<<blocks, 256, 0, s>>>(a); break;
+    case GP_Q16: k_pre_count<GP_Q16, POSED, COMPACT><<<blocks, 256, 0, s>>>(a); break;
+    case GP_QM: k_pre_count<GP_QM, POSED, COMPACT><<<blocks, 256, 0, s>>>(a); break;
+    default: k_pre_count<GP_F32, POSED, COMPACT><<<blocks, 256, 0, s>>>(a); break;
   }
   return hipGetLastError();
 }
@@ -717,10 +779,20 @@ static PreArgs pre_args(const RenderConst& rc, const Workspace& ws, uint32_t sen
 hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s) {
   if (d.gauss <= 0) return hipSuccess;
   const PreArgs a = pre_args(rc, ws, 0u);
+  if (d.posed) {
+    int64_t blocks = (d.gauss + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    return launch_count_p<true, false>(a, rc.attr_dtype, (unsigned)blocks, s);
+  }
+  // groups of at most 8 slices: most Gaussians are far from all of them
+  if (d.emit_width <= 8) {
+    int64_t blocks = (d.gauss + kCountChunk - 1) / kCountChunk;
+    if (blocks > 16384) blocks = 16384;
+    return launch_count_p<false, true>(a, rc.attr_dtype, (unsigned)blocks, s);
+  }
   int64_t blocks = (d.gauss + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  return d.posed ? launch_count_p<true>(a, rc.attr_dtype, (unsigned)blocks, s)
-                 : launch_count_p<false>(a, rc.attr_dtype, (unsigned)blocks, s);
+  return launch_count_p<false, false>(a, rc.attr_dtype, (unsigned)blocks, s);
 }
 
 hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, uint32_t sentinel_bin,

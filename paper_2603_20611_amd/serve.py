@@ -41,6 +41,27 @@ class Server:
         B.check(B.load().gp_serve_submit(self._h, C.byref(r), C.c_void_p(out.data_ptr()), C.byref(t)))
         return t.value
 
+    def submit_many(self, reqs, outs, t_arrival_ms=None):
+        """Queues several requests in one call.  reqs: dicts with volume, z, sigma_z, width,
+        height and optional x0, y0, dx, dy; outs: float32 CUDA tensors; t_arrival_ms: arrival
+        times on the server's clock (clock_ms), or None for now.  Returns the tickets."""
+        n = len(reqs)
+        arr = (B.Request * max(n, 1))()
+        for i, r in enumerate(reqs):
+            arr[i] = B.Request(int(r["volume"]), float(r["z"]), float(r["sigma_z"]), float(r.get("x0", 0.0)),
+                               float(r.get("y0", 0.0)), float(r.get("dx", 1.0)), float(r.get("dy", 1.0)),
+                               int(r["width"]), int(r["height"]))
+        ptrs = (C.c_void_p * max(n, 1))(*[o.data_ptr() for o in outs])
+        tarr = None if t_arrival_ms is None else (C.c_double * max(n, 1))(*[float(t) for t in t_arrival_ms])
+        tickets = (C.c_uint64 * max(n, 1))()
+        B.check(B.load().gp_serve_submit_many(self._h, arr, ptrs, tarr, n, tickets))
+        return list(tickets[:n])
+
+    @staticmethod
+    def clock_ms():
+        """The server's clock (milliseconds, steady)."""
+        return B.load().gp_clock_ms()
+
     def poll(self, ticket, timeout_us=-1):
         """Returns a ServeResult, or None while pending (GP_EAGAIN)."""
         res = B.ServeResult()

@@ -332,3 +332,52 @@ def test_volumes_added_while_serving(gp):
         assert x.status == 0 and torch.equal(o, outs[j])
     quiet.close()
     sv.close()
+
+
+def test_submit_many_and_arrival_stamps(gp):
+    """Requests queued in one call render what single submissions render, and a
+    request's latency runs from the arrival stamp it was given."""
+    from paper_2603_20611_amd import serve
+    _say("submit_many, arrival stamps")
+    vols = _volumes([5000, 9000], seed=80)
+    sv, ids = _server(vols)
+    reqs = _requests(12, len(vols), seed=81)
+    single, _ = _run(sv, reqs)
+    outs = [torch.empty(r["width"] * r["height"], device="cuda") for r in reqs]
+    now = serve.Server.clock_ms()
+    stamps = [now - 40.0] * len(reqs)
+    tickets = sv.submit_many([dict(r, volume=ids[r["volume"]]) for r in reqs], outs, stamps)
+    res = [sv.poll(t, timeout_us=30_000_000) for t in tickets]
+    torch.cuda.synchronize()
+    assert all(x.status == 0 for x in res)
+    assert min(x.latency_ms for x in res) >= 40.0
+    for o, r, a in zip(outs, reqs, single):
+        assert np.array_equal(o.cpu().numpy().reshape(r["height"], r["width"]), a)
+    sv.close()
+
+
+def test_small_bucket_overflow_reruns_in_the_largest(gp):
+    """A request whose lists the admission estimate undercounts (a thin slab with 5 %
+    very wide Gaussians on a 1024^2 grid: 4.5 M entries against an estimate of
+    1.2 M) is first replayed in the smallest capacity bucket (4 M entries),
+    overflows it, and is replayed in the largest: the image is still the oracle's."""
+    from paper_2603_20611_amd import binding as B, serve
+    _say("bucket overflow rerun")
+    vol, _ = _slab_volume(60000, seed=82)
+    sv = serve.Server(max_gaussians=1 << 22, max_records=1 << 22, max_instances=1 << 24, max_bins=1 << 16,
+                      max_batch=8, slots=1)
+    sv.add_volume(torch.from_numpy(vol).cuda().contiguous())
+    r = dict(volume=0, z=16.0, sigma_z=3.0, width=1024, height=1024, dx=EXTENT[0] / 1024, dy=EXTENT[1] / 1024)
+    img, res = _run(sv, [r])
+    assert res[0].status == 0
+    assert sv.stats().retries >= 1
+    rng = np.random.default_rng(83)
+    im = img[0].astype(np.float64)
+    iy, ix = np.unravel_index(int(np.argmax(im)), im.shape)
+    px = np.concatenate([rng.integers(0, 1024, 30), [ix]])
+    py = np.concatenate([rng.integers(0, 1024, 30), [iy]])
+    ref = focus.render_pixels(_dequant(vol, B.GP_Q16), _slice(r), px, py)
+    err = float(np.abs(im[py, px] - ref).max()) / abs(float(ref[-1]))
+    _say(f"rerun image: rel err {err:.2e}, retries {sv.stats().retries}")
+    assert err <= 1e-5
+    sv.close()
