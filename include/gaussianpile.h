@@ -86,9 +86,14 @@ typedef int32_t gp_status;
  * sqrt(2 pi det Sigma_e / det Sigma_2d), i.e. the paper's value times
  * sqrt(2 pi det Sigma_e) with det Sigma_e = det Sigma sigma_z^2 / (sigma_z^2 +
  * Sigma_zz) (0 for sigma_z = 0, det Sigma for sigma_z = +inf).  Forward and
- * backward; the membership (bins) does not change. */
+ * backward; the membership (bins) does not change.
+ * GP_FLAG_FORWARD_ONLY: the render keeps no bookkeeping for a backward (the
+ * per-record tile rectangles and instance slots, 16 B per record, are not
+ * written); images are identical, and gp_render_backward on that workspace
+ * returns GP_ESTATE.  For inference: stacks rendered for viewing, serving. */
 #define GP_FLAG_EXACT 1u
 #define GP_FLAG_CONV_EXACT 2u
+#define GP_FLAG_FORWARD_ONLY 4u
 typedef struct gp_render_opts {
   float q_cut;        /* default 2 ln 255 = 11.0825...: opacity_r >= 1/255 */
   float bbox_sigmas;  /* default 3 */

@@ -16,6 +16,7 @@ GP_OK, GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_EOVERFLOW, GP_EAGAIN, GP_ECANCELED, GP_
 GP_F32, GP_BF16, GP_F16, GP_Q16, GP_QM = 0, 1, 2, 3, 4
 GP_FLAG_EXACT = 1
 GP_FLAG_CONV_EXACT = 2
+GP_FLAG_FORWARD_ONLY = 4
 GP_ADAM_CLAMP_ALPHA, GP_ADAM_ZERO_GRAD = 1, 2
 STAGES = ("preprocess", "emit", "sort", "raster_fwd", "raster_bwd", "preprocess_bwd")
 STATUS_NAMES = {0: "GP_OK", -1: "GP_EINVAL", -2: "GP_ENOMEM", -3: "GP_EHIP", -4: "GP_EOVERFLOW",

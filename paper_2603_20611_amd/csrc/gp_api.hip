@@ -254,7 +254,7 @@ static gp_status check_opts(const gp_render_opts* o) {
   if (!o) return einval("opts: NULL");
   if (!(o->q_cut >= 0.f) || !(o->bbox_sigmas > 0.f) || !(o->scale_mod > 0.f))
     return einval("opts: q_cut >= 0, bbox_sigmas > 0 and scale_mod > 0 required");
-  if (o->flags & ~(GP_FLAG_EXACT | GP_FLAG_CONV_EXACT)) return einval("opts: unknown flag");
+  if (o->flags & ~(GP_FLAG_EXACT | GP_FLAG_CONV_EXACT | GP_FLAG_FORWARD_ONLY)) return einval("opts: unknown flag");
   return GP_OK;
 }
 
@@ -569,8 +569,10 @@ gp_status gp_render_slices_posed(gp_workspace* w, const gp_gaussians* g, const g
   if ((st = upload_batch(ws, plan, s)) != GP_OK) return st;
   LaunchDims d{plan.total_gauss, plan.nbins, emit_width_for(ns)};
   d.posed = poses ? 1 : 0;
+  d.host_batch = 1;
   if ((st = enqueue_forward(ws, make_render_const(o, g->attr_dtype, ws), d, s)) != GP_OK) return st;
   ws->have_forward = true;
+  ws->fwd_forward_only = (o->flags & GP_FLAG_FORWARD_ONLY) != 0;
   ws->fwd_means = g->means;
   ws->fwd_attrs = g->attrs;
   ws->fwd_n = g->n;
@@ -599,7 +601,8 @@ gp_status gp_render_backward_posed(gp_workspace* w, const gp_gaussians* g, const
   if (grad_stride < g->n) return einval("backward: grad_stride < n");
   if (g->attr_dtype == GP_QM) return einval("backward: coded (GP_QM) Gaussians are render-only");
   if (ns < 0 || (ns > 0 && (!hs || !grad_out || !grad))) return einval("backward: bad arguments");
-  if (!ws->have_forward || ws->fwd_means != g->means || ws->fwd_attrs != g->attrs || ws->fwd_n != g->n ||
+  if (!ws->have_forward || ws->fwd_forward_only || ws->fwd_means != g->means || ws->fwd_attrs != g->attrs ||
+      ws->fwd_n != g->n ||
       ws->fwd_stride != g->stride || ws->fwd_nslices != ns || ws->fwd_posed != (poses ? 1 : 0) ||
       ws->fwd_slice_hash != slices_hash(hs, poses, ns, o)) {
     set_error("backward: the workspace does not hold the forward of these Gaussians and slices");

@@ -59,11 +59,14 @@ struct BatchHdr {
 };
 
 // Rasteriser work counters, handed out by atomics (reset at the start of every
-// forward).  (One queue per XCD, each draining a contiguous
-// eighth of the tiles, was measured 35 % slower than one queue shared by all:
-// with every XCD on the same slices at once, records one XCD brings in are
-// still cached for the others.)
-enum { kWorkRasterFwd = 0, kWorkRasterBwd = 1, kWorkCount = 4 };
+// forward): one shared queue, and eight per-XCD queues on cache lines of their
+// own (kWorkXcd + 32 q) for the deep-stack raster.  (One queue per XCD, each
+// draining a contiguous eighth of the tiles, was measured 35 % slower than one
+// queue shared by all: with every XCD on the same slices at once, records one
+// XCD brings in are still cached for the others.  The per-XCD queues of the
+// deep-stack raster interleave 4 x 4-tile units instead, so that every XCD
+// works on every slice group.)
+enum { kWorkRasterFwd = 0, kWorkRasterBwd = 1, kWorkXcd = 32, kWorkCount = kWorkXcd + 8 * 32 };
 
 __device__ __forceinline__ uint32_t wave_take(uint32_t* counter) {
   uint32_t v = 0;
@@ -103,6 +106,7 @@ struct LaunchDims {
   int64_t bins;         // bins to cover (also fixes the sort's key width)
   int32_t emit_width = 1;   // lanes per Gaussian in the emit (1, 2, 4, 8 or 16)
   int32_t posed = 0;        // the slices carry camera poses
+  int32_t host_batch = 0;   // the host staging holds this batch (not a capture for later batches)
 };
 // Emit width for groups of at most `slices` slices each.
 inline int32_t emit_width_for(int64_t slices) {
@@ -218,6 +222,7 @@ struct Workspace {
 
   // state of the last forward (checked by the backward)
   bool have_forward = false;
+  bool fwd_forward_only = false;    // rendered with GP_FLAG_FORWARD_ONLY: no backward
   const void* fwd_means = nullptr;
   const void* fwd_attrs = nullptr;
   int64_t fwd_n = 0, fwd_stride = 0;

@@ -77,11 +77,14 @@ struct Volume {
   void* attrs = nullptr;
   int64_t n = 0, stride = 0;
   size_t bytes = 0;
-  // admission estimate: mu_z histogram (unit bins from z_lo) and lateral size
+  // admission estimate: for each sigma_z of kSigmaGrid, cover[k][b] = the
+  // Gaussians whose axial window (q_ax <= q_cut) reaches unit depth bin b
+  // (from z_lo); and the mean and mean square of each Gaussian's lateral
+  // footprint width, 2 bbox sqrt(max(Sigma_xx, Sigma_yy)) in world units
   float z_lo = 0.f;
-  std::vector<int64_t> zcum;   // zcum[i] = Gaussians with mu_z < z_lo + i
-  float s_axial_max = 0.f;     // largest scale (bounds sqrt(Sigma_zz))
-  float s_lateral_mean = 0.f;  // mean of each Gaussian's largest scale
+  int nbins = 0;
+  std::vector<int32_t> cover;   // [kSigmaGrid][nbins]
+  double foot_m1 = 0.0, foot_m2 = 0.0;
 };
 
 // Where a volume's resident planes are.  Copied into each request when it is
@@ -159,28 +162,35 @@ int64_t tiles_of(const gp_request& r) {
   return (int64_t)((r.width + kTile - 1) / kTile) * ((r.height + kTile - 1) / kTile);
 }
 
-// Gaussians of the request's volume whose mu_z lies inside the widest axial
-// window any of them can have on this slice: an upper bound of its records.
+// sigma_z values of the admission tables (a request takes the first one at
+// least its own; beyond the last, every Gaussian counts)
+constexpr float kSigmaGrid[] = {0.f, 0.25f, 0.5f, 0.75f, 1.f, 1.5f, 2.f, 3.f, 4.f, 6.f, 8.f, 12.f, 16.f, 32.f};
+constexpr int kNSigma = sizeof(kSigmaGrid) / sizeof(kSigmaGrid[0]);
+
+// Records of a request: the Gaussians of its volume whose axial window at the
+// tabulated sigma_z at least the request's reaches the slice's depth bin (an
+// upper bound of the records up to the bin's width).
 double est_records(const Server* sv, const gp_request& r) {
   const Volume& v = sv->vols[r.volume_id];
-  const double D = (double)r.sigma_z * r.sigma_z + (double)v.s_axial_max * v.s_axial_max;
-  const double w = std::sqrt((double)sv->cfg.opts.q_cut * D);
-  const int nb = (int)v.zcum.size() - 1;
-  auto cum = [&](double z) {
-    const double u = z - v.z_lo;
-    if (u <= 0) return (int64_t)0;
-    if (u >= nb) return v.zcum[nb];
-    return v.zcum[(int)u];
-  };
-  return (double)(cum(r.z + w + 1.0) - cum(r.z - w));
+  int k = 0;
+  while (k < kNSigma && kSigmaGrid[k] < r.sigma_z) ++k;
+  if (k == kNSigma || !std::isfinite(r.z)) return (double)v.n;
+  const double u = (double)r.z - v.z_lo;
+  if (u < 0.0 || u >= (double)v.nbins) {
+    // outside the tabulated range: the nearest bin's coverage
+    const int b = u < 0.0 ? 0 : v.nbins - 1;
+    return (double)v.cover[(size_t)k * v.nbins + b];
+  }
+  return (double)v.cover[(size_t)k * v.nbins + (int)u];
 }
 
-// Estimate of a request's tile-list entries: its record bound times the tiles
-// of a footprint of the volume's mean size (scaled up after each overflow).
+// Tile-list entries of a request: its records times the expected tiles of a
+// footprint box over the volume's Gaussians, E[(w / (16 dx) + 1) (w / (16 dy) + 1)]
+// (scaled up after each overflow).
 double est_instances(const Server* sv, const gp_request& r, double records) {
   const Volume& v = sv->vols[r.volume_id];
-  const double px = 2.0 * sv->cfg.opts.bbox_sigmas * v.s_lateral_mean / std::min(r.dx, r.dy);
-  const double per = (px / kTile + 1.0) * (px / kTile + 1.0);
+  const double ax = 1.0 / (kTile * (double)r.dx), ay = 1.0 / (kTile * (double)r.dy);
+  const double per = v.foot_m2 * ax * ay + v.foot_m1 * (ax + ay) + 1.0;
   return records * per * sv->tiles_factor;
 }
 
@@ -532,6 +542,7 @@ gp_status gp_server_create(gp_server** out, const gp_server_cfg* cfg) {
     }
   }
   sv->rc = make_render_const(&cfg->opts, cfg->attr_dtype, sv->slots[0]->ws);
+  sv->rc.flags |= GP_FLAG_FORWARD_ONLY;   // served slices are never differentiated
   if (cfg->use_graphs) {
     for (Slot* sl : sv->slots) {
       if ((st = capture_slot(sv, sl)) != GP_OK) {
@@ -606,33 +617,73 @@ gp_status gp_server_add_volume(gp_server* s, const gp_gaussians* g, int32_t* vol
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  // admission statistics from the float32 source
-  std::vector<float> z((size_t)g->n), l((size_t)(3 * g->n));
+  // admission statistics from the float32 source: each Gaussian's covariance
+  // diagonal (float64), its axial window per tabulated sigma_z as a run of
+  // depth bins (difference arrays), and the moments of its footprint width
+  std::vector<float> z((size_t)g->n), l((size_t)(7 * g->n));
   if (e == hipSuccess) e = hipMemcpy(z.data(), m + 2 * g->stride, sizeof(float) * g->n, hipMemcpyDeviceToHost);
-  for (int r = 0; r < 3 && e == hipSuccess; ++r)
+  for (int r = 0; r < 7 && e == hipSuccess; ++r)
     e = hipMemcpy(l.data() + r * g->n, a + r * g->stride, sizeof(float) * g->n, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return release(hip_fail(e, "add_volume"));
-  float zl = INFINITY, zh = -INFINITY, smax = 0.f;
-  double ssum = 0.0;
+  const double q_cut = sv->cfg.opts.q_cut, mod = sv->cfg.opts.scale_mod, kb = sv->cfg.opts.bbox_sigmas;
+  std::vector<double> szz((size_t)g->n, -1.0);
+  float zl = INFINITY, zh = -INFINITY;
+  double m1 = 0.0, m2 = 0.0;
+  int64_t nf = 0;
   for (int64_t i = 0; i < g->n; ++i) {
-    if (std::isfinite(z[i])) { zl = std::min(zl, z[i]); zh = std::max(zh, z[i]); }
-    float li = std::max(l[i], std::max(l[g->n + i], l[2 * g->n + i]));
-    li = std::min(li, 80.f);
-    const float si = std::exp(li) * sv->cfg.opts.scale_mod;
-    if (std::isfinite(si)) { smax = std::max(smax, si); ssum += si; }
+    const double qw = l[3 * g->n + i], qx = l[4 * g->n + i], qy = l[5 * g->n + i], qz = l[6 * g->n + i];
+    const double qn = std::sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    double sc[3];
+    for (int k = 0; k < 3; ++k) sc[k] = std::exp(std::min<double>(l[k * g->n + i], 80.0)) * mod;
+    if (!std::isfinite(z[i]) || !(qn > 0.0) || !std::isfinite(qn)) continue;
+    const double w = qw / qn, x = qx / qn, y = qy / qn, zz = qz / qn;
+    // rows of R(q); Sigma_aa = sum_k R[a][k]^2 s_k^2
+    const double R0[3] = {1 - 2 * (y * y + zz * zz), 2 * (x * y - w * zz), 2 * (x * zz + w * y)};
+    const double R1[3] = {2 * (x * y + w * zz), 1 - 2 * (x * x + zz * zz), 2 * (y * zz - w * x)};
+    const double R2[3] = {2 * (x * zz - w * y), 2 * (y * zz + w * x), 1 - 2 * (x * x + y * y)};
+    double sxx = 0.0, syy = 0.0, sz = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double v2 = sc[k] * sc[k];
+      sxx += R0[k] * R0[k] * v2;
+      syy += R1[k] * R1[k] * v2;
+      sz += R2[k] * R2[k] * v2;
+    }
+    if (!std::isfinite(sxx + syy + sz)) continue;
+    szz[(size_t)i] = sz;
+    zl = std::min(zl, z[i]);
+    zh = std::max(zh, z[i]);
+    const double wf = 2.0 * kb * std::sqrt(std::max(sxx, syy));
+    m1 += wf;
+    m2 += wf * wf;
+    ++nf;
   }
   if (!(zl <= zh)) zl = zh = 0.f;
-  const int nb = (int)std::min<double>(1 << 20, std::floor(zh - zl) + 2);
+  const int nb = (int)std::min<double>(1 << 16, std::floor(zh - zl) + 2);
   v.z_lo = std::floor(zl);
-  v.zcum.assign((size_t)nb + 1, 0);
-  for (int64_t i = 0; i < g->n; ++i) {
-    if (!std::isfinite(z[i])) continue;
-    const int b = std::min(nb - 1, std::max(0, (int)(z[i] - v.z_lo)));
-    v.zcum[(size_t)b + 1] += 1;
+  v.nbins = nb;
+  v.foot_m1 = nf ? m1 / (double)nf : 0.0;
+  v.foot_m2 = nf ? m2 / (double)nf : 0.0;
+  v.cover.assign((size_t)kNSigma * nb, 0);
+  std::vector<int32_t> diff((size_t)nb + 1);
+  for (int k = 0; k < kNSigma; ++k) {
+    std::fill(diff.begin(), diff.end(), 0);
+    const double s2 = (double)kSigmaGrid[k] * kSigmaGrid[k];
+    for (int64_t i = 0; i < g->n; ++i) {
+      if (szz[(size_t)i] < 0.0) continue;
+      const double h = std::sqrt(q_cut * (s2 + szz[(size_t)i])) * 1.001 + 1e-3;
+      // bins b whose depth range [z_lo + b, z_lo + b + 1) meets [mu_z - h, mu_z + h]
+      const double lo = (double)z[i] - h - v.z_lo, hi = (double)z[i] + h - v.z_lo;
+      const int b0 = (int)std::max(0.0, std::floor(lo)), b1 = (int)std::min<double>(nb - 1, std::floor(hi));
+      if (b0 > b1) continue;
+      diff[(size_t)b0] += 1;
+      diff[(size_t)b1 + 1] -= 1;
+    }
+    int32_t run = 0;
+    for (int b = 0; b < nb; ++b) {
+      run += diff[(size_t)b];
+      v.cover[(size_t)k * nb + b] = run;
+    }
   }
-  for (int i = 0; i < nb; ++i) v.zcum[(size_t)i + 1] += v.zcum[(size_t)i];
-  v.s_axial_max = smax;
-  v.s_lateral_mean = (float)(ssum / (double)g->n);
   std::lock_guard<std::mutex> lk(sv->mu);
   *volume_id = (int32_t)sv->vols.size();
   sv->vols.push_back(std::move(v));

@@ -43,8 +43,8 @@ __global__ void k_reset(const BatchHdr* __restrict__ hdr, uint32_t* __restrict__
     ctr[kCtrRecords] = 0u;
     ctr[kCtrInstances] = 0u;
     if (clear_overflow) ctr[kCtrOverflow] = 0u;
-    for (int i = 0; i < kWorkCount; ++i) work[i] = 0u;
   }
+  for (int64_t i = t; i < kWorkCount; i += stride) work[i] = 0u;
   for (int64_t i = t; i < n; i += stride) {
     bin_lo[i] = 0u;
     bin_hi[i] = 0u;
@@ -424,7 +424,8 @@ __device__ __forceinline__ void slots_wave(const PreArgs& a, int t0, int* list, 
     // marked so that no later kernel reads them
     a.ctr[kCtrOverflow] = 1u;
     a.g_nrec[t] = 0u;
-    for (uint32_t r = rbase; r < rbase + nrec && r < a.rc.rec_cap; ++r) a.rec_meta[r].slice = kInvalidSlice;
+    if (!(a.rc.flags & GP_FLAG_FORWARD_ONLY))
+      for (uint32_t r = rbase; r < rbase + nrec && r < a.rc.rec_cap; ++r) a.rec_meta[r].slice = kInvalidSlice;
     for (uint32_t s = ibase; s < ibase + ninst && s < a.rc.inst_cap; ++s) a.inst_key[s] = a.sentinel_bin;
     nrec = 0u;
   }
@@ -576,7 +577,7 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
         make_record(cov64[gi], L.p, L.c, POSED ? a.poses + 12 * k : nullptr, sl, k, slot, a.rc.flags, rect,
                     pay, meta);
         a.rec_pay[rid] = pay;
-        a.rec_meta[rid] = meta;
+        if (!(a.rc.flags & GP_FLAG_FORWARD_ONLY)) a.rec_meta[rid] = meta;
         for (int ty = rect.ty0; ty <= rect.ty1; ++ty) {
           for (int tx = rect.tx0; tx <= rect.tx1; ++tx, ++slot) {
             a.inst_key[slot] = (uint32_t)(sl.tile_base + ty * sl.ntx + tx);

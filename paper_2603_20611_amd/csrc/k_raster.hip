@@ -184,6 +184,16 @@ __device__ __forceinline__ int slice_of(const FwdArgs& a, int n_slices, int tps,
 // resolved and its list range loaded after the first batch, its slice found
 // and first ids loaded after the second, its first records gathered after the
 // third), so a new tile rarely starts by waiting on memory.
+//
+// XQ (deep stacks on one grid whose tiles form whole 4 x 4-tile units, the
+// units a multiple of 8): eight queues, one per XCD (workgroups are placed on
+// the XCDs in turn, so workgroup w runs on XCD w mod 8).  Queue q serves the
+// units q, q + 8, ... of every slice group, a unit's 16 tiles consecutively:
+// the tiles that share a Gaussian's records mostly run on one XCD at about
+// the same time and meet in its L2, while every XCD still works through the
+// slice groups at the pace of the others.  A wavefront whose queue runs dry
+// takes tickets from the next queues.
+template <bool XQ>
 __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   __shared__ float4 buf0[64];   // x, y, a, b of the batch's records
   __shared__ float4 buf1[64];   // c, w, g, h
@@ -198,12 +208,26 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   const int col0 = (m & 3) * 4;
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
   const float fx0 = (float)col0, fy0 = (float)row0;
-  uint32_t* counter = a.work + kWorkRasterFwd;
   // work items (queue tickets) -> first bin; rem = further slices of the item
   const int sg = (tps > 0 && n_bins >= kGroupMinBins) ? kSliceGroup : 1;
   const int n_items = sg > 1 ? ((n_slices + sg - 1) / sg) * tps : n_bins;
+  // XQ: items per slice group and queue, the unit row length, this queue
+  const int ipg = XQ ? tps >> 3 : 0;
+  const int ntx4 = XQ ? a.slices[0].ntx >> 2 : 1;
+  const uint32_t n_q = XQ ? (uint32_t)(((n_slices + sg - 1) / sg) * ipg) : 0u;
+  int q = XQ ? (int)(blockIdx.x & 7u) : 0;
+  uint32_t* counter = XQ ? a.work + kWorkXcd + 32 * q : a.work + kWorkRasterFwd;
   auto first_bin = [&](uint32_t t, int& rem) -> int {
     rem = 0;
+    if constexpr (XQ) {
+      if (t >= n_q) return -1;
+      const int g = (int)t / ipg, r = (int)t - g * ipg;
+      const int u = q + 8 * (r >> 4), j = r & 15;
+      const int ux = u % ntx4, uy = u / ntx4;
+      const int tt = ((uy << 2) + (j >> 2)) * (ntx4 << 2) + (ux << 2) + (j & 3);
+      rem = min(sg, n_slices - g * sg) - 1;
+      return g * sg * tps + tt;
+    }
     if (t >= (uint32_t)n_items) return -1;
     if (sg == 1) return (int)t;
     const int g = (int)t / tps, tt = (int)t - g * tps;
@@ -214,8 +238,10 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
   // the first tile, fetched without overlap
   int rem = 0;
   // the first two items of every workgroup are fixed; the counter hands out the rest
-  const uint32_t fixed = 2u * gridDim.x;
-  int item = first_bin(blockIdx.x, rem);
+  const uint32_t gq = XQ ? gridDim.x >> 3 : gridDim.x;   // workgroups per queue
+  const uint32_t local = XQ ? blockIdx.x >> 3 : blockIdx.x;
+  const uint32_t fixed = 2u * gq;
+  int item = first_bin(local, rem);
   if (item < 0) return;
   uint32_t start = a.bin_lo[item], end = a.bin_hi[item];
   int k = slice_of(a, n_slices, tps, item);
@@ -226,7 +252,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
     n1 = src[1];
   }
   uint32_t rid_next = (start + 64 + lane < end) ? a.list[start + 64 + lane] : 0u;
-  uint32_t ticket = blockIdx.x + gridDim.x;
+  uint32_t ticket = local + gq;
 
   while (item >= 0) {
     const int bin = item;
@@ -252,6 +278,15 @@ __global__ __launch_bounds__(64) void k_raster_fwd(FwdArgs a) {
           nrem = rem - 1;
         } else {
           nitem = first_bin(ticket, nrem);
+          if constexpr (XQ) {
+            // this queue is done: take from the next ones
+            for (int k = 1; k < 8 && nitem < 0; ++k) {
+              q = (q + 1) & 7;
+              counter = a.work + kWorkXcd + 32 * q;
+              ticket = wave_take(counter) + fixed;
+              nitem = first_bin(ticket, nrem);
+            }
+          }
           took = true;
         }
         if (nitem >= 0) {
@@ -533,7 +568,20 @@ hipError_t launch_raster_fwd(const RenderConst& rc, const Workspace& ws, const L
     return hipGetLastError();
   }
   const int64_t blocks = d.bins < 8192 ? d.bins : 8192;
-  k_raster_fwd<<<(unsigned)blocks, 64, 0, s>>>(a);
+  // per-XCD queues for a deep stack on one grid of whole 4 x 4-tile units (the
+  // staged batch on the host tells; a capture for later batches does not)
+  bool xq = false;
+  if (d.host_batch && ws.h_hdr->n_slices > 0) {
+    const int tps = ws.h_hdr->tiles_per_slice;
+    const SliceDev& s0 = ws.h_slices[0];
+    xq = tps > 0 && ws.h_hdr->n_bins >= kGroupMinBins && s0.ntx * s0.nty == tps && s0.ntx % 4 == 0 &&
+         s0.nty % 4 == 0 && (tps / 16) % 8 == 0 && blocks >= 64;
+  }
+  if (xq) {
+    k_raster_fwd<true><<<(unsigned)(blocks & ~7ll), 64, 0, s>>>(a);
+  } else {
+    k_raster_fwd<false><<<(unsigned)blocks, 64, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 

@@ -258,6 +258,26 @@ def test_forward_is_deterministic(gp):
     assert torch.equal(a, b)
 
 
+def test_forward_only_flag(gp):
+    """GP_FLAG_FORWARD_ONLY renders the same images and bins and keeps no state for
+    a backward."""
+    from paper_2603_20611_amd import binding as B, render
+    _say("forward-only flag")
+    p, slices, _ = synth.tiny(4)
+    params = _gpu_params(p)
+    ws = render.Workspace()
+    a = render.render(params, slices, ws=ws).clone()
+    ws_f = render.Workspace()
+    b = render.render(params, slices, B.default_opts(flags=B.GP_FLAG_FORWARD_ONLY), ws=ws_f).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    _check_bins(ws_f, p, slices)
+    g = torch.zeros(b.numel(), device="cuda")
+    with pytest.raises(B.GpError) as e:
+        render.render_backward(params, slices, g, ws_f, B.default_opts(flags=B.GP_FLAG_FORWARD_ONLY))
+    assert e.value.status == B.GP_ESTATE
+
+
 def test_auto_workspace_grows_without_reporting_overflow(gp):
     from paper_2603_20611_amd import render
     _say("auto-sized workspace growth")

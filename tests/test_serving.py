@@ -158,29 +158,18 @@ def test_graph_and_plain_launches_agree(gp):
         assert np.array_equal(x, y)
 
 
-def _slab_volume(n, seed):
-    """A thin slab (mu_z in [15, 17]) of 95 % small and 5 % very wide
-    Gaussians: the admission estimate, built on the mean footprint, undercounts
-    its tile-list entries by about 1.6-1.9x."""
-    rng = np.random.default_rng(seed)
-    p = _volumes([n], seed=seed)[0].copy()
-    big = rng.uniform(size=n) < 0.05
-    p[2] = rng.uniform(15.0, 17.0, n)
-    p[3:6] = np.log(0.4)
-    p[3:6, big] = np.log(15.0)
-    return p.astype(np.float32), rng
-
-
 def test_overflowing_batches_are_rerun_alone(gp):
+    """Requests whose lists the admission estimate undercounts about 3x (6,000 small
+    Gaussians centred on tile corners of the 256^2 grid, each box on four tiles):
+    one alone fits the 30,000-entry capacity, two together do not, so the batches
+    the estimate admits overflow, are split, and every request reruns alone and
+    matches the oracle."""
     from paper_2603_20611_amd import binding as B
     _say("overflow retry")
-    vol, rng = _slab_volume(4000, seed=44)
-    reqs = []
-    for _ in range(12):
-        res = int(rng.choice([192, 256]))
-        reqs.append(dict(volume=0, z=float(rng.uniform(15.0, 17.0)), sigma_z=3.0, width=res, height=res,
-                         dx=EXTENT[0] / res, dy=EXTENT[1] / res))
-    # a request alone needs at most ~26k entries; two together overflow 30k
+    vol = _corner_volume(6000, 256, seed=44)
+    rng = np.random.default_rng(45)
+    reqs = [dict(volume=0, z=float(rng.uniform(15.0, 17.0)), sigma_z=3.0, width=256, height=256,
+                 dx=EXTENT[0] / 256, dy=EXTENT[1] / 256) for _ in range(12)]
     sv, _ = _server([vol], max_instances=30000, max_records=1 << 16, slots=1)
     imgs, res = _run(sv, reqs)
     st = sv.stats()
@@ -356,14 +345,31 @@ def test_submit_many_and_arrival_stamps(gp):
     sv.close()
 
 
+def _corner_volume(n, res, seed):
+    """n small isotropic Gaussians centred on tile corners of a res^2 grid over the
+    serving extent (each 3-sigma box straddles a corner: 4 tiles, against the 2.2
+    of a box of its width at a random offset), in a slab around z = 16."""
+    rng = np.random.default_rng(seed)
+    t = res // 16
+    dx = EXTENT[0] / res
+    p = np.zeros((11, n), np.float32)
+    p[0] = rng.integers(1, t, n) * 16 * dx
+    p[1] = rng.integers(1, t, n) * 16 * dx
+    p[2] = rng.uniform(15.5, 16.5, n)
+    p[3:6] = np.log(0.16)
+    p[6] = 1.0
+    p[10] = rng.uniform(0.1, 1.0, n)
+    return p
+
+
 def test_small_bucket_overflow_reruns_in_the_largest(gp):
-    """A request whose lists the admission estimate undercounts (a thin slab with 5 %
-    very wide Gaussians on a 1024^2 grid: 4.5 M entries against an estimate of
-    1.2 M) is first replayed in the smallest capacity bucket (4 M entries),
+    """A request whose lists the admission estimate undercounts (1.1 M Gaussians
+    centred on tile corners of a 1024^2 grid: 4.4 M entries against an estimate of
+    2.4 M) is first replayed in the smallest capacity bucket (4 M entries),
     overflows it, and is replayed in the largest: the image is still the oracle's."""
     from paper_2603_20611_amd import binding as B, serve
     _say("bucket overflow rerun")
-    vol, _ = _slab_volume(60000, seed=82)
+    vol = _corner_volume(1_100_000, 1024, seed=82)
     sv = serve.Server(max_gaussians=1 << 22, max_records=1 << 22, max_instances=1 << 24, max_bins=1 << 16,
                       max_batch=8, slots=1)
     sv.add_volume(torch.from_numpy(vol).cuda().contiguous())
