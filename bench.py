@@ -436,8 +436,10 @@ def extras_leg(params, slices, dev, steps=5):
     codec (encoding the set, and the 400-slice stack rendered from the coded
     set), an oblique batch (64 slices of 256 x 256 tilted by 30 degrees about x
     through the volume's centre, 1 apart along their normal) and one densify /
-    prune pass over the whole set with synthetic statistics."""
+    prune pass over the whole set with synthetic statistics.  The oblique batch is
+    timed beside the same 64 slices untilted."""
     import torch
+    from paper_2603_20611_amd import binding as B
     from paper_2603_20611_amd import render
 
     def timed(fn):
@@ -475,10 +477,20 @@ def extras_leg(params, slices, dev, steps=5):
     obl = [dict(z=float(k) + 0.5, sigma_z=SIGMA_Z, x0=-RES / 2.0, y0=-RES / 2.0, dx=1.0, dy=1.0, width=RES,
                 height=RES, pose=pose) for k in range(-32, 32)]
     img_o = torch.empty(len(obl) * RES * RES, device=dev)
-    ws_o = fixed_ws(lambda w: render.render(params, obl, ws=w, out=img_o))
-    t_ob = timed(lambda: render.render(params, obl, ws=ws_o, out=img_o))
+    # forward-only renders, as on the forward line, so that the two rates compare
+    fo = B.default_opts(flags=B.GP_FLAG_FORWARD_ONLY)
+    ws_o = fixed_ws(lambda w: render.render(params, obl, fo, ws=w, out=img_o))
+    t_ob = timed(lambda: render.render(params, obl, fo, ws=ws_o, out=img_o))
+    # the same 64 slices untilted (axial, through the centre) for comparison
+    ax64 = [dict(z=N_SLICES / 2.0 + float(k) + 0.5, sigma_z=SIGMA_Z, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=RES,
+                 height=RES) for k in range(-32, 32)]
+    ws_x = fixed_ws(lambda w: render.render(params, ax64, fo, ws=w, out=img_o))
+    t_ax = timed(lambda: render.render(params, ax64, fo, ws=ws_x, out=img_o))
     res["oblique"] = {"slices": len(obl), "tilt_deg": 30.0, "forward_ms": round(1e3 * t_ob, 4),
-                      "mpix_per_s": round(len(obl) * RES * RES / t_ob / 1e6, 1)}
+                      "mpix_per_s": round(len(obl) * RES * RES / t_ob / 1e6, 1),
+                      "axial_same_slices_ms": round(1e3 * t_ax, 4),
+                      "axial_same_slices_mpix_per_s": round(len(ax64) * RES * RES / t_ax / 1e6, 1),
+                      "oblique_over_axial_time": round(t_ob / t_ax, 3)}
     rng = np.random.default_rng(11)
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)

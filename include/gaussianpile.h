@@ -394,7 +394,9 @@ typedef struct gp_serve_result {
   int32_t status;              /* GP_OK, GP_EOVERFLOW, GP_ECANCELED, GP_EHIP     */
   int32_t batch_size;          /* requests in the batch that rendered it        */
   int64_t batch_id;
-  double latency_ms;           /* submit -> completion observed by the server   */
+  double latency_ms;           /* arrival (the submit call, or the stamp given to
+                                  gp_serve_submit_many) -> completion observed by
+                                  the server                                   */
 } gp_serve_result;
 
 typedef struct gp_server_stats {

@@ -299,14 +299,18 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
     bool sorted = true;
     for (int k = G.k0 + 1; k < G.k1 && sorted; ++k)
       sorted = hs[k].z >= hs[k - 1].z && hs[k].sigma_z == hs[G.k0].sigma_z;
-    G.flags = sorted && !poses ? kGroupSortedZ : 0;
+    // one camera pose for the whole group (bitwise): an axial stack in that frame
+    bool shared = poses != nullptr;
+    for (int k = G.k0 + 1; k < G.k1 && shared; ++k)
+      shared = std::memcmp(poses + 12 * (size_t)k, poses + 12 * (size_t)G.k0, 12 * sizeof(float)) == 0;
+    G.flags = (sorted && (!poses || shared) ? kGroupSortedZ : 0) | (shared ? kGroupSharedPose : 0);
     G.zlo = INFINITY; G.zhi = -INFINITY; G.sz2max = 0.f; G.pad = 0.f;
     for (int k = G.k0; k < G.k1; ++k) {
       G.zlo = std::min(G.zlo, hs[k].z);
       G.zhi = std::max(G.zhi, hs[k].z);
       G.sz2max = std::max(G.sz2max, hs[k].sigma_z * hs[k].sigma_z);
     }
-    if (poses) {   // depths are in each slice's own frame: no world-depth shortcut
+    if (poses && !shared) {   // depths are in each slice's own frame: no world-depth shortcut
       G.zlo = -INFINITY;
       G.zhi = INFINITY;
     }

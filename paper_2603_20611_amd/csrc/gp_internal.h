@@ -154,6 +154,11 @@ __host__ __device__ inline uint32_t rec_ntiles(const RecMeta& m) {
 // GroupDev.flags: the group's slices have non-decreasing z and one sigma_z, so
 // each Gaussian's kept slices form a range found by binary search.
 constexpr int32_t kGroupSortedZ = 1;
+// GroupDev.flags: every slice of a posed group has the same camera pose (bit
+// for bit), so the group is an axial stack in that camera frame: the
+// Gaussian's camera-frame view is computed once and, with kGroupSortedZ, its
+// kept slices are found by binary search on the camera-frame depths.
+constexpr int32_t kGroupSharedPose = 2;
 
 // The workspace: library-owned device buffers, sized by capacity.
 struct Workspace {

@@ -69,6 +69,7 @@ struct PreArgs {
   uint32_t sentinel_bin;
   const float* poses;   // [n_slices][12] of a posed batch
   int emit_chunk;       // Gaussians per workgroup round of the emit
+  int count_lg;         // log2 of the lanes per near Gaussian in the compacting count
 };
 
 // (z, sigma_z) of slice k: from the workgroup's LDS copy when there is one
@@ -233,6 +234,22 @@ __device__ __forceinline__ bool far_from_group(const PreArgs& a, const GroupDev&
   return d * d > a.rc.q_cut * (G.sz2max + smax * smax) * 1.001f;
 }
 
+// far_from_group() for a group whose slices share one camera pose: the same
+// test on the mean's depth in that camera frame (the operations of the
+// specified pose transform, so the same bits as the per-slice view) against
+// the group's camera-frame depth range; the camera-frame Sigma_zz is bounded by
+// max_i s_i^2 as in the world frame (a rotation keeps the eigenvalues).
+__device__ __forceinline__ bool far_from_pose(const PreArgs& a, const GroupDev& G, const float* p) {
+#pragma clang fp contract(off)
+  if (a.rc.flags & GP_FLAG_EXACT) return false;
+  const float* P = a.poses + 12 * G.k0;
+  const float mz = ((P[6] * p[0] + P[7] * p[1]) + P[8] * p[2]) + P[11];
+  const float lmax = fmaxf(p[3], fmaxf(p[4], p[5]));
+  const float smax = exp_spec(lmax) * a.rc.scale_mod;
+  const float d = fmaxf(fmaxf(G.zlo - mz, mz - G.zhi), 0.0f);
+  return d * d > a.rc.q_cut * (G.sz2max + smax * smax) * 1.001f;
+}
+
 // Records and list entries of Gaussian L on its slices (L loaded; L.ok false
 // for a Gaussian culled on every slice); *kr receives its kept slice range.
 template <bool POSED>
@@ -246,16 +263,38 @@ __device__ __forceinline__ void count_slices(const PreArgs& a, const float2* zs,
   }
   uint32_t nrec = 0, ninst = 0;
   if constexpr (POSED) {
-    for (int k = kb; k < ke; ++k) {
-      // the Gaussian in the slice's camera frame
-      SpecAxial ax;
-      SpecRect rect;
+    if (L.G.flags & kGroupSharedPose) {
+      // one camera frame for the group: its view once, and with sorted depths
+      // the kept range by binary search, as for axial slices (the emit's view
+      // of every slice is the same bits)
       SpecCov cv;
       float mv[3];
-      spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
-      if (!footprint(a, cv, mv, k, ax, rect)) continue;
-      nrec += 1u;
-      ninst += (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
+      spec_pose(L.c, L.p, a.poses + 12 * L.G.k0, cv, mv);
+      if (kb < ke && !(a.rc.flags & GP_FLAG_EXACT) && (L.G.flags & kGroupSortedZ))
+        kept_range(a, zs, L.G, mv[2], cv.szz, &kb, &ke);
+      // the sigma_z part of the footprint once per sigma_z, as for axial slices
+      SpecSigma sg;
+      uint32_t sg_key = 0u;
+      bool sg_have = false;
+      for (int k = kb; k < ke; ++k) {
+        SpecAxial ax;
+        SpecRect rect;
+        if (!footprint_axial(a, cv, mv, slice_geo(a.slices[k]), ax, rect, sg, sg_key, sg_have)) continue;
+        nrec += 1u;
+        ninst += (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
+      }
+    } else {
+      for (int k = kb; k < ke; ++k) {
+        // the Gaussian in the slice's camera frame
+        SpecAxial ax;
+        SpecRect rect;
+        SpecCov cv;
+        float mv[3];
+        spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
+        if (!footprint(a, cv, mv, k, ax, rect)) continue;
+        nrec += 1u;
+        ninst += (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
+      }
     }
   } else {
     // the next slice's fields are in flight while this slice is tested
@@ -281,6 +320,41 @@ __device__ __forceinline__ void count_slices(const PreArgs& a, const float2* zs,
   *kr = (uint32_t)kb | ((uint32_t)ke << 16);
 }
 
+// count_slices() of an axial Gaussian by 2^lg lanes together: lane li of the
+// group tests slices kb + li, kb + li + 2^lg, ...; the sums are formed across
+// the group (every lane of the wavefront takes part, `active` false for lanes
+// without a Gaussian).  Integer sums: the same values as one lane's loop.
+__device__ __forceinline__ void count_slices_lanes(const PreArgs& a, const float2* zs, Loaded& L, bool active,
+                                                   int lg, uint32_t* nrec_out, uint32_t* ninst_out, uint32_t* kr) {
+  const int cl = 1 << lg, li = (int)(threadIdx.x & (cl - 1));
+  int kb = L.G.k0, ke = L.G.k1;
+  if (!active || !L.ok) {
+    ke = kb;
+  } else if (!(a.rc.flags & GP_FLAG_EXACT) && (L.G.flags & kGroupSortedZ)) {
+    kept_range(a, zs, L.G, L.p[2], L.c.szz, &kb, &ke);
+  }
+  uint32_t nrec = 0, ninst = 0;
+  SpecSigma sg;
+  uint32_t sg_key = 0u;
+  bool sg_have = false;
+  for (int k = kb + li; k < ke; k += cl) {
+    const SliceGeo geo = slice_geo(a.slices[k]);
+    SpecAxial ax;
+    SpecRect rect;
+    if (footprint_axial(a, L.c, L.p, geo, ax, rect, sg, sg_key, sg_have)) {
+      nrec += 1u;
+      ninst += (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
+    }
+  }
+  for (int o = 1; o < cl; o <<= 1) {
+    nrec += __shfl_xor(nrec, o, 64);
+    ninst += __shfl_xor(ninst, o, 64);
+  }
+  *nrec_out = nrec;
+  *ninst_out = ninst;
+  *kr = (uint32_t)kb | ((uint32_t)ke << 16);
+}
+
 // Per-Gaussian outputs of the count and the wavefront's sums (whole wavefronts).
 __device__ __forceinline__ void count_store(const PreArgs& a, int t, uint32_t nrec, uint32_t ninst, uint32_t kr) {
   a.g_nrec[t] = nrec;
@@ -299,8 +373,14 @@ template <int DT, bool POSED>
 __device__ __forceinline__ void count_one(const PreArgs& a, const float2* zs, int n_groups, int t) {
   Loaded L;
   load_params<DT>(a, n_groups, t, L);
-  // the world-depth shortcuts hold for axial slices only
-  if (!POSED && L.ok && far_from_group(a, L.G, L.p)) L.ok = false;   // culled on every slice
+  // the world-depth shortcuts hold for axial slices, and in the camera frame
+  // for a group of slices sharing one pose
+  bool far = false;
+  if (L.ok) {
+    if (!POSED) far = far_from_group(a, L.G, L.p);
+    else if (L.G.flags & kGroupSharedPose) far = far_from_pose(a, L.G, L.p);
+  }
+  if (far) L.ok = false;   // culled on every slice
   else activate(a, L);
   uint32_t nrec, ninst, kr;
   count_slices<POSED>(a, zs, L, &nrec, &ninst, &kr);
@@ -457,7 +537,9 @@ struct EmitGauss {
 
 // footprint() of an axial slice for the emit: the stored sigma_z part when the
 // slice's sigma_z^2 is the key's, else computed from the reloaded Gaussian t.
-template <int DT>
+// With POSED, e holds the Gaussian in the camera frame its group's slices share
+// (the reload takes the same view).
+template <int DT, bool POSED>
 __device__ __forceinline__ bool footprint_emit(const PreArgs& a, int n_groups, int t, const EmitGauss& e, int k,
                                                SpecAxial& ax, SpecRect& rect) {
   const SliceDev& sl = a.slices[k];
@@ -469,7 +551,14 @@ __device__ __forceinline__ bool footprint_emit(const PreArgs& a, int n_groups, i
     Loaded L;
     load_params<DT>(a, n_groups, t, L);
     activate(a, L);
-    g = spec_sigma(L.c, ax, a.rc.bbox);
+    if constexpr (POSED) {
+      SpecCov cv;
+      float mv[3];
+      spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
+      g = spec_sigma(cv, ax, a.rc.bbox);
+    } else {
+      g = spec_sigma(L.c, ax, a.rc.bbox);
+    }
   }
   const bool vis = spec_rect_from(g, e.mx, e.my, ax, sl.x0, sl.y0, sl.dx, sl.dy, sl.ntx, sl.nty, rect);
   if (exact) {
@@ -481,7 +570,7 @@ __device__ __forceinline__ bool footprint_emit(const PreArgs& a, int n_groups, i
 
 template <int DT, int W, bool POSED>
 __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const int* list, uint32_t j0,
-                                          uint32_t n_active, double (*cov64)[6], EmitGauss* eg) {
+                                          uint32_t n_active, double (*cov64)[6], EmitGauss* eg, float4* pw) {
   const int lane = threadIdx.x & 63;
   const uint32_t j = j0 + (uint32_t)lane;
   const int t = j < n_active ? list[j] : 0;
@@ -500,6 +589,21 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
       const SpecAxial ax0 = spec_axial(Lq.p[2], c.szz, s0.z, s0.sigma_z);
       eg[lane] = EmitGauss{Lq.p[0], Lq.p[1], Lq.p[2], Lq.p[10], c.s0, c.s1, c.s2, c.szz,
                            __float_as_uint(ax0.s2), spec_sigma(c, ax0, a.rc.bbox)};
+    } else {
+      // slices sharing one pose: the Gaussian's view in that camera frame,
+      // kept like an axial Gaussian's (the world mean for the record)
+      const bool sh = (Lq.G.flags & kGroupSharedPose) != 0;
+      pw[lane] = make_float4(Lq.p[0], Lq.p[1], Lq.p[2], sh ? 1.0f : 0.0f);
+      if (sh) {
+        activate(a, Lq);
+        SpecCov cv;
+        float mv[3];
+        spec_pose(Lq.c, Lq.p, a.poses + 12 * Lq.G.k0, cv, mv);
+        const SliceDev& s0 = a.slices[krange & 0xFFFFu];
+        const SpecAxial ax0 = spec_axial(mv[2], cv.szz, s0.z, s0.sigma_z);
+        eg[lane] = EmitGauss{mv[0], mv[1], mv[2], Lq.p[10], cv.s0, cv.s1, cv.s2, cv.szz,
+                             __float_as_uint(ax0.s2), spec_sigma(cv, ax0, a.rc.bbox)};
+      }
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -517,9 +621,28 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
     if (j0 + (uint32_t)gi >= n_active) continue;
     Loaded L;
     EmitGauss e{};
+    bool shared_view = false;
     if constexpr (POSED) {
-      load_params<DT>(a, n_groups, tg, L);
-      activate(a, L);
+      const float4 w4 = pw[gi];
+      shared_view = w4.w != 0.0f;
+      if (shared_view) {
+        // the camera-frame view its entry's lane formed; the record takes the
+        // world mean, the intensity and the scales
+        e = eg[gi];
+#pragma unroll
+        for (int r = 0; r < 11; ++r) L.p[r] = 0.0f;
+        L.p[0] = w4.x;
+        L.p[1] = w4.y;
+        L.p[2] = w4.z;
+        L.p[10] = e.inten;
+        L.c = SpecCov{};
+        L.c.s0 = e.s0;
+        L.c.s1 = e.s1;
+        L.c.s2 = e.s2;
+      } else {
+        load_params<DT>(a, n_groups, tg, L);
+        activate(a, L);
+      }
     } else {
       // the group's Gaussian as its entry's lane activated it (the same values)
       e = eg[gi];
@@ -546,11 +669,15 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
       bool kept = false;
       if constexpr (POSED) {
         if (k < ke) {
-          spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
-          kept = footprint(a, cv, mv, k, ax, rect);
+          if (shared_view) {
+            kept = footprint_emit<DT, true>(a, n_groups, tg, e, k, ax, rect);
+          } else {
+            spec_pose(L.c, L.p, a.poses + 12 * k, cv, mv);
+            kept = footprint(a, cv, mv, k, ax, rect);
+          }
         }
       } else {
-        kept = k < ke && footprint_emit<DT>(a, n_groups, tg, e, k, ax, rect);
+        kept = k < ke && footprint_emit<DT, false>(a, n_groups, tg, e, k, ax, rect);
       }
       const uint32_t nt = kept ? (uint32_t)((rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1)) : 0u;
       uint32_t rpos = 0u, ipos = 0u, rtot = 1u, itot = nt;
@@ -652,12 +779,24 @@ __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
       }
       __syncthreads();
       const int n = s_n;
-      for (int j = threadIdx.x; j < n; j += 256) {
-        const int i = s_list[j];
+      // the near Gaussians, 2^count_lg lanes each (one slice per lane and
+      // round): a narrow batch has few near Gaussians per chunk, and one lane
+      // each would leave a single wavefront running long serial chains
+      const int lg = a.count_lg;
+      for (int jb = 0; jb < n; jb += (256 >> lg)) {
+        const int j = jb + (int)(threadIdx.x >> lg);
+        const bool active = j < n;
+        const int i = active ? s_list[j] : 0;
         Loaded L;
         load_params<DT>(a, n_groups, base + i, L);
         activate(a, L);
-        count_slices<POSED>(a, zs, L, &s_nrec[i], &s_ninst[i], &s_kr[i]);
+        uint32_t nr, ni, kr;
+        count_slices_lanes(a, zs, L, active, lg, &nr, &ni, &kr);
+        if (active && (threadIdx.x & ((1u << lg) - 1u)) == 0u) {
+          s_nrec[i] = nr;
+          s_ninst[i] = ni;
+          s_kr[i] = kr;
+        }
       }
       __syncthreads();
       // whole wavefronts (chunk and base are multiples of 64; total is too)
@@ -672,18 +811,22 @@ __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
 
 // A workgroup takes `chunk` consecutive Gaussians at a time (a multiple of 256,
 // at most kEmitChunk): their slots (wavefront scans), then the emit of those
-// that have records, 64 per wavefront.  A batch of a few slices reaches a small
-// fraction of a large set, and without the gathering most lanes would idle on
-// Gaussians without records; a deep stack reaches nearly all of them and takes
-// 256 at a time (one wavefront's worth each, the most parallel form).
-constexpr int kEmitChunk = 2048;
+// that have records, spread over the four wavefronts.  A batch of a few slices
+// reaches a small fraction of a large set, and without the gathering most
+// lanes would idle on Gaussians without records; 512 at a time gives a grid of
+// about four workgroups per CU on 500k Gaussians (2,048 at a time left one per
+// CU and took 0.028 ms per 8-slice emit against 0.018).  A deep stack reaches
+// nearly all of them and takes 256 at a time (one wavefront's worth each, the
+// most parallel form).
+constexpr int kEmitChunk = 512;
 
 template <int DT, int W, bool POSED>
 __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   __shared__ int list[kEmitChunk];
   __shared__ int n_list;
   __shared__ double cov64[4][64][6];
-  __shared__ EmitGauss egs[4][POSED ? 1 : 64];
+  __shared__ EmitGauss egs[4][64];
+  __shared__ float4 pws[4][POSED ? 64 : 1];
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   const int wave = threadIdx.x >> 6;
@@ -703,7 +846,7 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane(n_w[wave]);
-      if (n > 0u) emit_wave<DT, W, POSED>(a, n_groups, wl, 0u, n, cov64[wave], egs[wave]);
+      if (n > 0u) emit_wave<DT, W, POSED>(a, n_groups, wl, 0u, n, cov64[wave], egs[wave], pws[wave]);
     }
     return;
   }
@@ -713,8 +856,14 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
     for (int t0 = base + wave * 64; t0 < min(base + chunk, total); t0 += 256) slots_wave(a, t0, list, &n_list);
     __syncthreads();
     const uint32_t n = (uint32_t)n_list;
-    for (uint32_t j0 = (uint32_t)wave * 64u; j0 < n; j0 += 256u)
-      emit_wave<DT, W, POSED>(a, n_groups, list, j0, n, cov64[wave], egs[wave]);
+    // the list spread over the four wavefronts in whole rounds of 64 / W
+    // entries: a short list (a narrow batch) in one wavefront would leave the
+    // other three idle and take W serial rounds
+    constexpr uint32_t kRound = 64u / (uint32_t)W;
+    uint32_t q = ((n + 3u) / 4u + kRound - 1u) / kRound * kRound;
+    q = q > 64u ? 64u : (q < kRound ? kRound : q);
+    for (uint32_t j0 = (uint32_t)wave * q; j0 < n; j0 += 4u * q)
+      emit_wave<DT, W, POSED>(a, n_groups, list, j0, j0 + q < n ? j0 + q : n, cov64[wave], egs[wave], pws[wave]);
     __syncthreads();   // list and n_list are rewritten by the next chunk
   }
 }
@@ -774,7 +923,7 @@ hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDi
 static PreArgs pre_args(const RenderConst& rc, const Workspace& ws, uint32_t sentinel_bin) {
   return PreArgs{rc, ws.d_hdr, ws.d_groups, ws.d_slices, ws.d_ctr, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase,
                  ws.d_g_nrec, ws.d_g_ninst, ws.d_g_krange, ws.d_wave_cnt, ws.d_inst_key, ws.d_inst_val,
-                 sentinel_bin, ws.d_poses, 256};
+                 sentinel_bin, ws.d_poses, 256, 0};
 }
 
 hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s) {
@@ -787,9 +936,11 @@ hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const La
   }
   // groups of at most 8 slices: most Gaussians are far from all of them
   if (d.emit_width <= 8) {
+    PreArgs ac = a;
+    while ((1 << ac.count_lg) < d.emit_width) ++ac.count_lg;   // one lane per slice of a group
     int64_t blocks = (d.gauss + kCountChunk - 1) / kCountChunk;
     if (blocks > 16384) blocks = 16384;
-    return launch_count_p<false, true>(a, rc.attr_dtype, (unsigned)blocks, s);
+    return launch_count_p<false, true>(ac, rc.attr_dtype, (unsigned)blocks, s);
   }
   int64_t blocks = (d.gauss + 255) / 256;
   if (blocks > 16384) blocks = 16384;

@@ -14,7 +14,9 @@
 // where W* is the (symmetric) window filter of the three coefficient maps.
 //
 // Two stencil kernels, each over 32 x 16 output tiles with a 5-pixel halo in
-// LDS and the 11-tap filter applied separably (rows, then columns):
+// LDS and the 11-tap filter applied separably (columns, then rows: the column
+// pass covers only the output rows, and the smaller LDS footprint lets four
+// and six workgroups share a CU, so that a 256^2 x 8 batch runs in one round):
 //   k_ssim_stats: five window sums -> S and the three coefficient maps;
 //   k_ssim_grad:  window sums of the three maps -> dL/dI.
 // Both compute in float64: the moments form of the variances (E[x^2] - mx^2)
@@ -55,7 +57,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 __global__ __launch_bounds__(256) void k_ssim_stats(SsimArgs a) {
   __shared__ float xs[kRH][kRW], ys[kRH][kRW];
-  __shared__ double hs[5][kRH][kSW];
+  __shared__ double vs[5][kSH][kRW];   // column sums (36 KB in all: four workgroups per CU)
   __shared__ double red[4];
   const int s = blockIdx.z;
   const int ox = blockIdx.x * kSW, oy = blockIdx.y * kSH;
@@ -70,23 +72,25 @@ __global__ __launch_bounds__(256) void k_ssim_stats(SsimArgs a) {
     ys[r][c] = in ? Y[(int64_t)gy * a.W + gx] : 0.f;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kRH * kSW; i += 256) {
-    const int r = i / kSW, c = i % kSW;
+  // the filter along columns first (the output rows over the halo's width),
+  // then along rows
+  for (int i = threadIdx.x; i < kSH * kRW; i += 256) {
+    const int r = i / kRW, c = i % kRW;
     double sx = 0.0, sy = 0.0, sxx = 0.0, syy = 0.0, sxy = 0.0;
 #pragma unroll
     for (int k = 0; k <= 2 * kR; ++k) {
-      const double u = xs[r][c + k], v = ys[r][c + k], wk = a.w[k];
+      const double u = xs[r + k][c], v = ys[r + k][c], wk = a.w[k];
       sx += wk * u;
       sy += wk * v;
       sxx += wk * (u * u);
       syy += wk * (v * v);
       sxy += wk * (u * v);
     }
-    hs[0][r][c] = sx;
-    hs[1][r][c] = sy;
-    hs[2][r][c] = sxx;
-    hs[3][r][c] = syy;
-    hs[4][r][c] = sxy;
+    vs[0][r][c] = sx;
+    vs[1][r][c] = sy;
+    vs[2][r][c] = sxx;
+    vs[3][r][c] = syy;
+    vs[4][r][c] = sxy;
   }
   __syncthreads();
   double part_l1 = 0.0, part_d = 0.0;
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(256) void k_ssim_stats(SsimArgs a) {
     for (int k = 0; k <= 2 * kR; ++k) {
       const double wk = a.w[k];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) m[q] += wk * hs[q][r + k][c];
+      for (int q = 0; q < 5; ++q) m[q] += wk * vs[q][r][c + k];
     }
     const double mx = m[0], my = m[1];
     const double vx = m[2] - mx * mx, vy = m[3] - my * my, cxy = m[4] - mx * my;
@@ -147,8 +151,9 @@ __global__ __launch_bounds__(256) void k_ssim_loss_sum(const double* __restrict_
 }
 
 __global__ __launch_bounds__(256) void k_ssim_grad(SsimArgs a) {
+  // the three maps with their halo (26 KB: six workgroups per CU); after the
+  // column pass its first kSH rows hold the column sums
   __shared__ double ms[3][kRH][kRW];
-  __shared__ double hs[3][kRH][kSW];
   const int s = blockIdx.z;
   const int ox = blockIdx.x * kSW, oy = blockIdx.y * kSH;
   const int64_t base = (int64_t)s * a.H * a.W;
@@ -161,34 +166,49 @@ __global__ __launch_bounds__(256) void k_ssim_grad(SsimArgs a) {
     for (int q = 0; q < 3; ++q) ms[q][r][c] = in ? a.maps[q * a.npix + o] : 0.0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kRH * kSW; i += 256) {
-    const int r = i / kSW, c = i % kSW;
-    double t[3] = {0.0, 0.0, 0.0};
+  constexpr int kCol = (kSH * kRW + 255) / 256;   // column sums per thread
+  double t[kCol][3];
 #pragma unroll
-    for (int k = 0; k <= 2 * kR; ++k) {
-      const double wk = a.w[k];
+  for (int it = 0; it < kCol; ++it) {
+    const int i = threadIdx.x + it * 256;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) t[q] += wk * ms[q][r][c + k];
+    for (int q = 0; q < 3; ++q) t[it][q] = 0.0;
+    if (i < kSH * kRW) {
+      const int r = i / kRW, c = i % kRW;
+#pragma unroll
+      for (int k = 0; k <= 2 * kR; ++k) {
+        const double wk = a.w[k];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) t[it][q] += wk * ms[q][r + k][c];
+      }
     }
+  }
+  __syncthreads();   // every column sum read its inputs before any is stored
 #pragma unroll
-    for (int q = 0; q < 3; ++q) hs[q][r][c] = t[q];
+  for (int it = 0; it < kCol; ++it) {
+    const int i = threadIdx.x + it * 256;
+    if (i < kSH * kRW) {
+      const int r = i / kRW, c = i % kRW;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) ms[q][r][c] = t[it][q];
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kSH * kSW; i += 256) {
     const int r = i / kSW, c = i % kSW;
     const int gx = ox + c, gy = oy + r;
     if (gx >= a.W || gy >= a.H) continue;
-    double t[3] = {0.0, 0.0, 0.0};
+    double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k <= 2 * kR; ++k) {
       const double wk = a.w[k];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) t[q] += wk * hs[q][r + k][c];
+      for (int q = 0; q < 3; ++q) u[q] += wk * ms[q][r][c + k];
     }
     const int64_t o = base + (int64_t)gy * a.W + gx;
     const double xv = a.x[o], yv = a.y[o];
     const double sg = xv > yv ? 1.0 : (xv < yv ? -1.0 : 0.0);
-    const double dS = t[0] + 2.0 * xv * t[1] + yv * t[2];
+    const double dS = u[0] + 2.0 * xv * u[1] + yv * u[2];
     a.grad[o] = (float)(a.inv_n * (sg - a.lam * dS));
   }
 }

@@ -46,6 +46,12 @@ def _slices(case):
         R = np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])
         return [dict(z=x, sigma_z=1.5, x0=0.0, y0=0.0, dx=1.0, dy=0.5, width=48, height=33,
                      pose=np.concatenate([R.reshape(-1), np.zeros(3)]).astype(np.float32)) for x in (20.0, 33.5)]
+    if case == "tilted_stack":
+        # 20 parallel planes of one pose 0.8 apart along the normal (an axial stack
+        # in the camera frame: binary search on the camera-frame depths, 16-wide emit)
+        R = Rotation.from_euler("xyz", [30.0, 0.0, 10.0], degrees=True).as_matrix()
+        return [dict(z=-8.0 + 0.8 * k, sigma_z=1.2, x0=-34.0, y0=-30.0, dx=1.0, dy=1.0, width=68, height=60,
+                     pose=_about(R, c, (0.0, 0.0, 0.0))) for k in range(20)]
     if case == "mixed":
         R = Rotation.from_euler("zyx", [70.0, 10.0, -20.0], degrees=True).as_matrix()
         return [dict(z=5.0, sigma_z=0.8, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=64, height=48),
@@ -77,7 +83,7 @@ def _split(flat, slices):
     return out
 
 
-@pytest.mark.parametrize("case", ["tilted", "sagittal", "mixed"])
+@pytest.mark.parametrize("case", ["tilted", "sagittal", "mixed", "tilted_stack"])
 def test_oblique_forward_matches_oracle(gp, case):
     from paper_2603_20611_amd import render
     _say(f"forward {case}")
