@@ -285,7 +285,7 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
     tb += (int64_t)d.ntx * d.nty;
     off += (int64_t)hs[k].width * hs[k].height;
   }
-  int64_t gb = 0;
+  int64_t gb = 0, max_group_bins = 0;
   for (int g = 0; g < ng; ++g) {
     GroupDev& G = ws->h_groups[g];
     G.means = static_cast<const float*>(groups[g].g->means);
@@ -315,6 +315,11 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
       G.zhi = INFINITY;
     }
     for (int k = G.k0; k < G.k1; ++k) ws->h_slices[k].group = g;
+    if (G.k1 > G.k0) {
+      const int64_t first = ws->h_slices[G.k0].tile_base;
+      const SliceDev& last = ws->h_slices[G.k1 - 1];
+      max_group_bins = std::max<int64_t>(max_group_bins, (int64_t)last.tile_base + (int64_t)last.ntx * last.nty - first);
+    }
     gb += (groups[g].g->n + 63) / 64 * 64;
   }
   ws->h_hdr->n_groups = ng;
@@ -327,6 +332,7 @@ gp_status stage_batch(Workspace* ws, const GroupIn* groups, int ng, const gp_sli
     if (ws->h_slices[k].ntx * ws->h_slices[k].nty != tps) tps = 0;
   ws->h_hdr->tiles_per_slice = tps;
   plan->ns = ns; plan->ng = ng; plan->nbins = nbins; plan->total_gauss = total_gauss; plan->npix = off;
+  plan->max_group_bins = max_group_bins;
   plan->attr_dtype = ng > 0 ? groups[0].g->attr_dtype : GP_F32;
   plan->posed = poses ? 1 : 0;
   if (poses) std::memcpy(ws->h_poses, poses, sizeof(float) * 12 * (size_t)ns);
@@ -366,7 +372,9 @@ gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hi
     gp_status st = reserve_lists(ws, guess_rec, 4 * guess_rec);
     if (st != GP_OK) return st;
   }
-  const int bits = key_bits(d.bins);
+  // sort by the bits that tell one group's bins apart (entries are written
+  // group after group; a group's bins are one contiguous run of keys)
+  const int bits = key_bits(d.sort_bins > 0 ? std::min(d.sort_bins, d.bins) : d.bins);
   gp_status st = reserve_sort(ws, bits);
   if (st != GP_OK) return st;
   const bool clear_ovf = ws->auto_size || ws->overflow_per_forward;
@@ -400,10 +408,12 @@ gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hi
   GP_HIP(timed(ws, GP_STAGE_EMIT, s, [&] { return launch_pre_emit(rc, *ws, d, sentinel, s); }));
   GP_HIP(timed(ws, GP_STAGE_SORT, s, [&] {
     const int64_t n_sort = ws->auto_size ? std::min<int64_t>(ws->last_instances, icap) : icap;
-    hipError_t e = launch_radix_sort(ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, d_count,
+    const uint32_t* d_end = ws->d_ctr + kCtrSortEnd;   // before the first overflowed Gaussian's slots
+    hipError_t e = launch_radix_sort(ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, d_count, d_end,
                                      std::max<int64_t>(n_sort, 1), bits, ws->d_hist,
                                      reinterpret_cast<uint32_t*>(ws->d_scan_part), s, &ws->d_list_key, &ws->d_list);
-    if (e == hipSuccess) e = launch_bin_ranges(ws->d_hdr, ws->d_list_key, d_count, icap, ws->d_bin_lo, ws->d_bin_hi, s);
+    if (e == hipSuccess)
+      e = launch_bin_ranges(ws->d_hdr, ws->d_list_key, d_count, d_end, icap, ws->d_bin_lo, ws->d_bin_hi, s);
     return e;
   }));
   GP_HIP(timed(ws, GP_STAGE_RASTER_FWD, s, [&] { return launch_raster_fwd(rc, *ws, d, s); }));
@@ -798,7 +808,7 @@ gp_status gp_voxelize(gp_workspace* w, const gp_gaussians* g, const gp_volume_gr
     if ((st = reserve_sort(ws, bits)) != GP_OK) return st;
     ws->last_stream = s;
     GP_HIP(launch_vox_emit(*ws, g, grid, o, L, s));
-    GP_HIP(launch_radix_sort(ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, ws->d_ctr + kCtrInstances,
+    GP_HIP(launch_radix_sort(ws->d_inst_key, ws->d_inst_val, ws->d_key2, ws->d_val2, ws->d_ctr + kCtrInstances, nullptr,
                              std::max<int64_t>(K, 1), bits, ws->d_hist, reinterpret_cast<uint32_t*>(ws->d_scan_part),
                              s, &ws->d_list_key, &ws->d_list));
     GP_HIP(launch_vox_ranges(*ws, L, (uint32_t)K, s));

@@ -107,6 +107,11 @@ struct LaunchDims {
   int32_t emit_width = 1;   // lanes per Gaussian in the emit (1, 2, 4, 8 or 16)
   int32_t posed = 0;        // the slices carry camera poses
   int32_t host_batch = 0;   // the host staging holds this batch (not a capture for later batches)
+  // the most bins of one group (0: `bins`).  The emit writes a batch's list
+  // entries group after group and a group's bins are one contiguous run of
+  // keys, so a stable sort by the low bits that tell one group's bins apart
+  // leaves every bin's entries contiguous and in Gaussian order.
+  int64_t sort_bins = 0;
 };
 // Emit width for groups of at most `slices` slices each.
 inline int32_t emit_width_for(int64_t slices) {
@@ -117,7 +122,10 @@ inline int32_t emit_width_for(int64_t slices) {
 
 // Counters written by the preprocess.
 // (records and instances are adjacent: the wavefront scan writes both as one uint2)
-enum { kCtrRecords = 0, kCtrInstances = 1, kCtrOverflow = 2, kCtrCount = 4 };
+// kCtrSortEnd: the first instance slot of an overflowed Gaussian (every later
+// slot is one too: slots are a scan in Gaussian order), all ones if none; the
+// sort and the bin ranges stop there.
+enum { kCtrRecords = 0, kCtrInstances = 1, kCtrOverflow = 2, kCtrSortEnd = 3, kCtrCount = 4 };
 
 // Record payload in pixel space, 32 bytes, gathered by the rasterisers:
 //   the mean in pixel-index units as ax + xr, ay + yr, with the anchors ax, ay
@@ -270,6 +278,7 @@ struct GroupIn {
 struct BatchPlan {
   int32_t ns, ng;
   int64_t nbins, total_gauss, npix;
+  int64_t max_group_bins;   // the most bins of one group
   int32_t attr_dtype;
   int32_t posed;
 };
@@ -305,9 +314,11 @@ int64_t scan_parts_needed(int64_t max_n);
 int radix_passes(int bits);
 int64_t radix_hist_entries(int bits, int64_t cap);
 hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* d_count,
+                             const uint32_t* d_count2,
                              int64_t cap, int bits, uint32_t* hist, uint32_t* scan_part, hipStream_t s,
                              uint32_t** k_out, uint32_t** v_out);
-hipError_t launch_bin_ranges(const BatchHdr* hdr, const uint32_t* key, const uint32_t* d_count, int64_t cap,
+hipError_t launch_bin_ranges(const BatchHdr* hdr, const uint32_t* key, const uint32_t* d_count,
+                             const uint32_t* d_count2, int64_t cap,
                              uint32_t* lo, uint32_t* hi, hipStream_t s);
 inline int key_bits(int64_t n_bins) {
   int b = 0;

@@ -122,6 +122,11 @@ struct Bucket {
   int64_t gauss, bins, rec, inst;
 };
 constexpr int kMaxBuckets = 3;
+// The captured launches sort list entries by the low 14 bits of their bin:
+// enough for a group (one volume's consecutive requests) of up to 16,383
+// tiles, four 1024^2 slices.  Larger groups are split; a single request of
+// more tiles is launched without the graphs, with the bits it needs.
+constexpr int64_t kGroupSortBins = 16383;
 
 struct Slot {
   Server* sv = nullptr;
@@ -132,6 +137,7 @@ struct Slot {
   bool busy = false, finished = false;
   bool rerun = false;         // overflowed a smaller bucket: replay the largest
   int bucket = 0;
+  int64_t group_bins = 0;     // the most bins of one group of the batch
   double est_rec = 0.0, est_inst = 0.0;   // admission estimates of the batch
   int64_t batch_id = 0;
   double t_done = 0.0;
@@ -206,7 +212,9 @@ gp_status capture_slot(Server* sv, Slot* sl) {
     const Bucket& k = sv->buckets[b];
     hipGraph_t graph = nullptr;
     GP_HIP(hipStreamBeginCapture(sl->stream, hipStreamCaptureModeThreadLocal));
-    const gp_status st = enqueue_forward(sl->ws, sv->rc, LaunchDims{k.gauss, k.bins}, sl->stream, k.rec, k.inst);
+    LaunchDims d{k.gauss, k.bins};
+    d.sort_bins = kGroupSortBins;
+    const gp_status st = enqueue_forward(sl->ws, sv->rc, d, sl->stream, k.rec, k.inst);
     hipError_t e = hipStreamEndCapture(sl->stream, &graph);
     if (st != GP_OK) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -238,10 +246,11 @@ gp_status launch_bucket(Server* sv, Slot* sl, const BatchPlan* plan, int b) {
   Workspace* ws = sl->ws;
   sl->bucket = b;
   const Bucket& k = sv->buckets[b];
-  if (sv->cfg.use_graphs) {
+  if (sv->cfg.use_graphs && sl->group_bins <= kGroupSortBins) {
     GP_HIP(hipGraphLaunch(sl->exec[b], sl->stream));
   } else {
-    const LaunchDims d = plan ? LaunchDims{plan->total_gauss, plan->nbins} : LaunchDims{k.gauss, k.bins};
+    LaunchDims d = plan ? LaunchDims{plan->total_gauss, plan->nbins} : LaunchDims{k.gauss, k.bins};
+    d.sort_bins = sl->group_bins;
     const gp_status st = enqueue_forward(ws, sv->rc, d, sl->stream, k.rec, k.inst);
     if (st != GP_OK) return st;
   }
@@ -271,11 +280,16 @@ gp_status launch_batch(Server* sv, Slot* sl) {
   std::vector<gp_slice> hs(reqs.size());
   std::vector<float*> outs(reqs.size());
   sets.reserve(reqs.size());
+  int64_t group_tiles = 0;
   for (size_t k = 0; k < reqs.size(); ++k) {
     const gp_request& r = reqs[k].r;
     hs[k] = gp_slice{r.z, r.sigma_z, r.x0, r.y0, r.dx, r.dy, r.width, r.height};
     outs[k] = reqs[k].out;
-    if (groups.empty() || sets.back().means != reqs[k].vol.means) {
+    // a new group for a new volume, or where the group would outgrow the
+    // captured sort's bits
+    const int64_t t = tiles_of(r);
+    if (groups.empty() || sets.back().means != reqs[k].vol.means || group_tiles + t > kGroupSortBins) {
+      group_tiles = 0;
       const VolView& v = reqs[k].vol;
       sets.push_back(gp_gaussians{v.means, v.attrs, v.n, v.stride,
                                   sv->cfg.attr_dtype == GP_QM ? GP_QM : GP_F32, sv->cfg.attr_dtype});
@@ -283,12 +297,14 @@ gp_status launch_batch(Server* sv, Slot* sl) {
     } else {
       groups.back().k1 = (int32_t)k + 1;
     }
+    group_tiles += t;
   }
   for (size_t g = 0; g < groups.size(); ++g) groups[g].g = &sets[g];
   BatchPlan plan{};
   gp_status st = stage_batch(ws, groups.data(), (int)groups.size(), hs.data(), (int)hs.size(), nullptr,
                              outs.data(), &plan);
   if (st != GP_OK) return st;
+  sl->group_bins = plan.max_group_bins;
   if ((st = upload_batch(ws, plan, sl->stream)) != GP_OK) return st;
   return launch_bucket(sv, sl, &plan, pick_bucket(sv, plan, sl->est_rec, sl->est_inst));
 }
@@ -334,24 +350,36 @@ bool take_batch(Server* sv, Slot* sl) {
   if (sv->queue.empty()) return false;
   int64_t bins = 0, gauss = 0;
   double inst = 0.0, recs = 0.0;
+  // volumes in the batch and the tiles of each one's last group (launch_batch
+  // groups a volume's requests in this order and starts a new group, which
+  // counts the volume's Gaussians again, past kGroupSortBins tiles)
   std::vector<int32_t> vols_in;
+  std::vector<int64_t> vol_tiles;
   sl->est_rec = sl->est_inst = 0.0;
   while (!sv->queue.empty() && (int)sl->reqs.size() < sv->cfg.max_batch) {
     const Request& r = sv->queue.front();
     if (r.solo && !sl->reqs.empty()) break;
-    const bool new_vol = std::find(vols_in.begin(), vols_in.end(), r.r.volume_id) == vols_in.end();
-    const int64_t add_g = new_vol ? (sv->vols[r.r.volume_id].n + 63) / 64 * 64 : 0;
+    const size_t vi = (size_t)(std::find(vols_in.begin(), vols_in.end(), r.r.volume_id) - vols_in.begin());
+    const bool new_vol = vi == vols_in.size();
+    const int64_t t = tiles_of(r.r);
+    const bool new_group = new_vol || vol_tiles[vi] + t > kGroupSortBins;
+    const int64_t add_g = new_group ? (sv->vols[r.r.volume_id].n + 63) / 64 * 64 : 0;
     const double add_r = est_records(sv, r.r);
     const double add_i = est_instances(sv, r.r, add_r);
     if (!sl->reqs.empty() && (bins + tiles_of(r.r) > sv->cfg.max_bins || gauss + add_g > sv->cfg.max_gaussians ||
                               inst + add_i > (double)sv->cfg.max_instances ||
                               recs + add_r > (double)sv->cfg.max_records))
       break;
-    bins += tiles_of(r.r);
+    bins += t;
     gauss += add_g;
     inst += add_i;
     recs += add_r;
-    if (new_vol) vols_in.push_back(r.r.volume_id);
+    if (new_vol) {
+      vols_in.push_back(r.r.volume_id);
+      vol_tiles.push_back(t);
+    } else {
+      vol_tiles[vi] = new_group ? t : vol_tiles[vi] + t;
+    }
     sl->reqs.push_back(r);
     const Volume& v = sv->vols[r.r.volume_id];
     sl->reqs.back().vol = VolView{v.means, v.attrs, v.n, v.stride};

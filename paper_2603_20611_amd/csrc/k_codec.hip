@@ -195,7 +195,7 @@ hipError_t launch_encode(const float* means, const float* attrs, int64_t n, int6
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // stable sort by the low 32 key bits, then by the high 10 (keys gathered in that order)
   uint32_t *k_sorted = nullptr, *i_sorted = nullptr;
-  e = launch_radix_sort(t.key_lo, t.idx, t.key2, t.val2, t.count, n, 32, t.hist, t.scan_part, s, &k_sorted, &i_sorted);
+  e = launch_radix_sort(t.key_lo, t.idx, t.key2, t.val2, t.count, nullptr, n, 32, t.hist, t.scan_part, s, &k_sorted, &i_sorted);
   if (e != hipSuccess) return e;
   uint32_t* hi_perm = (k_sorted == t.key_lo) ? t.key2 : t.key_lo;   // the buffer the sort left free
   k_codec_gather_u32<<<blocks, 256, 0, s>>>(t.key_hi, i_sorted, n, hi_perm);
@@ -203,7 +203,7 @@ hipError_t launch_encode(const float* means, const float* attrs, int64_t n, int6
   uint32_t* i_free = (i_sorted == t.idx) ? t.val2 : t.idx;
   uint32_t* v_alt = (hi_perm == t.key_lo) ? t.key2 : t.key_lo;
   uint32_t *k2 = nullptr, *perm = nullptr;
-  e = launch_radix_sort(hi_perm, i_sorted, v_alt, i_free, t.count, n, 10, t.hist, t.scan_part, s, &k2, &perm);
+  e = launch_radix_sort(hi_perm, i_sorted, v_alt, i_free, t.count, nullptr, n, 10, t.hist, t.scan_part, s, &k2, &perm);
   if (e != hipSuccess) return e;
   k_codec_gather_codes<<<blocks, 256, 0, s>>>(t.codes, perm, n, stride_out, codes_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;

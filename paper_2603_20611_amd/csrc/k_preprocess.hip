@@ -42,6 +42,7 @@ __global__ void k_reset(const BatchHdr* __restrict__ hdr, uint32_t* __restrict__
   if (t == 0) {
     ctr[kCtrRecords] = 0u;
     ctr[kCtrInstances] = 0u;
+    ctr[kCtrSortEnd] = 0xFFFFFFFFu;
     if (clear_overflow) ctr[kCtrOverflow] = 0u;
   }
   for (int64_t i = t; i < kWorkCount; i += stride) work[i] = 0u;
@@ -501,8 +502,10 @@ __device__ __forceinline__ void slots_wave(const PreArgs& a, int t0, int* list, 
   a.g_ninst[t] = ibase;
   if (!fits) {
     // overflow: this Gaussian's slots inside the capacity stay unused and are
-    // marked so that no later kernel reads them
+    // marked so that no later kernel reads them; the sort ends before the
+    // first of them
     a.ctr[kCtrOverflow] = 1u;
+    atomicMin(&a.ctr[kCtrSortEnd], ibase);
     a.g_nrec[t] = 0u;
     if (!(a.rc.flags & GP_FLAG_FORWARD_ONLY))
       for (uint32_t r = rbase; r < rbase + nrec && r < a.rc.rec_cap; ++r) a.rec_meta[r].slice = kInvalidSlice;

@@ -207,16 +207,22 @@ struct RadixArgs {
   uint32_t* hist;         // [digits][nblocks]
   const uint32_t* rowtot; // [digits] row totals of hist
   const uint32_t* count;  // element count (device)
+  const uint32_t* count2; // a second bound on it (device), or null
   uint32_t cap;           // element capacity
   int nblocks, shift, bits;
 };
+
+__device__ __forceinline__ uint32_t sort_count(const RadixArgs& a) {
+  const uint32_t n = min(*a.count, a.cap);
+  return a.count2 ? min(n, *a.count2) : n;
+}
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(RadixArgs a) {
   __shared__ uint32_t h[kMaxDigits];
   const int R = 1 << a.bits;
   for (int i = threadIdx.x; i < R; i += kSortThreads) h[i] = 0u;
   __syncthreads();
-  const uint32_t n = min(*a.count, a.cap);
+  const uint32_t n = sort_count(a);
   // consecutive tiles on one XCD (workgroups go to the eight XCDs in turn):
   // their counts share cache lines of the [digit][tile] matrix, which then
   // merge in that XCD's L2 instead of being written partially by eight
@@ -282,7 +288,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RadixArgs a) {
   __shared__ uint32_t wrun[kSortWaves][kMaxDigits];   // per-wavefront digit counts, then running positions
   uint32_t* const wtot = sk;                     // the wavefront totals of the scan (before sk is used)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const uint32_t n = min(*a.count, a.cap);
+  const uint32_t n = sort_count(a);
   // consecutive tiles on one XCD, as in the histogram: a digit's runs of
   // adjacent tiles are adjacent in the output, and their shared lines then
   // merge in that XCD's L2
@@ -513,9 +519,11 @@ __global__ __launch_bounds__(256) void k_hist_rowscan(uint32_t* __restrict__ his
 // Bin ranges from the sorted keys: [lo, hi) of every non-empty bin (the reset
 // kernel zeroes both arrays first, so empty bins read as empty).
 __global__ __launch_bounds__(256) void k_bin_ranges(const BatchHdr* __restrict__ hdr, const uint32_t* __restrict__ key,
-                                                    const uint32_t* __restrict__ count, uint32_t cap,
+                                                    const uint32_t* __restrict__ count,
+                                                    const uint32_t* __restrict__ count2, uint32_t cap,
                                                     uint32_t* __restrict__ lo, uint32_t* __restrict__ hi) {
-  const uint32_t n = min(*count, cap);
+  uint32_t n = min(*count, cap);
+  if (count2) n = min(n, *count2);
   const uint32_t n_bins = (uint32_t)hdr->n_bins;
   // four consecutive keys per thread (one 16-byte load); the neighbours across
   // a thread boundary come from the adjacent lanes, across a wavefront
@@ -562,11 +570,12 @@ int64_t radix_hist_entries(int bits, int64_t cap) {
   return ((int64_t)1 << db) * ((cap + kSortTile - 1) / kSortTile) + kMaxDigits;   // matrix, row totals
 }
 
-// Stable sort of `count` (device) pairs by the low `bits` bits of the key.
+// Stable sort of min(*count, *count2, cap) pairs (count2 may be null) by the
+// low `bits` bits of the key.
 // Ping-pongs between (k0, v0) and (k1, v1); returns in *k_out / *v_out the
 // buffers that hold the result.
 hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* d_count,
-                             int64_t cap, int bits, uint32_t* hist, uint32_t* scan_part, hipStream_t s,
+                             const uint32_t* d_count2, int64_t cap, int bits, uint32_t* hist, uint32_t* scan_part, hipStream_t s,
                              uint32_t** k_out, uint32_t** v_out) {
   const int passes = radix_passes(bits);
   *k_out = k0;
@@ -579,7 +588,7 @@ hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
     const int shift = p * db;
     const int pb = std::min(db, bits - shift);
     uint32_t* rowtot = hist + ((size_t)1 << db) * nblocks;
-    RadixArgs a{ki, vi, ko, vo, hist, rowtot, d_count, (uint32_t)cap, nblocks, shift, pb};
+    RadixArgs a{ki, vi, ko, vo, hist, rowtot, d_count, d_count2, (uint32_t)cap, nblocks, shift, pb};
     k_radix_hist<<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a);
     k_hist_rowscan<<<1 << pb, 256, 0, s>>>(hist, nblocks, rowtot);
     switch (pb) {
@@ -603,11 +612,11 @@ hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
   return hipSuccess;
 }
 
-hipError_t launch_bin_ranges(const BatchHdr* hdr, const uint32_t* key, const uint32_t* d_count, int64_t cap,
-                             uint32_t* lo, uint32_t* hi, hipStream_t s) {
+hipError_t launch_bin_ranges(const BatchHdr* hdr, const uint32_t* key, const uint32_t* d_count,
+                             const uint32_t* d_count2, int64_t cap, uint32_t* lo, uint32_t* hi, hipStream_t s) {
   int64_t blocks = (cap + 255) / 256;
   blocks = blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
-  k_bin_ranges<<<(unsigned)blocks, 256, 0, s>>>(hdr, key, d_count, (uint32_t)cap, lo, hi);
+  k_bin_ranges<<<(unsigned)blocks, 256, 0, s>>>(hdr, key, d_count, d_count2, (uint32_t)cap, lo, hi);
   return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@
 // pass covers only the output rows, and the smaller LDS footprint lets four
 // and six workgroups share a CU, so that a 256^2 x 8 batch runs in one round):
 //   k_ssim_stats: five window sums -> S and the three coefficient maps;
-//   k_ssim_grad:  window sums of the three maps -> dL/dI.
+//   k_ssim_grad:  window sums of the three maps -> dL/dI (its first workgroup
+//                 also adds up the loss terms).
 // Both compute in float64: the moments form of the variances (E[x^2] - mx^2)
 // and the sum mx-term + 2 I x2-term cancel to a few bits in smooth regions,
 // and the whole loss costs about 300 flops per pixel, far from any bound.
@@ -131,11 +132,11 @@ __global__ __launch_bounds__(256) void k_ssim_stats(SsimArgs a) {
   }
 }
 
-// The two loss terms from the per-block sums, in a fixed order (one writer:
-// deterministic, and no contended atomics).
-__global__ __launch_bounds__(256) void k_ssim_loss_sum(const double* __restrict__ part, int64_t nblocks,
-                                                       double inv_n, float* __restrict__ loss) {
-  __shared__ double red[4];
+// The two loss terms from the per-block sums of k_ssim_stats, in a fixed order
+// (one writer: deterministic, and no contended atomics).  Run by the first
+// workgroup of k_ssim_grad, which starts after every sum is written.
+__device__ void ssim_loss_sum(const double* __restrict__ part, int64_t nblocks, double inv_n,
+                              float* __restrict__ loss, double* red) {
   double s1 = 0.0, s2 = 0.0;
   for (int64_t b = threadIdx.x; b < nblocks; b += 256) {
     s1 += part[2 * b];
@@ -211,6 +212,10 @@ __global__ __launch_bounds__(256) void k_ssim_grad(SsimArgs a) {
     const double dS = u[0] + 2.0 * xv * u[1] + yv * u[2];
     a.grad[o] = (float)(a.inv_n * (sg - a.lam * dS));
   }
+  if (a.loss && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+    __shared__ double red[4];
+    ssim_loss_sum(a.part, (int64_t)gridDim.x * gridDim.y * gridDim.z, a.inv_n, a.loss, red);
+  }
 }
 
 // Scratch of the allocation-free loss entry point: the coefficient maps of up to
@@ -278,9 +283,6 @@ hipError_t launch_ssim_loss(const float* x, const float* y, int n_slices, int wi
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_ssim_grad<<<grid, 256, 0, s>>>(a);
-  e = hipGetLastError();
-  if (e != hipSuccess || !loss) return e;
-  k_ssim_loss_sum<<<1, 256, 0, s>>>(a.part, (int64_t)grid.x * grid.y * grid.z, a.inv_n, loss);
   return hipGetLastError();
 }
 

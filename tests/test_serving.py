@@ -275,6 +275,57 @@ def test_bench_config_mixed_grids(gp):
     sv.close()
 
 
+def test_split_groups_and_oversized_request(gp):
+    """Batches sort list entries by the low bits that tell one group's bins apart
+    (14 bits in the captured launches), so the server splits a volume's requests
+    into groups of at most 16,383 tiles, and launches a batch holding a single
+    request of more tiles without the graphs.  Six 1024^2 requests on one volume
+    (two groups) in one batch, then one 2560^2 request (25,600 tiles) beside a
+    512^2 one: sampled pixels against the oracle on the dequantised parameters
+    (1e-5), and each image equal bit for bit to the same request rendered alone."""
+    from paper_2603_20611_amd import binding as B, serve
+    _say("split groups and an oversized request")
+    vols = synth.serving_volumes(2, 60_000, 120_000, (512.0, 512.0, 128.0), seed=15)
+    sv = serve.Server(**BENCH_SERVER)
+    for v in vols:
+        sv.add_volume(torch.from_numpy(v).cuda().contiguous())
+    torch.cuda.synchronize()
+    reqs = [dict(volume=0, z=20.0 + 15.0 * k, sigma_z=[0.5, 1.0, 2.0][k % 3], width=1024, height=1024, dx=0.5, dy=0.5)
+            for k in range(6)]
+    # second batch: the oversized request beside a 512^2 one (launched without the graphs)
+    reqs += [dict(volume=1, z=64.0, sigma_z=1.0, width=2560, height=2560, dx=0.2, dy=0.2),
+             dict(volume=0, z=70.0, sigma_z=3.0, width=512, height=512, dx=1.0, dy=1.0)]
+    outs = [torch.empty(r["width"] * r["height"], device="cuda") for r in reqs]
+    res = []
+    for lo, hi in ((0, 6), (6, 8)):
+        tickets = sv.submit_many(reqs[lo:hi], outs[lo:hi])
+        res += [sv.poll(t, timeout_us=60_000_000) for t in tickets]
+        torch.cuda.synchronize()
+    assert all(x.status == 0 for x in res)
+    _say(f"batch sizes {[x.batch_size for x in res]}")
+    assert res[0].batch_size == 6 and res[6].batch_size == 2, "the requests did not share their batches"
+    rng = np.random.default_rng(16)
+    worst = 0.0
+    for r, o in zip(reqs, outs):
+        img = o.cpu().numpy().astype(np.float64).reshape(r["height"], r["width"])
+        sl = dict(z=r["z"], sigma_z=r["sigma_z"], x0=0.0, y0=0.0, dx=r["dx"], dy=r["dy"], width=r["width"],
+                  height=r["height"])
+        iy, ix = np.unravel_index(int(np.argmax(img)), img.shape)
+        px = np.concatenate([rng.integers(0, r["width"], 20), [ix]])
+        py = np.concatenate([rng.integers(0, r["height"], 20), [iy]])
+        ref = focus.render_pixels(_dequant(vols[r["volume"]], B.GP_Q16), sl, px, py)
+        worst = max(worst, float(np.abs(img[py, px] - ref).max()) / max(abs(float(ref[-1])), 1e-30))
+        alone = torch.empty_like(o)
+        x = sv.poll(sv.submit(r["volume"], r["z"], r["sigma_z"], alone, r["width"], r["height"], dx=r["dx"],
+                              dy=r["dy"]), timeout_us=60_000_000)
+        torch.cuda.synchronize()
+        assert x.status == 0 and x.batch_size == 1
+        assert torch.equal(alone, o)
+    _say(f"kernel arithmetic {worst:.2e}")
+    assert worst <= 1e-5
+    sv.close()
+
+
 def test_volumes_added_while_serving(gp):
     """Volumes added from another thread while requests are admitted and launched:
     every request completes and matches the image it renders on a quiet server."""
