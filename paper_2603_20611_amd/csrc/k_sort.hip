@@ -187,8 +187,11 @@ namespace {
 
 constexpr int kSortThreads = 512;                         // threads per block
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kPerWave = 1024;                            // elements per wavefront
-constexpr int kSortTile = kSortWaves * kPerWave;          // elements per block
+// elements per wavefront: 1,024 (8,192 per block), or 256 (2,048 per block)
+// for sorts of at most kSmallSort pairs, which would otherwise run on a few
+// dozen blocks (a training batch's 0.5 M pairs: 59 tiles of 8,192)
+constexpr int kPerWaveBig = 1024, kPerWaveSmall = 256;
+constexpr int64_t kSmallSort = 1 << 21;
 constexpr int kMaxDigitBits = 9;
 constexpr int kMaxDigits = 1 << kMaxDigitBits;
 constexpr int kDigPerThread = kMaxDigits / kSortThreads;  // 1 or 2
@@ -217,7 +220,9 @@ __device__ __forceinline__ uint32_t sort_count(const RadixArgs& a) {
   return a.count2 ? min(n, *a.count2) : n;
 }
 
+template <int PW>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(RadixArgs a) {
+  constexpr int kSortTile = kSortWaves * PW;
   __shared__ uint32_t h[kMaxDigits];
   const int R = 1 << a.bits;
   for (int i = threadIdx.x; i < R; i += kSortThreads) h[i] = 0u;
@@ -280,8 +285,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(RadixArgs a) {
 // (elements and the block's digit offsets) is issued before the first wait;
 // the digit width is a template parameter so that the matching unrolls; LDS
 // is 80 KB, two blocks per CU.
-template <int BITS>
+template <int BITS, int PW>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RadixArgs a) {
+  constexpr int kPerWave = PW, kSortTile = kSortWaves * PW;
   constexpr int kChunks = kPerWave / 64;         // chunks per wavefront
   constexpr int R = 1 << BITS;
   __shared__ uint32_t sk[kSortTile], sv[kSortTile];
@@ -563,11 +569,34 @@ __global__ __launch_bounds__(256) void k_bin_ranges(const BatchHdr* __restrict__
 
 int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + kMaxDigitBits - 1) / kMaxDigitBits; }
 
+static int64_t sort_tile(int64_t cap) { return kSortWaves * (cap <= kSmallSort ? kPerWaveSmall : kPerWaveBig); }
+
+// Count-matrix entries for a sort of any extent up to `cap` (a smaller extent
+// may take the small tiles and so more of them): the most tiles over both
+// regimes, times the digits of a pass, plus the row totals.
 int64_t radix_hist_entries(int bits, int64_t cap) {
   const int passes = radix_passes(bits);
   if (passes == 0) return 1;
   const int db = (bits + passes - 1) / passes;
-  return ((int64_t)1 << db) * ((cap + kSortTile - 1) / kSortTile) + kMaxDigits;   // matrix, row totals
+  const int64_t small_tile = (int64_t)kSortWaves * kPerWaveSmall, big_tile = (int64_t)kSortWaves * kPerWaveBig;
+  const int64_t small_tiles = (std::min(cap, kSmallSort) + small_tile - 1) / small_tile;
+  const int64_t big_tiles = cap > kSmallSort ? (cap + big_tile - 1) / big_tile : 0;
+  return ((int64_t)1 << db) * std::max(small_tiles, big_tiles) + kMaxDigits;   // matrix, row totals
+}
+
+template <int PW>
+static void launch_scatter(int pb, unsigned grid, const RadixArgs& a, hipStream_t s) {
+  switch (pb) {
+    case 1: k_radix_scatter<1, PW><<<grid, kSortThreads, 0, s>>>(a); break;
+    case 2: k_radix_scatter<2, PW><<<grid, kSortThreads, 0, s>>>(a); break;
+    case 3: k_radix_scatter<3, PW><<<grid, kSortThreads, 0, s>>>(a); break;
+    case 4: k_radix_scatter<4, PW><<<grid, kSortThreads, 0, s>>>(a); break;
+    case 5: k_radix_scatter<5, PW><<<grid, kSortThreads, 0, s>>>(a); break;
+    case 6: k_radix_scatter<6, PW><<<grid, kSortThreads, 0, s>>>(a); break;
+    case 7: k_radix_scatter<7, PW><<<grid, kSortThreads, 0, s>>>(a); break;
+    case 8: k_radix_scatter<8, PW><<<grid, kSortThreads, 0, s>>>(a); break;
+    default: k_radix_scatter<9, PW><<<grid, kSortThreads, 0, s>>>(a); break;
+  }
 }
 
 // Stable sort of min(*count, *count2, cap) pairs (count2 may be null) by the
@@ -582,25 +611,24 @@ hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
   *v_out = v0;
   if (passes == 0 || cap <= 0) return hipSuccess;
   const int db = (bits + passes - 1) / passes;
-  const int nblocks = (int)((cap + kSortTile - 1) / kSortTile);
+  const int64_t tile = sort_tile(cap);
+  const bool small = tile < (int64_t)kSortWaves * kPerWaveBig;
+  const int nblocks = (int)((cap + tile - 1) / tile);
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * db;
     const int pb = std::min(db, bits - shift);
     uint32_t* rowtot = hist + ((size_t)1 << db) * nblocks;
     RadixArgs a{ki, vi, ko, vo, hist, rowtot, d_count, d_count2, (uint32_t)cap, nblocks, shift, pb};
-    k_radix_hist<<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a);
-    k_hist_rowscan<<<1 << pb, 256, 0, s>>>(hist, nblocks, rowtot);
-    switch (pb) {
-      case 1: k_radix_scatter<1><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
-      case 2: k_radix_scatter<2><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
-      case 3: k_radix_scatter<3><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
-      case 4: k_radix_scatter<4><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
-      case 5: k_radix_scatter<5><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
-      case 6: k_radix_scatter<6><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
-      case 7: k_radix_scatter<7><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
-      case 8: k_radix_scatter<8><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
-      default: k_radix_scatter<9><<<8 * ((nblocks + 7) / 8), kSortThreads, 0, s>>>(a); break;
+    const unsigned grid = 8u * (unsigned)((nblocks + 7) / 8);
+    if (small) {
+      k_radix_hist<kPerWaveSmall><<<grid, kSortThreads, 0, s>>>(a);
+      k_hist_rowscan<<<1 << pb, 256, 0, s>>>(hist, nblocks, rowtot);
+      launch_scatter<kPerWaveSmall>(pb, grid, a, s);
+    } else {
+      k_radix_hist<kPerWaveBig><<<grid, kSortThreads, 0, s>>>(a);
+      k_hist_rowscan<<<1 << pb, 256, 0, s>>>(hist, nblocks, rowtot);
+      launch_scatter<kPerWaveBig>(pb, grid, a, s);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
