@@ -235,6 +235,33 @@ __device__ __forceinline__ bool far_from_group(const PreArgs& a, const GroupDev&
   return d * d > a.rc.q_cut * (G.sz2max + smax * smax) * 1.001f;
 }
 
+// Whether flattened Gaussian t may have records on its group's slices: in
+// range and not far_from_group(), from its depth and log-scales only (the
+// compacting count's first look at every Gaussian; a near one is loaded whole
+// and checked afterwards, so a non-finite parameter elsewhere still culls it).
+template <int DT>
+__device__ __forceinline__ bool maybe_near(const PreArgs& a, int n_groups, int t) {
+  if constexpr (DT == GP_QM) {
+    Loaded L;
+    load_params<DT>(a, n_groups, t, L);
+    return L.ok && !far_from_group(a, L.G, L.p);
+  } else {
+    const int wave0 = t & ~63;
+    int g = 0;
+    for (int jg = 1; jg < n_groups; ++jg)
+      if (a.groups[jg].gbase <= wave0) g = jg;
+    const GroupDev& G = a.groups[g];
+    const int j = t - G.gbase;
+    if (j >= G.n) return false;
+    float p[6];
+    p[2] = G.means[2 * G.stride + j];
+    p[3] = load_attr<DT>(G.attrs, 0, G.stride, j);
+    p[4] = load_attr<DT>(G.attrs, 1, G.stride, j);
+    p[5] = load_attr<DT>(G.attrs, 2, G.stride, j);
+    return !far_from_group(a, G, p);
+  }
+}
+
 // far_from_group() for a group whose slices share one camera pose: the same
 // test on the mean's depth in that camera frame (the operations of the
 // specified pose transform, so the same bits as the per-slice view) against
@@ -772,12 +799,11 @@ __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
       if (threadIdx.x == 0) s_n = 0;
       __syncthreads();
       for (int i = threadIdx.x; i < kCountChunk; i += 256) {
-        Loaded L;
-        load_params<DT>(a, n_groups, base + i, L);
-        const bool near = L.ok && !far_from_group(a, L.G, L.p);
+        const int t = base + i;
+        const bool near = t < total && maybe_near<DT>(a, n_groups, t);
         s_nrec[i] = 0u;
         s_ninst[i] = 0u;
-        s_kr[i] = (uint32_t)L.G.k0 | ((uint32_t)L.G.k0 << 16);
+        s_kr[i] = 0u;   // read only for Gaussians with records
         if (near) s_list[atomicAdd(&s_n, 1)] = i;
       }
       __syncthreads();
