@@ -84,11 +84,23 @@ struct GroupDev {
   int32_t attr_dtype;
   int32_t k0, k1;      // slices [k0, k1) of the batch
   int32_t gbase;       // first flattened Gaussian index (multiple of 64)
-  int32_t flags;       // kGroupSortedZ
+  int32_t flags;       // kGroupSortedZ, kGroupSharedPose
   float zlo, zhi;      // depth range of the group's slices
   float sz2max;        // largest sigma_z^2 of the group's slices (+inf if any is infinite)
   float pad;
 };
+
+// Group of flattened Gaussian index wave0 (a multiple of 64; groups start at
+// multiples of 64 in ascending order): the last group whose base is at most
+// wave0, by binary search (uniform over a wavefront, so scalar loads).
+__device__ __forceinline__ int group_of(const GroupDev* groups, int n_groups, int wave0) {
+  int lo = 0, hi = n_groups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].gbase <= wave0) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
 // Rendering constants of one call (sizes that vary per batch live in BatchHdr).
 struct RenderConst {

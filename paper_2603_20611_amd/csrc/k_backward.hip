@@ -50,9 +50,7 @@ template <int DT, bool POSED>
 __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, int t) {
   const uint32_t nrec = a.g_nrec[t];
   if (nrec == 0) return;
-  int g = 0;
-  for (int jg = 1; jg < n_groups; ++jg)
-    if (a.groups[jg].gbase <= (t & ~63)) g = jg;
+  const int g = group_of(a.groups, n_groups, (t & ~63));
   const GroupDev G = a.groups[g];
   const int j = t - G.gbase;
   if (j >= G.n) return;

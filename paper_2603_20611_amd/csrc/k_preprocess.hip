@@ -140,9 +140,7 @@ struct Loaded {
 template <int DT>
 __device__ __forceinline__ void load_params(const PreArgs& a, int n_groups, int t, Loaded& L) {
   const int wave0 = t & ~63;
-  int g = 0;   // groups start at multiples of 64
-  for (int jg = 1; jg < n_groups; ++jg)
-    if (a.groups[jg].gbase <= wave0) g = jg;
+  const int g = group_of(a.groups, n_groups, wave0);
   L.G = a.groups[g];
   L.j = t - L.G.gbase;
   const bool in_range = L.j < L.G.n;
@@ -247,9 +245,7 @@ __device__ __forceinline__ bool maybe_near(const PreArgs& a, int n_groups, int t
     return L.ok && !far_from_group(a, L.G, L.p);
   } else {
     const int wave0 = t & ~63;
-    int g = 0;
-    for (int jg = 1; jg < n_groups; ++jg)
-      if (a.groups[jg].gbase <= wave0) g = jg;
+    const int g = group_of(a.groups, n_groups, wave0);
     const GroupDev& G = a.groups[g];
     const int j = t - G.gbase;
     if (j >= G.n) return false;
