@@ -325,8 +325,8 @@ def contention_leg(dev, vols, seconds=3.0, iters_alone=30, rate=500.0):
     return out
 
 
-def serving_leg(dev, vols, seconds=1.5, rates_batched=(2000, 4000, 8000, 16000, 24000, 28000, 30000, 32000, 34000,
-                                                      36000, 40000, 48000),
+def serving_leg(dev, vols, seconds=1.5, rates_batched=(2000, 4000, 8000, 16000, 24000, 32000, 40000, 44000, 48000,
+                                                      52000, 56000, 60000, 64000, 72000),
                 rates_plain=(1000, 2000, 4000, 6000, 7000, 8000, 9000, 10000, 12000), saturation_requests=2000):
     """Serving workload: 64 resident volumes (log-uniform 20k..1M Gaussians, the
     microscopy generator in a 512x512x128 extent, GP_Q16 storage), open-loop
