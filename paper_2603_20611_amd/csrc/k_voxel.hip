@@ -11,7 +11,7 @@
 //   scan          instance slots in Gaussian order;
 //   k_vox_emit    one (tile, Gaussian) pair per tile of each box;
 //   radix sort    stable, by tile: every list ends in Gaussian order;
-//   k_vox_fwd     one wavefront per tile (shared work counter); lane (x, y) of
+//   k_vox_fwd     one wavefront per tile pair (shared work counter); lane (x, y) of
 //                 the 8 x 8 face owns the column of 8 voxels along z, so the
 //                 x-y part of the quadratic form is shared by 8 voxels.
 // Backward:
@@ -64,6 +64,7 @@ struct VoxArgs {
   uint32_t* work;
   float* grad;
   int64_t grad_stride;
+  int tile_group;         // forward: consecutive tiles per work item
 };
 
 struct VoxGauss {
@@ -175,17 +176,26 @@ __device__ __forceinline__ void vox_tile_xyz(const VoxArgs& a, int tile, int* tx
   *tz = tile / (a.ntx * a.nty);
 }
 
-// One wavefront per tile; lane (lx, ly) owns the column of 8 voxels along z.
-// Each workgroup's first tile is its own index; the shared counter hands out
-// the rest (every workgroup taking a ticket at once serialised on it).
+// One wavefront per work item of tile_group consecutive tiles, rendered in
+// turn; lane (lx, ly) owns the column of 8 voxels along z.  Each workgroup's
+// first item is its own index; the shared counter hands out the rest (every
+// workgroup taking a ticket at once serialised on it).
 __global__ __launch_bounds__(64) void k_vox_fwd(VoxArgs a) {
   __shared__ float4 b0[64], b1[64], b2[64];
   const int lane = threadIdx.x;
   const int lx = lane & 7, ly = lane >> 3;
   uint32_t* counter = a.work + kWorkRasterFwd;
+  const int G = a.tile_group;   // consecutive tiles per work item
+  const uint32_t n_items = (uint32_t)((a.n_tiles + G - 1) / G);
   const uint32_t t0 = blockIdx.x;
-  for (int tile = t0 < (uint32_t)a.n_tiles ? (int)t0 : -1; tile >= 0;) {
-    const uint32_t ticket = wave_take(counter) + gridDim.x;   // resolved after this tile
+  int left = 0;   // further tiles of the current item
+  uint32_t ticket = 0u;
+  for (int tile = t0 < n_items ? (int)t0 * G : -1; tile >= 0;) {
+    if (left == 0) {
+      ticket = wave_take(counter) + gridDim.x;   // resolved after this item
+      left = min(G, a.n_tiles - tile);
+    }
+    --left;
     int tx, ty, tz;
     vox_tile_xyz(a, tile, &tx, &ty, &tz);
     const float fx = (float)(tx * kVT + lx), fy = (float)(ty * kVT + ly), fz0 = (float)(tz * kVT);
@@ -226,7 +236,8 @@ __global__ __launch_bounds__(64) void k_vox_fwd(VoxArgs a) {
         if (iz < a.nz) a.vol[((int64_t)iz * a.ny + iy) * a.nx + ix] = acc[k];
       }
     }
-    tile = ticket < (uint32_t)a.n_tiles ? (int)ticket : -1;
+    if (left > 0) ++tile;
+    else tile = ticket < n_items ? (int)ticket * G : -1;
   }
 }
 
@@ -431,6 +442,7 @@ static VoxArgs vox_args(const Workspace& ws, const gp_gaussians* g, const gp_vol
   a.list = ws.d_list;
   a.mom = ws.d_vox_mom;
   a.work = ws.d_work;
+  a.tile_group = 1;
   return a;
 }
 
@@ -475,6 +487,11 @@ hipError_t launch_vox_fwd(const Workspace& ws, const gp_gaussians* g, const gp_v
   VoxArgs a = vox_args(ws, g, grid, o, L);
   a.vol = vol;
   const int64_t blocks = L.n_tiles < 8192 ? L.n_tiles : 8192;
+  // pairs of consecutive tiles (along x) per work item while there are still
+  // two items per workgroup: the second tile's gathers find most of its
+  // records in the cache (256 x 256 x 400 voxels: 0.79 -> 0.62 ms; four
+  // tiles 0.62-0.64, eight 0.65-0.66)
+  a.tile_group = L.n_tiles >= 2 * blocks ? 2 : 1;
   k_vox_fwd<<<(unsigned)blocks, 64, 0, s>>>(a);
   return hipGetLastError();
 }
