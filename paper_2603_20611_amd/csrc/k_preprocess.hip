@@ -594,9 +594,16 @@ __device__ __forceinline__ bool footprint_emit(const PreArgs& a, int n_groups, i
   return vis;
 }
 
+// Instances a group of W lanes stages in LDS per slice round before writing
+// them out as one run (consecutive lanes, consecutive slots; each lane's own
+// loop over its tiles left a wavefront's stores scattered over 64 places); a
+// round with more goes out directly.  400-slice stack: emit 0.232 -> 0.224 ms.
+constexpr int kStagePerLane = 4;
+
 template <int DT, int W, bool POSED>
 __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const int* list, uint32_t j0,
-                                          uint32_t n_active, double (*cov64)[6], EmitGauss* eg, float4* pw) {
+                                          uint32_t n_active, double (*cov64)[6], EmitGauss* eg, float4* pw,
+                                          uint2* stage) {
   const int lane = threadIdx.x & 63;
   const uint32_t j = j0 + (uint32_t)lane;
   const int t = j < n_active ? list[j] : 0;
@@ -721,6 +728,8 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
         ipos = inc - nt;
         itot = __shfl(inc, W - 1, W);
       }
+      // uniform over the group of W lanes
+      const bool staged = W >= 8 && itot <= (uint32_t)(kStagePerLane * W);
       if (kept) {
         const SliceDev& sl = a.slices[k];
         const uint32_t rid = rec_run + rpos;
@@ -731,12 +740,33 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
                     pay, meta);
         a.rec_pay[rid] = pay;
         if (!(a.rc.flags & GP_FLAG_FORWARD_ONLY)) a.rec_meta[rid] = meta;
-        for (int ty = rect.ty0; ty <= rect.ty1; ++ty) {
-          for (int tx = rect.tx0; tx <= rect.tx1; ++tx, ++slot) {
-            a.inst_key[slot] = (uint32_t)(sl.tile_base + ty * sl.ntx + tx);
-            a.inst_val[slot] = rid;
+        if (!staged) {
+          for (int ty = rect.ty0; ty <= rect.ty1; ++ty) {
+            for (int tx = rect.tx0; tx <= rect.tx1; ++tx, ++slot) {
+              a.inst_key[slot] = (uint32_t)(sl.tile_base + ty * sl.ntx + tx);
+              a.inst_val[slot] = rid;
+            }
           }
+        } else {
+          uint2* st = stage + sub * (kStagePerLane * W) + ipos;
+          for (int ty = rect.ty0; ty <= rect.ty1; ++ty)
+            for (int tx = rect.tx0; tx <= rect.tx1; ++tx, ++st) *st = make_uint2((uint32_t)(sl.tile_base + ty * sl.ntx + tx), rid);
         }
+      }
+      if (staged) {
+        // the group's instances of this round, consecutive lanes to consecutive slots
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint2* st = stage + sub * (kStagePerLane * W);
+        for (uint32_t q = (uint32_t)li; q < itot; q += W) {
+          const uint2 v = st[q];
+          a.inst_key[inst_run + q] = v.x;
+          a.inst_val[inst_run + q] = v.y;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
       if (W > 1) {
         rec_run += rtot;
@@ -852,6 +882,7 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   __shared__ double cov64[4][64][6];
   __shared__ EmitGauss egs[4][64];
   __shared__ float4 pws[4][POSED ? 64 : 1];
+  __shared__ uint2 stg[4][W >= 8 ? kStagePerLane * 64 : 1];
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   const int wave = threadIdx.x >> 6;
@@ -871,7 +902,7 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane(n_w[wave]);
-      if (n > 0u) emit_wave<DT, W, POSED>(a, n_groups, wl, 0u, n, cov64[wave], egs[wave], pws[wave]);
+      if (n > 0u) emit_wave<DT, W, POSED>(a, n_groups, wl, 0u, n, cov64[wave], egs[wave], pws[wave], stg[wave]);
     }
     return;
   }
@@ -888,7 +919,8 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
     uint32_t q = ((n + 3u) / 4u + kRound - 1u) / kRound * kRound;
     q = q > 64u ? 64u : (q < kRound ? kRound : q);
     for (uint32_t j0 = (uint32_t)wave * q; j0 < n; j0 += 4u * q)
-      emit_wave<DT, W, POSED>(a, n_groups, list, j0, j0 + q < n ? j0 + q : n, cov64[wave], egs[wave], pws[wave]);
+      emit_wave<DT, W, POSED>(a, n_groups, list, j0, j0 + q < n ? j0 + q : n, cov64[wave], egs[wave], pws[wave],
+                              stg[wave]);
     __syncthreads();   // list and n_list are rewritten by the next chunk
   }
 }
