@@ -95,7 +95,9 @@ __device__ __forceinline__ void stage_record(const float4 r0, const float4 r1, f
   s1 = make_float4(r1.x, r1.y, smooth ? exp2f(2.0f * r0.z) : -1.0f, smooth ? exp2f(r0.w) : 0.0f);
 }
 
-// Product with 0 * anything = 0 (also 0 * inf).
+// Product with 0 * anything = 0 (also 0 * inf).  For wavefront-uniform
+// control flow only: in a lane-divergent branch the compiler did not keep
+// this asm inside the branch (the backward measured wrong moments with it).
 __device__ __forceinline__ float mul0(float x, float y) {
   float r;
   asm("v_mul_legacy_f32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
@@ -520,6 +522,10 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
         float dx[kTile];
 #pragma unroll
         for (int c = 0; c < kTile; ++c) dx[c] = ox + (float)c;
+        // the forward's row recurrence over each four-pixel segment for the
+        // records it allows (same conditions, same reasoning: no clamping)
+        const bool smooth = ca >= kSmoothA && fabsf(cb2) <= kSmoothB;
+        const float gx = smooth ? __builtin_amdgcn_exp2f(2.0f * ca) : 0.f;
         for (int rr = 0; rr < 4; ++rr) {
           const int row = 4 * (int)rq + rr;
           const float dy = oy + (float)row;
@@ -531,11 +537,32 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
           for (int q = 0; q < 4; ++q) {
             const float4 g4 = grow[q];
             const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+            float ev[4];
+            const float d0 = dx[4 * q];
+            if (smooth) {
+              // a ratio that overflows meets e = 0 (as in the forward); held
+              // finite, the plain products give 0 there (gx <= 1: no later
+              // overflow).  The forward's 0 * inf = 0 multiply written as asm
+              // is not used here: in this lane-divergent branch the compiler
+              // did not keep it inside the branch (wrong moments measured).
+              ev[0] = __builtin_amdgcn_exp2f(fmaf(fmaf(ca, d0, by), d0, cy));
+              float r = fminf(__builtin_amdgcn_exp2f(fmaf(ca, fmaf(2.0f, d0, 1.0f), by)), 0x1p127f);
+              ev[1] = ev[0] * r;
+              r *= gx;
+              ev[2] = ev[1] * r;
+              r *= gx;
+              ev[3] = ev[2] * r;
+            } else {
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                const float d = dx[4 * q + c];
+                ev[c] = __builtin_amdgcn_exp2f(fmaf(fmaf(ca, d, by), d, cy));
+              }
+            }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
               const float d = dx[4 * q + c];
-              const float p = fmaf(fmaf(ca, d, by), d, cy);
-              const float we = gv[c] * __builtin_amdgcn_exp2f(p);
+              const float we = gv[c] * ev[c];
               const float wd = we * d;
               s0 += we;
               sx += wd;
