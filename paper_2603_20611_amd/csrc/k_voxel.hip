@@ -101,6 +101,10 @@ __device__ __forceinline__ bool vox_axis(float mu, float saa, float o, float h, 
   return true;
 }
 
+// Records with a diagonal coefficient >= -4 (sigma >= 0.42 voxel along that
+// axis) take the product recurrence along it.
+constexpr float kVoxSmooth = -4.0f;
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_vox_count(VoxArgs a) {
   const int j = blockIdx.x * 256 + threadIdx.x;
@@ -137,7 +141,11 @@ __global__ __launch_bounds__(256) void k_vox_count(VoxArgs a) {
                      g.p[10]);
     r1 = make_float4(k * P[0][0] * a.dx * a.dx, k * P[1][1] * a.dy * a.dy, k * P[2][2] * a.dz * a.dz,
                      2.0f * k * P[0][1] * a.dx * a.dy);
-    r2 = make_float4(2.0f * k * P[0][2] * a.dx * a.dz, 2.0f * k * P[1][2] * a.dy * a.dz, 0.f, 0.f);
+    // the per-voxel ratio's change along z (forward columns) and along x
+    // (backward rows) for the product recurrence, -1 where it is not used
+    const float czz = r1.z, cxx = r1.x;
+    r2 = make_float4(2.0f * k * P[0][2] * a.dx * a.dz, 2.0f * k * P[1][2] * a.dy * a.dz,
+                     czz >= kVoxSmooth ? exp2f(2.0f * czz) : -1.0f, cxx >= kVoxSmooth ? exp2f(2.0f * cxx) : -1.0f);
   }
   a.rec[j] = r0;
   a.rec[a.n + j] = r1;
@@ -219,11 +227,30 @@ __global__ __launch_bounds__(64) void k_vox_fwd(VoxArgs a) {
         const float pxy = fmaf(fmaf(r1.x, ddx, r1.w * ddy), ddx, r1.y * ddy * ddy);
         const float lz = fmaf(r2.x, ddx, r2.y * ddy);
         const float dz0 = fz0 - r0.z;
+        if (r2.z > 0.0f) {
+          // two four-voxel segments, each from an exact exp2 by the product
+          // recurrence along z (the raster's reasoning with czz >= -4; the
+          // ratio held finite in place of a 0 * inf = 0 multiply)
 #pragma unroll
-        for (int k = 0; k < kVT; ++k) {
-          const float dz = dz0 + (float)k;
-          const float q = fmaf(fmaf(r1.z, dz, lz), dz, pxy);
-          acc[k] = fmaf(r0.w, __builtin_amdgcn_exp2f(q), acc[k]);
+          for (int h = 0; h < kVT; h += 4) {
+            const float dz = dz0 + (float)h;
+            float e = __builtin_amdgcn_exp2f(fmaf(fmaf(r1.z, dz, lz), dz, pxy));
+            float r = fminf(__builtin_amdgcn_exp2f(fmaf(r1.z, fmaf(2.0f, dz, 1.0f), lz)), 0x1p127f);
+            acc[h] = fmaf(r0.w, e, acc[h]);
+#pragma unroll
+            for (int k = 1; k < 4; ++k) {
+              e *= r;
+              r *= r2.z;
+              acc[h + k] = fmaf(r0.w, e, acc[h + k]);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < kVT; ++k) {
+            const float dz = dz0 + (float)k;
+            const float q = fmaf(fmaf(r1.z, dz, lz), dz, pxy);
+            acc[k] = fmaf(r0.w, __builtin_amdgcn_exp2f(q), acc[k]);
+          }
         }
       }
       __syncthreads();
@@ -280,11 +307,31 @@ __global__ __launch_bounds__(256) void k_vox_bwd(VoxArgs a) {
           const float c0 = fmaf(fmaf(r1.y, dy, r2.y * dz), dy, r1.z * dz * dz);
           const float* grow = G + (z * kVT + y) * kVT;
           float s0 = 0.f, sx = 0.f, sxx = 0.f;
+          float ev[kVT];
+          if (r2.w > 0.0f) {
+            // the product recurrence along x over two four-voxel segments
+#pragma unroll
+            for (int h = 0; h < kVT; h += 4) {
+              const float d = dxs[h];
+              ev[h] = __builtin_amdgcn_exp2f(fmaf(fmaf(r1.x, d, bx), d, c0));
+              float r = fminf(__builtin_amdgcn_exp2f(fmaf(r1.x, fmaf(2.0f, d, 1.0f), bx)), 0x1p127f);
+#pragma unroll
+              for (int k = 1; k < 4; ++k) {
+                ev[h + k] = ev[h + k - 1] * r;
+                r *= r2.w;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < kVT; ++c) {
+              const float d = dxs[c];
+              ev[c] = __builtin_amdgcn_exp2f(fmaf(fmaf(r1.x, d, bx), d, c0));
+            }
+          }
 #pragma unroll
           for (int c = 0; c < kVT; ++c) {
             const float d = dxs[c];
-            const float q = fmaf(fmaf(r1.x, d, bx), d, c0);
-            const float we = grow[c] * __builtin_amdgcn_exp2f(q);
+            const float we = grow[c] * ev[c];
             const float wd = we * d;
             s0 += we;
             sx += wd;
