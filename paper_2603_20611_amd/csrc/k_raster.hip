@@ -95,12 +95,14 @@ __device__ __forceinline__ void stage_record(const float4 r0, const float4 r1, f
   s1 = make_float4(r1.x, r1.y, smooth ? exp2f(2.0f * r0.z) : -1.0f, smooth ? exp2f(r0.w) : 0.0f);
 }
 
-// Product with 0 * anything = 0 (also 0 * inf).  For wavefront-uniform
-// control flow only: in a lane-divergent branch the compiler did not keep
-// this asm inside the branch (the backward measured wrong moments with it).
+// Product with 0 * anything = 0 (also 0 * inf).  The compiler does not see
+// inside the asm, so it inserts no wait state for an operand just written by
+// a transcendental (v_exp_f32), which gfx950 requires before a VALU reads it:
+// the asm carries its own (without it, a variant that multiplied an exp2
+// result at once read stale values).
 __device__ __forceinline__ float mul0(float x, float y) {
   float r;
-  asm("v_mul_legacy_f32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
+  asm("s_nop 0\n\tv_mul_legacy_f32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
   return r;
 }
 
@@ -542,9 +544,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
             if (smooth) {
               // a ratio that overflows meets e = 0 (as in the forward); held
               // finite, the plain products give 0 there (gx <= 1: no later
-              // overflow).  The forward's 0 * inf = 0 multiply written as asm
-              // is not used here: in this lane-divergent branch the compiler
-              // did not keep it inside the branch (wrong moments measured).
+              // overflow), with no asm multiply.
               ev[0] = __builtin_amdgcn_exp2f(fmaf(fmaf(ca, d0, by), d0, cy));
               float r = fminf(__builtin_amdgcn_exp2f(fmaf(ca, fmaf(2.0f, d0, 1.0f), by)), 0x1p127f);
               ev[1] = ev[0] * r;
