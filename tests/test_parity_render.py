@@ -149,6 +149,30 @@ def test_forward_work_schedules(gp, case):
     assert err <= FWD_TOL
 
 
+@pytest.mark.parametrize("n_big", [4, 8])
+def test_forward_bin_groups_mixed_grids(gp, n_big):
+    """Slices of two grid sizes (no slice groups): work items of 2 (16,640 bins) or
+    4 (33,024 bins) consecutive bins.  Tile lists bit-exact, and sampled pixels of
+    every slice, its brightest included, against the oracle pixel by pixel."""
+    _say(f"bin groups over mixed grids: {n_big} slices of 1024 x 1024 and one of 256 x 256")
+    p = synth.gaussians_uniform(3000, (1024.0, 1024.0, 16.0), np.log(6.0), 0.4, seed=31)
+    slices = [dict(z=2.0 + 1.5 * k, sigma_z=1.0, x0=0.0, y0=0.0, dx=1.0, dy=1.0, width=1024, height=1024)
+              for k in range(n_big)]
+    slices.append(dict(z=8.0, sigma_z=2.0, x0=256.0, y0=384.0, dx=1.0, dy=1.0, width=256, height=256))
+    params, ws, imgs = _render_gpu(gp, p, slices)
+    _check_bins(ws, p, slices)
+    rng = np.random.default_rng(32)
+    worst = 0.0
+    for sl, img in zip(slices, imgs):
+        iy, ix = np.unravel_index(int(np.argmax(img)), img.shape)
+        px = np.concatenate([rng.integers(0, sl["width"], 20), [ix]])
+        py = np.concatenate([rng.integers(0, sl["height"], 20), [iy]])
+        ref = focus.render_pixels(p, sl, px, py)
+        worst = max(worst, float(np.abs(img[py, px] - ref).max()) / max(abs(float(ref[-1])), 1e-30))
+    _say(f"sampled rel err {worst:.3e}")
+    assert worst <= FWD_TOL
+
+
 def test_full_size_sampled(gp):
     """The benchmark's workload at full size (500k Gaussians, 400 slices of 256 x 256,
     sigma_z = 3) in its launch configuration (a fixed workspace sized by one counted
