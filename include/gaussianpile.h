@@ -378,7 +378,9 @@ typedef struct gp_server_cfg {
   int32_t max_batch;           /* requests per batch (1 = one launch each)      */
   int32_t slots;               /* batches in flight, 1..4                       */
   int32_t attr_dtype;          /* GP_Q16, GP_F16, GP_BF16 or GP_F32              */
-  int32_t use_graphs;          /* replay a captured graph per slot (else launch) */
+  int32_t use_graphs;          /* replay a captured graph per slot (else launch;
+                                  a batch holding one request of more than
+                                  16,383 tiles is always launched)              */
   int32_t device;              /* HIP device                                    */
   gp_render_opts opts;
 } gp_server_cfg;
