@@ -436,21 +436,94 @@ __device__ __forceinline__ void cov_f64(const float* p, float mod, double* out) 
 
 // Image quantities of a kept (Gaussian, slice) pair, not part of the membership
 // specification: computed in float64 from the Gaussian's float64 covariance
-// (cov, world frame) and binary32 mean and intensity, rounded once.  A thin,
-// elongated Gaussian makes Sigma_2d ill-conditioned, and its conic taken from
-// binary32 covariance entries would be off by ~1e-5 of the record's peak; the
-// pixel-space mean at large pixel coordinates likewise.  pose: the slice's
-// camera pose (Sigma_c = R_c Sigma R_c^T, mu_c = R_c mu + t) or nullptr.
+// and binary32 mean and intensity, rounded once.  A thin, elongated Gaussian
+// makes Sigma_2d ill-conditioned, and its conic taken from binary32
+// covariance entries would be off by ~1e-5 of the record's peak; the
+// pixel-space mean at large pixel coordinates likewise.  Every operation runs
+// in a fixed order (no contraction), so that equal inputs give equal records
+// in every instantiation of the emit.
+//
+// RecSigma is the part that depends on the slice only through sigma_z (the
+// conditioned 2D covariance, its determinant and the conic up to the pixel
+// pitch): equal for every slice of one sigma_z, so the emit forms it once
+// per Gaussian and reuses it on its slices.  sdet is sqrt(det) in binary32,
+// NaN when det is not positive (the record is then zeroed, as any non-finite
+// one); conv the exact convolution's factor.
+struct RecSigma {
+  double invD, u, v, ta, tb, tc;
+  float sdet, conv;
+};
+
+// cov: xx, xy, xz, yy, yz, zz (in the slice's frame); sc0, sc1, sc2: the activated scales.
+__device__ __forceinline__ RecSigma rec_sigma(const double* cov, float sc0, float sc1, float sc2, float sigma_z,
+                                              uint32_t flags) {
+#pragma clang fp contract(off)
+  const double sxx = cov[0], sxy = cov[1], sxz = cov[2], syy = cov[3], syz = cov[4], szz = cov[5];
+  const double s2 = (double)sigma_z * (double)sigma_z;
+  RecSigma r;
+  r.invD = 1.0 / (s2 + szz);          // 0 for sigma_z = inf
+  r.u = sxz * r.invD;
+  r.v = syz * r.invD;
+  const double A = sxx - r.u * sxz, B = sxy - r.u * syz, C = syy - r.v * syz;
+  const double det = A * C - B * B;
+  const double inv_det = 1.0 / det;
+  const double L2 = 1.4426950408889634;
+  r.ta = -0.5 * L2 * C * inv_det;
+  r.tb = L2 * B * inv_det;
+  r.tc = -0.5 * L2 * A * inv_det;
+  r.sdet = det > 0.0 ? sqrtf((float)det) : __builtin_nanf("");
+  r.conv = 1.0f;
+  // exact convolution integral: times sqrt(2 pi det Sigma_e), det Sigma_e = det Sigma w
+  if (flags & GP_FLAG_CONV_EXACT) {
+    const double v0 = (double)sc0 * (double)sc0, v1 = (double)sc1 * (double)sc1, v2 = (double)sc2 * (double)sc2;
+    r.conv = sqrtf((float)(6.283185307179586 * ((v0 * v1) * v2) / (1.0 + szz / s2)));
+  }
+  return r;
+}
+
+// The record of a Gaussian with mean mu (slice frame) and intensity on slice sl.
+__device__ __forceinline__ void rec_pay(const RecSigma& r, double mx, double my, double mz, float inten,
+                                        const SliceDev& sl, uint32_t flags, RecPay& pay) {
+#pragma clang fp contract(off)
+  const double m = mz - (double)sl.z;
+  const float rho = expf(-0.5f * (float)(m * m * r.invD));
+  float at = inten * rho / r.sdet;
+  if (flags & GP_FLAG_CONV_EXACT) at *= r.conv;
+  // pixel-index mean as a binary32 anchor (nearest integer) plus remainder
+  const double px = (((mx - r.u * m) - (double)sl.x0) / (double)sl.dx) - 0.5;
+  const double py = (((my - r.v * m) - (double)sl.y0) / (double)sl.dy) - 0.5;
+  pay.ax = (float)rint(px);
+  pay.ay = (float)rint(py);
+  pay.xr = (float)(px - (double)pay.ax);
+  pay.yr = (float)(py - (double)pay.ay);
+  pay.a = (float)(r.ta * (double)sl.dx * (double)sl.dx);
+  pay.b = (float)(r.tb * (double)sl.dx * (double)sl.dy);
+  pay.c = (float)(r.tc * (double)sl.dy * (double)sl.dy);
+  pay.w = at;
+  const bool good = isfinite(at) && isfinite(pay.ax) && isfinite(pay.ay) && isfinite(pay.xr) && isfinite(pay.yr) &&
+                    isfinite(pay.a) && isfinite(pay.b) && isfinite(pay.c);
+  if (!good) pay.xr = pay.yr = pay.ax = pay.ay = pay.a = pay.b = pay.c = pay.w = 0.0f;
+}
+
+__device__ __forceinline__ RecMeta rec_meta(uint32_t ibase, const SpecRect& rect, int k) {
+  RecMeta meta;
+  meta.ibase = ibase;
+  meta.rx = (uint32_t)rect.tx0 | ((uint32_t)rect.tx1 << 16);
+  meta.ry = (uint32_t)rect.ty0 | ((uint32_t)rect.ty1 << 16);
+  meta.slice = (uint32_t)k;
+  return meta;
+}
+
+// The record of (Gaussian, slice k) from its world covariance (cov), binary32
+// parameters p and activated scales c.  pose: the slice's camera pose
+// (Sigma_c = R_c Sigma R_c^T, mu_c = R_c mu + t) or nullptr.
 __device__ __forceinline__ void make_record(const double* cov, const float* p, const SpecCov& c, const float* pose,
-                                            const SliceDev& sl, int k, uint32_t ibase, uint32_t flags,
-                                            const SpecRect& rect, RecPay& pay, RecMeta& meta) {
-  // a fixed operation order (no contraction), so that equal inputs give equal
-  // records in every instantiation of the emit
+                                            const SliceDev& sl, uint32_t flags, RecPay& pay) {
 #pragma clang fp contract(off)
   double mu[3] = {p[0], p[1], p[2]};
-  double sxx = cov[0], sxy = cov[1], sxz = cov[2], syy = cov[3], syz = cov[4], szz = cov[5];
+  double cv[6] = {cov[0], cov[1], cov[2], cov[3], cov[4], cov[5]};
   if (pose) {
-    const double S[3][3] = {{sxx, sxy, sxz}, {sxy, syy, syz}, {sxz, syz, szz}};
+    const double S[3][3] = {{cov[0], cov[1], cov[2]}, {cov[1], cov[3], cov[4]}, {cov[2], cov[4], cov[5]}};
     double T[3][3], mc[3];   // T = R_c Sigma
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -463,40 +536,10 @@ __device__ __forceinline__ void make_record(const double* cov, const float* p, c
     auto E = [&](int i, int j) {
       return (T[i][0] * (double)pose[3 * j] + T[i][1] * (double)pose[3 * j + 1]) + T[i][2] * (double)pose[3 * j + 2];
     };
-    sxx = E(0, 0); sxy = E(0, 1); sxz = E(0, 2); syy = E(1, 1); syz = E(1, 2); szz = E(2, 2);
+    cv[0] = E(0, 0); cv[1] = E(0, 1); cv[2] = E(0, 2); cv[3] = E(1, 1); cv[4] = E(1, 2); cv[5] = E(2, 2);
     mu[0] = mc[0]; mu[1] = mc[1]; mu[2] = mc[2];
   }
-  const double v0 = (double)c.s0 * (double)c.s0, v1 = (double)c.s1 * (double)c.s1, v2 = (double)c.s2 * (double)c.s2;
-  const double s2 = (double)sl.sigma_z * (double)sl.sigma_z;
-  const double invD = 1.0 / (s2 + szz);          // 0 for sigma_z = inf
-  const double u = sxz * invD, v = syz * invD;
-  const double A = sxx - u * sxz, B = sxy - u * syz, C = syy - v * syz;
-  const double det = A * C - B * B;
-  const double m = mu[2] - (double)sl.z;
-  const float rho = expf(-0.5f * (float)(m * m * invD));
-  float at = p[10] * rho / sqrtf((float)det);
-  // exact convolution integral: times sqrt(2 pi det Sigma_e), det Sigma_e = det Sigma w
-  if (flags & GP_FLAG_CONV_EXACT) at *= sqrtf((float)(6.283185307179586 * ((v0 * v1) * v2) / (1.0 + szz / s2)));
-  const double inv_det = 1.0 / det;
-  const double L2 = 1.4426950408889634;
-  // pixel-index mean as a binary32 anchor (nearest integer) plus remainder
-  const double px = (((mu[0] - u * m) - (double)sl.x0) / (double)sl.dx) - 0.5;
-  const double py = (((mu[1] - v * m) - (double)sl.y0) / (double)sl.dy) - 0.5;
-  pay.ax = (float)rint(px);
-  pay.ay = (float)rint(py);
-  pay.xr = (float)(px - (double)pay.ax);
-  pay.yr = (float)(py - (double)pay.ay);
-  pay.a = (float)(-0.5 * L2 * C * inv_det * (double)sl.dx * (double)sl.dx);
-  pay.b = (float)(L2 * B * inv_det * (double)sl.dx * (double)sl.dy);
-  pay.c = (float)(-0.5 * L2 * A * inv_det * (double)sl.dy * (double)sl.dy);
-  pay.w = at;
-  const bool good = det > 0.0 && isfinite(at) && isfinite(pay.ax) && isfinite(pay.ay) && isfinite(pay.xr) &&
-                    isfinite(pay.yr) && isfinite(pay.a) && isfinite(pay.b) && isfinite(pay.c);
-  if (!good) pay.xr = pay.yr = pay.ax = pay.ay = pay.a = pay.b = pay.c = pay.w = 0.0f;
-  meta.ibase = ibase;
-  meta.rx = (uint32_t)rect.tx0 | ((uint32_t)rect.tx1 << 16);
-  meta.ry = (uint32_t)rect.ty0 | ((uint32_t)rect.ty1 << 16);
-  meta.slice = (uint32_t)k;
+  rec_pay(rec_sigma(cv, c.s0, c.s1, c.s2, sl.sigma_z, flags), mu[0], mu[1], mu[2], p[10], sl, flags, pay);
 }
 
 // Slots of the 64 consecutive Gaussians t0 .. t0 + 63 of one wavefront.
@@ -549,20 +592,22 @@ __device__ __forceinline__ void slots_wave(const PreArgs& a, int t0, int* list, 
 // and adjacent instance runs.  (With one lane per Gaussian and many slices per
 // Gaussian, every lane would stream to its own region and L2 would evict
 // partly written lines.)  W = 1 is the one-lane form, used when each Gaussian
-// has at most one slice.  Each lane first computes the float64 covariance of
-// its own entry's Gaussian into LDS, once for all of its records.
-// What the emit of an axial batch needs of an activated Gaussian: the mean,
-// the intensity, the scales and Sigma_zz, and the sigma_z part of its
-// footprint for the sigma_z of its first kept slice (key: the bits of that
-// sigma_z^2).
+// has at most one slice.  Each lane first forms what the records of its own
+// entry's Gaussian share into LDS, once for all of them: for axial slices the
+// sigma_z parts of the footprint and of the record (RecSigma), for posed ones
+// the float64 world covariance.
+// What the emit needs of an activated Gaussian: the mean, the intensity, the
+// scales and Sigma_zz, and the sigma_z part of its footprint (the u, v, rx, ry
+// of SpecSigma) for the sigma_z of its first kept slice (key: the bits of that
+// sigma_z).
 struct EmitGauss {
   float mx, my, mz, inten, s0, s1, s2, szz;
   uint32_t key;
-  SpecSigma g;
+  float gu, gv, grx, gry;
 };
 
 // footprint() of an axial slice for the emit: the stored sigma_z part when the
-// slice's sigma_z^2 is the key's, else computed from the reloaded Gaussian t.
+// slice's sigma_z is the key's, else computed from the reloaded Gaussian t.
 // With POSED, e holds the Gaussian in the camera frame its group's slices share
 // (the reload takes the same view).
 template <int DT, bool POSED>
@@ -572,8 +617,9 @@ __device__ __forceinline__ bool footprint_emit(const PreArgs& a, int n_groups, i
   const bool exact = (a.rc.flags & GP_FLAG_EXACT) != 0;
   ax = spec_axial(e.mz, e.szz, sl.z, sl.sigma_z);
   if (!exact && !(ax.q <= a.rc.q_cut)) return false;
-  SpecSigma g = e.g;
-  if (__float_as_uint(ax.s2) != e.key) {
+  // (the rectangle reads only u, v, rx and ry)
+  SpecSigma g{0.0f, 0.0f, 0.0f, 0.0f, e.gu, e.gv, e.grx, e.gry};
+  if (__float_as_uint(sl.sigma_z) != e.key) {
     Loaded L;
     load_params<DT>(a, n_groups, t, L);
     activate(a, L);
@@ -602,8 +648,8 @@ constexpr int kStagePerLane = 4;
 
 template <int DT, int W, bool POSED>
 __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const int* list, uint32_t j0,
-                                          uint32_t n_active, double (*cov64)[6], EmitGauss* eg, float4* pw,
-                                          uint2* stage) {
+                                          uint32_t n_active, double (*cov64)[6], RecSigma* rsg, EmitGauss* eg,
+                                          float4* pw, uint2* stage) {
   const int lane = threadIdx.x & 63;
   const uint32_t j = j0 + (uint32_t)lane;
   const int t = j < n_active ? list[j] : 0;
@@ -614,15 +660,19 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
     krange = a.g_krange[t];
     Loaded Lq;
     load_params<DT>(a, n_groups, t, Lq);
-    cov_f64(Lq.p, a.rc.scale_mod, cov64[lane]);
     if (!POSED) {
+      double cw[6];
+      cov_f64(Lq.p, a.rc.scale_mod, cw);
       activate(a, Lq);
       const SpecCov& c = Lq.c;
       const SliceDev& s0 = a.slices[krange & 0xFFFFu];   // the first kept slice
       const SpecAxial ax0 = spec_axial(Lq.p[2], c.szz, s0.z, s0.sigma_z);
+      const SpecSigma g0 = spec_sigma(c, ax0, a.rc.bbox);
       eg[lane] = EmitGauss{Lq.p[0], Lq.p[1], Lq.p[2], Lq.p[10], c.s0, c.s1, c.s2, c.szz,
-                           __float_as_uint(ax0.s2), spec_sigma(c, ax0, a.rc.bbox)};
+                           __float_as_uint(s0.sigma_z), g0.u, g0.v, g0.rx, g0.ry};
+      rsg[lane] = rec_sigma(cw, c.s0, c.s1, c.s2, s0.sigma_z, a.rc.flags);
     } else {
+      cov_f64(Lq.p, a.rc.scale_mod, cov64[lane]);
       // slices sharing one pose: the Gaussian's view in that camera frame,
       // kept like an axial Gaussian's (the world mean for the record)
       const bool sh = (Lq.G.flags & kGroupSharedPose) != 0;
@@ -634,8 +684,9 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
         spec_pose(Lq.c, Lq.p, a.poses + 12 * Lq.G.k0, cv, mv);
         const SliceDev& s0 = a.slices[krange & 0xFFFFu];
         const SpecAxial ax0 = spec_axial(mv[2], cv.szz, s0.z, s0.sigma_z);
+        const SpecSigma g0 = spec_sigma(cv, ax0, a.rc.bbox);
         eg[lane] = EmitGauss{mv[0], mv[1], mv[2], Lq.p[10], cv.s0, cv.s1, cv.s2, cv.szz,
-                             __float_as_uint(ax0.s2), spec_sigma(cv, ax0, a.rc.bbox)};
+                             __float_as_uint(s0.sigma_z), g0.u, g0.v, g0.rx, g0.ry};
       }
     }
   }
@@ -679,17 +730,6 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
     } else {
       // the group's Gaussian as its entry's lane activated it (the same values)
       e = eg[gi];
-#pragma unroll
-      for (int r = 0; r < 11; ++r) L.p[r] = 0.0f;
-      L.p[0] = e.mx;
-      L.p[1] = e.my;
-      L.p[2] = e.mz;
-      L.p[10] = e.inten;
-      L.c = SpecCov{};
-      L.c.s0 = e.s0;
-      L.c.s1 = e.s1;
-      L.c.s2 = e.s2;
-      L.c.szz = e.szz;
     }
     const int kb = (int)(g_kr & 0xFFFFu), ke = (int)(g_kr >> 16);
     uint32_t rec_run = g_rb, inst_run = g_ib;
@@ -735,11 +775,24 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
         const uint32_t rid = rec_run + rpos;
         uint32_t slot = inst_run + ipos;
         RecPay pay;
-        RecMeta meta;
-        make_record(cov64[gi], L.p, L.c, POSED ? a.poses + 12 * k : nullptr, sl, k, slot, a.rc.flags, rect,
-                    pay, meta);
+        if constexpr (POSED) {
+          make_record(cov64[gi], L.p, L.c, a.poses + 12 * k, sl, a.rc.flags, pay);
+        } else {
+          RecSigma r;
+          if (__float_as_uint(sl.sigma_z) == e.key) {
+            r = rsg[gi];
+          } else {
+            // another sigma_z: the float64 covariance again, from the reloaded parameters
+            Loaded Lr;
+            load_params<DT>(a, n_groups, tg, Lr);
+            double cw[6];
+            cov_f64(Lr.p, a.rc.scale_mod, cw);
+            r = rec_sigma(cw, e.s0, e.s1, e.s2, sl.sigma_z, a.rc.flags);
+          }
+          rec_pay(r, (double)e.mx, (double)e.my, (double)e.mz, e.inten, sl, a.rc.flags, pay);
+        }
         a.rec_pay[rid] = pay;
-        if (!(a.rc.flags & GP_FLAG_FORWARD_ONLY)) a.rec_meta[rid] = meta;
+        if (!(a.rc.flags & GP_FLAG_FORWARD_ONLY)) a.rec_meta[rid] = rec_meta(slot, rect, k);
         if (!staged) {
           for (int ty = rect.ty0; ty <= rect.ty1; ++ty) {
             for (int tx = rect.tx0; tx <= rect.tx1; ++tx, ++slot) {
@@ -879,7 +932,8 @@ template <int DT, int W, bool POSED>
 __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   __shared__ int list[kEmitChunk];
   __shared__ int n_list;
-  __shared__ double cov64[4][64][6];
+  __shared__ double cov64[4][POSED ? 64 : 1][6];
+  __shared__ RecSigma rsgs[4][POSED ? 1 : 64];
   __shared__ EmitGauss egs[4][64];
   __shared__ float4 pws[4][POSED ? 64 : 1];
   __shared__ uint2 stg[4][W >= 8 ? kStagePerLane * 64 : 1];
@@ -902,7 +956,8 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane(n_w[wave]);
-      if (n > 0u) emit_wave<DT, W, POSED>(a, n_groups, wl, 0u, n, cov64[wave], egs[wave], pws[wave], stg[wave]);
+      if (n > 0u) emit_wave<DT, W, POSED>(a, n_groups, wl, 0u, n, cov64[wave], rsgs[wave], egs[wave], pws[wave],
+                                          stg[wave]);
     }
     return;
   }
@@ -919,8 +974,8 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
     uint32_t q = ((n + 3u) / 4u + kRound - 1u) / kRound * kRound;
     q = q > 64u ? 64u : (q < kRound ? kRound : q);
     for (uint32_t j0 = (uint32_t)wave * q; j0 < n; j0 += 4u * q)
-      emit_wave<DT, W, POSED>(a, n_groups, list, j0, j0 + q < n ? j0 + q : n, cov64[wave], egs[wave], pws[wave],
-                              stg[wave]);
+      emit_wave<DT, W, POSED>(a, n_groups, list, j0, j0 + q < n ? j0 + q : n, cov64[wave], rsgs[wave], egs[wave],
+                              pws[wave], stg[wave]);
     __syncthreads();   // list and n_list are rewritten by the next chunk
   }
 }
