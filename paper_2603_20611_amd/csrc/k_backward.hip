@@ -10,12 +10,17 @@
 //   mu_2d = (mu_x - u m, mu_y - v m), q_ax = m^2 / D, opacity_r = exp(-q_ax / 2)
 //   alpha~ = alpha opacity_r / sqrt(AC - B^2), conic = (C, -B, A) / (AC - B^2)
 //
-// One thread per Gaussian sums, for each of its records (one per slice it
-// reaches), the six moments of the record's tiles in footprint order,
-// applies the chain rule, accumulates over records in slice order and finally
-// maps Sigma = R diag(s^2) R^T back to (log-scale, quaternion).  The gradient is
-// added to the caller's buffer with plain loads and stores: every element has
-// exactly one writer, so the result is deterministic.
+// L lanes per Gaussian (L = 1 for deep stacks, where nearly every Gaussian
+// has records and one lane each already fills the chip; L = 4 or 8 for
+// batches of at most that many slices, where few Gaussians have records and
+// one lane's serial chain over them set the kernel's time): lane i of the
+// group takes the Gaussian's records i, i + L, ... (one per slice it
+// reaches), sums the six moments of each record's tiles in footprint order
+// and applies the chain rule; the group adds its lanes' sums by a fixed
+// butterfly, and its first lane maps Sigma = R diag(s^2) R^T back to
+// (log-scale, quaternion).  The gradient is added to the caller's buffer
+// with plain loads and stores: every element has exactly one writer, so the
+// result is deterministic.
 #include "gp_internal.h"
 #include "gp_spec.h"
 
@@ -46,24 +51,34 @@ struct BwdPreArgs {
   int chunk;                // Gaussians per workgroup round (a multiple of 256, at most kBwdChunk)
 };
 
-template <int DT, bool POSED>
-__device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, int t) {
-  const uint32_t nrec = a.g_nrec[t];
-  if (nrec == 0) return;
-  const int g = group_of(a.groups, n_groups, (t & ~63));
-  const GroupDev G = a.groups[g];
-  const int j = t - G.gbase;
-  if (j >= G.n) return;
-  const uint32_t rbase = a.g_rbase[t];
-
+// Every lane of a group of L calls this for the group's Gaussian t (active
+// false: the group has none); the group's lanes exchange their sums.
+template <int DT, bool POSED, int L>
+__device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, int t, bool active) {
+  const uint32_t li = L > 1 ? (threadIdx.x & (uint32_t)(L - 1)) : 0u;
+  bool go = active;
+  uint32_t nrec = 0u, rbase = 0u;
+  int j = 0;
+  GroupDev G{};
+  if (go) {
+    nrec = a.g_nrec[t];
+    G = a.groups[group_of(a.groups, n_groups, (t & ~63))];
+    j = t - G.gbase;
+    go = nrec > 0u && j < G.n;
+  }
   float p[11];
-  p[0] = G.means[j];
-  p[1] = G.means[G.stride + j];
-  p[2] = G.means[2 * G.stride + j];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) p[3 + r] = load_attr<DT>(G.attrs, r, G.stride, j);
-  SpecCov c;
-  spec_cov(p[3], p[4], p[5], p[6], p[7], p[8], p[9], a.rc.scale_mod, c);
+  for (int r = 0; r < 11; ++r) p[r] = 0.0f;
+  SpecCov c{};
+  if (go) {
+    rbase = a.g_rbase[t];
+    p[0] = G.means[j];
+    p[1] = G.means[G.stride + j];
+    p[2] = G.means[2 * G.stride + j];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) p[3 + r] = load_attr<DT>(G.attrs, r, G.stride, j);
+    spec_cov(p[3], p[4], p[5], p[6], p[7], p[8], p[9], a.rc.scale_mod, c);
+  }
   const float alpha = p[10];
 
   float gmx = 0.f, gmy = 0.f, gmz = 0.f, galpha = 0.f;
@@ -74,12 +89,12 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
 
   // the next record's bookkeeping is loaded while this record is summed (the
   // moments' addresses depend on it: two dependent loads per record otherwise)
-  const uint32_t rend = rbase + nrec < a.rc.rec_cap ? rbase + nrec : a.rc.rec_cap;
+  const uint32_t rend = !go ? 0u : (rbase + nrec < a.rc.rec_cap ? rbase + nrec : a.rc.rec_cap);
   RecMeta meta_next{};
-  if (rbase < rend) meta_next = a.rec_meta[rbase];
-  for (uint32_t r = rbase; r < rend; ++r) {
+  if (rbase + li < rend) meta_next = a.rec_meta[rbase + li];
+  for (uint32_t r = rbase + li; r < rend; r += (uint32_t)L) {
     const RecMeta meta = meta_next;
-    if (r + 1u < rend) meta_next = a.rec_meta[r + 1u];
+    if (r + (uint32_t)L < rend) meta_next = a.rec_meta[r + (uint32_t)L];
     const SliceDev sl = a.slices[meta.slice];
     const uint32_t ntiles = rec_ntiles(meta);
     float M0 = 0.f, Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
@@ -188,6 +203,27 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
     st_rad = fmaxf(st_rad, a.rc.bbox * fmaxf(sqrtf(A) / ddx, sqrtf(C) / ddy));
     st_cnt += 1;
   }
+  if constexpr (L > 1) {
+    // the group's sums (the same butterfly on every lane: a fixed order)
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) {
+      gmx += __shfl_xor(gmx, o, 64);
+      gmy += __shfl_xor(gmy, o, 64);
+      gmz += __shfl_xor(gmz, o, 64);
+      galpha += __shfl_xor(galpha, o, 64);
+      gxx += __shfl_xor(gxx, o, 64);
+      gxy += __shfl_xor(gxy, o, 64);
+      gxz += __shfl_xor(gxz, o, 64);
+      gyy += __shfl_xor(gyy, o, 64);
+      gyz += __shfl_xor(gyz, o, 64);
+      gzz += __shfl_xor(gzz, o, 64);
+      gls += __shfl_xor(gls, o, 64);
+      st_norm += __shfl_xor(st_norm, o, 64);
+      st_cnt += __shfl_xor(st_cnt, o, 64);
+      st_rad = fmaxf(st_rad, __shfl_xor(st_rad, o, 64));
+    }
+  }
+  if (!go || li != 0u) return;
 
   // Sigma = M M^T with M = R diag(s): dL/dM = 2 Gs M, Gs symmetric
   const float Gs[3][3] = {{gxx, 0.5f * gxy, 0.5f * gxz},
@@ -241,15 +277,15 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
 
 // A workgroup takes `chunk` Gaussians at a time (512), gathers those with
 // records (a batch of a few slices reaches a small fraction of a large set)
-// into LDS and gives them to its 256 lanes, so that lanes do not idle on
-// Gaussians without records.  Each Gaussian still has exactly one writer; the
-// order in which a workgroup visits its Gaussians does not change any result.
-// 512 rather than 2,048 at a time: four times the workgroups to hide the
-// latency of each lane's chain over its records (measured 0.036 -> 0.034 ms on
-// an 8-slice batch, 0.80 -> 0.56 ms on the 400-slice stack).
+// into LDS and gives them to its lanes, L per Gaussian, so that lanes do not
+// idle on Gaussians without records.  Each Gaussian still has exactly one
+// writer; the order in which a workgroup visits its Gaussians does not change
+// any result.  512 rather than 2,048 at a time: four times the workgroups to
+// hide the latency of each lane's chain over its records (measured 0.036 ->
+// 0.034 ms on an 8-slice batch, 0.80 -> 0.56 ms on the 400-slice stack).
 constexpr int kBwdChunk = 512;
 
-template <int DT, bool POSED>
+template <int DT, bool POSED, int L>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
   __shared__ int s_list[kBwdChunk];
   __shared__ int s_n;
@@ -271,20 +307,39 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
     }
     __syncthreads();
     const int n = s_n;
-    for (int j = threadIdx.x; j < n; j += 256) backward_one<DT, POSED>(a, n_groups, s_list[j]);
+    // rounds of 256 / L Gaussians (the bound is uniform over the workgroup,
+    // so every lane of a group reaches its exchanges)
+    for (int jb = 0; jb < n; jb += 256 / L) {
+      const int jj = jb + (int)(threadIdx.x / L);
+      const bool act = jj < n;
+      backward_one<DT, POSED, L>(a, n_groups, act ? s_list[jj] : 0, act);
+    }
     __syncthreads();   // s_list and s_n are rewritten by the next chunk
   }
 }
 
-template <bool POSED>
-hipError_t launch_bwd_p(const BwdPreArgs& a, int attr_dtype, unsigned blocks, hipStream_t s) {
+template <bool POSED, int L>
+hipError_t launch_bwd_l(const BwdPreArgs& a, int attr_dtype, unsigned blocks, hipStream_t s) {
   switch (attr_dtype) {
-    case GP_BF16: k_preprocess_bwd<GP_BF16, POSED><<<blocks, 256, 0, s>>>(a); break;
-    case GP_F16: k_preprocess_bwd<GP_F16, POSED><<<blocks, 256, 0, s>>>(a); break;
-    case GP_Q16: k_preprocess_bwd<GP_Q16, POSED><<<blocks, 256, 0, s>>>(a); break;
-    default: k_preprocess_bwd<GP_F32, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case GP_BF16: k_preprocess_bwd<GP_BF16, POSED, L><<<blocks, 256, 0, s>>>(a); break;
+    case GP_F16: k_preprocess_bwd<GP_F16, POSED, L><<<blocks, 256, 0, s>>>(a); break;
+    case GP_Q16: k_preprocess_bwd<GP_Q16, POSED, L><<<blocks, 256, 0, s>>>(a); break;
+    default: k_preprocess_bwd<GP_F32, POSED, L><<<blocks, 256, 0, s>>>(a); break;
   }
   return hipGetLastError();
+}
+
+// Lanes per Gaussian for a batch emitted `width` lanes wide (at most `width`
+// slices per Gaussian set): 1 for a single slice or a deep stack, else 4 or 8.
+inline int bwd_lanes(int width) { return width <= 1 || width >= 16 ? 1 : (width <= 4 ? 4 : 8); }
+
+template <bool POSED>
+hipError_t launch_bwd_p(const BwdPreArgs& a, int attr_dtype, int width, unsigned blocks, hipStream_t s) {
+  switch (bwd_lanes(width)) {
+    case 8: return launch_bwd_l<POSED, 8>(a, attr_dtype, blocks, s);
+    case 4: return launch_bwd_l<POSED, 4>(a, attr_dtype, blocks, s);
+    default: return launch_bwd_l<POSED, 1>(a, attr_dtype, blocks, s);
+  }
 }
 
 }  // namespace
@@ -311,8 +366,8 @@ hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, flo
                kBwdChunk};
   int64_t blocks = (d.gauss + a.chunk - 1) / a.chunk;
   if (blocks > 16384) blocks = 16384;
-  return d.posed ? launch_bwd_p<true>(a, rc.attr_dtype, (unsigned)blocks, s)
-                 : launch_bwd_p<false>(a, rc.attr_dtype, (unsigned)blocks, s);
+  return d.posed ? launch_bwd_p<true>(a, rc.attr_dtype, d.emit_width, (unsigned)blocks, s)
+                 : launch_bwd_p<false>(a, rc.attr_dtype, d.emit_width, (unsigned)blocks, s);
 }
 
 }  // namespace gp
