@@ -12,7 +12,19 @@
 
 #include "../../include/gaussianpile.h"
 
+// The amdgcn legacy multiply intrinsic, declared by its LLVM name.
+extern "C" __device__ float gp_fmul_legacy(float, float) __asm("llvm.amdgcn.fmul.legacy");
+
 namespace gp {
+
+// Product with 0 * anything = 0 (also 0 * inf): v_mul_legacy_f32 through the
+// compiler's own intrinsic, so that it schedules the product like any other
+// and inserts the wait state gfx950 requires between a transcendental
+// (v_exp_f32) and a VALU instruction reading its result only where one is
+// needed.  (Written as inline asm, the product is opaque to the hazard
+// recognizer: a variant that multiplied an exp2 result at once read stale
+// values, so an asm form must carry a wait state of its own.)
+__device__ __forceinline__ float mul0(float x, float y) { return gp_fmul_legacy(x, y); }
 
 // Attribute row r (0..7: l_x, l_y, l_z, q_w, q_x, q_y, q_z, alpha) of Gaussian
 // j, converted to float32.

@@ -95,18 +95,21 @@ __device__ __forceinline__ void stage_record(const float4 r0, const float4 r1, f
   s1 = make_float4(r1.x, r1.y, smooth ? exp2f(2.0f * r0.z) : -1.0f, smooth ? exp2f(r0.w) : 0.0f);
 }
 
-// Product with 0 * anything = 0 (also 0 * inf).  The compiler does not see
-// inside the asm, so it inserts no wait state for an operand just written by
-// a transcendental (v_exp_f32), which gfx950 requires before a VALU reads it:
-// the asm carries its own (without it, a variant that multiplied an exp2
-// result at once read stale values).
-__device__ __forceinline__ float mul0(float x, float y) {
+
+
+
+
+// The forward's step keeps the same product written as inline asm: the
+// compiler's own schedule of the step with the intrinsic measured 1 % slower
+// on the 400-slice stack (0.686 -> 0.693 ms).  The compiler cannot see
+// inside the asm, so the asm carries the wait state that gfx950 needs before
+// a VALU instruction reads a transcendental's result (its operands are often
+// fresh exp2 results).
+__device__ __forceinline__ float mul0_asm(float x, float y) {
   float r;
   asm("s_nop 0\n\tv_mul_legacy_f32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
   return r;
 }
-
-
 
 // One step of a half-wavefront: staged record (r0, r1) over the lane's 2 x 4
 // pixels whose first pixel is (fx0, fy0) from the tile origin, added to acc
@@ -129,16 +132,16 @@ __device__ __forceinline__ void raster_step(const float4 r0, const float4 r1, fl
     e10 = __builtin_amdgcn_exp2f(p10);
     float q0 = __builtin_amdgcn_exp2f(fmaf(r0.z, t, by0));
     float q1 = q0 * r1.w;
-    e01 = mul0(e00, q0);
-    e11 = mul0(e10, q1);
+    e01 = mul0_asm(e00, q0);
+    e11 = mul0_asm(e10, q1);
     q0 *= r1.z;
     q1 *= r1.z;
-    e02 = mul0(e01, q0);
-    e12 = mul0(e11, q1);
+    e02 = mul0_asm(e01, q0);
+    e12 = mul0_asm(e11, q1);
     q0 *= r1.z;
     q1 *= r1.z;
-    e03 = mul0(e02, q0);
-    e13 = mul0(e12, q1);
+    e03 = mul0_asm(e02, q0);
+    e13 = mul0_asm(e12, q1);
   } else {
     const float dy1 = dy0 + 1.0f;
     const float by1 = r0.w * dy1, cy1 = r1.x * dy1 * dy1;
@@ -542,16 +545,15 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
             float ev[4];
             const float d0 = dx[4 * q];
             if (smooth) {
-              // a ratio that overflows meets e = 0 (as in the forward); held
-              // finite, the plain products give 0 there (gx <= 1: no later
-              // overflow), with no asm multiply.
+              // a ratio that overflows meets e = 0 (as in the forward), and
+              // the products with 0 * inf = 0 give 0 there
               ev[0] = __builtin_amdgcn_exp2f(fmaf(fmaf(ca, d0, by), d0, cy));
-              float r = fminf(__builtin_amdgcn_exp2f(fmaf(ca, fmaf(2.0f, d0, 1.0f), by)), 0x1p127f);
-              ev[1] = ev[0] * r;
+              float r = __builtin_amdgcn_exp2f(fmaf(ca, fmaf(2.0f, d0, 1.0f), by));
+              ev[1] = mul0(ev[0], r);
               r *= gx;
-              ev[2] = ev[1] * r;
+              ev[2] = mul0(ev[1], r);
               r *= gx;
-              ev[3] = ev[2] * r;
+              ev[3] = mul0(ev[2], r);
             } else {
 #pragma unroll
               for (int c = 0; c < 4; ++c) {

@@ -229,17 +229,17 @@ __global__ __launch_bounds__(64) void k_vox_fwd(VoxArgs a) {
         const float dz0 = fz0 - r0.z;
         if (r2.z > 0.0f) {
           // two four-voxel segments, each from an exact exp2 by the product
-          // recurrence along z (the raster's reasoning with czz >= -4; the
-          // ratio held finite in place of a 0 * inf = 0 multiply)
+          // recurrence along z (the raster's reasoning with czz >= -4: a
+          // ratio that overflows meets e = 0, and 0 * inf = 0)
 #pragma unroll
           for (int h = 0; h < kVT; h += 4) {
             const float dz = dz0 + (float)h;
             float e = __builtin_amdgcn_exp2f(fmaf(fmaf(r1.z, dz, lz), dz, pxy));
-            float r = fminf(__builtin_amdgcn_exp2f(fmaf(r1.z, fmaf(2.0f, dz, 1.0f), lz)), 0x1p127f);
+            float r = __builtin_amdgcn_exp2f(fmaf(r1.z, fmaf(2.0f, dz, 1.0f), lz));
             acc[h] = fmaf(r0.w, e, acc[h]);
 #pragma unroll
             for (int k = 1; k < 4; ++k) {
-              e *= r;
+              e = mul0(e, r);
               r *= r2.z;
               acc[h + k] = fmaf(r0.w, e, acc[h + k]);
             }
@@ -314,10 +314,10 @@ __global__ __launch_bounds__(256) void k_vox_bwd(VoxArgs a) {
             for (int h = 0; h < kVT; h += 4) {
               const float d = dxs[h];
               ev[h] = __builtin_amdgcn_exp2f(fmaf(fmaf(r1.x, d, bx), d, c0));
-              float r = fminf(__builtin_amdgcn_exp2f(fmaf(r1.x, fmaf(2.0f, d, 1.0f), bx)), 0x1p127f);
+              float r = __builtin_amdgcn_exp2f(fmaf(r1.x, fmaf(2.0f, d, 1.0f), bx));
 #pragma unroll
               for (int k = 1; k < 4; ++k) {
-                ev[h + k] = ev[h + k - 1] * r;
+                ev[h + k] = mul0(ev[h + k - 1], r);
                 r *= r2.w;
               }
             }
