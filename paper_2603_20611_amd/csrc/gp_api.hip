@@ -625,7 +625,7 @@ gp_status gp_render_backward_posed(gp_workspace* w, const gp_gaussians* g, const
   if (ns == 0 || g->n == 0) return GP_OK;
   GP_HIP(hipSetDevice(ws->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  LaunchDims d{ws->fwd_gauss, ws->fwd_nbins, emit_width_for(ns)};
+  LaunchDims d{ws->fwd_gauss, ws->fwd_nbins};
   d.posed = ws->fwd_posed;
   GP_HIP(timed(ws, GP_STAGE_RASTER_BWD, s, [&] { return launch_raster_bwd(ws->fwd_rc, *ws, grad_out, d, s); }));
   GP_HIP(timed(ws, GP_STAGE_PREPROCESS_BWD, s,

@@ -10,15 +10,14 @@
 //   mu_2d = (mu_x - u m, mu_y - v m), q_ax = m^2 / D, opacity_r = exp(-q_ax / 2)
 //   alpha~ = alpha opacity_r / sqrt(AC - B^2), conic = (C, -B, A) / (AC - B^2)
 //
-// L lanes per Gaussian (L = 1 for deep stacks, where nearly every Gaussian
-// has records and one lane each already fills the chip; L = 4 or 8 for
-// batches of at most that many slices, where few Gaussians have records and
-// one lane's serial chain over them set the kernel's time): lane i of the
-// group takes the Gaussian's records i, i + L, ... (one per slice it
-// reaches), sums the six moments of each record's tiles in footprint order
-// and applies the chain rule; the group adds its lanes' sums by a fixed
-// butterfly, and its first lane maps Sigma = R diag(s^2) R^T back to
-// (log-scale, quaternion).  The gradient is added to the caller's buffer
+// L lanes per Gaussian (1, 2, 4 or 8: the most that still give every
+// Gaussian of a workgroup's list its lanes in one round; a batch of a few
+// slices leaves few Gaussians with records, and one lane's serial chain over
+// up to eight of them had set the kernel's time): lane i of the group takes
+// the Gaussian's records i, i + L, ... (one per slice it reaches), sums the
+// six moments of each record's tiles in footprint order and applies the
+// chain rule; the group adds its lanes' sums by a fixed butterfly, and its
+// first lane maps Sigma = R diag(s^2) R^T back to (log-scale, quaternion).  The gradient is added to the caller's buffer
 // with plain loads and stores: every element has exactly one writer, so the
 // result is deterministic.
 #include "gp_internal.h"
@@ -285,7 +284,19 @@ __device__ __forceinline__ void backward_one(const BwdPreArgs& a, int n_groups, 
 // 0.034 ms on an 8-slice batch, 0.80 -> 0.56 ms on the 400-slice stack).
 constexpr int kBwdChunk = 512;
 
+// The workgroup's list of n Gaussians, L lanes each, in rounds of 256 / L
+// (the bound is uniform over the workgroup, so every lane of a group reaches
+// its exchanges).
 template <int DT, bool POSED, int L>
+__device__ __forceinline__ void backward_list(const BwdPreArgs& a, int n_groups, const int* list, int n) {
+  for (int jb = 0; jb < n; jb += 256 / L) {
+    const int jj = jb + (int)(threadIdx.x / L);
+    const bool act = jj < n;
+    backward_one<DT, POSED, L>(a, n_groups, act ? list[jj] : 0, act);
+  }
+}
+
+template <int DT, bool POSED>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
   __shared__ int s_list[kBwdChunk];
   __shared__ int s_n;
@@ -307,39 +318,24 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdPreArgs a) {
     }
     __syncthreads();
     const int n = s_n;
-    // rounds of 256 / L Gaussians (the bound is uniform over the workgroup,
-    // so every lane of a group reaches its exchanges)
-    for (int jb = 0; jb < n; jb += 256 / L) {
-      const int jj = jb + (int)(threadIdx.x / L);
-      const bool act = jj < n;
-      backward_one<DT, POSED, L>(a, n_groups, act ? s_list[jj] : 0, act);
-    }
+    // as many lanes per Gaussian as fit the list in one round (n is uniform)
+    if (n <= 32) backward_list<DT, POSED, 8>(a, n_groups, s_list, n);
+    else if (n <= 64) backward_list<DT, POSED, 4>(a, n_groups, s_list, n);
+    else if (n <= 128) backward_list<DT, POSED, 2>(a, n_groups, s_list, n);
+    else backward_list<DT, POSED, 1>(a, n_groups, s_list, n);
     __syncthreads();   // s_list and s_n are rewritten by the next chunk
   }
 }
 
-template <bool POSED, int L>
-hipError_t launch_bwd_l(const BwdPreArgs& a, int attr_dtype, unsigned blocks, hipStream_t s) {
+template <bool POSED>
+hipError_t launch_bwd_p(const BwdPreArgs& a, int attr_dtype, unsigned blocks, hipStream_t s) {
   switch (attr_dtype) {
-    case GP_BF16: k_preprocess_bwd<GP_BF16, POSED, L><<<blocks, 256, 0, s>>>(a); break;
-    case GP_F16: k_preprocess_bwd<GP_F16, POSED, L><<<blocks, 256, 0, s>>>(a); break;
-    case GP_Q16: k_preprocess_bwd<GP_Q16, POSED, L><<<blocks, 256, 0, s>>>(a); break;
-    default: k_preprocess_bwd<GP_F32, POSED, L><<<blocks, 256, 0, s>>>(a); break;
+    case GP_BF16: k_preprocess_bwd<GP_BF16, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case GP_F16: k_preprocess_bwd<GP_F16, POSED><<<blocks, 256, 0, s>>>(a); break;
+    case GP_Q16: k_preprocess_bwd<GP_Q16, POSED><<<blocks, 256, 0, s>>>(a); break;
+    default: k_preprocess_bwd<GP_F32, POSED><<<blocks, 256, 0, s>>>(a); break;
   }
   return hipGetLastError();
-}
-
-// Lanes per Gaussian for a batch emitted `width` lanes wide (at most `width`
-// slices per Gaussian set): 1 for a single slice or a deep stack, else 4 or 8.
-inline int bwd_lanes(int width) { return width <= 1 || width >= 16 ? 1 : (width <= 4 ? 4 : 8); }
-
-template <bool POSED>
-hipError_t launch_bwd_p(const BwdPreArgs& a, int attr_dtype, int width, unsigned blocks, hipStream_t s) {
-  switch (bwd_lanes(width)) {
-    case 8: return launch_bwd_l<POSED, 8>(a, attr_dtype, blocks, s);
-    case 4: return launch_bwd_l<POSED, 4>(a, attr_dtype, blocks, s);
-    default: return launch_bwd_l<POSED, 1>(a, attr_dtype, blocks, s);
-  }
 }
 
 }  // namespace
@@ -366,8 +362,8 @@ hipError_t launch_preprocess_bwd(const RenderConst& rc, const Workspace& ws, flo
                kBwdChunk};
   int64_t blocks = (d.gauss + a.chunk - 1) / a.chunk;
   if (blocks > 16384) blocks = 16384;
-  return d.posed ? launch_bwd_p<true>(a, rc.attr_dtype, d.emit_width, (unsigned)blocks, s)
-                 : launch_bwd_p<false>(a, rc.attr_dtype, d.emit_width, (unsigned)blocks, s);
+  return d.posed ? launch_bwd_p<true>(a, rc.attr_dtype, (unsigned)blocks, s)
+                 : launch_bwd_p<false>(a, rc.attr_dtype, (unsigned)blocks, s);
 }
 
 }  // namespace gp
