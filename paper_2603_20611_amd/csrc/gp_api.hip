@@ -379,8 +379,8 @@ gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hi
   if (st != GP_OK) return st;
   const bool clear_ovf = ws->auto_size || ws->overflow_per_forward;
   GP_HIP(timed(ws, GP_STAGE_PREPROCESS, s, [&] {
-    hipError_t e = launch_reset(*ws, clear_ovf, d, s);
-    if (e == hipSuccess) e = launch_pre_count(rc, *ws, d, s);
+    // (the count also resets the forward's counters)
+    hipError_t e = launch_pre_count(rc, *ws, d, clear_ovf, s);
     if (e == hipSuccess)
       e = launch_scan_u32x2(ws->d_wave_cnt, ws->d_wave_cnt, &ws->d_hdr->n_waves, d.gauss / 64, ws->d_scan_part,
                             reinterpret_cast<uint2*>(ws->d_ctr + kCtrRecords), s);

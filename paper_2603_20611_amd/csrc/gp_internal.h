@@ -326,7 +326,10 @@ void workspace_free(Workspace* ws);
 // k_preprocess.hip
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDims& d, hipStream_t s);
-hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s);
+// Count of the forward, which also resets its counters, work queues and bin
+// ranges (one launch fewer per forward).
+hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, bool clear_overflow,
+                            hipStream_t s);
 hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, uint32_t sentinel_bin,
                            hipStream_t s);
 // k_sort.hip

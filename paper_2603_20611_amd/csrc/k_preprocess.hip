@@ -16,6 +16,8 @@
 // and instance slots in Gaussian order; k_pre_emit writes the records and one
 // (bin, record) pair per footprint tile.  Slots are therefore identical from
 // run to run.
+#include <algorithm>
+
 #include "gp_internal.h"
 #include "gp_spec.h"
 
@@ -33,9 +35,12 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) 
 }
 
 // Zeroes the per-forward counters, the work queues and the bin ranges of the
-// batch described by the device header.
-__global__ void k_reset(const BatchHdr* __restrict__ hdr, uint32_t* __restrict__ ctr, uint32_t* __restrict__ work,
-                        uint32_t* __restrict__ bin_lo, uint32_t* __restrict__ bin_hi, int clear_overflow) {
+// batch described by the device header (run by every thread of a grid; the
+// count does it on its way, the stand-alone kernel for a batch without
+// Gaussians).
+__device__ __forceinline__ void reset_forward(const BatchHdr* __restrict__ hdr, uint32_t* __restrict__ ctr,
+                                              uint32_t* __restrict__ work, uint32_t* __restrict__ bin_lo,
+                                              uint32_t* __restrict__ bin_hi, int clear_overflow) {
   const int64_t n = hdr->n_bins;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -50,6 +55,11 @@ __global__ void k_reset(const BatchHdr* __restrict__ hdr, uint32_t* __restrict__
     bin_lo[i] = 0u;
     bin_hi[i] = 0u;
   }
+}
+
+__global__ void k_reset(const BatchHdr* __restrict__ hdr, uint32_t* __restrict__ ctr, uint32_t* __restrict__ work,
+                        uint32_t* __restrict__ bin_lo, uint32_t* __restrict__ bin_hi, int clear_overflow) {
+  reset_forward(hdr, ctr, work, bin_lo, bin_hi, clear_overflow);
 }
 
 struct PreArgs {
@@ -71,6 +81,11 @@ struct PreArgs {
   const float* poses;   // [n_slices][12] of a posed batch
   int emit_chunk;       // Gaussians per workgroup round of the emit
   int count_lg;         // log2 of the lanes per near Gaussian in the compacting count
+  // the count's own reset of the forward
+  uint32_t* work;
+  uint32_t* bin_lo;
+  uint32_t* bin_hi;
+  int clear_overflow;
 };
 
 // (z, sigma_z) of slice k: from the workgroup's LDS copy when there is one
@@ -863,6 +878,7 @@ __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   const int n_slices = a.hdr->n_slices;
+  reset_forward(a.hdr, a.ctr, a.work, a.bin_lo, a.bin_hi, a.clear_overflow);
   const float2* zs = nullptr;
   if (!POSED && n_slices <= kZsLds) {
     for (int i = threadIdx.x; i < n_slices; i += 256) zs_lds[i] = make_float2(a.slices[i].z, a.slices[i].sigma_z);
@@ -1035,28 +1051,27 @@ hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDi
 static PreArgs pre_args(const RenderConst& rc, const Workspace& ws, uint32_t sentinel_bin) {
   return PreArgs{rc, ws.d_hdr, ws.d_groups, ws.d_slices, ws.d_ctr, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase,
                  ws.d_g_nrec, ws.d_g_ninst, ws.d_g_krange, ws.d_wave_cnt, ws.d_inst_key, ws.d_inst_val,
-                 sentinel_bin, ws.d_poses, 256, 0};
+                 sentinel_bin, ws.d_poses, 256, 0, ws.d_work, ws.d_bin_lo, ws.d_bin_hi, 0};
 }
 
-hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, hipStream_t s) {
-  if (d.gauss <= 0) return hipSuccess;
-  const PreArgs a = pre_args(rc, ws, 0u);
-  if (d.posed) {
-    int64_t blocks = (d.gauss + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
-    return launch_count_p<true, false>(a, rc.attr_dtype, (unsigned)blocks, s);
-  }
+hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, bool clear_overflow,
+                            hipStream_t s) {
+  if (d.gauss <= 0) return launch_reset(ws, clear_overflow, d, s);
+  PreArgs a = pre_args(rc, ws, 0u);
+  a.clear_overflow = clear_overflow ? 1 : 0;
+  // enough workgroups for the reset of the bin ranges too (16 bins per thread)
+  const int64_t reset_blocks = (d.bins + 4095) / 4096;
+  auto grid = [&](int64_t per_block) {
+    int64_t blocks = std::max<int64_t>((d.gauss + per_block - 1) / per_block, reset_blocks);
+    return (unsigned)(blocks > 16384 ? 16384 : blocks);
+  };
+  if (d.posed) return launch_count_p<true, false>(a, rc.attr_dtype, grid(256), s);
   // groups of at most 8 slices: most Gaussians are far from all of them
   if (d.emit_width <= 8) {
-    PreArgs ac = a;
-    while ((1 << ac.count_lg) < d.emit_width) ++ac.count_lg;   // one lane per slice of a group
-    int64_t blocks = (d.gauss + kCountChunk - 1) / kCountChunk;
-    if (blocks > 16384) blocks = 16384;
-    return launch_count_p<false, true>(ac, rc.attr_dtype, (unsigned)blocks, s);
+    while ((1 << a.count_lg) < d.emit_width) ++a.count_lg;   // one lane per slice of a group
+    return launch_count_p<false, true>(a, rc.attr_dtype, grid(kCountChunk), s);
   }
-  int64_t blocks = (d.gauss + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
-  return launch_count_p<false, false>(a, rc.attr_dtype, (unsigned)blocks, s);
+  return launch_count_p<false, false>(a, rc.attr_dtype, grid(256), s);
 }
 
 hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, uint32_t sentinel_bin,
