@@ -330,8 +330,10 @@ hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDi
 // ranges (one launch fewer per forward).
 hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, bool clear_overflow,
                             hipStream_t s);
+// scanned: the wavefront counts were scanned (else the emit forms the bases
+// and writes the totals itself).
 hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, uint32_t sentinel_bin,
-                           hipStream_t s);
+                           bool scanned, hipStream_t s);
 // k_sort.hip
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, const int32_t* d_n, int64_t max_n, uint32_t* part,
                            uint32_t* total, hipStream_t s);

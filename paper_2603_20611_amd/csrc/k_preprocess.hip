@@ -74,12 +74,13 @@ struct PreArgs {
   uint32_t* g_nrec;
   uint32_t* g_ninst;
   uint32_t* g_krange;
-  uint2* wave_cnt;      // per wavefront (records, instances); scanned in place
+  uint2* wave_cnt;      // per wavefront (records, instances), or their exclusive scan (scanned)
   uint32_t* inst_key;   // bin of every instance slot
   uint32_t* inst_val;   // record of every instance slot
   uint32_t sentinel_bin;
   const float* poses;   // [n_slices][12] of a posed batch
   int emit_chunk;       // Gaussians per workgroup round of the emit
+  int scanned;          // wave_cnt already holds the scan (else the emit forms its bases and the totals)
   int count_lg;         // log2 of the lanes per near Gaussian in the compacting count
   // the count's own reset of the forward
   uint32_t* work;
@@ -565,7 +566,7 @@ __device__ __forceinline__ void make_record(const double* cov, const float* p, c
 // g_ninst (overwritten with the instance base) receive them.  Gaussians that
 // have records are appended to the workgroup's list in LDS (in any order:
 // every output position is fixed by the scan).
-__device__ __forceinline__ void slots_wave(const PreArgs& a, int t0, int* list, int* n_list) {
+__device__ __forceinline__ void slots_wave(const PreArgs& a, int t0, uint2 wb, int* list, int* n_list) {
   const int lane = threadIdx.x & 63;
   const int t = t0 + lane;
   uint32_t nrec = a.g_nrec[t];
@@ -576,7 +577,6 @@ __device__ __forceinline__ void slots_wave(const PreArgs& a, int t0, int* list, 
     const uint32_t ur = __shfl_up(pr, d, 64), ui = __shfl_up(pi, d, 64);
     if (lane >= d) { pr += ur; pi += ui; }
   }
-  const uint2 wb = a.wave_cnt[t0 >> 6];
   const uint32_t rbase = wb.x + pr - nrec, ibase = wb.y + pi - ninst;
   const bool fits = (uint64_t)rbase + nrec <= a.rc.rec_cap && (uint64_t)ibase + ninst <= a.rc.inst_cap;
   a.g_rbase[t] = rbase;
@@ -851,6 +851,45 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The (records, instances) counts of wavefronts [0, w_end) added up by the
+// workgroup's 256 threads (every thread gets the sum; integer sums, so the
+// order does not matter).  With the count's per-wavefront sums unscanned,
+// each workgroup of the emit forms its own bases this way (the scan kernel
+// is one launch fewer; the wavefront counts are a few tens of KB in L2).
+// Not inlined: inlined, it raised the emit's registers past the four
+// wavefronts per SIMD it runs at (127 -> 139 VGPRs).
+__device__ __attribute__((noinline)) uint2 block_wave_sum(const uint2* __restrict__ cnt, int w_end, uint2* sh) {
+  uint2 s = make_uint2(0u, 0u);
+#pragma unroll 8
+  for (int w = (int)threadIdx.x; w < w_end; w += 256) {
+    const uint2 v = cnt[w];
+    s.x += v.x;
+    s.y += v.y;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    s.x += __shfl_xor(s.x, o, 64);
+    s.y += __shfl_xor(s.y, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const uint2 r = make_uint2((sh[0].x + sh[1].x) + (sh[2].x + sh[3].x), (sh[0].y + sh[1].y) + (sh[2].y + sh[3].y));
+  __syncthreads();   // sh is rewritten by the next call
+  return r;
+}
+
+// The first slots of wavefront t0 / 64: from the scan, or the workgroup's base
+// for wavefront w0 plus the counts of wavefronts w0 .. t0 / 64 - 1.
+__device__ __forceinline__ uint2 wave_base(const PreArgs& a, uint2 bb, int w0, int t0) {
+  if (a.scanned) return a.wave_cnt[t0 >> 6];
+  for (int w = w0; w < (t0 >> 6); ++w) {
+    const uint2 v = a.wave_cnt[w];
+    bb.x += v.x;
+    bb.y += v.y;
+  }
+  return bb;
+}
+
 // Grid-stride over whole wavefronts of flattened Gaussians, so that a launch
 // sized for the workspace capacity serves any batch (sizes from the header).
 // The binary searches over slice depths read (z, sigma_z) from an LDS copy
@@ -955,19 +994,32 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   __shared__ uint2 stg[4][W >= 8 ? kStagePerLane * 64 : 1];
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
+  __shared__ uint2 s_sum[4];
   const int wave = threadIdx.x >> 6;
   const int chunk = a.emit_chunk;
+  if (!a.scanned && blockIdx.x == 0) {
+    // the totals, which the sort and the host read
+    const uint2 tot = block_wave_sum(a.wave_cnt, a.hdr->n_waves, s_sum);
+    if (threadIdx.x == 0) {
+      a.ctr[kCtrRecords] = tot.x;
+      a.ctr[kCtrInstances] = tot.y;
+    }
+  }
   if (chunk == 256) {
-    // one wavefront's 64 Gaussians at a time, synchronised within the wavefront only
+    // one wavefront's 64 Gaussians at a time, synchronised within the
+    // wavefront only (the workgroup meets once per round, for its base)
     __shared__ int n_w[4];
     int* wl = list + wave * 64;
     const int lane = threadIdx.x & 63;
-    for (int t0 = blockIdx.x * 256 + wave * 64; t0 < total; t0 += gridDim.x * 256) {
+    for (int base = blockIdx.x * 256; base < total; base += gridDim.x * 256) {
+      const uint2 bb = a.scanned ? make_uint2(0u, 0u) : block_wave_sum(a.wave_cnt, base >> 6, s_sum);
+      const int t0 = base + wave * 64;
+      if (t0 >= total) continue;
       if (lane == 0) n_w[wave] = 0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      slots_wave(a, t0, wl, &n_w[wave]);
+      slots_wave(a, t0, wave_base(a, bb, base >> 6, t0), wl, &n_w[wave]);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -979,8 +1031,10 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   }
   for (int base = blockIdx.x * chunk; base < total; base += gridDim.x * chunk) {
     if (threadIdx.x == 0) n_list = 0;
+    const uint2 bb = a.scanned ? make_uint2(0u, 0u) : block_wave_sum(a.wave_cnt, base >> 6, s_sum);
     __syncthreads();
-    for (int t0 = base + wave * 64; t0 < min(base + chunk, total); t0 += 256) slots_wave(a, t0, list, &n_list);
+    for (int t0 = base + wave * 64; t0 < min(base + chunk, total); t0 += 256)
+      slots_wave(a, t0, wave_base(a, bb, base >> 6, t0), list, &n_list);
     __syncthreads();
     const uint32_t n = (uint32_t)n_list;
     // the list spread over the four wavefronts in whole rounds of 64 / W
@@ -1051,7 +1105,7 @@ hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDi
 static PreArgs pre_args(const RenderConst& rc, const Workspace& ws, uint32_t sentinel_bin) {
   return PreArgs{rc, ws.d_hdr, ws.d_groups, ws.d_slices, ws.d_ctr, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase,
                  ws.d_g_nrec, ws.d_g_ninst, ws.d_g_krange, ws.d_wave_cnt, ws.d_inst_key, ws.d_inst_val,
-                 sentinel_bin, ws.d_poses, 256, 0, ws.d_work, ws.d_bin_lo, ws.d_bin_hi, 0};
+                 sentinel_bin, ws.d_poses, 256, 1, 0, ws.d_work, ws.d_bin_lo, ws.d_bin_hi, 0};
 }
 
 hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, bool clear_overflow,
@@ -1075,9 +1129,10 @@ hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const La
 }
 
 hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, uint32_t sentinel_bin,
-                           hipStream_t s) {
+                           bool scanned, hipStream_t s) {
   if (d.gauss <= 0) return hipSuccess;
   PreArgs a = pre_args(rc, ws, sentinel_bin);
+  a.scanned = scanned ? 1 : 0;
   // few slices per Gaussian set (narrow emit): most Gaussians have no record
   a.emit_chunk = d.emit_width >= 16 ? 256 : kEmitChunk;
   int64_t blocks = (d.gauss + a.emit_chunk - 1) / a.emit_chunk;
