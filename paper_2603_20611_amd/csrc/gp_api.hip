@@ -117,7 +117,8 @@ gp_status reserve_small(Workspace* ws, int64_t n_slices, int64_t n_groups, int64
     GP_HIP(dev_alloc(&ws->d_g_nrec, cap));
     GP_HIP(dev_alloc(&ws->d_g_ninst, cap));
     GP_HIP(dev_alloc(&ws->d_g_krange, cap));
-    GP_HIP(dev_alloc(&ws->d_wave_cnt, cap / 64 + 1));
+    // the wavefront counts, then the counts of 512-Gaussian chunks
+    GP_HIP(dev_alloc(&ws->d_wave_cnt, cap / 64 + 1 + cap / 512 + 1));
     ws->gauss_cap = cap;
     ws->wave_cap = cap / 64 + 1;
   }
@@ -379,7 +380,7 @@ gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hi
   if (st != GP_OK) return st;
   const bool clear_ovf = ws->auto_size || ws->overflow_per_forward;
   constexpr int64_t kEmitBasesMaxWaves = 16384;
-  const bool scanned = ws->auto_size || d.emit_width >= 16 || d.gauss / 64 > kEmitBasesMaxWaves;
+  const bool scanned = ws->auto_size || d.posed || d.emit_width >= 16 || d.gauss / 64 > kEmitBasesMaxWaves;
   GP_HIP(timed(ws, GP_STAGE_PREPROCESS, s, [&] {
     // (the count also resets the forward's counters).  The wavefront counts
     // are scanned here when the host reads the totals before the emit
@@ -389,7 +390,7 @@ gp_status enqueue_forward(Workspace* ws, RenderConst rc, const LaunchDims& d, hi
     // kEmitBasesMaxWaves wavefronts (a served batch's capacity); otherwise
     // the emit forms its bases and the totals (8-slice batch: 0.0277 +
     // 0.0183 -> 0.0205 + 0.0226 ms).
-    hipError_t e = launch_pre_count(rc, *ws, d, clear_ovf, s);
+    hipError_t e = launch_pre_count(rc, *ws, d, clear_ovf, scanned, s);
     if (e == hipSuccess && scanned)
       e = launch_scan_u32x2(ws->d_wave_cnt, ws->d_wave_cnt, &ws->d_hdr->n_waves, d.gauss / 64, ws->d_scan_part,
                             reinterpret_cast<uint2*>(ws->d_ctr + kCtrRecords), s);

@@ -328,8 +328,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDims& d, hipStream_t s);
 // Count of the forward, which also resets its counters, work queues and bin
 // ranges (one launch fewer per forward).
+// scanned: the wavefront counts will be scanned by the scan kernel (else the
+// compacting count also writes 512-Gaussian chunk totals for the emit).
 hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, bool clear_overflow,
-                            hipStream_t s);
+                            bool scanned, hipStream_t s);
 // scanned: the wavefront counts were scanned (else the emit forms the bases
 // and writes the totals itself).
 hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, uint32_t sentinel_bin,

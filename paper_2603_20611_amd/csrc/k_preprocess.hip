@@ -81,6 +81,7 @@ struct PreArgs {
   const float* poses;   // [n_slices][12] of a posed batch
   int emit_chunk;       // Gaussians per workgroup round of the emit
   int scanned;          // wave_cnt already holds the scan (else the emit forms its bases and the totals)
+  uint2* chunk_cnt;     // unscanned: the counts of 512-Gaussian chunks (compacting count), or null
   int count_lg;         // log2 of the lanes per near Gaussian in the compacting count
   // the count's own reset of the forward
   uint32_t* work;
@@ -851,17 +852,17 @@ __device__ __forceinline__ void emit_wave(const PreArgs& a, int n_groups, const 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The (records, instances) counts of wavefronts [0, w_end) added up by the
-// workgroup's 256 threads (every thread gets the sum; integer sums, so the
-// order does not matter).  With the count's per-wavefront sums unscanned,
-// each workgroup of the emit forms its own bases this way (the scan kernel
-// is one launch fewer; the wavefront counts are a few tens of KB in L2).
+// The (records, instances) counts cnt[0 .. n) added up by the workgroup's
+// 256 threads (every thread gets the sum; integer sums, so the order does not
+// matter).  With the counts unscanned, each workgroup of the emit forms its
+// own bases this way from the compacting count's 512-Gaussian chunk totals
+// (the scan kernel is one launch fewer; the totals are a few KB in L2).
 // Not inlined: inlined, it raised the emit's registers past the four
 // wavefronts per SIMD it runs at (127 -> 139 VGPRs).
-__device__ __attribute__((noinline)) uint2 block_wave_sum(const uint2* __restrict__ cnt, int w_end, uint2* sh) {
+__device__ __attribute__((noinline)) uint2 block_sum_u2(const uint2* __restrict__ cnt, int n, uint2* sh) {
   uint2 s = make_uint2(0u, 0u);
-#pragma unroll 8
-  for (int w = (int)threadIdx.x; w < w_end; w += 256) {
+#pragma unroll 4
+  for (int w = (int)threadIdx.x; w < n; w += 256) {
     const uint2 v = cnt[w];
     s.x += v.x;
     s.y += v.y;
@@ -878,14 +879,13 @@ __device__ __attribute__((noinline)) uint2 block_wave_sum(const uint2* __restric
   return r;
 }
 
-// The first slots of wavefront t0 / 64: from the scan, or the workgroup's base
-// for wavefront w0 plus the counts of wavefronts w0 .. t0 / 64 - 1.
-__device__ __forceinline__ uint2 wave_base(const PreArgs& a, uint2 bb, int w0, int t0) {
-  if (a.scanned) return a.wave_cnt[t0 >> 6];
-  for (int w = w0; w < (t0 >> 6); ++w) {
-    const uint2 v = a.wave_cnt[w];
-    bb.x += v.x;
-    bb.y += v.y;
+// The first slots of the k-th wavefront of a chunk whose counts are not
+// scanned: the workgroup's base for the chunk plus the counts of the chunk's
+// wavefronts before it (wc: those counts, staged in LDS by one load each).
+__device__ __forceinline__ uint2 wave_base(uint2 bb, const uint2* wc, int k) {
+  for (int w = 0; w < k; ++w) {
+    bb.x += wc[w].x;
+    bb.y += wc[w].y;
   }
   return bb;
 }
@@ -913,6 +913,7 @@ __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
   __shared__ int s_list[COMPACT ? kCountChunk : 1];
   __shared__ uint32_t s_nrec[COMPACT ? kCountChunk : 1], s_ninst[COMPACT ? kCountChunk : 1];
   __shared__ uint32_t s_kr[COMPACT ? kCountChunk : 1];
+  __shared__ uint2 s_csum[4];
   __shared__ int s_n;
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
@@ -963,11 +964,26 @@ __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
       }
       __syncthreads();
       // whole wavefronts (chunk and base are multiples of 64; total is too)
+      uint2 cs = make_uint2(0u, 0u);
       for (int i = threadIdx.x; i < kCountChunk; i += 256) {
         const int t = base + i;
         if ((t & ~63) < total) count_store(a, t, s_nrec[i], s_ninst[i], s_kr[i]);
+        cs.x += s_nrec[i];
+        cs.y += s_ninst[i];
+      }
+      if (a.chunk_cnt) {
+        // the chunk's totals, from which the emit forms its bases
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          cs.x += __shfl_xor(cs.x, o, 64);
+          cs.y += __shfl_xor(cs.y, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) s_csum[threadIdx.x >> 6] = cs;
       }
       __syncthreads();   // the LDS arrays are rewritten by the next chunk
+      if (a.chunk_cnt && threadIdx.x == 0)
+        a.chunk_cnt[base / kCountChunk] = make_uint2((s_csum[0].x + s_csum[1].x) + (s_csum[2].x + s_csum[3].x),
+                                                     (s_csum[0].y + s_csum[1].y) + (s_csum[2].y + s_csum[3].y));
     }
   }
 }
@@ -982,6 +998,8 @@ __global__ __launch_bounds__(256) void k_pre_count(PreArgs a) {
 // nearly all of them and takes 256 at a time (one wavefront's worth each, the
 // most parallel form).
 constexpr int kEmitChunk = 512;
+// (the emit reads the compacting count's chunk totals chunk by chunk)
+static_assert(kEmitChunk == kCountChunk, "emit and count chunks differ");
 
 template <int DT, int W, bool POSED>
 __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
@@ -995,11 +1013,17 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   const int total = a.hdr->total_gauss;
   const int n_groups = a.hdr->n_groups;
   __shared__ uint2 s_sum[4];
+  __shared__ uint2 s_wc[kEmitChunk / 64];
   const int wave = threadIdx.x >> 6;
   const int chunk = a.emit_chunk;
-  if (!a.scanned && blockIdx.x == 0) {
+  // unscanned counts come only with the compacting count, for groups of at
+  // most 8 slices (the deep-stack instantiations leave the code out: it cost
+  // them a wavefront per SIMD in registers)
+  constexpr bool kMayForm = W <= 8;
+  const bool form = kMayForm && !a.scanned;
+  if (form && blockIdx.x == 0) {
     // the totals, which the sort and the host read
-    const uint2 tot = block_wave_sum(a.wave_cnt, a.hdr->n_waves, s_sum);
+    const uint2 tot = block_sum_u2(a.chunk_cnt, (total + kCountChunk - 1) / kCountChunk, s_sum);
     if (threadIdx.x == 0) {
       a.ctr[kCtrRecords] = tot.x;
       a.ctr[kCtrInstances] = tot.y;
@@ -1007,19 +1031,16 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   }
   if (chunk == 256) {
     // one wavefront's 64 Gaussians at a time, synchronised within the
-    // wavefront only (the workgroup meets once per round, for its base)
+    // wavefront only (deep stacks: the counts are always scanned)
     __shared__ int n_w[4];
     int* wl = list + wave * 64;
     const int lane = threadIdx.x & 63;
-    for (int base = blockIdx.x * 256; base < total; base += gridDim.x * 256) {
-      const uint2 bb = a.scanned ? make_uint2(0u, 0u) : block_wave_sum(a.wave_cnt, base >> 6, s_sum);
-      const int t0 = base + wave * 64;
-      if (t0 >= total) continue;
+    for (int t0 = blockIdx.x * 256 + wave * 64; t0 < total; t0 += gridDim.x * 256) {
       if (lane == 0) n_w[wave] = 0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      slots_wave(a, t0, wave_base(a, bb, base >> 6, t0), wl, &n_w[wave]);
+      slots_wave(a, t0, a.wave_cnt[t0 >> 6], wl, &n_w[wave]);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1031,10 +1052,17 @@ __global__ __launch_bounds__(256) void k_pre_emit(PreArgs a) {
   }
   for (int base = blockIdx.x * chunk; base < total; base += gridDim.x * chunk) {
     if (threadIdx.x == 0) n_list = 0;
-    const uint2 bb = a.scanned ? make_uint2(0u, 0u) : block_wave_sum(a.wave_cnt, base >> 6, s_sum);
+    uint2 bb = make_uint2(0u, 0u);
+    if (form) {
+      bb = block_sum_u2(a.chunk_cnt, base / kCountChunk, s_sum);
+      if (threadIdx.x < kEmitChunk / 64) {
+        const int w = (base >> 6) + (int)threadIdx.x;
+        s_wc[threadIdx.x] = w < a.hdr->n_waves ? a.wave_cnt[w] : make_uint2(0u, 0u);
+      }
+    }
     __syncthreads();
     for (int t0 = base + wave * 64; t0 < min(base + chunk, total); t0 += 256)
-      slots_wave(a, t0, wave_base(a, bb, base >> 6, t0), list, &n_list);
+      slots_wave(a, t0, form ? wave_base(bb, s_wc, (t0 - base) >> 6) : a.wave_cnt[t0 >> 6], list, &n_list);
     __syncthreads();
     const uint32_t n = (uint32_t)n_list;
     // the list spread over the four wavefronts in whole rounds of 64 / W
@@ -1105,14 +1133,16 @@ hipError_t launch_reset(const Workspace& ws, bool clear_overflow, const LaunchDi
 static PreArgs pre_args(const RenderConst& rc, const Workspace& ws, uint32_t sentinel_bin) {
   return PreArgs{rc, ws.d_hdr, ws.d_groups, ws.d_slices, ws.d_ctr, ws.d_rec_pay, ws.d_rec_meta, ws.d_g_rbase,
                  ws.d_g_nrec, ws.d_g_ninst, ws.d_g_krange, ws.d_wave_cnt, ws.d_inst_key, ws.d_inst_val,
-                 sentinel_bin, ws.d_poses, 256, 1, 0, ws.d_work, ws.d_bin_lo, ws.d_bin_hi, 0};
+                 sentinel_bin, ws.d_poses, 256, 1, nullptr, 0, ws.d_work, ws.d_bin_lo, ws.d_bin_hi, 0};
 }
 
 hipError_t launch_pre_count(const RenderConst& rc, const Workspace& ws, const LaunchDims& d, bool clear_overflow,
-                            hipStream_t s) {
+                            bool scanned, hipStream_t s) {
   if (d.gauss <= 0) return launch_reset(ws, clear_overflow, d, s);
   PreArgs a = pre_args(rc, ws, 0u);
   a.clear_overflow = clear_overflow ? 1 : 0;
+  a.scanned = scanned ? 1 : 0;
+  if (!scanned) a.chunk_cnt = ws.d_wave_cnt + ws.wave_cap;
   // enough workgroups for the reset of the bin ranges too (16 bins per thread)
   const int64_t reset_blocks = (d.bins + 4095) / 4096;
   auto grid = [&](int64_t per_block) {
@@ -1133,6 +1163,7 @@ hipError_t launch_pre_emit(const RenderConst& rc, const Workspace& ws, const Lau
   if (d.gauss <= 0) return hipSuccess;
   PreArgs a = pre_args(rc, ws, sentinel_bin);
   a.scanned = scanned ? 1 : 0;
+  if (!scanned) a.chunk_cnt = ws.d_wave_cnt + ws.wave_cap;
   // few slices per Gaussian set (narrow emit): most Gaussians have no record
   a.emit_chunk = d.emit_width >= 16 ? 256 : kEmitChunk;
   int64_t blocks = (d.gauss + a.emit_chunk - 1) / a.emit_chunk;
