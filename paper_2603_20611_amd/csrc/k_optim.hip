@@ -28,14 +28,51 @@ __device__ __forceinline__ float adam1(float& p, float g, float& m, float& v, fl
   return p;
 }
 
-// grid.y = parameter row; each thread updates four consecutive elements.
+// grid.y = parameter row; each thread updates two groups of four consecutive
+// elements.
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   const int row = blockIdx.y;
   const float lr = a.lr[group_of_row(row)];
   const bool clamp = (a.flags & GP_ADAM_CLAMP_ALPHA) && row == 10;
   const bool zero = (a.flags & GP_ADAM_ZERO_GRAD) != 0;
   const int64_t base = (int64_t)row * a.stride;
-  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  // a workgroup covers 2,048 elements: each thread two groups of four, 1,024
+  // apart, loaded together when both are whole (eight loads in flight per
+  // array); a tail group takes the single-group path
+  const int64_t b0 = (int64_t)blockIdx.x * 2048 + threadIdx.x * 4;
+  const int64_t b1 = b0 + 1024;
+  const bool aligned = (a.stride & 3) == 0;
+  if (aligned && b1 + 4 <= a.n) {
+    float* __restrict__ P = a.p + base;
+    float* __restrict__ Gr = a.g + base;
+    float* __restrict__ M = a.m + base;
+    float* __restrict__ V = a.v + base;
+    float4 p[2] = {*reinterpret_cast<float4*>(P + b0), *reinterpret_cast<float4*>(P + b1)};
+    const float4 g[2] = {*reinterpret_cast<const float4*>(Gr + b0), *reinterpret_cast<const float4*>(Gr + b1)};
+    float4 m[2] = {*reinterpret_cast<float4*>(M + b0), *reinterpret_cast<float4*>(M + b1)};
+    float4 v[2] = {*reinterpret_cast<float4*>(V + b0), *reinterpret_cast<float4*>(V + b1)};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      adam1(p[h].x, g[h].x, m[h].x, v[h].x, lr, a);
+      adam1(p[h].y, g[h].y, m[h].y, v[h].y, lr, a);
+      adam1(p[h].z, g[h].z, m[h].z, v[h].z, lr, a);
+      adam1(p[h].w, g[h].w, m[h].w, v[h].w, lr, a);
+      if (clamp) {
+        p[h].x = fmaxf(p[h].x, 0.f); p[h].y = fmaxf(p[h].y, 0.f); p[h].z = fmaxf(p[h].z, 0.f); p[h].w = fmaxf(p[h].w, 0.f);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t i = h ? b1 : b0;
+      *reinterpret_cast<float4*>(P + i) = p[h];
+      *reinterpret_cast<float4*>(M + i) = m[h];
+      *reinterpret_cast<float4*>(V + i) = v[h];
+      if (zero) *reinterpret_cast<float4*>(Gr + i) = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return;
+  }
+  for (int h = 0; h < 2; ++h) {
+  const int64_t i0 = h ? b1 : b0;
   if (i0 >= a.n) return;
   const bool vec = (i0 + 4 <= a.n) && ((a.stride & 3) == 0);
   if (vec) {
@@ -64,6 +101,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
       a.v[base + i] = v;
       if (zero) a.g[base + i] = 0.f;
     }
+  }
   }
 }
 
@@ -97,7 +135,7 @@ hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, int64_
   a.inv_bc1 = (float)(1.0 / (1.0 - std::pow((double)c.beta1, (double)c.step)));
   a.inv_bc2 = (float)(1.0 / (1.0 - std::pow((double)c.beta2, (double)c.step)));
   a.flags = c.flags;
-  const int64_t per_block = 256 * 4;
+  const int64_t per_block = 2048;
   dim3 grid((unsigned)((n + per_block - 1) / per_block), 11);
   k_adam<<<grid, 256, 0, s>>>(a);
   return hipGetLastError();
